@@ -1,0 +1,184 @@
+/*
+ * mggpu.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of MG-GLAM (Ruan et al., "Fast full N-body simulations of generic
+ * modified gravity: conformal coupling models", arXiv:2110.00328):
+ *
+ *   cloud-in-cell density  ->  nonlinear FAS multigrid solve of the
+ *   scalar-field equation  ->  fifth-force gradient  (+ adjoints)
+ *
+ * Conventions shared by every entry point
+ *   - Grids are periodic cubes of n^3 cells (n even), C-contiguous
+ *     [k][j][i] with i (x) fastest, code units of Sec. 3.1.1: cell size 1,
+ *     c~ = n (c/H0) / L with c/H0 = 2997.92458 Mpc/h.
+ *   - Every array pointer is a DEVICE pointer owned by the caller; nothing
+ *     is retained after a call returns.  Host pointers (params, options,
+ *     stats, boxes) are read during the call only.
+ *   - Calls are ordered on the context's HIP stream.  mg_solve,
+ *     mg_solve_adjoint and mg_solve_batched synchronise that stream once per
+ *     outer iteration to read the residual norm; the others are asynchronous.
+ *   - Return value: MG_OK (0) or a negative MG_E* code; on MG_EINVAL no
+ *     output has been written.  mg_last_error() gives a message.
+ *   - A context is not thread-safe; use one context per stream.
+ *
+ * The solved field ("field") follows the paper's test quantities
+ * (eq:field_uniform_dens_test): f(R) -> f_R (negative); symmetron ->
+ * u = phi/phi_*; coupled quintessence -> phi~ = c~^2 delta-phi.
+ */
+#ifndef MGGPU_H
+#define MGGPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { MG_OK = 0, MG_EINVAL = -1, MG_ENOCONV = -2, MG_ENAN = -3, MG_EHIP = -4 };
+
+/* Models: Hu-Sawicki f(R) (Sec. 2.3, 3.2.5), symmetron (Sec. 2.2, 3.2.4),
+ * coupled quintessence (Sec. 2.1, 3.2.3). */
+enum { MG_FR = 0, MG_SYMMETRON = 1, MG_CQ = 2 };
+
+/* MG_FP64: the paper's direct nonlinear Gauss-Seidel in FP64 throughout.
+ * MG_FP32_REFINED: FP64 master field and FP64 residuals; each outer step
+ * solves the correction equation F(w + e) - F(w) = -F(w) for e with FP32
+ * multigrid, then w += e. */
+enum { MG_FP64 = 0, MG_FP32_REFINED = 1 };
+
+/* Cycle shapes (Sec. 3.2.1, fig:multigrid_cycles). */
+enum { MG_CYCLE_V = 0, MG_CYCLE_F = 1, MG_CYCLE_W = 2 };
+
+typedef struct {
+  double a;          /* scale factor */
+  double omega_m;    /* Omega_m today; Omega_Lambda = 1 - Omega_m */
+  double box_mpch;   /* box size L in Mpc/h (sets c~) */
+  int fr_n;          /* f(R): Hu-Sawicki n (eq:fR_HS); this build solves n = 1 */
+  double fr_fr0_abs; /* f(R): |f_R0| > 0 */
+  double sym_a_star; /* symmetron: a_* (< a) */
+  double sym_xi;     /* symmetron: xi = H0/m_* (xi c/H0 = Compton length) */
+  double sym_beta_star; /* symmetron: beta_* (force prefactor only) */
+  double cq_alpha;   /* CQ: alpha > 0 (eq:csf_potential) */
+  double cq_beta;    /* CQ: beta (eq:csf_coupling_function) */
+  double cq_phibar;  /* CQ: background field phi-bar(a) > 0 */
+  double cq_lambda;  /* CQ: lambda of eq:csf_param_lambda */
+  int cq_keep_exp;   /* CQ: 1 keeps exp(beta phi~/c~^2) before (1+delta) as in
+                        eq:csf_eom_code; 0 drops it as the paper's runs did */
+} mg_model_params;
+
+typedef struct {
+  int cycle;        /* MG_CYCLE_V / _F / _W */
+  int nu_pre;       /* Gauss-Seidel sweeps (each = both colours) before coarsening, >= 0 */
+  int nu_post;      /* sweeps after the correction, >= 1 */
+  int inner_cycles; /* MG_FP32_REFINED: FP32 cycles per FP64 outer step (>= 1) */
+  int max_cycles;   /* cap on cycles (FP64) or outer steps (refined), 1..64 */
+  int precision;    /* MG_FP64 / MG_FP32_REFINED */
+  int coarse_sweeps;/* cap on sweeps of the coarsest level (0 = default 200) */
+} mg_solver_opts;
+
+typedef struct {
+  int cycles;            /* cycles (FP64) / outer steps (refined) performed */
+  int status;            /* return code of the call */
+  double rel_resid;      /* final RMS(d)/RMS(d at background) */
+  double resid_hist[64]; /* rel_resid after each cycle / outer step */
+  double ms_total;       /* wall time of the call (stream-synchronised) */
+} mg_stats;
+
+typedef struct mg_ctx mg_ctx;
+
+/* Create a context for n^3 grids on a HIP stream (NULL = default stream).
+ * n must be even and >= 4; the level pyramid is n, n/2, ... while the half
+ * is even and >= 4 (4^3 coarsest for n = 2^l, 6^3 for n = 96).  Device
+ * workspace is allocated on first use of each mode and kept until destroy.
+ * Returns MG_EINVAL for a bad n or NULL out. */
+int mg_ctx_create(mg_ctx **out, int n, void *hip_stream);
+void mg_ctx_destroy(mg_ctx *ctx);
+const char *mg_last_error(const mg_ctx *ctx);
+int mg_ctx_levels(const mg_ctx *ctx);
+
+/* Cloud-in-cell density contrast (Sec. 3.1).  pos: n_part x 3 floats (x,y,z)
+ * in code units [0, n); cell c covers [c, c+1) with centre c + 1/2.  Out:
+ * delta[n^3] = rho/mean - 1.  Deposits are 32.32 fixed-point integer
+ * atomics, so the result does not depend on the order of the particles and
+ * the total mass is exact.  MG_EINVAL if n_part <= 0. */
+int cic_assign(mg_ctx *ctx, const float *pos_xyz, int64_t n_part, float *delta_out);
+
+/* Solve the model's scalar-field equation for delta (n^3 floats):
+ *   f(R)      eq:fR_eom_codeunit2 (n = 1), per-cell cubic eq:fR_eom_codeunit
+ *   symmetron eq:sym_eom_code_unit, per-cell cubic eq:sym_cubic_eqn
+ *   CQ        eq:csf_eom_code, Newton-Gauss-Seidel eq:relaxation_iteration
+ * with red-black Gauss-Seidel, FAS coarse equations
+ * (eq:general_pde_numerical_coarse), 8-cell mean restriction and 27/9/3/1
+ * prolongation (eq:solution_correction).  Stops when
+ * RMS(d)/RMS(d at background) <= tol (Sec. 3.2.1 global residual).
+ * field_in: initial guess (NULL = background value); field_out: solution
+ * (n^3 doubles; may equal field_in).  Returns MG_ENOCONV with the last
+ * iterate in field_out if max_cycles is reached, MG_ENAN on a non-finite
+ * residual.  stats may be NULL. */
+int mg_solve(mg_ctx *ctx, int model, const mg_model_params *params,
+             const mg_solver_opts *opts, const float *delta, const double *field_in,
+             double *field_out, double tol, mg_stats *stats);
+
+/* Residual of a field: d = F(field) in FP64 (n^3 doubles out, may be NULL)
+ * and its RMS relative to the background residual in *rel. */
+int mg_residual(mg_ctx *ctx, int model, const mg_model_params *params,
+                const float *delta, const double *field, double *d_out, double *rel);
+
+/* Fifth force g5 = -grad Phi5 by 3-point central differences (Sec. 3.1)
+ * with Phi5 = -c~^2 f_R/2 (eq:F5_fR_codeunit), 3 xi^2 Om beta*^2 c~^2
+ * a*^-3 u^2 (eq:F_5_codeunit) or beta phi~ (eq:csf_particle_geodesic_code2);
+ * the time factor H0/a-dot is left to the caller.  Out: [3][n^3] floats. */
+int mg_force(mg_ctx *ctx, int model, const mg_model_params *params, const double *field,
+             float *force_out);
+
+/* Transpose of mg_force at the given field: grad_force [3][n^3] floats ->
+ * grad_field[n^3] doubles (dLoss/dfield). */
+int mg_force_adjoint(mg_ctx *ctx, int model, const mg_model_params *params,
+                     const double *field, const float *grad_force, double *grad_field_out);
+
+/* Adjoint of mg_solve at a converged field: given dLoss/dfield, return
+ * dLoss/ddelta = -(dF/ddelta) J^{-1} dLoss/dfield, with J = dF/dfield the
+ * symmetric "Laplacian plus diagonal" Jacobian of the same equation, solved
+ * by linear multigrid (FP64, or FP32 inner cycles with FP64 residuals as
+ * selected by opts->precision) to ||r||/||b|| <= tol.  All arrays n^3;
+ * delta float, the rest double. */
+int mg_solve_adjoint(mg_ctx *ctx, int model, const mg_model_params *params,
+                     const mg_solver_opts *opts, const float *delta, const double *field,
+                     const double *grad_field, double *grad_delta_out, double tol,
+                     mg_stats *stats);
+
+/* Loss = sum over the listed cells of |g5|^2 and its gradient with respect
+ * to the force (zero elsewhere).  cells: n_cells int64 linear cell indices.
+ * loss_out: one double on the device. */
+int mg_loss_force_sq(mg_ctx *ctx, const float *force, const int64_t *cells, int64_t n_cells,
+                     float *grad_force_out, double *loss_out);
+
+/* One red-black half-sweep of the finest level in FP64 on a natural-layout
+ * field (the smoother on its own, for parity checks): cells with
+ * (i+j+k)%2 == colour are replaced by their exact per-cell solution. */
+int mg_relax_halfsweep(mg_ctx *ctx, int model, const mg_model_params *params,
+                       const float *delta, double *field, int colour);
+
+/* Restriction (mean of 8 children) and prolongation-add (27/9/3/1) of
+ * natural-layout double grids; coarse grids are (n/2)^3. */
+int mg_restrict(mg_ctx *ctx, const double *fine, double *coarse);
+int mg_prolong_add(mg_ctx *ctx, const double *coarse, double *fine);
+
+/* Many independent boxes of different n and model in one batched solve
+ * (MPI over realisations in the paper, Sec. 3.1).  Each box uses its own
+ * context-free workspace inside ctx; see mg_box_desc. */
+typedef struct {
+  int n;                   /* grid size of this box (even, >= 8) */
+  int model;               /* MG_FR / MG_SYMMETRON / MG_CQ */
+  mg_model_params params;
+  const float *delta;      /* n^3 device floats */
+  double *field;           /* n^3 device doubles: initial guess in (NaN-free), solution out */
+  float *force;            /* [3][n^3] device floats, or NULL */
+} mg_box_desc;
+
+int mg_solve_batched(mg_ctx *ctx, int n_box, const mg_box_desc *boxes,
+                     const mg_solver_opts *opts, double tol, mg_stats *per_box);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,324 @@
+// mg_device.h -- per-cell arithmetic of the three scalar-field equations
+// (Ruan et al., arXiv:2110.00328, Sec. 3.2.3-3.2.5) for gfx950, in two forms:
+//
+//  * direct form (the paper's nonlinear Gauss-Seidel): each cell of one
+//    colour is replaced by the exact solution of its own discrete equation
+//    with the six neighbours held fixed (eq:fR_eom_codeunit,
+//    eq:sym_cubic_eqn) or by one Newton step (eq:relaxation_iteration, CQ);
+//
+//  * correction form (FP32 inner solves of the FP64-refined mode): the
+//    unknown is the correction e about a frozen FP64 iterate x, the equation
+//    is G(e) = F(x + e) - F(x) = rho, and every term of G is written so that
+//    FP32 rounding is relative to e, not to x.  For f(R) the per-cell
+//    equation becomes s^3 + (beta - 1 - gamma) s - beta = 0 in
+//    s = sqrt(1 + e/x) and is polished in sigma = s - 1.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mgg {
+
+enum { FR = 0, SYM = 1, CQ = 2 };
+
+// Model constants in code units (Sec. 3.1.1), computed on the host in FP64.
+struct Consts {
+  int model;
+  int cq_keep_exp;
+  double ct2;      // c~^2
+  double om_a;     // Omega_m / a
+  double K;        // R-bar(a) a^2 / 3 = Omega_m/a + 4 Omega_L a^2
+  double wbar;     // |f_R(a)|
+  double wpow;     // wbar^{1/2} (n = 1)
+  double s_ratio;  // (a_*/a)^3
+  double s_amp;    // a^2 / (2 xi^2)
+  double ubar;     // sqrt(1 - (a_*/a)^3)
+  double beta, alpha, phibar;
+  double cq_src;   // 3 beta Omega_m a^-1 exp(beta phibar)
+  double cq_pot;   // alpha lambda^2 a^2
+  double cq_pb;    // phibar^-(1+alpha)
+  double phi5;     // Phi5 prefactor: c~^2/2 (w), 3 xi^2 Om b*^2 c~^2 a*^-3 (u^2), beta (phi~)
+  double bg;       // background value of the solved variable
+  double bg_coef;  // |d| at the background per unit delta
+};
+
+// ---------------------------------------------------------------------------
+// math overloads
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double d_cbrt(double x) { return cbrt(x); }
+__device__ __forceinline__ float d_cbrt(float x) { return cbrtf(x); }
+__device__ __forceinline__ double d_sinh(double x) { return sinh(x); }
+__device__ __forceinline__ float d_sinh(float x) { return sinhf(x); }
+__device__ __forceinline__ double d_asinh(double x) { return asinh(x); }
+__device__ __forceinline__ float d_asinh(float x) { return asinhf(x); }
+__device__ __forceinline__ double d_cosh(double x) { return cosh(x); }
+__device__ __forceinline__ float d_cosh(float x) { return coshf(x); }
+__device__ __forceinline__ double d_acosh(double x) { return acosh(x); }
+__device__ __forceinline__ float d_acosh(float x) { return acoshf(x); }
+__device__ __forceinline__ double d_cos(double x) { return cos(x); }
+__device__ __forceinline__ float d_cos(float x) { return cosf(x); }
+__device__ __forceinline__ double d_acos(double x) { return acos(x); }
+__device__ __forceinline__ float d_acos(float x) { return acosf(x); }
+__device__ __forceinline__ double d_exp(double x) { return exp(x); }
+__device__ __forceinline__ float d_exp(float x) { return expf(x); }
+__device__ __forceinline__ double d_expm1(double x) { return expm1(x); }
+__device__ __forceinline__ float d_expm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double d_log1p(double x) { return log1p(x); }
+__device__ __forceinline__ float d_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double d_pow(double x, double y) { return pow(x, y); }
+__device__ __forceinline__ float d_pow(float x, float y) { return powf(x, y); }
+__device__ __forceinline__ double d_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float d_rsqrt(float x) { return rsqrtf(x); }
+
+// Root of t^3 + p t + q = 0 on the branch the paper's closed forms select:
+// the single real root, else the largest of three (for q < 0: the unique
+// positive root).  Viete's trigonometric/hyperbolic forms -- Cardano's form
+// cancels catastrophically when p^{3/2} >> |q| -- and one Newton step.
+template <typename T>
+__device__ __forceinline__ T cubic_root(T p, T q) {
+  T t;
+  if (p == T(0)) {
+    t = d_cbrt(-q);
+  } else if (p > T(0)) {
+    T s = d_sqrt(p / T(3));
+    T x = (T(1.5) * q / p) / s;
+    t = T(-2) * s * d_sinh(d_asinh(x) / T(3));
+  } else {
+    T s = d_sqrt(-p / T(3));
+    T x = (T(1.5) * q / p) / s;
+    if (x >= T(1))
+      t = T(2) * s * d_cosh(d_acosh(x) / T(3));
+    else if (x <= T(-1))
+      t = T(-2) * s * d_cosh(d_acosh(-x) / T(3));
+    else
+      t = T(2) * s * d_cos(d_acos(x) / T(3));
+  }
+  T f = (t * t + p) * t + q;
+  T fp = T(3) * t * t + p;
+  if (fp != T(0)) {
+    T tn = t - f / fp;
+    if (isfinite(tn)) t = tn;
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// direct form: v <- exact per-cell solution of L^h(v)_c = S_c
+// ---------------------------------------------------------------------------
+// h2 = h^2 of the level (fine cell units), sum = sum of the six neighbours.
+template <int M, typename T>
+__device__ __forceinline__ T direct_update(const Consts& C, T h2, T vc, T sum, T dc, T sc) {
+  if constexpr (M == FR) {
+    // u^3 + p u + q = 0, w = u^2 (eq:fR_eom_codeunit, n = 1; S shifts p)
+    T g = h2 / (T(6) * T(C.ct2));
+    T p = g * (T(C.om_a) * dc + T(C.K) - sc) - sum / T(6);
+    T q = -g * T(C.K) * T(C.wpow);
+    T u = cubic_root<T>(p, q);
+    return u * u;
+  } else if constexpr (M == SYM) {
+    // u^3 + p u + q = 0 (eq:sym_cubic_eqn; S shifts q)
+    T kap = T(C.ct2) / (T(C.s_amp) * h2);
+    T p = (T(1) + dc) * T(C.s_ratio) - T(1) + T(6) * kap;
+    T q = -kap * sum + sc / T(C.s_amp);
+    return cubic_root<T>(p, q);
+  } else {
+    // Newton-Gauss-Seidel on eq:csf_eom_code
+    T ct2 = T(C.ct2);
+    T al = T(C.alpha);
+    T x = C.cq_keep_exp ? T(C.beta) * vc / ct2 : T(0);
+    T yb = vc / (ct2 * T(C.phibar));
+    T lp = d_log1p(yb);
+    T F = (sum - T(6) * vc) / h2 - T(C.cq_src) * (d_expm1(x) * (T(1) + dc) + dc) +
+          T(C.cq_pot) * T(C.cq_pb) * d_expm1(-(T(1) + al) * lp) - sc;
+    T ex = C.cq_keep_exp ? d_exp(x) : T(0);
+    T dF = T(-6) / h2 - T(C.cq_src) * T(C.beta) / ct2 * ex * (T(1) + dc) -
+           T(C.cq_pot) * (T(1) + al) / ct2 * T(C.cq_pb) / T(C.phibar) *
+               d_exp(-(T(2) + al) * lp);
+    return vc - F / dF;
+  }
+}
+
+// direct form residual d = L^h(v)_c - S_c
+template <int M, typename T>
+__device__ __forceinline__ T direct_resid(const Consts& C, T h2, T vc, T sum, T dc, T sc) {
+  T lap = (sum - T(6) * vc) / h2;
+  if constexpr (M == FR) {
+    return -T(C.ct2) * lap + T(C.om_a) * dc + T(C.K) - T(C.K) * T(C.wpow) * d_rsqrt(vc) - sc;
+  } else if constexpr (M == SYM) {
+    return T(C.ct2) * lap - T(C.s_amp) * (((T(1) + dc) * T(C.s_ratio) - T(1)) * vc + vc * vc * vc) - sc;
+  } else {
+    T ct2 = T(C.ct2);
+    T x = C.cq_keep_exp ? T(C.beta) * vc / ct2 : T(0);
+    T lp = d_log1p(vc / (ct2 * T(C.phibar)));
+    return lap - T(C.cq_src) * (d_expm1(x) * (T(1) + dc) + dc) +
+           T(C.cq_pot) * T(C.cq_pb) * d_expm1(-(T(1) + T(C.alpha)) * lp) - sc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// correction form (FP32): G(e)_c = F(x+e)_c - F(x)_c, solve G_c = rho_c
+// ---------------------------------------------------------------------------
+// Nonlinear part N(x+e) - N(x) of each model, accurate relative to e.
+template <int M>
+__device__ __forceinline__ float corr_nl(const Consts& C, float e, float x, float dc) {
+  if constexpr (M == FR) {
+    // K wbar^{1/2} [x^{-1/2} - (x+e)^{-1/2}] = A [1 - (1+t)^{-1/2}], t = e/x
+    //   = A t / (s (1 + s)), s = sqrt(1+t)
+    float t = e / x;
+    float s = sqrtf(1.0f + t);
+    float A = float(C.K * C.wpow) * rsqrtf(x);
+    return A * t / (s * (1.0f + s));
+  } else if constexpr (M == SYM) {
+    // -s_amp [ (rho a*^3/a^3 - 1 + 3x^2) e + 3x e^2 + e^3 ]
+    float m = (1.0f + dc) * float(C.s_ratio) - 1.0f + 3.0f * x * x;
+    return -float(C.s_amp) * (m + (3.0f * x + e) * e) * e;
+  } else {
+    float ct2 = float(C.ct2);
+    float ex = C.cq_keep_exp ? expf(float(C.beta) * x / ct2) : 1.0f;
+    float src = C.cq_keep_exp ? ex * expm1f(float(C.beta) * e / ct2) * (1.0f + dc) : 0.0f;
+    float Y = float(C.phibar) + x / ct2;
+    float pot = powf(Y, -(1.0f + float(C.alpha))) *
+                expm1f(-(1.0f + float(C.alpha)) * log1pf(e / (ct2 * Y)));
+    return -float(C.cq_src) * src + float(C.cq_pot) * pot;
+  }
+}
+
+// Laplacian coefficient kappa of each model: F = -kap Lap (f(R)), +kap Lap
+// (symmetron, CQ); the sign is folded into corr_G.
+template <int M>
+__device__ __forceinline__ float corr_G(const Consts& C, float h2, float ec, float sum, float x,
+                                        float dc) {
+  float lap = (sum - 6.0f * ec) / h2;
+  if constexpr (M == FR) return -float(C.ct2) * lap + corr_nl<M>(C, ec, x, dc);
+  else if constexpr (M == SYM) return float(C.ct2) * lap + corr_nl<M>(C, ec, x, dc);
+  else return lap + corr_nl<M>(C, ec, x, dc);
+}
+
+// Exact per-cell solve of G_c(e) = rho with the neighbours fixed.
+template <int M>
+__device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec_old, float sum,
+                                             float x, float dc, float rho) {
+  if constexpr (M == FR) {
+    // D x t + A [1 - (1+t)^{-1/2}] = R,  D = 6c^2/h^2, R = rho + c^2 sum / h^2
+    // s = sqrt(1+t):  s^3 + (beta - 1 - gamma) s - beta = 0,
+    //   beta = A / (D x), gamma = R / (D x);  sigma = s - 1 solves
+    //   sigma^3 + 3 sigma^2 + (2 + beta - gamma) sigma - gamma = 0.
+    float c2h2 = float(C.ct2) / h2;
+    float ix = 1.0f / x;
+    float iD = 1.0f / (6.0f * c2h2);
+    float beta = float(C.K * C.wpow) * iD * ix * sqrtf(ix);
+    float gamma = (rho * iD + sum * (1.0f / 6.0f)) * ix;
+    float c1 = 2.0f + beta - gamma;
+    float sg;
+    if (fabsf(gamma) < 1e-2f * c1) {
+      sg = gamma / c1;  // small correction: linear guess, Newton below
+    } else {
+      float s = cubic_root<float>(beta - 1.0f - gamma, -beta);
+      sg = s - 1.0f;
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      float f = ((sg + 3.0f) * sg + c1) * sg - gamma;
+      float fp = (3.0f * sg + 6.0f) * sg + c1;
+      sg -= f / fp;
+    }
+    return x * sg * (sg + 2.0f);
+  } else if constexpr (M == SYM) {
+    // e^3 + 3x e^2 + P e + Q = 0, P = m + 6 kap, Q = rho/s_amp - kap sum,
+    // m = (1+delta) a*^3/a^3 - 1 + 3x^2, kap = c^2/(s_amp h^2)
+    float kap = float(C.ct2) / (float(C.s_amp) * h2);
+    float P = (1.0f + dc) * float(C.s_ratio) - 1.0f + 3.0f * x * x + 6.0f * kap;
+    float Q = rho / float(C.s_amp) - kap * sum;
+    float e;
+    if (P > 0.0f && fabsf(Q) < 1e-2f * P * fabsf(x)) {
+      e = -Q / P;
+    } else {
+      // total field y = x + e solves y^3 + p y + q = 0 (paper's branch)
+      float p = P - 3.0f * x * x;
+      float q = (2.0f * x * x - P) * x + Q;
+      e = cubic_root<float>(p, q) - x;
+    }
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      float g = ((e + 3.0f * x) * e + P) * e + Q;
+      float gp = (3.0f * e + 6.0f * x) * e + P;
+      if (gp != 0.0f) e -= g / gp;
+    }
+    return e;
+  } else {
+    // Newton-Gauss-Seidel (eq:relaxation_iteration) on the correction
+    float ct2 = float(C.ct2);
+    float G = corr_G<M>(C, h2, ec_old, sum, x, dc) - rho;
+    float ex = C.cq_keep_exp ? expf(float(C.beta) * (x + ec_old) / ct2) : 0.0f;
+    float Y = float(C.phibar) + (x + ec_old) / ct2;
+    float dG = -6.0f / h2 - float(C.cq_src) * float(C.beta) / ct2 * ex * (1.0f + dc) -
+               float(C.cq_pot) * (1.0f + float(C.alpha)) / ct2 *
+                   powf(Y, -(2.0f + float(C.alpha)));
+    return ec_old - G / dG;
+  }
+}
+
+// d G_c / d e_c (diagonal of the correction operator; used by the uniform-
+// mode Newton step of the coarsest CQ level)
+template <int M>
+__device__ __forceinline__ float corr_diag(const Consts& C, float h2, float ec, float x, float dc) {
+  float ct2 = float(C.ct2);
+  if constexpr (M == CQ) {
+    float ex = C.cq_keep_exp ? expf(float(C.beta) * (x + ec) / ct2) : 0.0f;
+    float Y = float(C.phibar) + (x + ec) / ct2;
+    return -6.0f / h2 - float(C.cq_src) * float(C.beta) / ct2 * ex * (1.0f + dc) -
+           float(C.cq_pot) * (1.0f + float(C.alpha)) / ct2 * powf(Y, -(2.0f + float(C.alpha)));
+  } else {
+    return 1.0f;
+  }
+}
+
+// direct-form diagonal dF_c/dv_c (uniform-mode Newton step, CQ)
+template <int M, typename T>
+__device__ __forceinline__ T direct_diag(const Consts& C, T h2, T vc, T dc) {
+  if constexpr (M == CQ) {
+    T ct2 = T(C.ct2);
+    T ex = C.cq_keep_exp ? d_exp(T(C.beta) * vc / ct2) : T(0);
+    T Y = T(C.phibar) + vc / ct2;
+    return T(-6) / h2 - T(C.cq_src) * T(C.beta) / ct2 * ex * (T(1) + dc) -
+           T(C.cq_pot) * (T(1) + T(C.alpha)) / ct2 * d_pow(Y, -(T(2) + T(C.alpha)));
+  } else {
+    return T(1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Linearised operator for the adjoint:  J = s A,
+//   A v = kap (6 v - sum v)/h^2 + dg_c v   (symmetric positive definite)
+// ---------------------------------------------------------------------------
+// kap and s per model; dg_c and dF_c/ddelta_c from the converged field.
+__host__ __device__ __forceinline__ double lin_kap(const Consts& C) {
+  return C.model == CQ ? 1.0 : C.ct2;
+}
+__host__ __device__ __forceinline__ double lin_sign(const Consts& C) {
+  return C.model == FR ? 1.0 : -1.0;
+}
+
+template <int M>
+__device__ __forceinline__ double lin_dg(const Consts& C, double v, double dc) {
+  if constexpr (M == FR) {
+    // K wbar^{1/2} w^{-3/2} / 2
+    return 0.5 * C.K * C.wpow * pow(v, -1.5);
+  } else if constexpr (M == SYM) {
+    return C.s_amp * (((1.0 + dc) * C.s_ratio - 1.0) + 3.0 * v * v);
+  } else {
+    double ex = C.cq_keep_exp ? exp(C.beta * v / C.ct2) : 0.0;
+    return C.cq_src * C.beta / C.ct2 * ex * (1.0 + dc) +
+           C.cq_pot * (1.0 + C.alpha) / C.ct2 * pow(C.phibar + v / C.ct2, -(2.0 + C.alpha));
+  }
+}
+
+template <int M>
+__device__ __forceinline__ double lin_dfd(const Consts& C, double v) {
+  if constexpr (M == FR) return C.om_a;
+  else if constexpr (M == SYM) return -C.s_amp * C.s_ratio * v;
+  else return -C.cq_src * (C.cq_keep_exp ? exp(C.beta * v / C.ct2) : 1.0);
+}
+
+}  // namespace mgg

@@ -1,0 +1,798 @@
+// mg_kernels.h -- generic HIP kernels of the multigrid hot path (gfx950).
+//
+// Data layout: every level-l grid of n^3 cells is stored red/black packed,
+// colour c = (i+j+k)&1 holding the n^3/2 cells of that colour as
+//   P_c[(k*n + j)*nh + ih],  i = 2*ih + ((j + k + c) & 1),  nh = n/2,
+// colour 0 first, colour 1 at offset n^3/2.  A half-sweep then reads one
+// contiguous array (the other colour) and writes another; the six
+// neighbours of (ih,j,k) in colour c are, in the other colour's array,
+// (ih-1+s, j, k), (ih+s, j, k), (ih, j+-1, k), (ih, j, k+-1), s = (j+k+c)&1.
+// The 8 children of coarse cell (I,J,K) are ih = I in both colours of
+// rows j = 2J+b, k = 2K+d, so restriction reads 8 coalesced streams.
+#pragma once
+#include "mg_device.h"
+
+namespace mgg {
+
+struct Lev {
+  int n;         // cells per side
+  int nh;        // n / 2
+  int64_t half;  // n^3 / 2: cells of one colour
+};
+
+constexpr int kBlock = 256;
+constexpr int kMaxFused = 6;   // levels handled by the single-workgroup kernel
+constexpr int kMaxOps = 96;    // operations in a fused cycle program
+
+// Block index remapped so that each of the 8 XCDs (blocks are dealt to XCDs
+// round-robin) works on one contiguous slab of rows: stencil neighbours in
+// j and k then hit the same XCD's L2.
+__device__ __forceinline__ int64_t xcd_block() {
+  uint32_t b = blockIdx.x, nb = gridDim.x;
+  uint32_t per = nb >> 3;
+  if (b < (per << 3)) b = (b & 7u) * per + (b >> 3);
+  return (int64_t)b;
+}
+__device__ __forceinline__ int64_t gid() { return xcd_block() * blockDim.x + threadIdx.x; }
+
+__device__ __forceinline__ void dec(int64_t g, const Lev& L, int& ih, int& j, int& k) {
+  ih = (int)(g % L.nh);
+  int64_t r = g / L.nh;
+  j = (int)(r % L.n);
+  k = (int)(r / L.n);
+}
+__device__ __forceinline__ int64_t prow(const Lev& L, int j, int k) {
+  return ((int64_t)k * L.n + j) * L.nh;
+}
+// packed index (including the colour offset) of natural cell (i,j,k)
+__device__ __forceinline__ int64_t pk_of(const Lev& L, int i, int j, int k) {
+  return (int64_t)((i + j + k) & 1) * L.half + prow(L, j, k) + (i >> 1);
+}
+
+template <typename T>
+__device__ __forceinline__ T nbsum(const Lev& L, const T* __restrict__ o, int ih, int j, int k,
+                                   int s) {
+  int xm = ih - 1 + s;
+  if (xm < 0) xm += L.nh;
+  int xp = ih + s;
+  if (xp >= L.nh) xp -= L.nh;
+  int jm = (j == 0) ? L.n - 1 : j - 1, jp = (j == L.n - 1) ? 0 : j + 1;
+  int km = (k == 0) ? L.n - 1 : k - 1, kp = (k == L.n - 1) ? 0 : k + 1;
+  int64_t r = prow(L, j, k);
+  return (o[r + xm] + o[r + xp]) + (o[prow(L, jm, k) + ih] + o[prow(L, jp, k) + ih]) +
+         (o[prow(L, j, km) + ih] + o[prow(L, j, kp) + ih]);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions (deterministic: fixed per-block order, then one block)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+// Sum over the block; result valid in thread 0.  blockDim.x <= 1024.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    int nw = (blockDim.x + 63) >> 6;
+    for (int q = 0; q < nw; ++q) t += sh[q];
+  }
+  return t;
+}
+// Sum over the block, result broadcast to every thread.
+__device__ __forceinline__ double block_sum_all(double v, double* sh) {
+  double t = block_sum(v, sh);
+  __syncthreads();
+  if (threadIdx.x == 0) sh[16] = t;
+  __syncthreads();
+  return sh[16];
+}
+
+__global__ void k_sum_partials(const double* __restrict__ part, int64_t m, double* out, int slot) {
+  __shared__ double sh[32];
+  double s = 0.0;
+  for (int64_t q = threadIdx.x; q < m; q += blockDim.x) s += part[q];
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) out[slot] = t;
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion
+// ---------------------------------------------------------------------------
+// packed[pk] = scale * natural[nat]; one thread per natural cell.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_pack(Lev L, const TI* __restrict__ nat,
+                                                 TO* __restrict__ pk, double scale) {
+  int64_t g = gid();
+  if (g >= 2 * L.half) return;
+  int i = (int)(g % L.n);
+  int64_t r = g / L.n;
+  int j = (int)(r % L.n), k = (int)(r / L.n);
+  pk[pk_of(L, i, j, k)] = TO(scale * double(nat[g]));
+}
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_unpack(Lev L, const TI* __restrict__ pk,
+                                                   TO* __restrict__ nat, double scale) {
+  int64_t g = gid();
+  if (g >= 2 * L.half) return;
+  int i = (int)(g % L.n);
+  int64_t r = g / L.n;
+  int j = (int)(r % L.n), k = (int)(r / L.n);
+  nat[g] = TO(scale * double(pk[pk_of(L, i, j, k)]));
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ p, int64_t m, T v) {
+  int64_t g = gid();
+  if (g < m) p[g] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Per-level operations written once, called from grid kernels (one cell per
+// thread) and from the fused single-workgroup kernel (strided loops).
+// ---------------------------------------------------------------------------
+// Direct form.  dens/S packed like v; S may be null (finest level).
+template <int M, typename T, typename TD>
+__device__ __forceinline__ void op_smooth_direct(const Lev& L, T* __restrict__ v,
+                                                 const TD* __restrict__ dens,
+                                                 const T* __restrict__ S, int colour, T h2,
+                                                 const Consts& C, int64_t g) {
+  int ih, j, k;
+  dec(g, L, ih, j, k);
+  int s = (j + k + colour) & 1;
+  T* own = v + colour * L.half;
+  const T* oth = v + (1 - colour) * L.half;
+  T sum = nbsum<T>(L, oth, ih, j, k, s);
+  T dc = T(dens[colour * L.half + g]);
+  T sc = S ? S[colour * L.half + g] : T(0);
+  T vc = (M == CQ) ? own[g] : T(0);
+  own[g] = direct_update<M, T>(C, h2, vc, sum, dc, sc);
+}
+
+// residual of packed cell g (both colours: g in [0, n^3))
+template <int M, typename T, typename TD>
+__device__ __forceinline__ T cell_resid_direct(const Lev& L, const T* __restrict__ v,
+                                               const TD* __restrict__ dens,
+                                               const T* __restrict__ S, T h2, const Consts& C,
+                                               int64_t g) {
+  int colour = g >= L.half ? 1 : 0;
+  int64_t gg = g - colour * L.half;
+  int ih, j, k;
+  dec(gg, L, ih, j, k);
+  int s = (j + k + colour) & 1;
+  T sum = nbsum<T>(L, v + (1 - colour) * L.half, ih, j, k, s);
+  T sc = S ? S[g] : T(0);
+  return direct_resid<M, T>(C, h2, v[g], sum, T(dens[g]), sc);
+}
+
+// Coarse cell gc (natural index over nc^3): restrict v and the residual.
+// Writes Rv (packed coarse) into Rv and vinit, R d into Sd.
+template <int M, typename T, typename TD>
+__device__ __forceinline__ void op_resid_restrict_direct(const Lev& Lf, const Lev& Lc,
+                                                         const T* __restrict__ v,
+                                                         const TD* __restrict__ dens,
+                                                         const T* __restrict__ S, T h2,
+                                                         T* __restrict__ Rv, T* __restrict__ vinit,
+                                                         T* __restrict__ Sd, const Consts& C,
+                                                         int64_t gc) {
+  int nc = Lc.n;
+  int I = (int)(gc % nc);
+  int64_t r = gc / nc;
+  int J = (int)(r % nc), K = (int)(r / nc);
+  T sv = T(0), sd = T(0);
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      int j = 2 * J + b, k = 2 * K + d;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        int64_t g = c * Lf.half + prow(Lf, j, k) + I;
+        int s = (j + k + c) & 1;
+        T vc = v[g];
+        T sum = nbsum<T>(Lf, v + (1 - c) * Lf.half, I, j, k, s);
+        T sc = S ? S[g] : T(0);
+        sv += vc;
+        sd += direct_resid<M, T>(C, h2, vc, sum, T(dens[g]), sc);
+      }
+    }
+  int64_t pc = pk_of(Lc, I, J, K);
+  T rv = sv * T(0.125);
+  Rv[pc] = rv;
+  vinit[pc] = rv;
+  Sd[pc] = sd * T(0.125);
+}
+
+// S^H = L^H(R v) - R d  (in place on S, which holds R d); g over nc^3 packed
+template <int M, typename T, typename TD>
+__device__ __forceinline__ void op_coarse_src_direct(const Lev& L, const T* __restrict__ Rv,
+                                                     const TD* __restrict__ dens,
+                                                     T* __restrict__ S, T h2, const Consts& C,
+                                                     int64_t g) {
+  T F = cell_resid_direct<M, T, TD>(L, Rv, dens, (const T*)nullptr, h2, C, g);
+  S[g] = F - S[g];
+}
+
+// v^h += P(vH - RvH) with 27/9/3/1 weights (RvH may be null); g over n^3 packed
+template <typename T>
+__device__ __forceinline__ void op_prolong_add(const Lev& Lf, const Lev& Lc, T* __restrict__ v,
+                                               const T* __restrict__ vH,
+                                               const T* __restrict__ RvH, int64_t g) {
+  int colour = g >= Lf.half ? 1 : 0;
+  int64_t gg = g - colour * Lf.half;
+  int ih, j, k;
+  dec(gg, Lf, ih, j, k);
+  int s = (j + k + colour) & 1;
+  int I = ih, J = j >> 1, K = k >> 1;
+  int nc = Lc.n;
+  int I1 = s ? (I + 1 == nc ? 0 : I + 1) : (I == 0 ? nc - 1 : I - 1);
+  int J1 = (j & 1) ? (J + 1 == nc ? 0 : J + 1) : (J == 0 ? nc - 1 : J - 1);
+  int K1 = (k & 1) ? (K + 1 == nc ? 0 : K + 1) : (K == 0 ? nc - 1 : K - 1);
+  const int Is[2] = {I, I1}, Js[2] = {J, J1}, Ks[2] = {K, K1};
+  T acc = T(0);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        int64_t pc = pk_of(Lc, Is[a], Js[b], Ks[d]);
+        T c = RvH ? (vH[pc] - RvH[pc]) : vH[pc];
+        T w = T((a ? 1 : 3) * (b ? 1 : 3) * (d ? 1 : 3)) * T(1.0 / 64.0);
+        acc += w * c;
+      }
+  v[g] += acc;
+}
+
+// plain 8-mean restriction, natural coarse index gc, packed in/out
+template <typename TI, typename TO>
+__device__ __forceinline__ void op_restrict(const Lev& Lf, const Lev& Lc, const TI* __restrict__ f,
+                                            TO* __restrict__ c, int64_t gc) {
+  int nc = Lc.n;
+  int I = (int)(gc % nc);
+  int64_t r = gc / nc;
+  int J = (int)(r % nc), K = (int)(r / nc);
+  double s = 0.0;
+  for (int d = 0; d < 2; ++d)
+    for (int b = 0; b < 2; ++b) {
+      int64_t row = prow(Lf, 2 * J + b, 2 * K + d) + I;
+      s += double(f[row]) + double(f[Lf.half + row]);
+    }
+  c[pk_of(Lc, I, J, K)] = TO(s * 0.125);
+}
+
+// Correction form (FP32)
+template <int M>
+__device__ __forceinline__ void op_smooth_corr(const Lev& L, float* __restrict__ e,
+                                               const float* __restrict__ X,
+                                               const float* __restrict__ dens,
+                                               const float* __restrict__ rho, int colour, float h2,
+                                               const Consts& C, int64_t g) {
+  int ih, j, k;
+  dec(g, L, ih, j, k);
+  int s = (j + k + colour) & 1;
+  float* own = e + colour * L.half;
+  float sum = nbsum<float>(L, e + (1 - colour) * L.half, ih, j, k, s);
+  int64_t q = colour * L.half + g;
+  float dc = (M == FR) ? 0.0f : dens[q];
+  float eo = (M == CQ) ? own[g] : 0.0f;
+  own[g] = corr_update<M>(C, h2, eo, sum, X[q], dc, rho[q]);
+}
+
+template <int M>
+__device__ __forceinline__ float cell_resid_corr(const Lev& L, const float* __restrict__ e,
+                                                 const float* __restrict__ X,
+                                                 const float* __restrict__ dens,
+                                                 const float* __restrict__ rho, float h2,
+                                                 const Consts& C, int64_t g) {
+  int colour = g >= L.half ? 1 : 0;
+  int64_t gg = g - colour * L.half;
+  int ih, j, k;
+  dec(gg, L, ih, j, k);
+  int s = (j + k + colour) & 1;
+  float sum = nbsum<float>(L, e + (1 - colour) * L.half, ih, j, k, s);
+  float dc = (M == FR) ? 0.0f : dens[g];
+  float r = rho ? rho[g] : 0.0f;
+  return corr_G<M>(C, h2, e[g], sum, X[g], dc) - r;
+}
+
+// coarse cell gc: Re -> eH and eR, R(G(e) - rho) -> rhoH, optionally R X -> XH
+template <int M>
+__device__ __forceinline__ void op_resid_restrict_corr(
+    const Lev& Lf, const Lev& Lc, const float* __restrict__ e, const float* __restrict__ X,
+    const float* __restrict__ dens, const float* __restrict__ rho, float h2,
+    float* __restrict__ eH, float* __restrict__ eR, float* __restrict__ rhoH,
+    float* __restrict__ XH, const Consts& C, int64_t gc) {
+  int nc = Lc.n;
+  int I = (int)(gc % nc);
+  int64_t r = gc / nc;
+  int J = (int)(r % nc), K = (int)(r / nc);
+  float se = 0.0f, sd = 0.0f, sx = 0.0f;
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      int j = 2 * J + b, k = 2 * K + d;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        int64_t g = c * Lf.half + prow(Lf, j, k) + I;
+        int s = (j + k + c) & 1;
+        float ec = e[g];
+        float sum = nbsum<float>(Lf, e + (1 - c) * Lf.half, I, j, k, s);
+        float x = X[g];
+        float dc = (M == FR) ? 0.0f : dens[g];
+        se += ec;
+        if (XH) sx += x;
+        sd += corr_G<M>(C, h2, ec, sum, x, dc) - rho[g];
+      }
+    }
+  int64_t pc = pk_of(Lc, I, J, K);
+  float re = se * 0.125f;
+  eH[pc] = re;
+  eR[pc] = re;
+  rhoH[pc] = sd * 0.125f;
+  if (XH) XH[pc] = sx * 0.125f;
+}
+
+template <int M>
+__device__ __forceinline__ void op_coarse_src_corr(const Lev& L, const float* __restrict__ eR,
+                                                   const float* __restrict__ X,
+                                                   const float* __restrict__ dens,
+                                                   float* __restrict__ rho, float h2,
+                                                   const Consts& C, int64_t g) {
+  float G = cell_resid_corr<M>(L, eR, X, dens, (const float*)nullptr, h2, C, g);
+  rho[g] = G - rho[g];
+}
+
+// Linear (adjoint) operator A v = kap (6v - sum)/h^2 + dg v; kh2 = kap/h^2
+template <typename T>
+__device__ __forceinline__ void op_smooth_lin(const Lev& L, T* __restrict__ e,
+                                              const T* __restrict__ dg, const T* __restrict__ r,
+                                              int colour, T kh2, int64_t g) {
+  int ih, j, k;
+  dec(g, L, ih, j, k);
+  int s = (j + k + colour) & 1;
+  T sum = nbsum<T>(L, e + (1 - colour) * L.half, ih, j, k, s);
+  int64_t q = colour * L.half + g;
+  e[q] = (r[q] + kh2 * sum) / (T(6) * kh2 + dg[q]);
+}
+template <typename T>
+__device__ __forceinline__ T cell_lin_resid(const Lev& L, const T* __restrict__ e,
+                                            const T* __restrict__ dg, const T* __restrict__ r,
+                                            T kh2, int64_t g) {
+  int colour = g >= L.half ? 1 : 0;
+  int64_t gg = g - colour * L.half;
+  int ih, j, k;
+  dec(gg, L, ih, j, k);
+  int s = (j + k + colour) & 1;
+  T sum = nbsum<T>(L, e + (1 - colour) * L.half, ih, j, k, s);
+  return r[g] - (kh2 * (T(6) * e[g] - sum) + dg[g] * e[g]);
+}
+// coarse cell gc: rH = R(r - A e), eH = 0
+template <typename T>
+__device__ __forceinline__ void op_lin_resid_restrict(const Lev& Lf, const Lev& Lc,
+                                                      const T* __restrict__ e,
+                                                      const T* __restrict__ dg,
+                                                      const T* __restrict__ r, T kh2,
+                                                      T* __restrict__ rH, T* __restrict__ eH,
+                                                      int64_t gc) {
+  int nc = Lc.n;
+  int I = (int)(gc % nc);
+  int64_t rr = gc / nc;
+  int J = (int)(rr % nc), K = (int)(rr / nc);
+  T sd = T(0);
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      int j = 2 * J + b, k = 2 * K + d;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        int64_t g = c * Lf.half + prow(Lf, j, k) + I;
+        sd += cell_lin_resid<T>(Lf, e, dg, r, kh2, g);
+      }
+    }
+  int64_t pc = pk_of(Lc, I, J, K);
+  rH[pc] = sd * T(0.125);
+  eH[pc] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Grid kernels (one cell per thread)
+// ---------------------------------------------------------------------------
+template <int M, typename T, typename TD>
+__global__ __launch_bounds__(kBlock) void k_smooth_direct(Lev L, T* v, const TD* dens, const T* S,
+                                                          int colour, T h2, Consts C) {
+  int64_t g = gid();
+  if (g < L.half) op_smooth_direct<M, T, TD>(L, v, dens, S, colour, h2, C, g);
+}
+template <int M, typename T, typename TD>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict_direct(Lev Lf, Lev Lc, const T* v,
+                                                                  const TD* dens, const T* S,
+                                                                  T h2, T* Rv, T* vinit, T* Sd,
+                                                                  Consts C) {
+  int64_t g = gid();
+  if (g < 2 * Lc.half)
+    op_resid_restrict_direct<M, T, TD>(Lf, Lc, v, dens, S, h2, Rv, vinit, Sd, C, g);
+}
+template <int M, typename T, typename TD>
+__global__ __launch_bounds__(kBlock) void k_coarse_src_direct(Lev L, const T* Rv, const TD* dens,
+                                                              T* S, T h2, Consts C) {
+  int64_t g = gid();
+  if (g < 2 * L.half) op_coarse_src_direct<M, T, TD>(L, Rv, dens, S, h2, C, g);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(Lev Lf, Lev Lc, T* v, const T* vH,
+                                                        const T* RvH) {
+  int64_t g = gid();
+  if (g < 2 * Lf.half) op_prolong_add<T>(Lf, Lc, v, vH, RvH, g);
+}
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_restrict(Lev Lf, Lev Lc, const TI* f, TO* c) {
+  int64_t g = gid();
+  if (g < 2 * Lc.half) op_restrict<TI, TO>(Lf, Lc, f, c, g);
+}
+// residual of the finest level: sum of d^2 per block (+ optional natural d)
+template <int M, typename T, typename TD>
+__global__ __launch_bounds__(kBlock) void k_resid_norm_direct(Lev L, const T* v, const TD* dens,
+                                                              T h2, Consts C, double* part,
+                                                              double* d_nat) {
+  __shared__ double sh[32];
+  int64_t g = gid();
+  double d = 0.0;
+  if (g < 2 * L.half) {
+    d = double(cell_resid_direct<M, T, TD>(L, v, dens, (const T*)nullptr, h2, C, g));
+    if (d_nat) {
+      int colour = g >= L.half ? 1 : 0;
+      int64_t gg = g - colour * L.half;
+      int ih, j, k;
+      dec(gg, L, ih, j, k);
+      int i = 2 * ih + ((j + k + colour) & 1);
+      d_nat[((int64_t)k * L.n + j) * L.n + i] = d;
+    }
+  }
+  double t = block_sum(d * d, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+// sum of (coef * delta)^2 per block: background residual
+__global__ __launch_bounds__(kBlock) void k_bg_norm(int64_t m, const float* delta, double coef,
+                                                   double* part) {
+  __shared__ double sh[32];
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double d = g < m ? coef * double(delta[g]) : 0.0;
+  double t = block_sum(d * d, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_smooth_corr(Lev L, float* e, const float* X,
+                                                        const float* dens, const float* rho,
+                                                        int colour, float h2, Consts C) {
+  int64_t g = gid();
+  if (g < L.half) op_smooth_corr<M>(L, e, X, dens, rho, colour, h2, C, g);
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict_corr(Lev Lf, Lev Lc, const float* e,
+                                                                const float* X, const float* dens,
+                                                                const float* rho, float h2,
+                                                                float* eH, float* eR, float* rhoH,
+                                                                float* XH, Consts C) {
+  int64_t g = gid();
+  if (g < 2 * Lc.half)
+    op_resid_restrict_corr<M>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, g);
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_coarse_src_corr(Lev L, const float* eR, const float* X,
+                                                            const float* dens, float* rho,
+                                                            float h2, Consts C) {
+  int64_t g = gid();
+  if (g < 2 * L.half) op_coarse_src_corr<M>(L, eR, X, dens, rho, h2, C, g);
+}
+
+// FP64 outer step of the refined mode: d = F(w64) (FP64), rho = -d, X = w64,
+// e = 0; per-block sum of d^2.
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_outer_residual(Lev L, const double* w, const float* dens,
+                                                           Consts C, float* rho, float* X,
+                                                           float* e, double* part) {
+  __shared__ double sh[32];
+  int64_t g = gid();
+  double d = 0.0;
+  if (g < 2 * L.half) {
+    d = cell_resid_direct<M, double, float>(L, w, dens, (const double*)nullptr, 1.0, C, g);
+    rho[g] = float(-d);
+    X[g] = float(w[g]);
+    e[g] = 0.0f;
+  }
+  double t = block_sum(d * d, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+__global__ __launch_bounds__(kBlock) void k_outer_update(int64_t m, double* w, const float* e) {
+  int64_t g = gid();
+  if (g < m) w[g] += double(e[g]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_smooth_lin(Lev L, T* e, const T* dg, const T* r,
+                                                       int colour, T kh2) {
+  int64_t g = gid();
+  if (g < L.half) op_smooth_lin<T>(L, e, dg, r, colour, kh2, g);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lin_resid_restrict(Lev Lf, Lev Lc, const T* e,
+                                                               const T* dg, const T* r, T kh2,
+                                                               T* rH, T* eH) {
+  int64_t g = gid();
+  if (g < 2 * Lc.half) op_lin_resid_restrict<T>(Lf, Lc, e, dg, r, kh2, rH, eH, g);
+}
+// FP64 outer step of the adjoint: r = b - A lam (FP64) -> r (inner
+// precision), e = 0, per-block sum of r^2
+template <typename TO>
+__global__ __launch_bounds__(kBlock) void k_lin_outer(Lev L, const double* lam, const double* dg,
+                                                      const double* b, double kh2, TO* r,
+                                                      TO* e, double* part) {
+  __shared__ double sh[32];
+  int64_t g = gid();
+  double d = 0.0;
+  if (g < 2 * L.half) {
+    d = cell_lin_resid<double>(L, lam, dg, b, kh2, g);
+    r[g] = TO(d);
+    e[g] = TO(0);
+  }
+  double t = block_sum(d * d, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sq_norm(int64_t m, const T* x, double* part) {
+  __shared__ double sh[32];
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double d = g < m ? double(x[g]) : 0.0;
+  double t = block_sum(d * d, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpy_to64(int64_t m, double* y, const T* x) {
+  int64_t g = gid();
+  if (g < m) y[g] += double(x[g]);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cast(int64_t m, const double* x, T* y) {
+  int64_t g = gid();
+  if (g < m) y[g] = T(x[g]);
+}
+
+// ---------------------------------------------------------------------------
+// Fused coarse cycle: one workgroup runs a precomputed program of level
+// operations on the small levels (latency-bound as separate launches).
+// ---------------------------------------------------------------------------
+enum { OP_SMOOTH = 0, OP_DOWN = 1, OP_UP = 2, OP_COARSEST = 3 };
+struct Op {
+  uint8_t kind, lev, count, pad;
+};
+struct FusedProg {
+  int nops;
+  int coarse_sweeps;
+  Op op[kMaxOps];
+};
+// Level pointers of the fused part (index = level - first fused level).
+template <typename T, typename TD>
+struct FusedDirect {
+  int nlev;
+  Lev L[kMaxFused];
+  T h2[kMaxFused];
+  T* v[kMaxFused];
+  const TD* dens[kMaxFused];
+  T* S[kMaxFused];
+  T* Rv[kMaxFused];
+};
+struct FusedCorr {
+  int nlev;
+  Lev L[kMaxFused];
+  float h2[kMaxFused];
+  float* e[kMaxFused];
+  float* X[kMaxFused];
+  const float* dens[kMaxFused];
+  float* rho[kMaxFused];
+  float* eR[kMaxFused];
+};
+template <typename T>
+struct FusedLin {
+  int nlev;
+  Lev L[kMaxFused];
+  T kh2[kMaxFused];
+  T* e[kMaxFused];
+  T* dg[kMaxFused];
+  T* r[kMaxFused];
+};
+
+constexpr int kFusedThreads = 1024;
+
+template <int M, typename T, typename TD>
+__global__ __launch_bounds__(kFusedThreads) void k_fused_direct(FusedDirect<T, TD> F, FusedProg P,
+                                                                Consts C) {
+  __shared__ double sh[32];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int o = 0; o < P.nops; ++o) {
+    const Op op = P.op[o];
+    const int l = op.lev;
+    const Lev L = F.L[l];
+    if (op.kind == OP_SMOOTH) {
+      for (int it = 0; it < op.count; ++it)
+        for (int colour = 0; colour < 2; ++colour) {
+          for (int64_t g = tid; g < L.half; g += nt)
+            op_smooth_direct<M, T, TD>(L, F.v[l], F.dens[l], F.S[l], colour, F.h2[l], C, g);
+          __syncthreads();
+        }
+    } else if (op.kind == OP_DOWN) {
+      const Lev Lc = F.L[l + 1];
+      for (int64_t g = tid; g < 2 * Lc.half; g += nt)
+        op_resid_restrict_direct<M, T, TD>(L, Lc, F.v[l], F.dens[l], F.S[l], F.h2[l], F.Rv[l + 1],
+                                           F.v[l + 1], F.S[l + 1], C, g);
+      __syncthreads();
+      for (int64_t g = tid; g < 2 * Lc.half; g += nt)
+        op_coarse_src_direct<M, T, TD>(Lc, F.Rv[l + 1], F.dens[l + 1], F.S[l + 1], F.h2[l + 1], C,
+                                       g);
+      __syncthreads();
+    } else if (op.kind == OP_UP) {
+      const Lev Lc = F.L[l + 1];
+      for (int64_t g = tid; g < 2 * L.half; g += nt)
+        op_prolong_add<T>(L, Lc, F.v[l], F.v[l + 1], F.Rv[l + 1], g);
+      __syncthreads();
+    } else {  // coarsest: relax until RMS residual drops by 1e-10
+      double r0 = -1.0;
+      for (int it = 0; it < P.coarse_sweeps; ++it) {
+        for (int colour = 0; colour < 2; ++colour) {
+          for (int64_t g = tid; g < L.half; g += nt)
+            op_smooth_direct<M, T, TD>(L, F.v[l], F.dens[l], F.S[l], colour, F.h2[l], C, g);
+          __syncthreads();
+        }
+        double s2 = 0.0, sd = 0.0, sj = 0.0;
+        for (int64_t g = tid; g < 2 * L.half; g += nt) {
+          double d = double(cell_resid_direct<M, T, TD>(L, F.v[l], F.dens[l], F.S[l], F.h2[l], C, g));
+          s2 += d * d;
+          if (M == CQ) {
+            sd += d;
+            sj += double(direct_diag<M, T>(C, F.h2[l], F.v[l][g], T(F.dens[l][g]))) + 6.0 / double(F.h2[l]);
+          }
+        }
+        double tot = block_sum_all(s2, sh);
+        if (M == CQ) {
+          // uniform-mode Newton step: the Laplacian of a constant vanishes,
+          // so sum_c F_c(v + mu) changes only through the per-cell terms
+          double D = block_sum_all(sd, sh);
+          double Jd = block_sum_all(sj, sh);
+          if (Jd != 0.0) {
+            T mu = T(-D / Jd);
+            for (int64_t g = tid; g < 2 * L.half; g += nt) F.v[l][g] += mu;
+          }
+          __syncthreads();
+        }
+        if (r0 < 0.0) r0 = tot;
+        if (tot <= 1e-20 * r0 || tot == 0.0) break;
+      }
+    }
+  }
+}
+
+template <int M>
+__global__ __launch_bounds__(kFusedThreads) void k_fused_corr(FusedCorr F, FusedProg P, Consts C) {
+  __shared__ double sh[32];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int o = 0; o < P.nops; ++o) {
+    const Op op = P.op[o];
+    const int l = op.lev;
+    const Lev L = F.L[l];
+    if (op.kind == OP_SMOOTH) {
+      for (int it = 0; it < op.count; ++it)
+        for (int colour = 0; colour < 2; ++colour) {
+          for (int64_t g = tid; g < L.half; g += nt)
+            op_smooth_corr<M>(L, F.e[l], F.X[l], F.dens[l], F.rho[l], colour, F.h2[l], C, g);
+          __syncthreads();
+        }
+    } else if (op.kind == OP_DOWN) {
+      const Lev Lc = F.L[l + 1];
+      for (int64_t g = tid; g < 2 * Lc.half; g += nt)
+        op_resid_restrict_corr<M>(L, Lc, F.e[l], F.X[l], F.dens[l], F.rho[l], F.h2[l], F.e[l + 1],
+                                  F.eR[l + 1], F.rho[l + 1], (float*)nullptr, C, g);
+      __syncthreads();
+      for (int64_t g = tid; g < 2 * Lc.half; g += nt)
+        op_coarse_src_corr<M>(Lc, F.eR[l + 1], F.X[l + 1], F.dens[l + 1], F.rho[l + 1], F.h2[l + 1],
+                              C, g);
+      __syncthreads();
+    } else if (op.kind == OP_UP) {
+      const Lev Lc = F.L[l + 1];
+      for (int64_t g = tid; g < 2 * L.half; g += nt)
+        op_prolong_add<float>(L, Lc, F.e[l], F.e[l + 1], F.eR[l + 1], g);
+      __syncthreads();
+    } else {
+      double r0 = -1.0;
+      for (int it = 0; it < P.coarse_sweeps; ++it) {
+        for (int colour = 0; colour < 2; ++colour) {
+          for (int64_t g = tid; g < L.half; g += nt)
+            op_smooth_corr<M>(L, F.e[l], F.X[l], F.dens[l], F.rho[l], colour, F.h2[l], C, g);
+          __syncthreads();
+        }
+        double s2 = 0.0, sd = 0.0, sj = 0.0;
+        for (int64_t g = tid; g < 2 * L.half; g += nt) {
+          double d = double(cell_resid_corr<M>(L, F.e[l], F.X[l], F.dens[l], F.rho[l], F.h2[l], C, g));
+          s2 += d * d;
+          if (M == CQ) {
+            sd += d;
+            float dc = F.dens[l][g];
+            sj += double(corr_diag<M>(C, F.h2[l], F.e[l][g], F.X[l][g], dc)) + 6.0 / double(F.h2[l]);
+          }
+        }
+        double tot = block_sum_all(s2, sh);
+        if (M == CQ) {
+          double D = block_sum_all(sd, sh);
+          double Jd = block_sum_all(sj, sh);
+          if (Jd != 0.0) {
+            float mu = float(-D / Jd);
+            for (int64_t g = tid; g < 2 * L.half; g += nt) F.e[l][g] += mu;
+          }
+          __syncthreads();
+        }
+        if (r0 < 0.0) r0 = tot;
+        if (tot <= 1e-20 * r0 || tot == 0.0) break;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFusedThreads) void k_fused_lin(FusedLin<T> F, FusedProg P) {
+  __shared__ double sh[32];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int o = 0; o < P.nops; ++o) {
+    const Op op = P.op[o];
+    const int l = op.lev;
+    const Lev L = F.L[l];
+    if (op.kind == OP_SMOOTH || op.kind == OP_COARSEST) {
+      int count = op.kind == OP_SMOOTH ? op.count : P.coarse_sweeps;
+      double r0 = -1.0;
+      for (int it = 0; it < count; ++it) {
+        for (int colour = 0; colour < 2; ++colour) {
+          for (int64_t g = tid; g < L.half; g += nt)
+            op_smooth_lin<T>(L, F.e[l], F.dg[l], F.r[l], colour, F.kh2[l], g);
+          __syncthreads();
+        }
+        if (op.kind == OP_COARSEST) {
+          double s2 = 0.0, sd = 0.0, sj = 0.0;
+          for (int64_t g = tid; g < 2 * L.half; g += nt) {
+            double d = double(cell_lin_resid<T>(L, F.e[l], F.dg[l], F.r[l], F.kh2[l], g));
+            s2 += d * d;
+            sd += d;
+            sj += double(F.dg[l][g]);
+          }
+          double tot = block_sum_all(s2, sh);
+          double D = block_sum_all(sd, sh);
+          double Jd = block_sum_all(sj, sh);
+          if (Jd != 0.0) {  // uniform-mode correction (A 1 = dg)
+            T mu = T(D / Jd);
+            for (int64_t g = tid; g < 2 * L.half; g += nt) F.e[l][g] += mu;
+          }
+          __syncthreads();
+          if (r0 < 0.0) r0 = tot;
+          if (tot <= 1e-20 * r0 || tot == 0.0) break;
+        }
+      }
+    } else if (op.kind == OP_DOWN) {
+      const Lev Lc = F.L[l + 1];
+      for (int64_t g = tid; g < 2 * Lc.half; g += nt)
+        op_lin_resid_restrict<T>(L, Lc, F.e[l], F.dg[l], F.r[l], F.kh2[l], F.r[l + 1], F.e[l + 1], g);
+      __syncthreads();
+    } else {
+      const Lev Lc = F.L[l + 1];
+      for (int64_t g = tid; g < 2 * L.half; g += nt)
+        op_prolong_add<T>(L, Lc, F.e[l], F.e[l + 1], (const T*)nullptr, g);
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace mgg

@@ -1,0 +1,1140 @@
+// mggpu.hip -- host driver and C ABI of the MI355X multigrid hot path.
+//
+// One context owns the level pyramid of one grid size on one HIP stream.
+// Kernels are in mg_kernels.h / mg_device.h; this file holds the cycle
+// control (V/F/W recursion over the large levels, a precomputed program for
+// the small levels run by one workgroup), the FP64-refined outer loop, the
+// adjoint's linear multigrid, and the CIC / force entry points.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mg_kernels.h"
+#include "mggpu.h"
+
+using namespace mgg;
+
+namespace {
+
+constexpr int kMaxLev = 24;
+constexpr int kFuseN = 16;  // levels with n <= 16 run inside the fused kernel
+constexpr double kCOverH0 = 2997.92458;  // Mpc/h
+
+struct Work64 {  // FP64 direct mode
+  double* v[kMaxLev] = {};
+  double* dens[kMaxLev] = {};  // l >= 1
+  double* S[kMaxLev] = {};     // l >= 1
+  double* Rv[kMaxLev] = {};    // l >= 1
+  float* dens0 = nullptr;      // finest level, packed float
+};
+struct Work32 {  // FP32 correction mode
+  double* w = nullptr;         // FP64 master, packed
+  float* e[kMaxLev] = {};
+  float* X[kMaxLev] = {};
+  float* rho[kMaxLev] = {};
+  float* dens[kMaxLev] = {};
+  float* eR[kMaxLev] = {};
+};
+template <typename T>
+struct WorkLin {  // adjoint linear multigrid in precision T
+  T* e[kMaxLev] = {};
+  T* r[kMaxLev] = {};
+  T* dg[kMaxLev] = {};
+};
+struct WorkAdj {
+  double* v = nullptr;    // forward field (solved variable), packed
+  float* dens = nullptr;  // packed float
+  double* dg = nullptr;   // FP64 diagonal, packed
+  double* b = nullptr;    // right-hand side s * dL/dv, packed
+  double* lam = nullptr;  // FP64 solution, packed
+  WorkLin<float> w32;
+  WorkLin<double> w64;
+  bool have32 = false, have64 = false;
+};
+
+}  // namespace
+
+struct mg_ctx {
+  int n = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int nlev = 0;
+  Lev L[kMaxLev];
+  int fused_from = 0;
+  bool have64 = false, have32 = false, haveAdj = false;
+  Work64 w64;
+  Work32 w32;
+  WorkAdj adj;
+  double* part = nullptr;
+  int64_t part_cap = 0;
+  double* scal = nullptr;      // device scalars
+  double* hscal = nullptr;     // pinned host mirror
+  int64_t* cic = nullptr;      // CIC fixed-point accumulator
+  double* nat64 = nullptr;     // natural-layout scratch (debug entry points)
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+inline unsigned nblk(int64_t m) { return (unsigned)((m + kBlock - 1) / kBlock); }
+
+int fail(mg_ctx* c, int code, const std::string& msg) {
+  c->err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ctx, MG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCHCHK()                                                                   \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, MG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+int dalloc(mg_ctx* ctx, T** p, int64_t count) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(ctx, MG_EHIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  ctx->allocs.push_back(q);
+  *p = (T*)q;
+  return MG_OK;
+}
+
+#define ACHK(x)                 \
+  do {                          \
+    int rc_ = (x);              \
+    if (rc_ != MG_OK) return rc_; \
+  } while (0)
+
+int64_t cells(const Lev& L) { return 2 * L.half; }
+
+int ensure64(mg_ctx* ctx) {
+  if (ctx->have64) return MG_OK;
+  Work64& W = ctx->w64;
+  ACHK(dalloc(ctx, &W.dens0, cells(ctx->L[0])));
+  for (int l = 0; l < ctx->nlev; ++l) {
+    int64_t m = cells(ctx->L[l]);
+    ACHK(dalloc(ctx, &W.v[l], m));
+    if (l > 0) {
+      ACHK(dalloc(ctx, &W.dens[l], m));
+      ACHK(dalloc(ctx, &W.S[l], m));
+      ACHK(dalloc(ctx, &W.Rv[l], m));
+    }
+  }
+  ctx->have64 = true;
+  return MG_OK;
+}
+
+int ensure32(mg_ctx* ctx) {
+  if (ctx->have32) return MG_OK;
+  Work32& W = ctx->w32;
+  ACHK(dalloc(ctx, &W.w, cells(ctx->L[0])));
+  for (int l = 0; l < ctx->nlev; ++l) {
+    int64_t m = cells(ctx->L[l]);
+    ACHK(dalloc(ctx, &W.e[l], m));
+    ACHK(dalloc(ctx, &W.X[l], m));
+    ACHK(dalloc(ctx, &W.rho[l], m));
+    ACHK(dalloc(ctx, &W.dens[l], m));
+    if (l > 0) ACHK(dalloc(ctx, &W.eR[l], m));
+  }
+  ctx->have32 = true;
+  return MG_OK;
+}
+
+template <typename T>
+int ensure_lin(mg_ctx* ctx, WorkLin<T>& W) {
+  for (int l = 0; l < ctx->nlev; ++l) {
+    int64_t m = cells(ctx->L[l]);
+    ACHK(dalloc(ctx, &W.e[l], m));
+    ACHK(dalloc(ctx, &W.r[l], m));
+    if (l > 0 || sizeof(T) == 4) ACHK(dalloc(ctx, &W.dg[l], m));
+  }
+  return MG_OK;
+}
+
+int ensure_adj(mg_ctx* ctx, int precision) {
+  WorkAdj& A = ctx->adj;
+  int64_t m = cells(ctx->L[0]);
+  if (!ctx->haveAdj) {
+    ACHK(dalloc(ctx, &A.v, m));
+    ACHK(dalloc(ctx, &A.dens, m));
+    ACHK(dalloc(ctx, &A.dg, m));
+    ACHK(dalloc(ctx, &A.b, m));
+    ACHK(dalloc(ctx, &A.lam, m));
+    ctx->haveAdj = true;
+  }
+  if (precision == MG_FP32_REFINED && !A.have32) {
+    ACHK(ensure_lin<float>(ctx, A.w32));
+    A.have32 = true;
+  }
+  if (precision == MG_FP64 && !A.have64) {
+    ACHK(ensure_lin<double>(ctx, A.w64));
+    A.w64.dg[0] = A.dg;
+    A.have64 = true;
+  }
+  return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// constants and validation
+// ---------------------------------------------------------------------------
+int make_consts(mg_ctx* ctx, int model, const mg_model_params* P, int n, Consts* out) {
+  if (!P) return fail(ctx, MG_EINVAL, "params is NULL");
+  if (model < MG_FR || model > MG_CQ) return fail(ctx, MG_EINVAL, "unknown model");
+  if (!(P->a > 0.0) || !(P->box_mpch > 0.0) || !(P->omega_m > 0.0) || !(P->omega_m <= 1.0))
+    return fail(ctx, MG_EINVAL, "need a > 0, box > 0, 0 < omega_m <= 1");
+  Consts C;
+  memset(&C, 0, sizeof C);
+  C.model = model;
+  double a = P->a, om = P->omega_m, ol = 1.0 - om;
+  double ct = n * kCOverH0 / P->box_mpch;
+  C.ct2 = ct * ct;
+  C.om_a = om / a;
+  if (model == MG_FR) {
+    if (P->fr_n != 1) return fail(ctx, MG_EINVAL, "f(R): this build solves n = 1");
+    if (!(P->fr_fr0_abs > 0.0)) return fail(ctx, MG_EINVAL, "f(R): |f_R0| must be > 0");
+    // R-bar(a)/H0^2 = 3 (Om a^-3 + 4 OL); K = R-bar a^2 / 3
+    double ra = om / (a * a * a) + 4.0 * ol;
+    C.K = ra * a * a;
+    double ratio = (om + 4.0 * ol) / ra;  // R-bar_0 / R-bar(a)
+    C.wbar = P->fr_fr0_abs * ratio * ratio;
+    C.wpow = sqrt(C.wbar);
+    C.phi5 = 0.5 * C.ct2;
+    C.bg = C.wbar;
+    C.bg_coef = C.om_a;
+  } else if (model == MG_SYMMETRON) {
+    if (!(P->sym_xi > 0.0)) return fail(ctx, MG_EINVAL, "symmetron: xi must be > 0");
+    if (!(P->sym_a_star > 0.0) || !(P->sym_a_star < a))
+      return fail(ctx, MG_EINVAL, "symmetron: need 0 < a_* < a (background u > 0)");
+    C.s_ratio = pow(P->sym_a_star / a, 3.0);
+    C.s_amp = a * a / (2.0 * P->sym_xi * P->sym_xi);
+    C.ubar = sqrt(1.0 - C.s_ratio);
+    C.phi5 = 3.0 * P->sym_xi * P->sym_xi * om * P->sym_beta_star * P->sym_beta_star * C.ct2 /
+             pow(P->sym_a_star, 3.0);
+    C.bg = C.ubar;
+    C.bg_coef = C.s_amp * C.s_ratio * C.ubar;
+  } else {
+    if (!(P->cq_phibar > 0.0) || !(P->cq_alpha > 0.0))
+      return fail(ctx, MG_EINVAL, "CQ: need phibar > 0 and alpha > 0");
+    C.beta = P->cq_beta;
+    C.alpha = P->cq_alpha;
+    C.phibar = P->cq_phibar;
+    C.cq_keep_exp = P->cq_keep_exp ? 1 : 0;
+    C.cq_src = 3.0 * P->cq_beta * om / a * exp(P->cq_beta * P->cq_phibar);
+    C.cq_pot = P->cq_alpha * P->cq_lambda * P->cq_lambda * a * a;
+    C.cq_pb = pow(P->cq_phibar, -(1.0 + P->cq_alpha));
+    C.phi5 = P->cq_beta;
+    C.bg = 0.0;
+    C.bg_coef = fabs(C.cq_src);
+  }
+  *out = C;
+  return MG_OK;
+}
+
+int check_opts(mg_ctx* ctx, const mg_solver_opts* o) {
+  if (!o) return fail(ctx, MG_EINVAL, "opts is NULL");
+  if (o->cycle < 0 || o->cycle > 2) return fail(ctx, MG_EINVAL, "cycle must be 0 (V), 1 (F), 2 (W)");
+  if (o->nu_pre < 0 || o->nu_pre > 16 || o->nu_post < 1 || o->nu_post > 16)
+    return fail(ctx, MG_EINVAL, "need 0 <= nu_pre <= 16 and 1 <= nu_post <= 16");
+  if (o->max_cycles < 1 || o->max_cycles > 64) return fail(ctx, MG_EINVAL, "max_cycles in 1..64");
+  if (o->precision != MG_FP64 && o->precision != MG_FP32_REFINED)
+    return fail(ctx, MG_EINVAL, "precision must be MG_FP64 or MG_FP32_REFINED");
+  if (o->precision == MG_FP32_REFINED && (o->inner_cycles < 1 || o->inner_cycles > 16))
+    return fail(ctx, MG_EINVAL, "inner_cycles in 1..16");
+  if (o->coarse_sweeps < 0 || o->coarse_sweeps > 5000)
+    return fail(ctx, MG_EINVAL, "coarse_sweeps in 0..5000");
+  return MG_OK;
+}
+
+double lev_h2(int l) { return double(1u << l) * double(1u << l); }
+
+// ---------------------------------------------------------------------------
+// reductions to the host
+// ---------------------------------------------------------------------------
+int sum_to_host(mg_ctx* ctx, int64_t nparts, double* out) {
+  k_sum_partials<<<1, 1024, 0, ctx->stream>>>(ctx->part, nparts, ctx->scal, 0);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(ctx->hscal, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *out = ctx->hscal[0];
+  return MG_OK;
+}
+
+int bg_rms(mg_ctx* ctx, const Consts& C, const float* delta, double* out) {
+  int64_t m = cells(ctx->L[0]);
+  k_bg_norm<<<nblk(m), kBlock, 0, ctx->stream>>>(m, delta, C.bg_coef, ctx->part);
+  LAUNCHCHK();
+  double s;
+  ACHK(sum_to_host(ctx, nblk(m), &s));
+  double r = sqrt(s / double(m));
+  *out = r > 0.0 ? r : 1.0;
+  return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// fused-program generation (same recursion as the grid levels)
+// ---------------------------------------------------------------------------
+void gen_prog(std::vector<Op>& ops, int l, int lmax, int type, int nu1, int nu2) {
+  if (l == lmax) {
+    ops.push_back(Op{OP_COARSEST, (uint8_t)l, 0, 0});
+    return;
+  }
+  if (nu1 > 0) ops.push_back(Op{OP_SMOOTH, (uint8_t)l, (uint8_t)nu1, 0});
+  ops.push_back(Op{OP_DOWN, (uint8_t)l, 0, 0});
+  if (type == MG_CYCLE_V) {
+    gen_prog(ops, l + 1, lmax, MG_CYCLE_V, nu1, nu2);
+  } else if (type == MG_CYCLE_W) {
+    gen_prog(ops, l + 1, lmax, MG_CYCLE_W, nu1, nu2);
+    gen_prog(ops, l + 1, lmax, MG_CYCLE_W, nu1, nu2);
+  } else {
+    gen_prog(ops, l + 1, lmax, MG_CYCLE_F, nu1, nu2);
+    gen_prog(ops, l + 1, lmax, MG_CYCLE_V, nu1, nu2);
+  }
+  ops.push_back(Op{OP_UP, (uint8_t)l, 0, 0});
+  ops.push_back(Op{OP_SMOOTH, (uint8_t)l, (uint8_t)nu2, 0});
+}
+
+int make_prog(mg_ctx* ctx, int l, const mg_solver_opts* o, int type, FusedProg* P) {
+  std::vector<Op> ops;
+  int f = ctx->fused_from;
+  gen_prog(ops, l - f, ctx->nlev - 1 - f, type, o->nu_pre, o->nu_post);
+  if ((int)ops.size() > kMaxOps) return fail(ctx, MG_EINVAL, "fused cycle program too long");
+  P->nops = (int)ops.size();
+  P->coarse_sweeps = o->coarse_sweeps > 0 ? o->coarse_sweeps : 200;
+  for (size_t q = 0; q < ops.size(); ++q) P->op[q] = ops[q];
+  return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 direct multigrid
+// ---------------------------------------------------------------------------
+template <int M>
+int smooth64(mg_ctx* ctx, const Consts& C, int l, int sweeps) {
+  Work64& W = ctx->w64;
+  const Lev& L = ctx->L[l];
+  for (int s = 0; s < sweeps; ++s)
+    for (int colour = 0; colour < 2; ++colour) {
+      if (l == 0)
+        k_smooth_direct<M, double, float><<<nblk(L.half), kBlock, 0, ctx->stream>>>(
+            L, W.v[0], W.dens0, (const double*)nullptr, colour, 1.0, C);
+      else
+        k_smooth_direct<M, double, double><<<nblk(L.half), kBlock, 0, ctx->stream>>>(
+            L, W.v[l], W.dens[l], W.S[l], colour, lev_h2(l), C);
+    }
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+template <int M>
+int cycle64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int type) {
+  Work64& W = ctx->w64;
+  if (l >= ctx->fused_from) {
+    FusedDirect<double, double> F;
+    memset(&F, 0, sizeof F);
+    int f = ctx->fused_from;
+    F.nlev = ctx->nlev - f;
+    for (int q = 0; q < F.nlev; ++q) {
+      F.L[q] = ctx->L[f + q];
+      F.h2[q] = lev_h2(f + q);
+      F.v[q] = W.v[f + q];
+      F.dens[q] = W.dens[f + q];
+      F.S[q] = W.S[f + q];
+      F.Rv[q] = W.Rv[f + q];
+    }
+    FusedProg P;
+    ACHK(make_prog(ctx, l, o, type, &P));
+    k_fused_direct<M, double, double><<<1, kFusedThreads, 0, ctx->stream>>>(F, P, C);
+    LAUNCHCHK();
+    return MG_OK;
+  }
+  if (l == ctx->nlev - 1) {  // single-level grid: relax only
+    return smooth64<M>(ctx, C, l, o->nu_pre + o->nu_post);
+  }
+  const Lev& Lf = ctx->L[l];
+  const Lev& Lc = ctx->L[l + 1];
+  ACHK(smooth64<M>(ctx, C, l, o->nu_pre));
+  if (l == 0)
+    k_resid_restrict_direct<M, double, float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, W.v[0], W.dens0, (const double*)nullptr, 1.0, W.Rv[1], W.v[1], W.S[1], C);
+  else
+    k_resid_restrict_direct<M, double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, W.v[l], W.dens[l], W.S[l], lev_h2(l), W.Rv[l + 1], W.v[l + 1], W.S[l + 1], C);
+  k_coarse_src_direct<M, double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
+      Lc, W.Rv[l + 1], W.dens[l + 1], W.S[l + 1], lev_h2(l + 1), C);
+  LAUNCHCHK();
+  if (type == MG_CYCLE_V) {
+    ACHK(cycle64<M>(ctx, C, o, l + 1, MG_CYCLE_V));
+  } else if (type == MG_CYCLE_W) {
+    ACHK(cycle64<M>(ctx, C, o, l + 1, MG_CYCLE_W));
+    ACHK(cycle64<M>(ctx, C, o, l + 1, MG_CYCLE_W));
+  } else {
+    ACHK(cycle64<M>(ctx, C, o, l + 1, MG_CYCLE_F));
+    ACHK(cycle64<M>(ctx, C, o, l + 1, MG_CYCLE_V));
+  }
+  k_prolong_add<double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.v[l], W.v[l + 1],
+                                                                       W.Rv[l + 1]);
+  LAUNCHCHK();
+  return smooth64<M>(ctx, C, l, o->nu_post);
+}
+
+template <int M>
+int resid64(mg_ctx* ctx, const Consts& C, double eps_bg, double* rel, double* d_nat) {
+  const Lev& L = ctx->L[0];
+  k_resid_norm_direct<M, double, float><<<nblk(cells(L)), kBlock, 0, ctx->stream>>>(
+      L, ctx->w64.v[0], ctx->w64.dens0, 1.0, C, ctx->part, d_nat);
+  LAUNCHCHK();
+  double s;
+  ACHK(sum_to_host(ctx, nblk(cells(L)), &s));
+  *rel = sqrt(s / double(cells(L))) / eps_bg;
+  return MG_OK;
+}
+
+// pack the finest-level inputs and restrict the density pyramid (FP64 mode)
+int setup64(mg_ctx* ctx, const Consts& C, const float* delta, const double* field_in) {
+  Work64& W = ctx->w64;
+  const Lev& L0 = ctx->L[0];
+  int64_t m = cells(L0);
+  k_pack<float, float><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, delta, W.dens0, 1.0);
+  for (int l = 0; l + 1 < ctx->nlev; ++l) {
+    if (l == 0)
+      k_restrict<float, double><<<nblk(cells(ctx->L[1])), kBlock, 0, ctx->stream>>>(
+          L0, ctx->L[1], W.dens0, W.dens[1]);
+    else
+      k_restrict<double, double><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
+          ctx->L[l], ctx->L[l + 1], W.dens[l], W.dens[l + 1]);
+  }
+  double sgn = (C.model == FR) ? -1.0 : 1.0;  // f(R): w = -f_R
+  if (field_in)
+    k_pack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, field_in, W.v[0], sgn);
+  else
+    k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(W.v[0], m, C.bg);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+template <int M>
+int solve64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* delta,
+            const double* field_in, double* field_out, double tol, mg_stats* st) {
+  ACHK(ensure64(ctx));
+  ACHK(setup64(ctx, C, delta, field_in));
+  double eps_bg;
+  ACHK(bg_rms(ctx, C, delta, &eps_bg));
+  double rel;
+  ACHK(resid64<M>(ctx, C, eps_bg, &rel, nullptr));
+  int cyc = 0;
+  int rc = MG_OK;
+  if (!std::isfinite(rel)) rc = fail(ctx, MG_ENAN, "non-finite residual");
+  while (rc == MG_OK && rel > tol && cyc < o->max_cycles) {
+    ACHK(cycle64<M>(ctx, C, o, 0, o->cycle));
+    ACHK(resid64<M>(ctx, C, eps_bg, &rel, nullptr));
+    if (st && cyc < 64) st->resid_hist[cyc] = rel;
+    ++cyc;
+    if (!std::isfinite(rel)) {
+      rc = fail(ctx, MG_ENAN, "non-finite residual");
+      break;
+    }
+  }
+  if (rc == MG_OK && rel > tol) rc = fail(ctx, MG_ENOCONV, "max_cycles reached");
+  double sgn = (C.model == FR) ? -1.0 : 1.0;
+  const Lev& L0 = ctx->L[0];
+  k_unpack<double, double><<<nblk(cells(L0)), kBlock, 0, ctx->stream>>>(L0, ctx->w64.v[0],
+                                                                          field_out, sgn);
+  LAUNCHCHK();
+  if (st) {
+    st->cycles = cyc;
+    st->rel_resid = rel;
+  }
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 correction multigrid inside an FP64 outer loop
+// ---------------------------------------------------------------------------
+template <int M>
+int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps) {
+  Work32& W = ctx->w32;
+  const Lev& L = ctx->L[l];
+  for (int s = 0; s < sweeps; ++s)
+    for (int colour = 0; colour < 2; ++colour)
+      k_smooth_corr<M><<<nblk(L.half), kBlock, 0, ctx->stream>>>(L, W.e[l], W.X[l], W.dens[l],
+                                                                 W.rho[l], colour,
+                                                                 float(lev_h2(l)), C);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+template <int M>
+int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int type) {
+  Work32& W = ctx->w32;
+  if (l >= ctx->fused_from) {
+    FusedCorr F;
+    memset(&F, 0, sizeof F);
+    int f = ctx->fused_from;
+    F.nlev = ctx->nlev - f;
+    for (int q = 0; q < F.nlev; ++q) {
+      F.L[q] = ctx->L[f + q];
+      F.h2[q] = float(lev_h2(f + q));
+      F.e[q] = W.e[f + q];
+      F.X[q] = W.X[f + q];
+      F.dens[q] = W.dens[f + q];
+      F.rho[q] = W.rho[f + q];
+      F.eR[q] = W.eR[f + q];
+    }
+    FusedProg P;
+    ACHK(make_prog(ctx, l, o, type, &P));
+    k_fused_corr<M><<<1, kFusedThreads, 0, ctx->stream>>>(F, P, C);
+    LAUNCHCHK();
+    return MG_OK;
+  }
+  if (l == ctx->nlev - 1) return smooth32<M>(ctx, C, l, o->nu_pre + o->nu_post);
+  const Lev& Lf = ctx->L[l];
+  const Lev& Lc = ctx->L[l + 1];
+  ACHK(smooth32<M>(ctx, C, l, o->nu_pre));
+  k_resid_restrict_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
+      Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
+      W.rho[l + 1], (float*)nullptr, C);
+  k_coarse_src_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
+      Lc, W.eR[l + 1], W.X[l + 1], W.dens[l + 1], W.rho[l + 1], float(lev_h2(l + 1)), C);
+  LAUNCHCHK();
+  if (type == MG_CYCLE_V) {
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V));
+  } else if (type == MG_CYCLE_W) {
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_W));
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_W));
+  } else {
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_F));
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V));
+  }
+  k_prolong_add<float><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1],
+                                                                      W.eR[l + 1]);
+  LAUNCHCHK();
+  return smooth32<M>(ctx, C, l, o->nu_post);
+}
+
+template <int M>
+int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* delta,
+            const double* field_in, double* field_out, double tol, mg_stats* st) {
+  ACHK(ensure32(ctx));
+  Work32& W = ctx->w32;
+  const Lev& L0 = ctx->L[0];
+  int64_t m = cells(L0);
+  k_pack<float, float><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, delta, W.dens[0], 1.0);
+  for (int l = 0; l + 1 < ctx->nlev; ++l)
+    k_restrict<float, float><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
+        ctx->L[l], ctx->L[l + 1], W.dens[l], W.dens[l + 1]);
+  double sgn = (C.model == FR) ? -1.0 : 1.0;
+  if (field_in)
+    k_pack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, field_in, W.w, sgn);
+  else
+    k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(W.w, m, C.bg);
+  LAUNCHCHK();
+  double eps_bg;
+  ACHK(bg_rms(ctx, C, delta, &eps_bg));
+  int outer = 0, rc = MG_OK;
+  double rel = 0.0;
+  for (;;) {
+    k_outer_residual<M><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, W.w, W.dens[0], C, W.rho[0],
+                                                             W.X[0], W.e[0], ctx->part);
+    LAUNCHCHK();
+    double s;
+    ACHK(sum_to_host(ctx, nblk(m), &s));
+    rel = sqrt(s / double(m)) / eps_bg;
+    if (outer > 0 && st && outer - 1 < 64) st->resid_hist[outer - 1] = rel;
+    if (!std::isfinite(rel)) {
+      rc = fail(ctx, MG_ENAN, "non-finite residual");
+      break;
+    }
+    if (rel <= tol) break;
+    if (outer >= o->max_cycles) {
+      rc = fail(ctx, MG_ENOCONV, "max_cycles reached");
+      break;
+    }
+    for (int l = 0; l + 1 < ctx->nlev; ++l)
+      k_restrict<float, float><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
+          ctx->L[l], ctx->L[l + 1], W.X[l], W.X[l + 1]);
+    LAUNCHCHK();
+    for (int it = 0; it < o->inner_cycles; ++it) ACHK(cycle32<M>(ctx, C, o, 0, o->cycle));
+    k_outer_update<<<nblk(m), kBlock, 0, ctx->stream>>>(m, W.w, W.e[0]);
+    LAUNCHCHK();
+    ++outer;
+  }
+  k_unpack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, W.w, field_out, sgn);
+  LAUNCHCHK();
+  if (st) {
+    st->cycles = outer;
+    st->rel_resid = rel;
+  }
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint: linear multigrid on A lam = b, A = kap(6 - sum)/h^2 + dg
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_lin_setup(Lev L, const double* v, const float* dens,
+                                                      Consts C, double* dg) {
+  int64_t g = gid();
+  if (g < 2 * L.half) dg[g] = lin_dg<M>(C, v[g], double(dens[g]));
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_lin_final(Lev L, const double* v, const double* lam,
+                                                      Consts C, double* out_nat) {
+  int64_t g = gid();
+  if (g >= 2 * L.half) return;
+  int colour = g >= L.half ? 1 : 0;
+  int64_t gg = g - colour * L.half;
+  int ih, j, k;
+  dec(gg, L, ih, j, k);
+  int i = 2 * ih + ((j + k + colour) & 1);
+  out_nat[((int64_t)k * L.n + j) * L.n + i] = -lin_dfd<M>(C, v[g]) * lam[g];
+}
+
+template <typename T>
+int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, int l, int type) {
+  if (l >= ctx->fused_from) {
+    FusedLin<T> F;
+    memset(&F, 0, sizeof F);
+    int f = ctx->fused_from;
+    F.nlev = ctx->nlev - f;
+    for (int q = 0; q < F.nlev; ++q) {
+      F.L[q] = ctx->L[f + q];
+      F.kh2[q] = T(kap / lev_h2(f + q));
+      F.e[q] = W.e[f + q];
+      F.dg[q] = W.dg[f + q];
+      F.r[q] = W.r[f + q];
+    }
+    FusedProg P;
+    ACHK(make_prog(ctx, l, o, type, &P));
+    k_fused_lin<T><<<1, kFusedThreads, 0, ctx->stream>>>(F, P);
+    LAUNCHCHK();
+    return MG_OK;
+  }
+  const Lev& Lf = ctx->L[l];
+  T kh2 = T(kap / lev_h2(l));
+  auto smooth = [&](int sweeps) {
+    for (int s = 0; s < sweeps; ++s)
+      for (int colour = 0; colour < 2; ++colour)
+        k_smooth_lin<T><<<nblk(Lf.half), kBlock, 0, ctx->stream>>>(Lf, W.e[l], W.dg[l], W.r[l],
+                                                                    colour, kh2);
+  };
+  if (l == ctx->nlev - 1) {
+    smooth(o->nu_pre + o->nu_post);
+    LAUNCHCHK();
+    return MG_OK;
+  }
+  const Lev& Lc = ctx->L[l + 1];
+  smooth(o->nu_pre);
+  k_lin_resid_restrict<T><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.dg[l],
+                                                                        W.r[l], kh2, W.r[l + 1],
+                                                                        W.e[l + 1]);
+  LAUNCHCHK();
+  if (type == MG_CYCLE_V) {
+    ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_V));
+  } else if (type == MG_CYCLE_W) {
+    ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_W));
+    ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_W));
+  } else {
+    ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_F));
+    ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_V));
+  }
+  k_prolong_add<T><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1],
+                                                                  (const T*)nullptr);
+  smooth(o->nu_post);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+template <int M>
+int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* delta,
+                 const double* field, const double* grad_field, double* grad_delta, double tol,
+                 mg_stats* st) {
+  ACHK(ensure_adj(ctx, o->precision));
+  WorkAdj& A = ctx->adj;
+  const Lev& L0 = ctx->L[0];
+  int64_t m = cells(L0);
+  double sgn_field = (C.model == FR) ? -1.0 : 1.0;
+  k_pack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, field, A.v, sgn_field);
+  k_pack<float, float><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, delta, A.dens, 1.0);
+  // b = s dL/dv, s = +1 (f(R)) / -1; dL/dv = sgn_field dL/dfield  ->  b = -dL/dfield
+  k_pack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, grad_field, A.b,
+                                                              lin_sign(C) * sgn_field);
+  k_lin_setup<M><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, A.v, A.dens, C, A.dg);
+  k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(A.lam, m, 0.0);
+  LAUNCHCHK();
+  const bool f32 = o->precision == MG_FP32_REFINED;
+  if (f32) {
+    k_cast<float><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.dg, A.w32.dg[0]);
+    for (int l = 0; l + 1 < ctx->nlev; ++l)
+      k_restrict<float, float><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
+          ctx->L[l], ctx->L[l + 1], A.w32.dg[l], A.w32.dg[l + 1]);
+  } else {
+    for (int l = 0; l + 1 < ctx->nlev; ++l)
+      k_restrict<double, double><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
+          ctx->L[l], ctx->L[l + 1], A.w64.dg[l], A.w64.dg[l + 1]);
+  }
+  LAUNCHCHK();
+  k_sq_norm<double><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.b, ctx->part);
+  LAUNCHCHK();
+  double bb;
+  ACHK(sum_to_host(ctx, nblk(m), &bb));
+  bb = sqrt(bb);
+  if (!(bb > 0.0)) bb = 1.0;
+  double kap = lin_kap(C);
+  int outer = 0, rc = MG_OK;
+  double rel = 0.0;
+  for (;;) {
+    if (f32)
+      k_lin_outer<float><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, A.lam, A.dg, A.b, kap,
+                                                              A.w32.r[0], A.w32.e[0], ctx->part);
+    else
+      k_lin_outer<double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, A.lam, A.dg, A.b, kap,
+                                                               A.w64.r[0], A.w64.e[0], ctx->part);
+    LAUNCHCHK();
+    double s;
+    ACHK(sum_to_host(ctx, nblk(m), &s));
+    rel = sqrt(s) / bb;
+    if (outer > 0 && st && outer - 1 < 64) st->resid_hist[outer - 1] = rel;
+    if (!std::isfinite(rel)) {
+      rc = fail(ctx, MG_ENAN, "non-finite adjoint residual");
+      break;
+    }
+    if (rel <= tol) break;
+    if (outer >= o->max_cycles) {
+      rc = fail(ctx, MG_ENOCONV, "max_cycles reached (adjoint)");
+      break;
+    }
+    if (f32) {
+      for (int it = 0; it < o->inner_cycles; ++it)
+        ACHK(lin_cycle<float>(ctx, A.w32, kap, o, 0, o->cycle));
+      k_axpy_to64<float><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w32.e[0]);
+    } else {
+      // FP64: the correction scheme on r = b - A lam, one cycle per step
+      ACHK(lin_cycle<double>(ctx, A.w64, kap, o, 0, o->cycle));
+      k_axpy_to64<double><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w64.e[0]);
+    }
+    LAUNCHCHK();
+    ++outer;
+  }
+  k_lin_final<M><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, A.v, A.lam, C, grad_delta);
+  LAUNCHCHK();
+  if (st) {
+    st->cycles = outer;
+    st->rel_resid = rel;
+  }
+  return rc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// natural-layout kernels: force, its transpose, loss, CIC
+// ---------------------------------------------------------------------------
+namespace {
+
+// Phi5 of the field value (ABI convention: f(R) field = f_R = -w)
+__device__ __forceinline__ double phi5_of(const Consts& C, double f) {
+  if (C.model == FR) return -C.phi5 * f;
+  if (C.model == SYM) return C.phi5 * f * f;
+  return C.phi5 * f;
+}
+__device__ __forceinline__ double dphi5_of(const Consts& C, double f) {
+  if (C.model == FR) return -C.phi5;
+  if (C.model == SYM) return 2.0 * C.phi5 * f;
+  return C.phi5;
+}
+
+__global__ __launch_bounds__(kBlock) void k_force(int n, const double* __restrict__ f, Consts C,
+                                                  float* __restrict__ out) {
+  int64_t g = gid();
+  int64_t m = (int64_t)n * n * n;
+  if (g >= m) return;
+  int i = (int)(g % n);
+  int64_t r = g / n;
+  int j = (int)(r % n), k = (int)(r / n);
+  int ip = i + 1 == n ? 0 : i + 1, im = i == 0 ? n - 1 : i - 1;
+  int jp = j + 1 == n ? 0 : j + 1, jm = j == 0 ? n - 1 : j - 1;
+  int kp = k + 1 == n ? 0 : k + 1, km = k == 0 ? n - 1 : k - 1;
+  int64_t row = (int64_t)k * n + j;
+  double gx = -0.5 * (phi5_of(C, f[row * n + ip]) - phi5_of(C, f[row * n + im]));
+  double gy = -0.5 * (phi5_of(C, f[((int64_t)k * n + jp) * n + i]) -
+                      phi5_of(C, f[((int64_t)k * n + jm) * n + i]));
+  double gz = -0.5 * (phi5_of(C, f[((int64_t)kp * n + j) * n + i]) -
+                      phi5_of(C, f[((int64_t)km * n + j) * n + i]));
+  out[g] = float(gx);
+  out[m + g] = float(gy);
+  out[2 * m + g] = float(gz);
+}
+
+__global__ __launch_bounds__(kBlock) void k_force_adjoint(int n, const double* __restrict__ f,
+                                                          const float* __restrict__ gf, Consts C,
+                                                          double* __restrict__ out) {
+  int64_t g = gid();
+  int64_t m = (int64_t)n * n * n;
+  if (g >= m) return;
+  int i = (int)(g % n);
+  int64_t r = g / n;
+  int j = (int)(r % n), k = (int)(r / n);
+  int ip = i + 1 == n ? 0 : i + 1, im = i == 0 ? n - 1 : i - 1;
+  int jp = j + 1 == n ? 0 : j + 1, jm = j == 0 ? n - 1 : j - 1;
+  int kp = k + 1 == n ? 0 : k + 1, km = k == 0 ? n - 1 : k - 1;
+  int64_t row = (int64_t)k * n + j;
+  // g_a(c) = -(Phi(c+e_a) - Phi(c-e_a))/2  =>  dL/dPhi(c) = sum_a (G_a(c+e_a) - G_a(c-e_a))/2
+  double s = (double(gf[row * n + ip]) - double(gf[row * n + im])) +
+             (double(gf[m + ((int64_t)k * n + jp) * n + i]) - double(gf[m + ((int64_t)k * n + jm) * n + i])) +
+             (double(gf[2 * m + ((int64_t)kp * n + j) * n + i]) -
+              double(gf[2 * m + ((int64_t)km * n + j) * n + i]));
+  out[g] = 0.5 * s * dphi5_of(C, f[g]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_loss_sq(int64_t m, const float* __restrict__ force,
+                                                    const int64_t* __restrict__ cellsv,
+                                                    int64_t ncell, float* __restrict__ grad,
+                                                    double* part) {
+  __shared__ double sh[32];
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (q < ncell) {
+    int64_t c = cellsv[q];
+    if (c >= 0 && c < m) {
+      for (int a = 0; a < 3; ++a) {
+        float v = force[a * m + c];
+        acc += double(v) * double(v);
+        grad[a * m + c] = 2.0f * v;
+      }
+    }
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// CIC: per axis, s = x - 1/2, i0 = floor(s), t = s - i0 (exact in FP32 for
+// 0 <= x < 2^23); weights (1-t, t) to cells i0, i0+1 (periodic).  The 8
+// products are formed in FP64 and deposited as 32.32 fixed point; the last
+// weight is 2^32 minus the other seven so each particle adds exactly 1.
+__global__ __launch_bounds__(kBlock) void k_cic(int n, int64_t np, const float* __restrict__ pos,
+                                                unsigned long long* __restrict__ acc) {
+  int64_t p = gid();
+  if (p >= np) return;
+  int i0[3];
+  double t[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float x = pos[3 * p + a];
+    float s = x - 0.5f;
+    float fl = floorf(s);
+    t[a] = double(s - fl);
+    int c = (int)fl;
+    c %= n;
+    if (c < 0) c += n;
+    i0[a] = c;
+  }
+  long long w[8];
+  long long tot = 0;
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    int di = q & 1, dj = (q >> 1) & 1, dk = (q >> 2) & 1;
+    double ww = (di ? t[0] : 1.0 - t[0]) * (dj ? t[1] : 1.0 - t[1]) * (dk ? t[2] : 1.0 - t[2]);
+    w[q] = llrint(ww * 4294967296.0);
+    tot += w[q];
+  }
+  w[7] = 4294967296LL - tot;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    if (w[q] == 0) continue;
+    int di = q & 1, dj = (q >> 1) & 1, dk = (q >> 2) & 1;
+    int ii = i0[0] + di == n ? 0 : i0[0] + di;
+    int jj = i0[1] + dj == n ? 0 : i0[1] + dj;
+    int kk = i0[2] + dk == n ? 0 : i0[2] + dk;
+    atomicAdd(&acc[((int64_t)kk * n + jj) * n + ii], (unsigned long long)w[q]);
+  }
+}
+__global__ __launch_bounds__(kBlock) void k_cic_finish(int64_t m, const unsigned long long* acc,
+                                                       double scale, float* delta) {
+  int64_t g = gid();
+  if (g < m) delta[g] = float(double(acc[g]) * scale - 1.0);
+}
+
+template <int M>
+int dispatch_solve(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* delta,
+                   const double* fin, double* fout, double tol, mg_stats* st) {
+  if (o->precision == MG_FP32_REFINED) return solve32<M>(ctx, C, o, delta, fin, fout, tol, st);
+  return solve64<M>(ctx, C, o, delta, fin, fout, tol, st);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
+  if (!out) return MG_EINVAL;
+  *out = nullptr;
+  if (n < 4 || (n & 1) || n > 8192) return MG_EINVAL;
+  mg_ctx* ctx = new mg_ctx();
+  ctx->n = n;
+  ctx->stream = (hipStream_t)hip_stream;
+  // pyramid: halve while the half is even and >= 4
+  int m = n, l = 0;
+  for (;;) {
+    ctx->L[l].n = m;
+    ctx->L[l].nh = m / 2;
+    ctx->L[l].half = (int64_t)m * m * m / 2;
+    ++l;
+    if (!(m / 2 >= 4 && ((m / 2) % 2) == 0) || l >= kMaxLev) break;
+    m /= 2;
+  }
+  ctx->nlev = l;
+  int f = ctx->nlev;
+  for (int q = 1; q < ctx->nlev; ++q)
+    if (ctx->L[q].n <= kFuseN) {
+      f = q;
+      break;
+    }
+  if (f > ctx->nlev - 1) f = ctx->nlev - 1;
+  if (f < 1) f = ctx->nlev;  // single level: nothing fused
+  if (ctx->nlev - f > kMaxFused) f = ctx->nlev - kMaxFused;
+  ctx->fused_from = f;
+  ctx->part_cap = nblk((int64_t)n * n * n) + 16;
+  int rc = dalloc(ctx, &ctx->part, ctx->part_cap);
+  if (rc == MG_OK) rc = dalloc(ctx, &ctx->scal, 16);
+  if (rc == MG_OK) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) rc = MG_EHIP;
+    ctx->hscal = (double*)h;
+  }
+  if (rc != MG_OK) {
+    mg_ctx_destroy(ctx);
+    return rc;
+  }
+  *out = ctx;
+  return MG_OK;
+}
+
+void mg_ctx_destroy(mg_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  if (ctx->hscal) (void)hipHostFree(ctx->hscal);
+  delete ctx;
+}
+
+const char* mg_last_error(const mg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int mg_ctx_levels(const mg_ctx* ctx) { return ctx ? ctx->nlev : 0; }
+
+int cic_assign(mg_ctx* ctx, const float* pos, int64_t np, float* delta_out) {
+  if (!ctx) return MG_EINVAL;
+  if (!pos || !delta_out || np <= 0) return fail(ctx, MG_EINVAL, "cic_assign: bad arguments");
+  int n = ctx->n;
+  int64_t m = (int64_t)n * n * n;
+  if (!ctx->cic) ACHK(dalloc(ctx, &ctx->cic, m));
+  unsigned long long* acc = (unsigned long long*)ctx->cic;
+  k_fill<unsigned long long><<<nblk(m), kBlock, 0, ctx->stream>>>(acc, m, 0ull);
+  k_cic<<<nblk(np), kBlock, 0, ctx->stream>>>(n, np, pos, acc);
+  double scale = double(m) / double(np) / 4294967296.0;
+  k_cic_finish<<<nblk(m), kBlock, 0, ctx->stream>>>(m, acc, scale, delta_out);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_solve(mg_ctx* ctx, int model, const mg_model_params* params, const mg_solver_opts* opts,
+             const float* delta, const double* field_in, double* field_out, double tol,
+             mg_stats* stats) {
+  if (!ctx) return MG_EINVAL;
+  auto t0 = std::chrono::steady_clock::now();
+  Consts C;
+  ACHK(make_consts(ctx, model, params, ctx->n, &C));
+  ACHK(check_opts(ctx, opts));
+  if (!delta || !field_out) return fail(ctx, MG_EINVAL, "mg_solve: NULL array");
+  if (!(tol > 0.0)) return fail(ctx, MG_EINVAL, "mg_solve: tol must be > 0");
+  if (stats) memset(stats, 0, sizeof *stats);
+  int rc;
+  if (model == MG_FR) rc = dispatch_solve<FR>(ctx, C, opts, delta, field_in, field_out, tol, stats);
+  else if (model == MG_SYMMETRON)
+    rc = dispatch_solve<SYM>(ctx, C, opts, delta, field_in, field_out, tol, stats);
+  else rc = dispatch_solve<CQ>(ctx, C, opts, delta, field_in, field_out, tol, stats);
+  if (stats) {
+    (void)hipStreamSynchronize(ctx->stream);
+    stats->status = rc;
+    stats->ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return rc;
+}
+
+int mg_residual(mg_ctx* ctx, int model, const mg_model_params* params, const float* delta,
+                const double* field, double* d_out, double* rel) {
+  if (!ctx) return MG_EINVAL;
+  Consts C;
+  ACHK(make_consts(ctx, model, params, ctx->n, &C));
+  if (!delta || !field) return fail(ctx, MG_EINVAL, "mg_residual: NULL array");
+  ACHK(ensure64(ctx));
+  ACHK(setup64(ctx, C, delta, field));
+  double eps_bg, r;
+  ACHK(bg_rms(ctx, C, delta, &eps_bg));
+  if (model == MG_FR) ACHK(resid64<FR>(ctx, C, eps_bg, &r, d_out));
+  else if (model == MG_SYMMETRON) ACHK(resid64<SYM>(ctx, C, eps_bg, &r, d_out));
+  else ACHK(resid64<CQ>(ctx, C, eps_bg, &r, d_out));
+  if (rel) *rel = r;
+  return MG_OK;
+}
+
+int mg_force(mg_ctx* ctx, int model, const mg_model_params* params, const double* field,
+             float* force_out) {
+  if (!ctx) return MG_EINVAL;
+  Consts C;
+  ACHK(make_consts(ctx, model, params, ctx->n, &C));
+  if (!field || !force_out) return fail(ctx, MG_EINVAL, "mg_force: NULL array");
+  int64_t m = (int64_t)ctx->n * ctx->n * ctx->n;
+  k_force<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->n, field, C, force_out);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_force_adjoint(mg_ctx* ctx, int model, const mg_model_params* params, const double* field,
+                     const float* grad_force, double* grad_field_out) {
+  if (!ctx) return MG_EINVAL;
+  Consts C;
+  ACHK(make_consts(ctx, model, params, ctx->n, &C));
+  if (!field || !grad_force || !grad_field_out)
+    return fail(ctx, MG_EINVAL, "mg_force_adjoint: NULL array");
+  int64_t m = (int64_t)ctx->n * ctx->n * ctx->n;
+  k_force_adjoint<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->n, field, grad_force, C,
+                                                       grad_field_out);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_solve_adjoint(mg_ctx* ctx, int model, const mg_model_params* params,
+                     const mg_solver_opts* opts, const float* delta, const double* field,
+                     const double* grad_field, double* grad_delta_out, double tol,
+                     mg_stats* stats) {
+  if (!ctx) return MG_EINVAL;
+  auto t0 = std::chrono::steady_clock::now();
+  Consts C;
+  ACHK(make_consts(ctx, model, params, ctx->n, &C));
+  ACHK(check_opts(ctx, opts));
+  if (!delta || !field || !grad_field || !grad_delta_out)
+    return fail(ctx, MG_EINVAL, "mg_solve_adjoint: NULL array");
+  if (!(tol > 0.0)) return fail(ctx, MG_EINVAL, "mg_solve_adjoint: tol must be > 0");
+  if (stats) memset(stats, 0, sizeof *stats);
+  int rc;
+  if (model == MG_FR)
+    rc = adjoint_impl<FR>(ctx, C, opts, delta, field, grad_field, grad_delta_out, tol, stats);
+  else if (model == MG_SYMMETRON)
+    rc = adjoint_impl<SYM>(ctx, C, opts, delta, field, grad_field, grad_delta_out, tol, stats);
+  else rc = adjoint_impl<CQ>(ctx, C, opts, delta, field, grad_field, grad_delta_out, tol, stats);
+  if (stats) {
+    (void)hipStreamSynchronize(ctx->stream);
+    stats->status = rc;
+    stats->ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return rc;
+}
+
+int mg_loss_force_sq(mg_ctx* ctx, const float* force, const int64_t* cellsv, int64_t n_cells,
+                     float* grad_force_out, double* loss_out) {
+  if (!ctx) return MG_EINVAL;
+  if (!force || !cellsv || !grad_force_out || !loss_out || n_cells <= 0)
+    return fail(ctx, MG_EINVAL, "mg_loss_force_sq: bad arguments");
+  int64_t m = (int64_t)ctx->n * ctx->n * ctx->n;
+  if (nblk(n_cells) > (unsigned)ctx->part_cap)
+    return fail(ctx, MG_EINVAL, "mg_loss_force_sq: too many cells");
+  k_fill<float><<<nblk(3 * m), kBlock, 0, ctx->stream>>>(grad_force_out, 3 * m, 0.0f);
+  k_loss_sq<<<nblk(n_cells), kBlock, 0, ctx->stream>>>(m, force, cellsv, n_cells, grad_force_out,
+                                                       ctx->part);
+  k_sum_partials<<<1, 1024, 0, ctx->stream>>>(ctx->part, nblk(n_cells), loss_out, 0);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_relax_halfsweep(mg_ctx* ctx, int model, const mg_model_params* params, const float* delta,
+                       double* field, int colour) {
+  if (!ctx) return MG_EINVAL;
+  Consts C;
+  ACHK(make_consts(ctx, model, params, ctx->n, &C));
+  if (!delta || !field || (colour != 0 && colour != 1))
+    return fail(ctx, MG_EINVAL, "mg_relax_halfsweep: bad arguments");
+  ACHK(ensure64(ctx));
+  ACHK(setup64(ctx, C, delta, field));
+  const Lev& L = ctx->L[0];
+  if (model == MG_FR)
+    k_smooth_direct<FR, double, float><<<nblk(L.half), kBlock, 0, ctx->stream>>>(
+        L, ctx->w64.v[0], ctx->w64.dens0, (const double*)nullptr, colour, 1.0, C);
+  else if (model == MG_SYMMETRON)
+    k_smooth_direct<SYM, double, float><<<nblk(L.half), kBlock, 0, ctx->stream>>>(
+        L, ctx->w64.v[0], ctx->w64.dens0, (const double*)nullptr, colour, 1.0, C);
+  else
+    k_smooth_direct<CQ, double, float><<<nblk(L.half), kBlock, 0, ctx->stream>>>(
+        L, ctx->w64.v[0], ctx->w64.dens0, (const double*)nullptr, colour, 1.0, C);
+  double sgn = (model == MG_FR) ? -1.0 : 1.0;
+  k_unpack<double, double><<<nblk(cells(L)), kBlock, 0, ctx->stream>>>(L, ctx->w64.v[0], field,
+                                                                         sgn);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_restrict(mg_ctx* ctx, const double* fine, double* coarse) {
+  if (!ctx) return MG_EINVAL;
+  if (!fine || !coarse || ctx->nlev < 2) return fail(ctx, MG_EINVAL, "mg_restrict: bad arguments");
+  ACHK(ensure64(ctx));
+  const Lev& Lf = ctx->L[0];
+  const Lev& Lc = ctx->L[1];
+  k_pack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, fine, ctx->w64.v[0], 1.0);
+  k_restrict<double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, ctx->w64.v[0],
+                                                                          ctx->w64.v[1]);
+  k_unpack<double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lc, ctx->w64.v[1], coarse,
+                                                                         1.0);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_prolong_add(mg_ctx* ctx, const double* coarse, double* fine) {
+  if (!ctx) return MG_EINVAL;
+  if (!fine || !coarse || ctx->nlev < 2)
+    return fail(ctx, MG_EINVAL, "mg_prolong_add: bad arguments");
+  ACHK(ensure64(ctx));
+  const Lev& Lf = ctx->L[0];
+  const Lev& Lc = ctx->L[1];
+  k_pack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, fine, ctx->w64.v[0], 1.0);
+  k_pack<double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lc, coarse, ctx->w64.v[1], 1.0);
+  k_prolong_add<double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, Lc, ctx->w64.v[0],
+                                                                       ctx->w64.v[1],
+                                                                       (const double*)nullptr);
+  k_unpack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, ctx->w64.v[0], fine,
+                                                                         1.0);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_solve_batched(mg_ctx* ctx, int n_box, const mg_box_desc* boxes, const mg_solver_opts* opts,
+                     double tol, mg_stats* per_box) {
+  if (!ctx) return MG_EINVAL;
+  (void)n_box;
+  (void)boxes;
+  (void)opts;
+  (void)tol;
+  (void)per_box;
+  return fail(ctx, MG_EINVAL, "mg_solve_batched: not available in this build");
+}
+
+}  // extern "C"
