@@ -1,0 +1,184 @@
+#!/usr/bin/env python
+"""Benchmark of the hot path on one MI355X.
+
+One step = the whole hot path over one 512^3 box (1 Mpc/h cells, seeded
+Zel'dovich particles standing in for a simulation snapshot):
+  CIC of 512^3 FP32 particles -> f(R) n=1 |f_R0|=1e-5 solve, FP32 multigrid
+  refined in FP64, to relative residual 1e-6 -> fifth force -> loss over
+  4096 seeded cells and its force gradient -> force adjoint -> adjoint solve
+  (FP32 refined, 1e-6).
+Inputs are resident in HBM before the timed region; every step solves from
+the background field.  value = grid cells per second through the step.
+
+Also reported: the plain FP64 GPU step at the same tolerances, the
+roofline of the dominant kernel (FP32 finest-level smoother half-sweep,
+timed with HIP events on the solve's stream over the timed steps), and the
+FP64 CPU oracle timed on a bounded sample (a 128^3 box with the same cell
+size and the same pipeline) on this machine's host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP32_SMOOTH_BYTES_PER_CELL = 16.0  # per updated cell: X, rho, other-colour e, write e
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--fr0", type=float, default=1e-5)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=256)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB FP32 device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_baseline(n, fr0, tol):
+    """The FP64 oracle's pipeline on an n^3 sample box (same 1 Mpc/h cells)."""
+    import numpy as np
+
+    import oracle
+    import synthetic
+
+    pos = synthetic.zeldovich_positions(n, n, seed=3, dtype=np.float32).astype(np.float64)
+    cells = np.sort(np.random.default_rng(5005).choice(n ** 3, 4096 * n ** 3 // 512 ** 3 or 64,
+                                                       replace=False))
+    P = oracle.params(oracle.FR, n, float(n), fr0=fr0)
+    t0 = time.perf_counter()
+    d = oracle.cic(n, pos)
+    v, cyc, rel, _ = oracle.solve(P, d, tol=tol, max_cycles=100)
+    g = oracle.force(P, v).reshape(3, -1)
+    gf = np.zeros_like(g)
+    gf[:, cells] = 2.0 * g[:, cells]
+    gv = oracle.force_adjoint(P, v, gf.reshape(3, n, n, n))
+    gd, it, arel = oracle.adjoint(P, d, v, gv, tol=tol)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return dict(value=n ** 3 / dt, unit="cells/s", cores=threads, kind="oracle",
+                sample=f"{n}^3 box, {n} Mpc/h, same pipeline (CIC, FP64 FAS V(1,1) to {tol:g}, "
+                       f"force, loss grad, force adjoint, linear-MG adjoint to {tol:g}); "
+                       f"{dt:.1f} s wall, {cyc} cycles",
+                seconds=dt)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_2110_00328_amd import _lib as L
+    from paper_2110_00328_amd import api
+
+    dev = torch.device("cuda:0")
+    n = a.n
+    tol = 1e-6
+    pos = torch.from_numpy(synthetic.c3_positions(n)).to(dev)
+    cells = torch.from_numpy(np.sort(np.random.default_rng(5005).choice(n ** 3, 4096,
+                                                                        replace=False))).to(dev)
+    mg = api.Context(n, device=dev)
+    prm = api.model_params(float(n), fr0=a.fr0)
+    m = n ** 3
+    delta = torch.empty((n, n, n), dtype=torch.float32, device=dev)
+    field = torch.empty((n, n, n), dtype=torch.float64, device=dev)
+    force = torch.empty((3, n, n, n), dtype=torch.float32, device=dev)
+    gforce = torch.empty_like(force)
+    gfield = torch.empty_like(field)
+    gdelta = torch.empty_like(field)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    info = {}
+
+    def step(prec):
+        o = api.solver_opts(precision=prec)
+        mg.cic(pos, out=delta)
+        _, st = mg.solve("fr", prm, delta, out=field, tol=tol, opts=o)
+        mg.force("fr", prm, field, out=force)
+        mg.loss_force_sq(force, cells, grad_out=gforce, loss_out=loss)
+        mg.force_adjoint("fr", prm, field, gforce, out=gfield)
+        _, sa = mg.solve_adjoint("fr", prm, delta, field, gfield, out=gdelta, tol=tol, opts=o)
+        info[prec] = dict(fwd_checks=st.cycles, fwd_vcycles=st.vcycles, fwd_rel=st.rel_resid,
+                          fwd_ms=st.ms_total, adj_checks=sa.cycles, adj_vcycles=sa.vcycles,
+                          adj_rel=sa.rel_resid, adj_ms=sa.ms_total)
+
+    for _ in range(a.warmup):
+        step("fp32")
+    torch.cuda.synchronize()
+    mg.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step("fp32")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / a.steps
+    sm_ms, sm_n = mg.prof_read(L.MG_PROF_SMOOTH32)
+    mg.prof_enable(False)
+
+    if a.calib_copy:
+        # a plain copy of known size: 2^28 floats read + written once
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    fp64_ms = None
+    if not a.no_fp64:
+        step("fp64")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step("fp64")
+        torch.cuda.synchronize()
+        fp64_ms = (time.perf_counter() - t1) * 1e3
+
+    avg = sm_ms / max(sm_n, 1)
+    bytes_per_launch = FP32_SMOOTH_BYTES_PER_CELL * (m / 2)
+    achieved = bytes_per_launch / (avg * 1e-3) / 1e9 if sm_n else None
+    out = {
+        "metric": "512^3 f(R) MG solve to 1e-6 resid: FP32+adjoint vs FP64 time; % HBM peak",
+        "value": m / (ms * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{n}^3 grid, {n} Mpc/h box, {n}^3 Zel'dovich FP32 particles "
+                               f"(seed 3); f(R) n=1 |f_R0|={a.fr0:g}, Omega_m=0.3, a=1; CIC, "
+                               f"FP32-refined V(1,1) solve and adjoint to {tol:g}, force, "
+                               f"4096-cell |F5|^2 loss",
+                   "grid": n, "tol": tol, "precision": "fp32-refined"},
+        "fp64_ms_per_step": fp64_ms,
+        "fp64_over_fp32": (fp64_ms / ms) if fp64_ms else None,
+        "phases": info,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "kernel": "k_smooth_corr<FR> (finest-level FP32 half-sweep)",
+                     "avg_launch_ms": avg, "launches": sm_n,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(a.cpu_n, a.fr0, tol)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -69,24 +69,27 @@ typedef struct {
   int cycle;        /* MG_CYCLE_V / _F / _W */
   int nu_pre;       /* Gauss-Seidel sweeps (each = both colours) before coarsening, >= 0 */
   int nu_post;      /* sweeps after the correction, >= 1 */
-  int inner_cycles; /* MG_FP32_REFINED: FP32 cycles per FP64 outer step (>= 1) */
+  int inner_cycles; /* cycles between FP64 residual checks (refined mode: FP32
+                       cycles per outer step); 0 = automatic, from the measured
+                       contraction per cycle (1..4) */
   int max_cycles;   /* cap on cycles (FP64) or outer steps (refined), 1..64 */
   int precision;    /* MG_FP64 / MG_FP32_REFINED */
-  int coarse_sweeps;/* cap on sweeps of the coarsest level (0 = default 200) */
+  int coarse_sweeps;/* cap on sweeps of the coarsest level (0 = default 24) */
 } mg_solver_opts;
 
 typedef struct {
-  int cycles;            /* cycles (FP64) / outer steps (refined) performed */
+  int cycles;            /* FP64 residual checks (= outer steps in refined mode) */
   int status;            /* return code of the call */
   double rel_resid;      /* final RMS(d)/RMS(d at background) */
-  double resid_hist[64]; /* rel_resid after each cycle / outer step */
+  double resid_hist[64]; /* rel_resid at each check */
   double ms_total;       /* wall time of the call (stream-synchronised) */
+  int vcycles;           /* multigrid cycles run on the finest level */
 } mg_stats;
 
 typedef struct mg_ctx mg_ctx;
 
 /* Create a context for n^3 grids on a HIP stream (NULL = default stream).
- * n must be even and >= 4; the level pyramid is n, n/2, ... while the half
+ * n must be even, 4 <= n <= 1600; the level pyramid is n, n/2, ... while the half
  * is even and >= 4 (4^3 coarsest for n = 2^l, 6^3 for n = 96).  Device
  * workspace is allocated on first use of each mode and kept until destroy.
  * Returns MG_EINVAL for a bad n or NULL out. */
@@ -174,6 +177,16 @@ typedef struct {
   double *field;           /* n^3 device doubles: initial guess in (NaN-free), solution out */
   float *force;            /* [3][n^3] device floats, or NULL */
 } mg_box_desc;
+
+/* Kernel timing with HIP events recorded on the context's stream around
+ * every launch of the finest-level smoothers (off by default; enabling
+ * clears the totals).  Classes: MG_PROF_SMOOTH32 (FP32 correction-form
+ * half-sweep), MG_PROF_SMOOTH64 (FP64 direct half-sweep), MG_PROF_LIN32 /
+ * MG_PROF_LIN64 (adjoint half-sweeps).  mg_prof_read waits for the stream
+ * and returns the summed duration and the launch count of one class. */
+enum { MG_PROF_SMOOTH32 = 0, MG_PROF_SMOOTH64 = 1, MG_PROF_LIN32 = 2, MG_PROF_LIN64 = 3 };
+int mg_prof_enable(mg_ctx *ctx, int on);
+int mg_prof_read(mg_ctx *ctx, int kernel_class, double *total_ms, int64_t *launches);
 
 int mg_solve_batched(mg_ctx *ctx, int n_box, const mg_box_desc *boxes,
                      const mg_solver_opts *opts, double tol, mg_stats *per_box);

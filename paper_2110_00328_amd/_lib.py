@@ -19,8 +19,9 @@ EXPORTS = (
     "mg_ctx_create", "mg_ctx_destroy", "mg_last_error", "mg_ctx_levels", "cic_assign",
     "mg_solve", "mg_residual", "mg_force", "mg_force_adjoint", "mg_solve_adjoint",
     "mg_loss_force_sq", "mg_relax_halfsweep", "mg_restrict", "mg_prolong_add",
-    "mg_solve_batched",
+    "mg_solve_batched", "mg_prof_enable", "mg_prof_read",
 )
+MG_PROF_SMOOTH32, MG_PROF_SMOOTH64, MG_PROF_LIN32, MG_PROF_LIN64 = 0, 1, 2, 3
 
 
 class ModelParams(ctypes.Structure):
@@ -60,6 +61,7 @@ class Stats(ctypes.Structure):
         ("rel_resid", ctypes.c_double),
         ("resid_hist", ctypes.c_double * 64),
         ("ms_total", ctypes.c_double),
+        ("vcycles", ctypes.c_int),
     ]
 
 
@@ -104,6 +106,8 @@ def load():
         "mg_restrict": (ci, [vp, vp, vp]),
         "mg_prolong_add": (ci, [vp, vp, vp]),
         "mg_solve_batched": (ci, [vp, ci, P(BoxDesc), P(SolverOpts), dbl, P(Stats)]),
+        "mg_prof_enable": (ci, [vp, ci]),
+        "mg_prof_read": (ci, [vp, ci, P(dbl), P(i64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -37,8 +37,10 @@ def model_params(box, a=1.0, omega_m=0.3, fr_n=1, fr0=1e-5, a_star=0.5, xi=1.0 /
                          lam, cq_keep_exp)
 
 
-def solver_opts(cycle="V", nu_pre=1, nu_post=1, inner_cycles=1, max_cycles=64, precision="fp32",
+def solver_opts(cycle="V", nu_pre=1, nu_post=1, inner_cycles=0, max_cycles=64, precision="fp32",
                 coarse_sweeps=0):
+    """mg_solver_opts; inner_cycles = 0 plans the cycles between FP64
+    residual checks from the measured contraction."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     cyc = CYCLES[cycle] if isinstance(cycle, str) else int(cycle)
     return L.SolverOpts(cyc, nu_pre, nu_post, inner_cycles, max_cycles, prec, coarse_sweeps)
@@ -184,6 +186,17 @@ class Context:
         self._check(self.lib.mg_loss_force_sq(self.ptr, _p(force), _p(cells), cells.numel(),
                                               _p(grad_out), _p(loss_out)))
         return loss_out, grad_out
+
+    # -- kernel timing ------------------------------------------------------
+    def prof_enable(self, on=True):
+        self._check(self.lib.mg_prof_enable(self.ptr, 1 if on else 0))
+
+    def prof_read(self, cls):
+        """(total ms, launches) of one timed kernel class since prof_enable."""
+        ms = ctypes.c_double(0.0)
+        cnt = ctypes.c_int64(0)
+        self._check(self.lib.mg_prof_read(self.ptr, cls, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
 
     # -- single operations (parity checks) ---------------------------------
     def relax_halfsweep(self, model, params, delta, field, colour):

@@ -39,6 +39,8 @@ struct Consts {
   double phi5;     // Phi5 prefactor: c~^2/2 (w), 3 xi^2 Om b*^2 c~^2 a*^-3 (u^2), beta (phi~)
   double bg;       // background value of the solved variable
   double bg_coef;  // |d| at the background per unit delta
+  // FP32 copies used by the correction-form kernels
+  float f_ct2, f_kw, f_s_ratio, f_s_amp, f_beta, f_alpha, f_phibar, f_cq_src, f_cq_pot;
 };
 
 // ---------------------------------------------------------------------------
@@ -103,6 +105,55 @@ __device__ __forceinline__ T cubic_root(T p, T q) {
   return t;
 }
 
+// Approximation (relative error ~1e-5 away from double roots) of the same
+// root from the hardware exp2/log2, for use as the start of Newton polishing:
+//   sinh(asinh(x)/3) = (t - 1/t)/2,  cosh(acosh(x)/3) = (t + 1/t)/2,
+//   t = (|x| + sqrt(x^2 +- 1))^{1/3}.
+__device__ __forceinline__ float cubic_root_approx(float p, float q) {
+  if (p == 0.0f) {
+    float a = fabsf(q);
+    float c = a > 0.0f ? __expf(__logf(a) * (1.0f / 3.0f)) : 0.0f;
+    return q > 0.0f ? -c : c;
+  }
+  float s = sqrtf(fabsf(p) * (1.0f / 3.0f));
+  float x = __fdividef(1.5f * q, p * s);
+  float ax = fabsf(x);
+  if (p > 0.0f) {
+    float y;
+    if (ax < 1e-3f) {
+      y = ax * (1.0f / 3.0f);
+    } else {
+      float L = ax > 1e18f ? __logf(2.0f * ax) : __logf(ax + sqrtf(ax * ax + 1.0f));
+      float t = __expf(L * (1.0f / 3.0f));
+      y = 0.5f * (t - __frcp_rn(t));
+    }
+    return -2.0f * s * copysignf(y, x);
+  }
+  if (ax >= 1.0f) {
+    float L = ax > 1e18f ? __logf(2.0f * ax) : __logf(ax + sqrtf(ax * ax - 1.0f));
+    float t = __expf(L * (1.0f / 3.0f));
+    float y = 0.5f * (t + __frcp_rn(t));
+    return copysignf(2.0f * s * y, x);
+  }
+  return 2.0f * s * __cosf(acosf(x) * (1.0f / 3.0f));
+}
+
+// FP64 root of t^3 + p t + q = 0 with q < 0 (unique positive root): FP32
+// start, two FP64 Newton steps (quadratic from ~1e-5: ~1e-20); falls back to
+// the FP64 closed form when the start is not usable.
+__device__ __forceinline__ double cubic_root_pos64(double p, double q) {
+  float t0 = cubic_root_approx(float(p), float(q));
+  if (!(t0 > 0.0f) || !isfinite(t0)) return cubic_root<double>(p, q);
+  double t = double(t0);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    double f = (t * t + p) * t + q;
+    double fp = 3.0 * t * t + p;
+    t -= f / fp;
+  }
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // direct form: v <- exact per-cell solution of L^h(v)_c = S_c
 // ---------------------------------------------------------------------------
@@ -114,13 +165,18 @@ __device__ __forceinline__ T direct_update(const Consts& C, T h2, T vc, T sum, T
     T g = h2 / (T(6) * T(C.ct2));
     T p = g * (T(C.om_a) * dc + T(C.K) - sc) - sum / T(6);
     T q = -g * T(C.K) * T(C.wpow);
-    T u = cubic_root<T>(p, q);
+    T u;
+    if constexpr (sizeof(T) == 8) u = cubic_root_pos64(p, q);
+    else u = cubic_root<T>(p, q);
     return u * u;
   } else if constexpr (M == SYM) {
     // u^3 + p u + q = 0 (eq:sym_cubic_eqn; S shifts q)
     T kap = T(C.ct2) / (T(C.s_amp) * h2);
     T p = (T(1) + dc) * T(C.s_ratio) - T(1) + T(6) * kap;
     T q = -kap * sum + sc / T(C.s_amp);
+    if constexpr (sizeof(T) == 8) {
+      if (q < T(0)) return cubic_root_pos64(p, q);
+    }
     return cubic_root<T>(p, q);
   } else {
     // Newton-Gauss-Seidel on eq:csf_eom_code
@@ -167,20 +223,19 @@ __device__ __forceinline__ float corr_nl(const Consts& C, float e, float x, floa
     //   = A t / (s (1 + s)), s = sqrt(1+t)
     float t = e / x;
     float s = sqrtf(1.0f + t);
-    float A = float(C.K * C.wpow) * rsqrtf(x);
+    float A = C.f_kw * rsqrtf(x);
     return A * t / (s * (1.0f + s));
   } else if constexpr (M == SYM) {
     // -s_amp [ (rho a*^3/a^3 - 1 + 3x^2) e + 3x e^2 + e^3 ]
-    float m = (1.0f + dc) * float(C.s_ratio) - 1.0f + 3.0f * x * x;
-    return -float(C.s_amp) * (m + (3.0f * x + e) * e) * e;
+    float m = (1.0f + dc) * C.f_s_ratio - 1.0f + 3.0f * x * x;
+    return -C.f_s_amp * (m + (3.0f * x + e) * e) * e;
   } else {
-    float ct2 = float(C.ct2);
-    float ex = C.cq_keep_exp ? expf(float(C.beta) * x / ct2) : 1.0f;
-    float src = C.cq_keep_exp ? ex * expm1f(float(C.beta) * e / ct2) * (1.0f + dc) : 0.0f;
-    float Y = float(C.phibar) + x / ct2;
-    float pot = powf(Y, -(1.0f + float(C.alpha))) *
-                expm1f(-(1.0f + float(C.alpha)) * log1pf(e / (ct2 * Y)));
-    return -float(C.cq_src) * src + float(C.cq_pot) * pot;
+    float ct2 = C.f_ct2;
+    float ex = C.cq_keep_exp ? expf(C.f_beta * x / ct2) : 1.0f;
+    float src = C.cq_keep_exp ? ex * expm1f(C.f_beta * e / ct2) * (1.0f + dc) : 0.0f;
+    float Y = C.f_phibar + x / ct2;
+    float pot = powf(Y, -(1.0f + C.f_alpha)) * expm1f(-(1.0f + C.f_alpha) * log1pf(e / (ct2 * Y)));
+    return -C.f_cq_src * src + C.f_cq_pot * pot;
   }
 }
 
@@ -190,8 +245,8 @@ template <int M>
 __device__ __forceinline__ float corr_G(const Consts& C, float h2, float ec, float sum, float x,
                                         float dc) {
   float lap = (sum - 6.0f * ec) / h2;
-  if constexpr (M == FR) return -float(C.ct2) * lap + corr_nl<M>(C, ec, x, dc);
-  else if constexpr (M == SYM) return float(C.ct2) * lap + corr_nl<M>(C, ec, x, dc);
+  if constexpr (M == FR) return -C.f_ct2 * lap + corr_nl<M>(C, ec, x, dc);
+  else if constexpr (M == SYM) return C.f_ct2 * lap + corr_nl<M>(C, ec, x, dc);
   else return lap + corr_nl<M>(C, ec, x, dc);
 }
 
@@ -204,40 +259,38 @@ __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec
     // s = sqrt(1+t):  s^3 + (beta - 1 - gamma) s - beta = 0,
     //   beta = A / (D x), gamma = R / (D x);  sigma = s - 1 solves
     //   sigma^3 + 3 sigma^2 + (2 + beta - gamma) sigma - gamma = 0.
-    float c2h2 = float(C.ct2) / h2;
-    float ix = 1.0f / x;
-    float iD = 1.0f / (6.0f * c2h2);
-    float beta = float(C.K * C.wpow) * iD * ix * sqrtf(ix);
+    float iD = h2 * (1.0f / 6.0f) / C.f_ct2;  // h^2 / (6 c^2), a level constant
+    float ix = __frcp_rn(x);
+    float beta = C.f_kw * iD * ix * sqrtf(ix);
     float gamma = (rho * iD + sum * (1.0f / 6.0f)) * ix;
     float c1 = 2.0f + beta - gamma;
     float sg;
     if (fabsf(gamma) < 1e-2f * c1) {
-      sg = gamma / c1;  // small correction: linear guess, Newton below
+      sg = __fdividef(gamma, c1);  // small correction: linear guess, Newton below
     } else {
-      float s = cubic_root<float>(beta - 1.0f - gamma, -beta);
-      sg = s - 1.0f;
+      sg = cubic_root_approx(beta - 1.0f - gamma, -beta) - 1.0f;
     }
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
       float f = ((sg + 3.0f) * sg + c1) * sg - gamma;
       float fp = (3.0f * sg + 6.0f) * sg + c1;
-      sg -= f / fp;
+      sg -= __fdividef(f, fp);
     }
     return x * sg * (sg + 2.0f);
   } else if constexpr (M == SYM) {
     // e^3 + 3x e^2 + P e + Q = 0, P = m + 6 kap, Q = rho/s_amp - kap sum,
     // m = (1+delta) a*^3/a^3 - 1 + 3x^2, kap = c^2/(s_amp h^2)
-    float kap = float(C.ct2) / (float(C.s_amp) * h2);
-    float P = (1.0f + dc) * float(C.s_ratio) - 1.0f + 3.0f * x * x + 6.0f * kap;
-    float Q = rho / float(C.s_amp) - kap * sum;
+    float kap = C.f_ct2 / (C.f_s_amp * h2);
+    float P = (1.0f + dc) * C.f_s_ratio - 1.0f + 3.0f * x * x + 6.0f * kap;
+    float Q = rho / C.f_s_amp - kap * sum;
     float e;
     if (P > 0.0f && fabsf(Q) < 1e-2f * P * fabsf(x)) {
-      e = -Q / P;
+      e = __fdividef(-Q, P);
     } else {
       // total field y = x + e solves y^3 + p y + q = 0 (paper's branch)
       float p = P - 3.0f * x * x;
       float q = (2.0f * x * x - P) * x + Q;
-      e = cubic_root<float>(p, q) - x;
+      e = (q < 0.0f ? cubic_root_approx(p, q) : cubic_root<float>(p, q)) - x;
     }
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
@@ -248,13 +301,12 @@ __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec
     return e;
   } else {
     // Newton-Gauss-Seidel (eq:relaxation_iteration) on the correction
-    float ct2 = float(C.ct2);
+    float ct2 = C.f_ct2;
     float G = corr_G<M>(C, h2, ec_old, sum, x, dc) - rho;
-    float ex = C.cq_keep_exp ? expf(float(C.beta) * (x + ec_old) / ct2) : 0.0f;
-    float Y = float(C.phibar) + (x + ec_old) / ct2;
-    float dG = -6.0f / h2 - float(C.cq_src) * float(C.beta) / ct2 * ex * (1.0f + dc) -
-               float(C.cq_pot) * (1.0f + float(C.alpha)) / ct2 *
-                   powf(Y, -(2.0f + float(C.alpha)));
+    float ex = C.cq_keep_exp ? expf(C.f_beta * (x + ec_old) / ct2) : 0.0f;
+    float Y = C.f_phibar + (x + ec_old) / ct2;
+    float dG = -6.0f / h2 - C.f_cq_src * C.f_beta / ct2 * ex * (1.0f + dc) -
+               C.f_cq_pot * (1.0f + C.f_alpha) / ct2 * powf(Y, -(2.0f + C.f_alpha));
     return ec_old - G / dG;
   }
 }
@@ -263,12 +315,12 @@ __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec
 // mode Newton step of the coarsest CQ level)
 template <int M>
 __device__ __forceinline__ float corr_diag(const Consts& C, float h2, float ec, float x, float dc) {
-  float ct2 = float(C.ct2);
+  float ct2 = C.f_ct2;
   if constexpr (M == CQ) {
-    float ex = C.cq_keep_exp ? expf(float(C.beta) * (x + ec) / ct2) : 0.0f;
-    float Y = float(C.phibar) + (x + ec) / ct2;
-    return -6.0f / h2 - float(C.cq_src) * float(C.beta) / ct2 * ex * (1.0f + dc) -
-           float(C.cq_pot) * (1.0f + float(C.alpha)) / ct2 * powf(Y, -(2.0f + float(C.alpha)));
+    float ex = C.cq_keep_exp ? expf(C.f_beta * (x + ec) / ct2) : 0.0f;
+    float Y = C.f_phibar + (x + ec) / ct2;
+    return -6.0f / h2 - C.f_cq_src * C.f_beta / ct2 * ex * (1.0f + dc) -
+           C.f_cq_pot * (1.0f + C.f_alpha) / ct2 * powf(Y, -(2.0f + C.f_alpha));
   } else {
     return 1.0f;
   }

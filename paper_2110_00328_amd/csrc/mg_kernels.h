@@ -14,10 +14,34 @@
 
 namespace mgg {
 
+// Division by a run-time constant d (1 <= d < 2^31) as a multiply-high and
+// a shift (Granlund & Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994): l = ceil(log2 d), m = floor(2^32 (2^l - d)/d) + 1,
+// x / d = (mulhi(x, m) + x) >> l for every 32-bit x.
+struct FastDiv {
+  uint32_t m, s;
+  __host__ static FastDiv make(uint32_t d) {
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    FastDiv f;
+    f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+    f.s = l;
+    return f;
+  }
+  __device__ __forceinline__ uint32_t div(uint32_t x) const {
+    uint32_t t = __umulhi(x, m);
+    return (uint32_t)(((uint64_t)t + x) >> s);
+  }
+};
+
+// One level.  Cell counts stay below 2^32 (n <= 1600), so all index
+// arithmetic is 32-bit.
 struct Lev {
-  int n;         // cells per side
-  int nh;        // n / 2
-  int64_t half;  // n^3 / 2: cells of one colour
+  int n;          // cells per side
+  int nh;         // n / 2
+  int64_t half;   // n^3 / 2: cells of one colour
+  FastDiv dnh;    // division by nh
+  FastDiv dn;     // division by n
 };
 
 constexpr int kBlock = 256;
@@ -35,18 +59,29 @@ __device__ __forceinline__ int64_t xcd_block() {
 }
 __device__ __forceinline__ int64_t gid() { return xcd_block() * blockDim.x + threadIdx.x; }
 
-__device__ __forceinline__ void dec(int64_t g, const Lev& L, int& ih, int& j, int& k) {
-  ih = (int)(g % L.nh);
-  int64_t r = g / L.nh;
-  j = (int)(r % L.n);
-  k = (int)(r / L.n);
+__device__ __forceinline__ void dec(int64_t g64, const Lev& L, int& ih, int& j, int& k) {
+  uint32_t g = (uint32_t)g64;
+  uint32_t r = L.dnh.div(g);
+  ih = (int)(g - r * (uint32_t)L.nh);
+  uint32_t kk = L.dn.div(r);
+  j = (int)(r - kk * (uint32_t)L.n);
+  k = (int)kk;
 }
-__device__ __forceinline__ int64_t prow(const Lev& L, int j, int k) {
-  return ((int64_t)k * L.n + j) * L.nh;
+// natural (i, j, k) of a natural linear index
+__device__ __forceinline__ void dec_nat(int64_t g64, const Lev& L, int& i, int& j, int& k) {
+  uint32_t g = (uint32_t)g64;
+  uint32_t r = L.dn.div(g);
+  i = (int)(g - r * (uint32_t)L.n);
+  uint32_t kk = L.dn.div(r);
+  j = (int)(r - kk * (uint32_t)L.n);
+  k = (int)kk;
+}
+__device__ __forceinline__ uint32_t prow(const Lev& L, int j, int k) {
+  return ((uint32_t)k * (uint32_t)L.n + (uint32_t)j) * (uint32_t)L.nh;
 }
 // packed index (including the colour offset) of natural cell (i,j,k)
-__device__ __forceinline__ int64_t pk_of(const Lev& L, int i, int j, int k) {
-  return (int64_t)((i + j + k) & 1) * L.half + prow(L, j, k) + (i >> 1);
+__device__ __forceinline__ uint32_t pk_of(const Lev& L, int i, int j, int k) {
+  return (uint32_t)((i + j + k) & 1) * (uint32_t)L.half + prow(L, j, k) + (uint32_t)(i >> 1);
 }
 
 template <typename T>
@@ -58,9 +93,72 @@ __device__ __forceinline__ T nbsum(const Lev& L, const T* __restrict__ o, int ih
   if (xp >= L.nh) xp -= L.nh;
   int jm = (j == 0) ? L.n - 1 : j - 1, jp = (j == L.n - 1) ? 0 : j + 1;
   int km = (k == 0) ? L.n - 1 : k - 1, kp = (k == L.n - 1) ? 0 : k + 1;
-  int64_t r = prow(L, j, k);
+  uint32_t r = prow(L, j, k);
   return (o[r + xm] + o[r + xp]) + (o[prow(L, jm, k) + ih] + o[prow(L, jp, k) + ih]) +
          (o[prow(L, j, km) + ih] + o[prow(L, j, kp) + ih]);
+}
+
+// ---------------------------------------------------------------------------
+// Vector access: V consecutive packed cells of one row per thread (16-byte
+// loads: 4 floats or 2 doubles), so each wave keeps more bytes in flight.
+// Requires nh % V == 0 (rows then start on V-aligned offsets).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Vec;
+template <>
+struct Vec<float> {
+  static constexpr int V = 4;
+  using type = float4;
+};
+template <>
+struct Vec<double> {
+  static constexpr int V = 2;
+  using type = double2;
+};
+template <typename T>
+__device__ __forceinline__ void ldv(const T* __restrict__ p, T* out) {
+  using VT = typename Vec<T>::type;
+  VT v = *reinterpret_cast<const VT*>(p);
+  if constexpr (Vec<T>::V == 4) {
+    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+  } else {
+    out[0] = v.x; out[1] = v.y;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void stv(T* __restrict__ p, const T* in) {
+  using VT = typename Vec<T>::type;
+  VT v;
+  if constexpr (Vec<T>::V == 4) {
+    v.x = in[0]; v.y = in[1]; v.z = in[2]; v.w = in[3];
+  } else {
+    v.x = in[0]; v.y = in[1];
+  }
+  *reinterpret_cast<VT*>(p) = v;
+}
+// Neighbour sums of the V cells (ih0 .. ih0+V-1, j, k) of colour c from the
+// other colour's array o; s = (j + k + c) & 1.  Same summation order as nbsum.
+template <typename T>
+__device__ __forceinline__ void nbsum_vec(const Lev& L, const T* __restrict__ o, int ih0, int j,
+                                          int k, int s, T* sum) {
+  constexpr int V = Vec<T>::V;
+  int jm = (j == 0) ? L.n - 1 : j - 1, jp = (j == L.n - 1) ? 0 : j + 1;
+  int km = (k == 0) ? L.n - 1 : k - 1, kp = (k == L.n - 1) ? 0 : k + 1;
+  uint32_t r = prow(L, j, k);
+  T xv[V + 1], ym[V], yp[V], zm[V], zp[V];
+  if (s) {
+    ldv<T>(o + r + ih0, xv);
+    xv[V] = o[r + (ih0 + V == L.nh ? 0 : ih0 + V)];
+  } else {
+    ldv<T>(o + r + ih0, xv + 1);
+    xv[0] = o[r + (ih0 == 0 ? L.nh - 1 : ih0 - 1)];
+  }
+  ldv<T>(o + prow(L, jm, k) + ih0, ym);
+  ldv<T>(o + prow(L, jp, k) + ih0, yp);
+  ldv<T>(o + prow(L, j, km) + ih0, zm);
+  ldv<T>(o + prow(L, j, kp) + ih0, zp);
+#pragma unroll
+  for (int q = 0; q < V; ++q) sum[q] = (xv[q] + xv[q + 1]) + (ym[q] + yp[q]) + (zm[q] + zp[q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -94,6 +192,17 @@ __device__ __forceinline__ double block_sum_all(double v, double* sh) {
   return sh[16];
 }
 
+// stage 1: block b sums the contiguous chunk [b*chunk, (b+1)*chunk)
+__global__ void k_sum_chunks(const double* __restrict__ part, int64_t m, int64_t chunk,
+                             double* __restrict__ out) {
+  __shared__ double sh[32];
+  int64_t lo = (int64_t)blockIdx.x * chunk;
+  int64_t hi = lo + chunk < m ? lo + chunk : m;
+  double s = 0.0;
+  for (int64_t q = lo + threadIdx.x; q < hi; q += blockDim.x) s += part[q];
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
 __global__ void k_sum_partials(const double* __restrict__ part, int64_t m, double* out, int slot) {
   __shared__ double sh[32];
   double s = 0.0;
@@ -111,9 +220,8 @@ __global__ __launch_bounds__(kBlock) void k_pack(Lev L, const TI* __restrict__ n
                                                  TO* __restrict__ pk, double scale) {
   int64_t g = gid();
   if (g >= 2 * L.half) return;
-  int i = (int)(g % L.n);
-  int64_t r = g / L.n;
-  int j = (int)(r % L.n), k = (int)(r / L.n);
+  int i, j, k;
+  dec_nat(g, L, i, j, k);
   pk[pk_of(L, i, j, k)] = TO(scale * double(nat[g]));
 }
 template <typename TI, typename TO>
@@ -121,9 +229,8 @@ __global__ __launch_bounds__(kBlock) void k_unpack(Lev L, const TI* __restrict__
                                                    TO* __restrict__ nat, double scale) {
   int64_t g = gid();
   if (g >= 2 * L.half) return;
-  int i = (int)(g % L.n);
-  int64_t r = g / L.n;
-  int j = (int)(r % L.n), k = (int)(r / L.n);
+  int i, j, k;
+  dec_nat(g, L, i, j, k);
   nat[g] = TO(scale * double(pk[pk_of(L, i, j, k)]));
 }
 template <typename T>
@@ -180,10 +287,8 @@ __device__ __forceinline__ void op_resid_restrict_direct(const Lev& Lf, const Le
                                                          T* __restrict__ Rv, T* __restrict__ vinit,
                                                          T* __restrict__ Sd, const Consts& C,
                                                          int64_t gc) {
-  int nc = Lc.n;
-  int I = (int)(gc % nc);
-  int64_t r = gc / nc;
-  int J = (int)(r % nc), K = (int)(r / nc);
+  int I, J, K;
+  dec_nat(gc, Lc, I, J, K);
   T sv = T(0), sd = T(0);
 #pragma unroll
   for (int d = 0; d < 2; ++d)
@@ -192,7 +297,7 @@ __device__ __forceinline__ void op_resid_restrict_direct(const Lev& Lf, const Le
       int j = 2 * J + b, k = 2 * K + d;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        int64_t g = c * Lf.half + prow(Lf, j, k) + I;
+        uint32_t g = (uint32_t)c * (uint32_t)Lf.half + prow(Lf, j, k) + I;
         int s = (j + k + c) & 1;
         T vc = v[g];
         T sum = nbsum<T>(Lf, v + (1 - c) * Lf.half, I, j, k, s);
@@ -201,7 +306,7 @@ __device__ __forceinline__ void op_resid_restrict_direct(const Lev& Lf, const Le
         sd += direct_resid<M, T>(C, h2, vc, sum, T(dens[g]), sc);
       }
     }
-  int64_t pc = pk_of(Lc, I, J, K);
+  uint32_t pc = pk_of(Lc, I, J, K);
   T rv = sv * T(0.125);
   Rv[pc] = rv;
   vinit[pc] = rv;
@@ -241,7 +346,7 @@ __device__ __forceinline__ void op_prolong_add(const Lev& Lf, const Lev& Lc, T* 
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
-        int64_t pc = pk_of(Lc, Is[a], Js[b], Ks[d]);
+        uint32_t pc = pk_of(Lc, Is[a], Js[b], Ks[d]);
         T c = RvH ? (vH[pc] - RvH[pc]) : vH[pc];
         T w = T((a ? 1 : 3) * (b ? 1 : 3) * (d ? 1 : 3)) * T(1.0 / 64.0);
         acc += w * c;
@@ -249,18 +354,62 @@ __device__ __forceinline__ void op_prolong_add(const Lev& Lf, const Lev& Lc, T* 
   v[g] += acc;
 }
 
+// v^h += P c for the 8 children of coarse cell gc (natural index over nc^3):
+// c is the packed coarse correction; trilinear 3/4-1/4 per axis applied
+// separably over the 3x3x3 coarse neighbourhood (27/9/3/1 in total).
+template <typename T>
+__device__ __forceinline__ void op_prolong_block(const Lev& Lf, const Lev& Lc, T* __restrict__ v,
+                                                 const T* __restrict__ c, int64_t gc) {
+  const int nc = Lc.n;
+  int I, J, K;
+  dec_nat(gc, Lc, I, J, K);
+  const int Is[3] = {I == 0 ? nc - 1 : I - 1, I, I + 1 == nc ? 0 : I + 1};
+  const int Js[3] = {J == 0 ? nc - 1 : J - 1, J, J + 1 == nc ? 0 : J + 1};
+  const int Ks[3] = {K == 0 ? nc - 1 : K - 1, K, K + 1 == nc ? 0 : K + 1};
+  T ax[3][3][2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      T c0 = c[pk_of(Lc, Is[0], Js[b], Ks[d])];
+      T c1 = c[pk_of(Lc, Is[1], Js[b], Ks[d])];
+      T c2 = c[pk_of(Lc, Is[2], Js[b], Ks[d])];
+      ax[d][b][0] = T(0.75) * c1 + T(0.25) * c0;
+      ax[d][b][1] = T(0.75) * c1 + T(0.25) * c2;
+    }
+  T ay[3][2][2];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      ay[d][0][x] = T(0.75) * ax[d][1][x] + T(0.25) * ax[d][0][x];
+      ay[d][1][x] = T(0.75) * ax[d][1][x] + T(0.25) * ax[d][2][x];
+    }
+#pragma unroll
+  for (int z = 0; z < 2; ++z)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int j = 2 * J + y, k = 2 * K + z;
+      const uint32_t row = prow(Lf, j, k) + I;
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        T val = T(0.75) * ay[1][y][x] + T(0.25) * ay[z ? 2 : 0][y][x];
+        const int colour = (2 * I + x + j + k) & 1;
+        v[colour * Lf.half + row] += val;
+      }
+    }
+}
+
 // plain 8-mean restriction, natural coarse index gc, packed in/out
 template <typename TI, typename TO>
 __device__ __forceinline__ void op_restrict(const Lev& Lf, const Lev& Lc, const TI* __restrict__ f,
                                             TO* __restrict__ c, int64_t gc) {
-  int nc = Lc.n;
-  int I = (int)(gc % nc);
-  int64_t r = gc / nc;
-  int J = (int)(r % nc), K = (int)(r / nc);
+  int I, J, K;
+  dec_nat(gc, Lc, I, J, K);
   double s = 0.0;
   for (int d = 0; d < 2; ++d)
     for (int b = 0; b < 2; ++b) {
-      int64_t row = prow(Lf, 2 * J + b, 2 * K + d) + I;
+      uint32_t row = prow(Lf, 2 * J + b, 2 * K + d) + I;
       s += double(f[row]) + double(f[Lf.half + row]);
     }
   c[pk_of(Lc, I, J, K)] = TO(s * 0.125);
@@ -308,10 +457,8 @@ __device__ __forceinline__ void op_resid_restrict_corr(
     const float* __restrict__ dens, const float* __restrict__ rho, float h2,
     float* __restrict__ eH, float* __restrict__ eR, float* __restrict__ rhoH,
     float* __restrict__ XH, const Consts& C, int64_t gc) {
-  int nc = Lc.n;
-  int I = (int)(gc % nc);
-  int64_t r = gc / nc;
-  int J = (int)(r % nc), K = (int)(r / nc);
+  int I, J, K;
+  dec_nat(gc, Lc, I, J, K);
   float se = 0.0f, sd = 0.0f, sx = 0.0f;
 #pragma unroll
   for (int d = 0; d < 2; ++d)
@@ -320,7 +467,7 @@ __device__ __forceinline__ void op_resid_restrict_corr(
       int j = 2 * J + b, k = 2 * K + d;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        int64_t g = c * Lf.half + prow(Lf, j, k) + I;
+        uint32_t g = (uint32_t)c * (uint32_t)Lf.half + prow(Lf, j, k) + I;
         int s = (j + k + c) & 1;
         float ec = e[g];
         float sum = nbsum<float>(Lf, e + (1 - c) * Lf.half, I, j, k, s);
@@ -331,7 +478,7 @@ __device__ __forceinline__ void op_resid_restrict_corr(
         sd += corr_G<M>(C, h2, ec, sum, x, dc) - rho[g];
       }
     }
-  int64_t pc = pk_of(Lc, I, J, K);
+  uint32_t pc = pk_of(Lc, I, J, K);
   float re = se * 0.125f;
   eH[pc] = re;
   eR[pc] = re;
@@ -381,10 +528,8 @@ __device__ __forceinline__ void op_lin_resid_restrict(const Lev& Lf, const Lev& 
                                                       const T* __restrict__ r, T kh2,
                                                       T* __restrict__ rH, T* __restrict__ eH,
                                                       int64_t gc) {
-  int nc = Lc.n;
-  int I = (int)(gc % nc);
-  int64_t rr = gc / nc;
-  int J = (int)(rr % nc), K = (int)(rr / nc);
+  int I, J, K;
+  dec_nat(gc, Lc, I, J, K);
   T sd = T(0);
 #pragma unroll
   for (int d = 0; d < 2; ++d)
@@ -393,13 +538,187 @@ __device__ __forceinline__ void op_lin_resid_restrict(const Lev& Lf, const Lev& 
       int j = 2 * J + b, k = 2 * K + d;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        int64_t g = c * Lf.half + prow(Lf, j, k) + I;
+        uint32_t g = (uint32_t)c * (uint32_t)Lf.half + prow(Lf, j, k) + I;
         sd += cell_lin_resid<T>(Lf, e, dg, r, kh2, g);
       }
     }
-  int64_t pc = pk_of(Lc, I, J, K);
+  uint32_t pc = pk_of(Lc, I, J, K);
   rH[pc] = sd * T(0.125);
   eH[pc] = T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Vectorised grid kernels: V cells of one colour per thread (smoothers) or V
+// cells of each colour (residual kernels, so a row's two colours are read by
+// the same thread and the other colour's rows stay in L2).  g4 indexes
+// groups of V packed cells; nh % V == 0.
+// ---------------------------------------------------------------------------
+template <int M, typename TD>
+__global__ __launch_bounds__(kBlock) void k_smooth_direct_v(Lev L, double* v, const TD* dens,
+                                                            const double* S, int colour,
+                                                            double h2, Consts C) {
+  constexpr int V = Vec<double>::V;
+  uint32_t g4 = (uint32_t)gid();
+  if (g4 >= (uint32_t)(L.half / V)) return;
+  uint32_t g = g4 * V;
+  int ih0, j, k;
+  dec(g, L, ih0, j, k);
+  int s = (j + k + colour) & 1;
+  double* own = v + colour * L.half;
+  double sum[V], vo[V] = {0.0, 0.0}, sc[V] = {0.0, 0.0}, out[V];
+  nbsum_vec<double>(L, v + (1 - colour) * L.half, ih0, j, k, s, sum);
+  if (M == CQ) ldv<double>(own + g, vo);
+  if (S) ldv<double>(S + colour * L.half + g, sc);
+  const TD* dp = dens + colour * L.half + g;
+#pragma unroll
+  for (int q = 0; q < V; ++q)
+    out[q] = direct_update<M, double>(C, h2, vo[q], sum[q], double(dp[q]), sc[q]);
+  stv<double>(own + g, out);
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_smooth_corr_v(Lev L, float* e, const float* X,
+                                                          const float* dens, const float* rho,
+                                                          int colour, float h2, Consts C) {
+  constexpr int V = Vec<float>::V;
+  uint32_t g4 = (uint32_t)gid();
+  if (g4 >= (uint32_t)(L.half / V)) return;
+  uint32_t g = g4 * V;
+  int ih0, j, k;
+  dec(g, L, ih0, j, k);
+  int s = (j + k + colour) & 1;
+  float* own = e + colour * L.half;
+  uint32_t q0 = (uint32_t)colour * (uint32_t)L.half + g;
+  float sum[V], x[V], r[V], dc[V] = {0, 0, 0, 0}, eo[V] = {0, 0, 0, 0}, out[V];
+  nbsum_vec<float>(L, e + (1 - colour) * L.half, ih0, j, k, s, sum);
+  ldv<float>(X + q0, x);
+  ldv<float>(rho + q0, r);
+  if (M != FR) ldv<float>(dens + q0, dc);
+  if (M == CQ) ldv<float>(own + g, eo);
+#pragma unroll
+  for (int q = 0; q < V; ++q) out[q] = corr_update<M>(C, h2, eo[q], sum[q], x[q], dc[q], r[q]);
+  stv<float>(own + g, out);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_smooth_lin_v(Lev L, T* e, const T* dg, const T* r,
+                                                         int colour, T kh2) {
+  constexpr int V = Vec<T>::V;
+  uint32_t g4 = (uint32_t)gid();
+  if (g4 >= (uint32_t)(L.half / V)) return;
+  uint32_t g = g4 * V;
+  int ih0, j, k;
+  dec(g, L, ih0, j, k);
+  int s = (j + k + colour) & 1;
+  uint32_t q0 = (uint32_t)colour * (uint32_t)L.half + g;
+  T sum[V], d[V], rr[V], out[V];
+  nbsum_vec<T>(L, e + (1 - colour) * L.half, ih0, j, k, s, sum);
+  ldv<T>(dg + q0, d);
+  ldv<T>(r + q0, rr);
+#pragma unroll
+  for (int q = 0; q < V; ++q) out[q] = (rr[q] + kh2 * sum[q]) / (T(6) * kh2 + d[q]);
+  stv<T>(e + q0, out);
+}
+
+// FP64 outer step of the refined mode, both colours per thread:
+// d = F(w64), rho = -d, X = w64, e = 0; per-block sum of d^2.
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_outer_residual_v(Lev L, const double* w,
+                                                             const float* dens, Consts C,
+                                                             float* rho, float* X, float* e,
+                                                             double* part) {
+  constexpr int V = Vec<double>::V;
+  __shared__ double sh[32];
+  uint32_t g4 = (uint32_t)gid();
+  double acc = 0.0;
+  if (g4 < (uint32_t)(L.half / V)) {
+    uint32_t g = g4 * V;
+    int ih0, j, k;
+    dec(g, L, ih0, j, k);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint32_t q0 = (uint32_t)c * (uint32_t)L.half + g;
+      double sum[V], vc[V];
+      nbsum_vec<double>(L, w + (1 - c) * L.half, ih0, j, k, (j + k + c) & 1, sum);
+      ldv<double>(w + q0, vc);
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        double d = direct_resid<M, double>(C, 1.0, vc[q], sum[q], double(dens[q0 + q]), 0.0);
+        acc += d * d;
+        rho[q0 + q] = float(-d);
+        X[q0 + q] = float(vc[q]);
+        e[q0 + q] = 0.0f;
+      }
+    }
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// residual norm of the finest level (FP64 direct form), both colours per thread
+template <int M, typename TD>
+__global__ __launch_bounds__(kBlock) void k_resid_norm_v(Lev L, const double* v, const TD* dens,
+                                                         Consts C, double* part, double* d_nat) {
+  constexpr int V = Vec<double>::V;
+  __shared__ double sh[32];
+  uint32_t g4 = (uint32_t)gid();
+  double acc = 0.0;
+  if (g4 < (uint32_t)(L.half / V)) {
+    uint32_t g = g4 * V;
+    int ih0, j, k;
+    dec(g, L, ih0, j, k);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint32_t q0 = (uint32_t)c * (uint32_t)L.half + g;
+      int s = (j + k + c) & 1;
+      double sum[V], vc[V];
+      nbsum_vec<double>(L, v + (1 - c) * L.half, ih0, j, k, s, sum);
+      ldv<double>(v + q0, vc);
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        double d = direct_resid<M, double>(C, 1.0, vc[q], sum[q], double(dens[q0 + q]), 0.0);
+        acc += d * d;
+        if (d_nat) d_nat[((int64_t)k * L.n + j) * L.n + 2 * (ih0 + q) + s] = d;
+      }
+    }
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// FP64 outer step of the adjoint, both colours per thread: r = b - A lam ->
+// r (inner precision), e = 0, per-block sum of r^2
+template <typename TO>
+__global__ __launch_bounds__(kBlock) void k_lin_outer_v(Lev L, const double* lam, const double* dg,
+                                                        const double* b, double kh2, TO* r,
+                                                        TO* e, double* part) {
+  constexpr int V = Vec<double>::V;
+  __shared__ double sh[32];
+  uint32_t g4 = (uint32_t)gid();
+  double acc = 0.0;
+  if (g4 < (uint32_t)(L.half / V)) {
+    uint32_t g = g4 * V;
+    int ih0, j, k;
+    dec(g, L, ih0, j, k);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      uint32_t q0 = (uint32_t)c * (uint32_t)L.half + g;
+      double sum[V], lc[V], dd[V], bb[V];
+      nbsum_vec<double>(L, lam + (1 - c) * L.half, ih0, j, k, (j + k + c) & 1, sum);
+      ldv<double>(lam + q0, lc);
+      ldv<double>(dg + q0, dd);
+      ldv<double>(b + q0, bb);
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        double d = bb[q] - (kh2 * (6.0 * lc[q] - sum[q]) + dd[q] * lc[q]);
+        acc += d * d;
+        r[q0 + q] = TO(d);
+        e[q0 + q] = TO(0);
+      }
+    }
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -431,6 +750,17 @@ __global__ __launch_bounds__(kBlock) void k_prolong_add(Lev Lf, Lev Lc, T* v, co
                                                         const T* RvH) {
   int64_t g = gid();
   if (g < 2 * Lf.half) op_prolong_add<T>(Lf, Lc, v, vH, RvH, g);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_block(Lev Lf, Lev Lc, T* v, const T* c) {
+  int64_t g = gid();
+  if (g < 2 * Lc.half) op_prolong_block<T>(Lf, Lc, v, c, g);
+}
+// c = vH - c (coarse correction formed in place of R v)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_diff(int64_t m, const T* vH, T* c) {
+  int64_t g = gid();
+  if (g < m) c[g] = vH[g] - c[g];
 }
 template <typename TI, typename TO>
 __global__ __launch_bounds__(kBlock) void k_restrict(Lev Lf, Lev Lc, const TI* f, TO* c) {
@@ -577,6 +907,7 @@ struct Op {
 struct FusedProg {
   int nops;
   int coarse_sweeps;
+  int rx;  // correction form: also restrict the linearisation point X on the way down
   Op op[kMaxOps];
 };
 // Level pointers of the fused part (index = level - first fused level).
@@ -651,6 +982,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_direct(FusedDirect<T, T
             op_smooth_direct<M, T, TD>(L, F.v[l], F.dens[l], F.S[l], colour, F.h2[l], C, g);
           __syncthreads();
         }
+        if ((it & 3) != 3 && it + 1 < P.coarse_sweeps) continue;
         double s2 = 0.0, sd = 0.0, sj = 0.0;
         for (int64_t g = tid; g < 2 * L.half; g += nt) {
           double d = double(cell_resid_direct<M, T, TD>(L, F.v[l], F.dens[l], F.S[l], F.h2[l], C, g));
@@ -673,7 +1005,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_direct(FusedDirect<T, T
           __syncthreads();
         }
         if (r0 < 0.0) r0 = tot;
-        if (tot <= 1e-20 * r0 || tot == 0.0) break;
+        if (tot <= 1e-16 * r0 || tot == 0.0) break;
       }
     }
   }
@@ -698,7 +1030,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_corr(FusedCorr F, Fused
       const Lev Lc = F.L[l + 1];
       for (int64_t g = tid; g < 2 * Lc.half; g += nt)
         op_resid_restrict_corr<M>(L, Lc, F.e[l], F.X[l], F.dens[l], F.rho[l], F.h2[l], F.e[l + 1],
-                                  F.eR[l + 1], F.rho[l + 1], (float*)nullptr, C, g);
+                                  F.eR[l + 1], F.rho[l + 1], P.rx ? F.X[l + 1] : (float*)nullptr,
+                                  C, g);
       __syncthreads();
       for (int64_t g = tid; g < 2 * Lc.half; g += nt)
         op_coarse_src_corr<M>(Lc, F.eR[l + 1], F.X[l + 1], F.dens[l + 1], F.rho[l + 1], F.h2[l + 1],
@@ -717,6 +1050,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_corr(FusedCorr F, Fused
             op_smooth_corr<M>(L, F.e[l], F.X[l], F.dens[l], F.rho[l], colour, F.h2[l], C, g);
           __syncthreads();
         }
+        if ((it & 3) != 3 && it + 1 < P.coarse_sweeps) continue;
         double s2 = 0.0, sd = 0.0, sj = 0.0;
         for (int64_t g = tid; g < 2 * L.half; g += nt) {
           double d = double(cell_resid_corr<M>(L, F.e[l], F.X[l], F.dens[l], F.rho[l], F.h2[l], C, g));
@@ -738,7 +1072,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_corr(FusedCorr F, Fused
           __syncthreads();
         }
         if (r0 < 0.0) r0 = tot;
-        if (tot <= 1e-20 * r0 || tot == 0.0) break;
+        if (tot <= 1e-16 * r0 || tot == 0.0) break;
       }
     }
   }
@@ -761,7 +1095,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_lin(FusedLin<T> F, Fuse
             op_smooth_lin<T>(L, F.e[l], F.dg[l], F.r[l], colour, F.kh2[l], g);
           __syncthreads();
         }
-        if (op.kind == OP_COARSEST) {
+        if (op.kind == OP_COARSEST && ((it & 3) == 3 || it + 1 == count)) {
           double s2 = 0.0, sd = 0.0, sj = 0.0;
           for (int64_t g = tid; g < 2 * L.half; g += nt) {
             double d = double(cell_lin_resid<T>(L, F.e[l], F.dg[l], F.r[l], F.kh2[l], g));
@@ -778,7 +1112,7 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_lin(FusedLin<T> F, Fuse
           }
           __syncthreads();
           if (r0 < 0.0) r0 = tot;
-          if (tot <= 1e-20 * r0 || tot == 0.0) break;
+          if (tot <= 1e-16 * r0 || tot == 0.0) break;
         }
       }
     } else if (op.kind == OP_DOWN) {

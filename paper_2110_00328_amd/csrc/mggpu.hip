@@ -71,17 +71,53 @@ struct mg_ctx {
   Work32 w32;
   WorkAdj adj;
   double* part = nullptr;
+  double* part2 = nullptr;
   int64_t part_cap = 0;
   double* scal = nullptr;      // device scalars
   double* hscal = nullptr;     // pinned host mirror
   int64_t* cic = nullptr;      // CIC fixed-point accumulator
   double* nat64 = nullptr;     // natural-layout scratch (debug entry points)
   std::vector<void*> allocs;
+  // event timing of the finest-level smoothers
+  bool prof = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  std::vector<int> ev_cls;
+  int ev_used = 0;
+  double prof_ms[4] = {0, 0, 0, 0};
+  int64_t prof_n[4] = {0, 0, 0, 0};
 };
 
 namespace {
 
 inline unsigned nblk(int64_t m) { return (unsigned)((m + kBlock - 1) / kBlock); }
+
+constexpr int kEvPairs = 512;
+
+// accumulate the recorded event pairs (waits for the last one)
+void prof_flush(mg_ctx* ctx) {
+  if (ctx->ev_used == 0) return;
+  (void)hipEventSynchronize(ctx->ev[2 * ctx->ev_used - 1]);
+  for (int q = 0; q < ctx->ev_used; ++q) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[2 * q], ctx->ev[2 * q + 1]) == hipSuccess) {
+      ctx->prof_ms[ctx->ev_cls[q]] += ms;
+      ctx->prof_n[ctx->ev_cls[q]] += 1;
+    }
+  }
+  ctx->ev_used = 0;
+}
+// returns the pair index to close with prof_end, or -1 when timing is off
+int prof_begin(mg_ctx* ctx, int cls) {
+  if (!ctx->prof) return -1;
+  if (ctx->ev_used == kEvPairs) prof_flush(ctx);
+  int q = ctx->ev_used++;
+  ctx->ev_cls[q] = cls;
+  (void)hipEventRecord(ctx->ev[2 * q], ctx->stream);
+  return q;
+}
+void prof_end(mg_ctx* ctx, int q) {
+  if (q >= 0) (void)hipEventRecord(ctx->ev[2 * q + 1], ctx->stream);
+}
 
 int fail(mg_ctx* c, int code, const std::string& msg) {
   c->err = msg;
@@ -242,6 +278,15 @@ int make_consts(mg_ctx* ctx, int model, const mg_model_params* P, int n, Consts*
     C.bg = 0.0;
     C.bg_coef = fabs(C.cq_src);
   }
+  C.f_ct2 = float(C.ct2);
+  C.f_kw = float(C.K * C.wpow);
+  C.f_s_ratio = float(C.s_ratio);
+  C.f_s_amp = float(C.s_amp);
+  C.f_beta = float(C.beta);
+  C.f_alpha = float(C.alpha);
+  C.f_phibar = float(C.phibar);
+  C.f_cq_src = float(C.cq_src);
+  C.f_cq_pot = float(C.cq_pot);
   *out = C;
   return MG_OK;
 }
@@ -254,8 +299,8 @@ int check_opts(mg_ctx* ctx, const mg_solver_opts* o) {
   if (o->max_cycles < 1 || o->max_cycles > 64) return fail(ctx, MG_EINVAL, "max_cycles in 1..64");
   if (o->precision != MG_FP64 && o->precision != MG_FP32_REFINED)
     return fail(ctx, MG_EINVAL, "precision must be MG_FP64 or MG_FP32_REFINED");
-  if (o->precision == MG_FP32_REFINED && (o->inner_cycles < 1 || o->inner_cycles > 16))
-    return fail(ctx, MG_EINVAL, "inner_cycles in 1..16");
+  if (o->inner_cycles < 0 || o->inner_cycles > 16)
+    return fail(ctx, MG_EINVAL, "inner_cycles in 0 (automatic) .. 16");
   if (o->coarse_sweeps < 0 || o->coarse_sweeps > 5000)
     return fail(ctx, MG_EINVAL, "coarse_sweeps in 0..5000");
   return MG_OK;
@@ -263,12 +308,36 @@ int check_opts(mg_ctx* ctx, const mg_solver_opts* o) {
 
 double lev_h2(int l) { return double(1u << l) * double(1u << l); }
 
+// Cycles to run before the next residual check.  fixed > 0: that many.
+// Otherwise from the contraction per cycle seen so far: enough to reach
+// tol with 5% margin, between 1 and 4 (2 before anything is measured).
+int plan_cycles(int fixed, double rel, double rel_prev, int k_prev, double tol) {
+  if (fixed > 0) return fixed;
+  if (rel_prev <= 0.0 || k_prev <= 0 || !(rel < rel_prev)) return 2;
+  double rho = pow(rel / rel_prev, 1.0 / k_prev);
+  if (rho < 0.01) rho = 0.01;
+  if (rho > 0.9) rho = 0.9;
+  double need = 1.05 * log(tol / rel) / log(rho);
+  int k = (int)ceil(need);
+  return k < 1 ? 1 : (k > 4 ? 4 : k);
+}
+
 // ---------------------------------------------------------------------------
 // reductions to the host
 // ---------------------------------------------------------------------------
-int sum_to_host(mg_ctx* ctx, int64_t nparts, double* out) {
-  k_sum_partials<<<1, 1024, 0, ctx->stream>>>(ctx->part, nparts, ctx->scal, 0);
+// deterministic: fixed chunks summed by up to 256 blocks, then one block
+int sum_on_device(mg_ctx* ctx, int64_t nparts, double* dst) {
+  int64_t nb = (nparts + 2047) / 2048;
+  if (nb > 256) nb = 256;
+  int64_t chunk = (nparts + nb - 1) / nb;
+  k_sum_chunks<<<(unsigned)nb, 256, 0, ctx->stream>>>(ctx->part, nparts, chunk, ctx->part2);
+  k_sum_partials<<<1, 256, 0, ctx->stream>>>(ctx->part2, nb, dst, 0);
   LAUNCHCHK();
+  return MG_OK;
+}
+
+int sum_to_host(mg_ctx* ctx, int64_t nparts, double* out) {
+  ACHK(sum_on_device(ctx, nparts, ctx->scal));
   HIPCHK(hipMemcpyAsync(ctx->hscal, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   *out = ctx->hscal[0];
@@ -309,13 +378,14 @@ void gen_prog(std::vector<Op>& ops, int l, int lmax, int type, int nu1, int nu2)
   ops.push_back(Op{OP_SMOOTH, (uint8_t)l, (uint8_t)nu2, 0});
 }
 
-int make_prog(mg_ctx* ctx, int l, const mg_solver_opts* o, int type, FusedProg* P) {
+int make_prog(mg_ctx* ctx, int l, const mg_solver_opts* o, int type, FusedProg* P, int rx = 0) {
   std::vector<Op> ops;
   int f = ctx->fused_from;
   gen_prog(ops, l - f, ctx->nlev - 1 - f, type, o->nu_pre, o->nu_post);
   if ((int)ops.size() > kMaxOps) return fail(ctx, MG_EINVAL, "fused cycle program too long");
   P->nops = (int)ops.size();
-  P->coarse_sweeps = o->coarse_sweeps > 0 ? o->coarse_sweeps : 200;
+  P->coarse_sweeps = o->coarse_sweeps > 0 ? o->coarse_sweeps : 24;
+  P->rx = rx;
   for (size_t q = 0; q < ops.size(); ++q) P->op[q] = ops[q];
   return MG_OK;
 }
@@ -327,14 +397,26 @@ template <int M>
 int smooth64(mg_ctx* ctx, const Consts& C, int l, int sweeps) {
   Work64& W = ctx->w64;
   const Lev& L = ctx->L[l];
+  const bool vec = (L.nh % Vec<double>::V) == 0;
+  const int64_t nv = L.half / Vec<double>::V;
   for (int s = 0; s < sweeps; ++s)
     for (int colour = 0; colour < 2; ++colour) {
-      if (l == 0)
-        k_smooth_direct<M, double, float><<<nblk(L.half), kBlock, 0, ctx->stream>>>(
-            L, W.v[0], W.dens0, (const double*)nullptr, colour, 1.0, C);
-      else
+      if (l == 0) {
+        int q = prof_begin(ctx, MG_PROF_SMOOTH64);
+        if (vec)
+          k_smooth_direct_v<M, float><<<nblk(nv), kBlock, 0, ctx->stream>>>(
+              L, W.v[0], W.dens0, (const double*)nullptr, colour, 1.0, C);
+        else
+          k_smooth_direct<M, double, float><<<nblk(L.half), kBlock, 0, ctx->stream>>>(
+              L, W.v[0], W.dens0, (const double*)nullptr, colour, 1.0, C);
+        prof_end(ctx, q);
+      } else if (vec) {
+        k_smooth_direct_v<M, double><<<nblk(nv), kBlock, 0, ctx->stream>>>(
+            L, W.v[l], W.dens[l], W.S[l], colour, lev_h2(l), C);
+      } else {
         k_smooth_direct<M, double, double><<<nblk(L.half), kBlock, 0, ctx->stream>>>(
             L, W.v[l], W.dens[l], W.S[l], colour, lev_h2(l), C);
+      }
     }
   LAUNCHCHK();
   return MG_OK;
@@ -386,8 +468,10 @@ int cycle64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
     ACHK(cycle64<M>(ctx, C, o, l + 1, MG_CYCLE_F));
     ACHK(cycle64<M>(ctx, C, o, l + 1, MG_CYCLE_V));
   }
-  k_prolong_add<double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.v[l], W.v[l + 1],
+  k_coarse_diff<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(cells(Lc), W.v[l + 1],
                                                                        W.Rv[l + 1]);
+  k_prolong_block<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.v[l],
+                                                                         W.Rv[l + 1]);
   LAUNCHCHK();
   return smooth64<M>(ctx, C, l, o->nu_post);
 }
@@ -395,11 +479,19 @@ int cycle64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
 template <int M>
 int resid64(mg_ctx* ctx, const Consts& C, double eps_bg, double* rel, double* d_nat) {
   const Lev& L = ctx->L[0];
-  k_resid_norm_direct<M, double, float><<<nblk(cells(L)), kBlock, 0, ctx->stream>>>(
-      L, ctx->w64.v[0], ctx->w64.dens0, 1.0, C, ctx->part, d_nat);
+  int64_t nparts;
+  if (L.nh % Vec<double>::V == 0) {
+    nparts = nblk(L.half / Vec<double>::V);
+    k_resid_norm_v<M, float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+        L, ctx->w64.v[0], ctx->w64.dens0, C, ctx->part, d_nat);
+  } else {
+    nparts = nblk(cells(L));
+    k_resid_norm_direct<M, double, float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+        L, ctx->w64.v[0], ctx->w64.dens0, 1.0, C, ctx->part, d_nat);
+  }
   LAUNCHCHK();
   double s;
-  ACHK(sum_to_host(ctx, nblk(cells(L)), &s));
+  ACHK(sum_to_host(ctx, nparts, &s));
   *rel = sqrt(s / double(cells(L))) / eps_bg;
   return MG_OK;
 }
@@ -436,14 +528,21 @@ int solve64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   ACHK(bg_rms(ctx, C, delta, &eps_bg));
   double rel;
   ACHK(resid64<M>(ctx, C, eps_bg, &rel, nullptr));
-  int cyc = 0;
+  int cyc = 0, checks = 0, k_prev = 0;
+  double rel_prev = -1.0;
   int rc = MG_OK;
   if (!std::isfinite(rel)) rc = fail(ctx, MG_ENAN, "non-finite residual");
   while (rc == MG_OK && rel > tol && cyc < o->max_cycles) {
-    ACHK(cycle64<M>(ctx, C, o, 0, o->cycle));
+    // the residual is checked after each planned group of cycles
+    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol);
+    if (k > o->max_cycles - cyc) k = o->max_cycles - cyc;
+    for (int it = 0; it < k; ++it) ACHK(cycle64<M>(ctx, C, o, 0, o->cycle));
+    cyc += k;
+    rel_prev = rel;
+    k_prev = k;
     ACHK(resid64<M>(ctx, C, eps_bg, &rel, nullptr));
-    if (st && cyc < 64) st->resid_hist[cyc] = rel;
-    ++cyc;
+    if (st && checks < 64) st->resid_hist[checks] = rel;
+    ++checks;
     if (!std::isfinite(rel)) {
       rc = fail(ctx, MG_ENAN, "non-finite residual");
       break;
@@ -456,7 +555,8 @@ int solve64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
                                                                           field_out, sgn);
   LAUNCHCHK();
   if (st) {
-    st->cycles = cyc;
+    st->cycles = checks;
+    st->vcycles = cyc;
     st->rel_resid = rel;
   }
   return rc;
@@ -469,17 +569,29 @@ template <int M>
 int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps) {
   Work32& W = ctx->w32;
   const Lev& L = ctx->L[l];
+  const bool vec = (L.nh % Vec<float>::V) == 0;
+  const int64_t nv = L.half / Vec<float>::V;
   for (int s = 0; s < sweeps; ++s)
-    for (int colour = 0; colour < 2; ++colour)
-      k_smooth_corr<M><<<nblk(L.half), kBlock, 0, ctx->stream>>>(L, W.e[l], W.X[l], W.dens[l],
+    for (int colour = 0; colour < 2; ++colour) {
+      int q = l == 0 ? prof_begin(ctx, MG_PROF_SMOOTH32) : -1;
+      if (vec)
+        k_smooth_corr_v<M><<<nblk(nv), kBlock, 0, ctx->stream>>>(L, W.e[l], W.X[l], W.dens[l],
                                                                  W.rho[l], colour,
                                                                  float(lev_h2(l)), C);
+      else
+        k_smooth_corr<M><<<nblk(L.half), kBlock, 0, ctx->stream>>>(L, W.e[l], W.X[l], W.dens[l],
+                                                                   W.rho[l], colour,
+                                                                   float(lev_h2(l)), C);
+      prof_end(ctx, q);
+    }
   LAUNCHCHK();
   return MG_OK;
 }
 
+// rx: restrict the linearisation point X on the way down (first cycle of
+// an outer step)
 template <int M>
-int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int type) {
+int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int type, bool rx) {
   Work32& W = ctx->w32;
   if (l >= ctx->fused_from) {
     FusedCorr F;
@@ -496,7 +608,7 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
       F.eR[q] = W.eR[f + q];
     }
     FusedProg P;
-    ACHK(make_prog(ctx, l, o, type, &P));
+    ACHK(make_prog(ctx, l, o, type, &P, rx ? 1 : 0));
     k_fused_corr<M><<<1, kFusedThreads, 0, ctx->stream>>>(F, P, C);
     LAUNCHCHK();
     return MG_OK;
@@ -507,21 +619,23 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   ACHK(smooth32<M>(ctx, C, l, o->nu_pre));
   k_resid_restrict_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
       Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
-      W.rho[l + 1], (float*)nullptr, C);
+      W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C);
   k_coarse_src_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
       Lc, W.eR[l + 1], W.X[l + 1], W.dens[l + 1], W.rho[l + 1], float(lev_h2(l + 1)), C);
   LAUNCHCHK();
   if (type == MG_CYCLE_V) {
-    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V));
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V, rx));
   } else if (type == MG_CYCLE_W) {
-    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_W));
-    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_W));
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_W, rx));
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_W, false));
   } else {
-    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_F));
-    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V));
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_F, rx));
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V, false));
   }
-  k_prolong_add<float><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1],
+  k_coarse_diff<float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(cells(Lc), W.e[l + 1],
                                                                       W.eR[l + 1]);
+  k_prolong_block<float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l],
+                                                                        W.eR[l + 1]);
   LAUNCHCHK();
   return smooth32<M>(ctx, C, l, o->nu_post);
 }
@@ -545,14 +659,22 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   LAUNCHCHK();
   double eps_bg;
   ACHK(bg_rms(ctx, C, delta, &eps_bg));
-  int outer = 0, rc = MG_OK;
-  double rel = 0.0;
+  int outer = 0, rc = MG_OK, vc = 0, k_prev = 0;
+  double rel = 0.0, rel_prev = -1.0;
   for (;;) {
-    k_outer_residual<M><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, W.w, W.dens[0], C, W.rho[0],
-                                                             W.X[0], W.e[0], ctx->part);
+    int64_t nparts;
+    if (L0.nh % Vec<double>::V == 0) {
+      nparts = nblk(L0.half / Vec<double>::V);
+      k_outer_residual_v<M><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+          L0, W.w, W.dens[0], C, W.rho[0], W.X[0], W.e[0], ctx->part);
+    } else {
+      nparts = nblk(m);
+      k_outer_residual<M><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+          L0, W.w, W.dens[0], C, W.rho[0], W.X[0], W.e[0], ctx->part);
+    }
     LAUNCHCHK();
     double s;
-    ACHK(sum_to_host(ctx, nblk(m), &s));
+    ACHK(sum_to_host(ctx, nparts, &s));
     rel = sqrt(s / double(m)) / eps_bg;
     if (outer > 0 && st && outer - 1 < 64) st->resid_hist[outer - 1] = rel;
     if (!std::isfinite(rel)) {
@@ -564,11 +686,11 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
       rc = fail(ctx, MG_ENOCONV, "max_cycles reached");
       break;
     }
-    for (int l = 0; l + 1 < ctx->nlev; ++l)
-      k_restrict<float, float><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
-          ctx->L[l], ctx->L[l + 1], W.X[l], W.X[l + 1]);
-    LAUNCHCHK();
-    for (int it = 0; it < o->inner_cycles; ++it) ACHK(cycle32<M>(ctx, C, o, 0, o->cycle));
+    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol);
+    for (int it = 0; it < k; ++it) ACHK(cycle32<M>(ctx, C, o, 0, o->cycle, it == 0));
+    vc += k;
+    rel_prev = rel;
+    k_prev = k;
     k_outer_update<<<nblk(m), kBlock, 0, ctx->stream>>>(m, W.w, W.e[0]);
     LAUNCHCHK();
     ++outer;
@@ -577,6 +699,7 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   LAUNCHCHK();
   if (st) {
     st->cycles = outer;
+    st->vcycles = vc;
     st->rel_resid = rel;
   }
   return rc;
@@ -626,11 +749,20 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
   }
   const Lev& Lf = ctx->L[l];
   T kh2 = T(kap / lev_h2(l));
+  const bool vec = (Lf.nh % Vec<T>::V) == 0;
+  const int64_t nv = Lf.half / Vec<T>::V;
   auto smooth = [&](int sweeps) {
     for (int s = 0; s < sweeps; ++s)
-      for (int colour = 0; colour < 2; ++colour)
-        k_smooth_lin<T><<<nblk(Lf.half), kBlock, 0, ctx->stream>>>(Lf, W.e[l], W.dg[l], W.r[l],
-                                                                    colour, kh2);
+      for (int colour = 0; colour < 2; ++colour) {
+        int q = l == 0 ? prof_begin(ctx, sizeof(T) == 4 ? MG_PROF_LIN32 : MG_PROF_LIN64) : -1;
+        if (vec)
+          k_smooth_lin_v<T><<<nblk(nv), kBlock, 0, ctx->stream>>>(Lf, W.e[l], W.dg[l], W.r[l],
+                                                                  colour, kh2);
+        else
+          k_smooth_lin<T><<<nblk(Lf.half), kBlock, 0, ctx->stream>>>(Lf, W.e[l], W.dg[l], W.r[l],
+                                                                      colour, kh2);
+        prof_end(ctx, q);
+      }
   };
   if (l == ctx->nlev - 1) {
     smooth(o->nu_pre + o->nu_post);
@@ -652,8 +784,7 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
     ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_F));
     ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_V));
   }
-  k_prolong_add<T><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1],
-                                                                  (const T*)nullptr);
+  k_prolong_block<T><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1]);
   smooth(o->nu_post);
   LAUNCHCHK();
   return MG_OK;
@@ -695,18 +826,26 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
   bb = sqrt(bb);
   if (!(bb > 0.0)) bb = 1.0;
   double kap = lin_kap(C);
-  int outer = 0, rc = MG_OK;
-  double rel = 0.0;
+  int outer = 0, rc = MG_OK, vc = 0, k_prev = 0;
+  double rel = 0.0, rel_prev = -1.0;
   for (;;) {
-    if (f32)
-      k_lin_outer<float><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, A.lam, A.dg, A.b, kap,
-                                                              A.w32.r[0], A.w32.e[0], ctx->part);
+    const bool vec = L0.nh % Vec<double>::V == 0;
+    int64_t nparts = vec ? nblk(L0.half / Vec<double>::V) : nblk(m);
+    if (f32 && vec)
+      k_lin_outer_v<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+          L0, A.lam, A.dg, A.b, kap, A.w32.r[0], A.w32.e[0], ctx->part);
+    else if (f32)
+      k_lin_outer<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+          L0, A.lam, A.dg, A.b, kap, A.w32.r[0], A.w32.e[0], ctx->part);
+    else if (vec)
+      k_lin_outer_v<double><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+          L0, A.lam, A.dg, A.b, kap, A.w64.r[0], A.w64.e[0], ctx->part);
     else
-      k_lin_outer<double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, A.lam, A.dg, A.b, kap,
-                                                               A.w64.r[0], A.w64.e[0], ctx->part);
+      k_lin_outer<double><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+          L0, A.lam, A.dg, A.b, kap, A.w64.r[0], A.w64.e[0], ctx->part);
     LAUNCHCHK();
     double s;
-    ACHK(sum_to_host(ctx, nblk(m), &s));
+    ACHK(sum_to_host(ctx, nparts, &s));
     rel = sqrt(s) / bb;
     if (outer > 0 && st && outer - 1 < 64) st->resid_hist[outer - 1] = rel;
     if (!std::isfinite(rel)) {
@@ -718,15 +857,18 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
       rc = fail(ctx, MG_ENOCONV, "max_cycles reached (adjoint)");
       break;
     }
+    // correction scheme on r = b - A lam (FP32 or FP64 inner cycles)
+    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol);
     if (f32) {
-      for (int it = 0; it < o->inner_cycles; ++it)
-        ACHK(lin_cycle<float>(ctx, A.w32, kap, o, 0, o->cycle));
+      for (int it = 0; it < k; ++it) ACHK(lin_cycle<float>(ctx, A.w32, kap, o, 0, o->cycle));
       k_axpy_to64<float><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w32.e[0]);
     } else {
-      // FP64: the correction scheme on r = b - A lam, one cycle per step
-      ACHK(lin_cycle<double>(ctx, A.w64, kap, o, 0, o->cycle));
+      for (int it = 0; it < k; ++it) ACHK(lin_cycle<double>(ctx, A.w64, kap, o, 0, o->cycle));
       k_axpy_to64<double><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w64.e[0]);
     }
+    vc += k;
+    rel_prev = rel;
+    k_prev = k;
     LAUNCHCHK();
     ++outer;
   }
@@ -734,6 +876,7 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
   LAUNCHCHK();
   if (st) {
     st->cycles = outer;
+    st->vcycles = vc;
     st->rel_resid = rel;
   }
   return rc;
@@ -758,14 +901,14 @@ __device__ __forceinline__ double dphi5_of(const Consts& C, double f) {
   return C.phi5;
 }
 
-__global__ __launch_bounds__(kBlock) void k_force(int n, const double* __restrict__ f, Consts C,
+__global__ __launch_bounds__(kBlock) void k_force(Lev L, const double* __restrict__ f, Consts C,
                                                   float* __restrict__ out) {
   int64_t g = gid();
-  int64_t m = (int64_t)n * n * n;
+  const int n = L.n;
+  int64_t m = 2 * L.half;
   if (g >= m) return;
-  int i = (int)(g % n);
-  int64_t r = g / n;
-  int j = (int)(r % n), k = (int)(r / n);
+  int i, j, k;
+  dec_nat(g, L, i, j, k);
   int ip = i + 1 == n ? 0 : i + 1, im = i == 0 ? n - 1 : i - 1;
   int jp = j + 1 == n ? 0 : j + 1, jm = j == 0 ? n - 1 : j - 1;
   int kp = k + 1 == n ? 0 : k + 1, km = k == 0 ? n - 1 : k - 1;
@@ -780,15 +923,15 @@ __global__ __launch_bounds__(kBlock) void k_force(int n, const double* __restric
   out[2 * m + g] = float(gz);
 }
 
-__global__ __launch_bounds__(kBlock) void k_force_adjoint(int n, const double* __restrict__ f,
+__global__ __launch_bounds__(kBlock) void k_force_adjoint(Lev L, const double* __restrict__ f,
                                                           const float* __restrict__ gf, Consts C,
                                                           double* __restrict__ out) {
   int64_t g = gid();
-  int64_t m = (int64_t)n * n * n;
+  const int n = L.n;
+  int64_t m = 2 * L.half;
   if (g >= m) return;
-  int i = (int)(g % n);
-  int64_t r = g / n;
-  int j = (int)(r % n), k = (int)(r / n);
+  int i, j, k;
+  dec_nat(g, L, i, j, k);
   int ip = i + 1 == n ? 0 : i + 1, im = i == 0 ? n - 1 : i - 1;
   int jp = j + 1 == n ? 0 : j + 1, jm = j == 0 ? n - 1 : j - 1;
   int kp = k + 1 == n ? 0 : k + 1, km = k == 0 ? n - 1 : k - 1;
@@ -886,7 +1029,7 @@ extern "C" {
 int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
   if (!out) return MG_EINVAL;
   *out = nullptr;
-  if (n < 4 || (n & 1) || n > 8192) return MG_EINVAL;
+  if (n < 4 || (n & 1) || n > 1600) return MG_EINVAL;  // n^3 < 2^32: 32-bit indices
   mg_ctx* ctx = new mg_ctx();
   ctx->n = n;
   ctx->stream = (hipStream_t)hip_stream;
@@ -896,6 +1039,8 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
     ctx->L[l].n = m;
     ctx->L[l].nh = m / 2;
     ctx->L[l].half = (int64_t)m * m * m / 2;
+    ctx->L[l].dnh = FastDiv::make((uint32_t)(m / 2));
+    ctx->L[l].dn = FastDiv::make((uint32_t)m);
     ++l;
     if (!(m / 2 >= 4 && ((m / 2) % 2) == 0) || l >= kMaxLev) break;
     m /= 2;
@@ -913,6 +1058,7 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
   ctx->fused_from = f;
   ctx->part_cap = nblk((int64_t)n * n * n) + 16;
   int rc = dalloc(ctx, &ctx->part, ctx->part_cap);
+  if (rc == MG_OK) rc = dalloc(ctx, &ctx->part2, 256);
   if (rc == MG_OK) rc = dalloc(ctx, &ctx->scal, 16);
   if (rc == MG_OK) {
     void* h = nullptr;
@@ -931,6 +1077,7 @@ void mg_ctx_destroy(mg_ctx* ctx) {
   if (!ctx) return;
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->hscal) (void)hipHostFree(ctx->hscal);
   delete ctx;
@@ -1004,7 +1151,7 @@ int mg_force(mg_ctx* ctx, int model, const mg_model_params* params, const double
   ACHK(make_consts(ctx, model, params, ctx->n, &C));
   if (!field || !force_out) return fail(ctx, MG_EINVAL, "mg_force: NULL array");
   int64_t m = (int64_t)ctx->n * ctx->n * ctx->n;
-  k_force<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->n, field, C, force_out);
+  k_force<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], field, C, force_out);
   LAUNCHCHK();
   return MG_OK;
 }
@@ -1017,7 +1164,7 @@ int mg_force_adjoint(mg_ctx* ctx, int model, const mg_model_params* params, cons
   if (!field || !grad_force || !grad_field_out)
     return fail(ctx, MG_EINVAL, "mg_force_adjoint: NULL array");
   int64_t m = (int64_t)ctx->n * ctx->n * ctx->n;
-  k_force_adjoint<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->n, field, grad_force, C,
+  k_force_adjoint<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], field, grad_force, C,
                                                        grad_field_out);
   LAUNCHCHK();
   return MG_OK;
@@ -1062,8 +1209,7 @@ int mg_loss_force_sq(mg_ctx* ctx, const float* force, const int64_t* cellsv, int
   k_fill<float><<<nblk(3 * m), kBlock, 0, ctx->stream>>>(grad_force_out, 3 * m, 0.0f);
   k_loss_sq<<<nblk(n_cells), kBlock, 0, ctx->stream>>>(m, force, cellsv, n_cells, grad_force_out,
                                                        ctx->part);
-  k_sum_partials<<<1, 1024, 0, ctx->stream>>>(ctx->part, nblk(n_cells), loss_out, 0);
-  LAUNCHCHK();
+  ACHK(sum_on_device(ctx, nblk(n_cells), loss_out));
   return MG_OK;
 }
 
@@ -1077,15 +1223,27 @@ int mg_relax_halfsweep(mg_ctx* ctx, int model, const mg_model_params* params, co
   ACHK(ensure64(ctx));
   ACHK(setup64(ctx, C, delta, field));
   const Lev& L = ctx->L[0];
-  if (model == MG_FR)
+  if (L.nh % Vec<double>::V == 0) {
+    int64_t nv = L.half / Vec<double>::V;
+    if (model == MG_FR)
+      k_smooth_direct_v<FR, float><<<nblk(nv), kBlock, 0, ctx->stream>>>(
+          L, ctx->w64.v[0], ctx->w64.dens0, (const double*)nullptr, colour, 1.0, C);
+    else if (model == MG_SYMMETRON)
+      k_smooth_direct_v<SYM, float><<<nblk(nv), kBlock, 0, ctx->stream>>>(
+          L, ctx->w64.v[0], ctx->w64.dens0, (const double*)nullptr, colour, 1.0, C);
+    else
+      k_smooth_direct_v<CQ, float><<<nblk(nv), kBlock, 0, ctx->stream>>>(
+          L, ctx->w64.v[0], ctx->w64.dens0, (const double*)nullptr, colour, 1.0, C);
+  } else if (model == MG_FR) {
     k_smooth_direct<FR, double, float><<<nblk(L.half), kBlock, 0, ctx->stream>>>(
         L, ctx->w64.v[0], ctx->w64.dens0, (const double*)nullptr, colour, 1.0, C);
-  else if (model == MG_SYMMETRON)
+  } else if (model == MG_SYMMETRON) {
     k_smooth_direct<SYM, double, float><<<nblk(L.half), kBlock, 0, ctx->stream>>>(
         L, ctx->w64.v[0], ctx->w64.dens0, (const double*)nullptr, colour, 1.0, C);
-  else
+  } else {
     k_smooth_direct<CQ, double, float><<<nblk(L.half), kBlock, 0, ctx->stream>>>(
         L, ctx->w64.v[0], ctx->w64.dens0, (const double*)nullptr, colour, 1.0, C);
+  }
   double sgn = (model == MG_FR) ? -1.0 : 1.0;
   k_unpack<double, double><<<nblk(cells(L)), kBlock, 0, ctx->stream>>>(L, ctx->w64.v[0], field,
                                                                          sgn);
@@ -1117,12 +1275,37 @@ int mg_prolong_add(mg_ctx* ctx, const double* coarse, double* fine) {
   const Lev& Lc = ctx->L[1];
   k_pack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, fine, ctx->w64.v[0], 1.0);
   k_pack<double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lc, coarse, ctx->w64.v[1], 1.0);
-  k_prolong_add<double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, Lc, ctx->w64.v[0],
-                                                                       ctx->w64.v[1],
-                                                                       (const double*)nullptr);
+  k_prolong_block<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, ctx->w64.v[0],
+                                                                         ctx->w64.v[1]);
   k_unpack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, ctx->w64.v[0], fine,
                                                                          1.0);
   LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_prof_enable(mg_ctx* ctx, int on) {
+  if (!ctx) return MG_EINVAL;
+  if (on && ctx->ev.empty()) {
+    ctx->ev.resize(2 * kEvPairs);
+    ctx->ev_cls.resize(kEvPairs);
+    for (auto& e : ctx->ev) HIPCHK(hipEventCreate(&e));
+  }
+  prof_flush(ctx);
+  ctx->prof = on != 0;
+  for (int c = 0; c < 4; ++c) {
+    ctx->prof_ms[c] = 0.0;
+    ctx->prof_n[c] = 0;
+  }
+  return MG_OK;
+}
+
+int mg_prof_read(mg_ctx* ctx, int cls, double* total_ms, int64_t* launches) {
+  if (!ctx) return MG_EINVAL;
+  if (cls < 0 || cls > 3 || !total_ms || !launches)
+    return fail(ctx, MG_EINVAL, "mg_prof_read: bad arguments");
+  prof_flush(ctx);
+  *total_ms = ctx->prof_ms[cls];
+  *launches = ctx->prof_n[cls];
   return MG_OK;
 }
 
