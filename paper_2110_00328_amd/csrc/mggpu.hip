@@ -75,7 +75,11 @@ struct mg_ctx {
   int64_t part_cap = 0;
   double* scal = nullptr;      // device scalars
   double* hscal = nullptr;     // pinned host mirror
-  int64_t* cic = nullptr;      // CIC fixed-point accumulator
+  int64_t* cic = nullptr;      // CIC fixed-point accumulator (direct path)
+  float* cic_sorted = nullptr;  // binned CIC: positions in tile order
+  int64_t cic_np = 0;
+  unsigned long long* cic_blocks = nullptr;  // per-tile private 17^3 blocks
+  uint32_t* cic_cnt = nullptr;  // counts, offsets, cursors per tile
   double* nat64 = nullptr;     // natural-layout scratch (debug entry points)
   std::vector<void*> allocs;
   // event timing of the finest-level smoothers
@@ -1012,6 +1016,167 @@ __global__ __launch_bounds__(kBlock) void k_cic_finish(int64_t m, const unsigned
   if (g < m) delta[g] = float(double(acc[g]) * scale - 1.0);
 }
 
+// ---- binned CIC: tiles of kT^3 cells ------------------------------------
+constexpr int kT = 16;          // tile edge (cells)
+constexpr int kTH = kT + 1;     // tile plus the +1 layer its particles reach
+constexpr int kTH3 = kTH * kTH * kTH;
+
+struct CicCell {
+  int i0[3];
+  double t[3];
+};
+// lower CIC cell and fractional offsets of one particle (same rule as k_cic)
+__device__ __forceinline__ CicCell cic_cell(int n, const float* __restrict__ pos, int64_t p) {
+  CicCell c;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float x = pos[3 * p + a];
+    float s = x - 0.5f;
+    float fl = floorf(s);
+    c.t[a] = double(s - fl);
+    int q = (int)fl;
+    q %= n;
+    if (q < 0) q += n;
+    c.i0[a] = q;
+  }
+  return c;
+}
+// 8 fixed-point weights summing to exactly 2^32 (corner q: dx = q&1, dy, dz)
+__device__ __forceinline__ void cic_weights(const CicCell& c, long long* w) {
+  long long tot = 0;
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    int di = q & 1, dj = (q >> 1) & 1, dk = (q >> 2) & 1;
+    double ww = (di ? c.t[0] : 1.0 - c.t[0]) * (dj ? c.t[1] : 1.0 - c.t[1]) *
+                (dk ? c.t[2] : 1.0 - c.t[2]);
+    w[q] = llrint(ww * 4294967296.0);
+    tot += w[q];
+  }
+  w[7] = 4294967296LL - tot;
+}
+__device__ __forceinline__ uint32_t tile_of(const CicCell& c, int nt) {
+  return ((uint32_t)(c.i0[2] / kT) * nt + (uint32_t)(c.i0[1] / kT)) * nt + (uint32_t)(c.i0[0] / kT);
+}
+
+// Wave-level runs of equal tiles: one atomic per run.  Returns, for every
+// active lane, the slot base of its run plus its rank in the run.
+__device__ __forceinline__ uint32_t run_reserve(uint32_t t, bool valid, uint32_t* ctr) {
+  const int lane = threadIdx.x & 63;
+  uint32_t prev = __shfl_up(t, 1, 64);
+  bool leader = !valid || lane == 0 || prev != t;
+  unsigned long long lead = __ballot(leader);
+  unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  int my_leader = 63 - __clzll(lead & upto);
+  unsigned long long above = lead & ~upto;
+  int run_end = above ? (__ffsll((long long)above) - 1) : 64;
+  uint32_t base = 0;
+  if (valid && leader) base = atomicAdd(ctr + t, (uint32_t)(run_end - lane));
+  base = __shfl(base, my_leader, 64);
+  return base + (uint32_t)(lane - my_leader);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cic_count(int n, int nt, int64_t np,
+                                                      const float* __restrict__ pos,
+                                                      uint32_t* cnt) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool valid = p < np;
+  uint32_t t = valid ? tile_of(cic_cell(n, pos, p), nt) : 0xffffffffu;
+  (void)run_reserve(t, valid, cnt);
+}
+// exclusive scan of m counts in one block: contiguous chunks per thread
+__global__ __launch_bounds__(1024) void k_scan1(const uint32_t* __restrict__ cnt, int64_t m,
+                                                uint32_t* __restrict__ off,
+                                                uint32_t* __restrict__ cur) {
+  __shared__ uint32_t sh[1024];
+  int64_t chunk = (m + 1023) / 1024;
+  int64_t lo = threadIdx.x * chunk, hi = lo + chunk < m ? lo + chunk : m;
+  uint32_t s = 0;
+  for (int64_t q = lo; q < hi; ++q) s += cnt[q];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
+    uint32_t v = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0u;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? sh[threadIdx.x - 1] : 0u;
+  for (int64_t q = lo; q < hi; ++q) {
+    off[q] = run;
+    cur[q] = run;
+    run += cnt[q];
+  }
+}
+__global__ __launch_bounds__(kBlock) void k_cic_scatter(int n, int nt, int64_t np,
+                                                        const float* __restrict__ pos,
+                                                        uint32_t* cur, float* __restrict__ sorted) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool valid = p < np;
+  uint32_t t = valid ? tile_of(cic_cell(n, pos, p), nt) : 0xffffffffu;
+  uint32_t slot = run_reserve(t, valid, cur);
+  if (valid) {
+    sorted[3 * (int64_t)slot + 0] = pos[3 * p + 0];
+    sorted[3 * (int64_t)slot + 1] = pos[3 * p + 1];
+    sorted[3 * (int64_t)slot + 2] = pos[3 * p + 2];
+  }
+}
+// one workgroup per tile: deposit into LDS, write the private 17^3 block
+__global__ __launch_bounds__(kBlock) void k_cic_tile(int n, int nt, const float* __restrict__ sorted,
+                                                     const uint32_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ cnt,
+                                                     unsigned long long* __restrict__ blocks) {
+  __shared__ unsigned long long acc[kTH3];
+  const uint32_t t = blockIdx.x;
+  for (int q = threadIdx.x; q < kTH3; q += blockDim.x) acc[q] = 0ull;
+  __syncthreads();
+  const int ti = (int)(t % nt), tj = (int)((t / nt) % nt), tk = (int)(t / ((uint32_t)nt * nt));
+  const uint32_t lo = off[t], m = cnt[t];
+  for (uint32_t q = threadIdx.x; q < m; q += blockDim.x) {
+    CicCell c = cic_cell(n, sorted, (int64_t)lo + q);
+    long long w[8];
+    cic_weights(c, w);
+    int a = c.i0[0] - ti * kT, b = c.i0[1] - tj * kT, d = c.i0[2] - tk * kT;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (w[r] == 0) continue;
+      int idx = ((d + ((r >> 2) & 1)) * kTH + (b + ((r >> 1) & 1))) * kTH + (a + (r & 1));
+      atomicAdd(&acc[idx], (unsigned long long)w[r]);
+    }
+  }
+  __syncthreads();
+  unsigned long long* dst = blocks + (int64_t)t * kTH3;
+  for (int q = threadIdx.x; q < kTH3; q += blockDim.x) dst[q] = acc[q];
+}
+// cell (i,j,k): sum of the private blocks that cover it (its own tile, and
+// the +1 layer of the lower neighbour tile on each axis where it is first)
+__global__ __launch_bounds__(kBlock) void k_cic_gather(Lev L, int nt,
+                                                       const unsigned long long* __restrict__ blocks,
+                                                       double scale, float* __restrict__ delta) {
+  int64_t g = gid();
+  if (g >= 2 * L.half) return;
+  int i, j, k;
+  dec_nat(g, L, i, j, k);
+  const int tc[3] = {i / kT, j / kT, k / kT};
+  const int lc[3] = {i % kT, j % kT, k % kT};
+  unsigned long long sum = 0ull;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    int tt[3], ll[3];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      int sft = (r >> a) & 1;  // 1: take the lower neighbour's +1 layer
+      if (sft && lc[a] != 0) ok = false;
+      tt[a] = sft ? (tc[a] == 0 ? nt - 1 : tc[a] - 1) : tc[a];
+      ll[a] = sft ? kT : lc[a];
+    }
+    if (!ok) continue;
+    uint32_t tile = ((uint32_t)tt[2] * nt + tt[1]) * nt + tt[0];
+    sum += blocks[(int64_t)tile * kTH3 + (ll[2] * kTH + ll[1]) * kTH + ll[0]];
+  }
+  delta[g] = float(double(sum) * scale - 1.0);
+}
+
 template <int M>
 int dispatch_solve(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* delta,
                    const double* fin, double* fout, double tol, mg_stats* st) {
@@ -1092,11 +1257,37 @@ int cic_assign(mg_ctx* ctx, const float* pos, int64_t np, float* delta_out) {
   if (!pos || !delta_out || np <= 0) return fail(ctx, MG_EINVAL, "cic_assign: bad arguments");
   int n = ctx->n;
   int64_t m = (int64_t)n * n * n;
+  double scale = double(m) / double(np) / 4294967296.0;
+  if (n % kT == 0 && np < (int64_t)0xffffffffLL) {
+    // binned path: count per tile, scan, scatter, per-tile LDS deposit, gather
+    int nt = n / kT;
+    int64_t ntiles = (int64_t)nt * nt * nt;
+    if (ctx->cic_np < np) {
+      ACHK(dalloc(ctx, &ctx->cic_sorted, 3 * np));
+      ctx->cic_np = np;
+    }
+    if (!ctx->cic_blocks) {
+      ACHK(dalloc(ctx, &ctx->cic_blocks, ntiles * kTH3));
+      ACHK(dalloc(ctx, &ctx->cic_cnt, 3 * ntiles));
+    }
+    uint32_t* cnt = ctx->cic_cnt;
+    uint32_t* off = cnt + ntiles;
+    uint32_t* cur = off + ntiles;
+    k_fill<uint32_t><<<nblk(ntiles), kBlock, 0, ctx->stream>>>(cnt, ntiles, 0u);
+    k_cic_count<<<nblk(np), kBlock, 0, ctx->stream>>>(n, nt, np, pos, cnt);
+    k_scan1<<<1, 1024, 0, ctx->stream>>>(cnt, ntiles, off, cur);
+    k_cic_scatter<<<nblk(np), kBlock, 0, ctx->stream>>>(n, nt, np, pos, cur, ctx->cic_sorted);
+    k_cic_tile<<<(unsigned)ntiles, kBlock, 0, ctx->stream>>>(n, nt, ctx->cic_sorted, off, cnt,
+                                                             ctx->cic_blocks);
+    k_cic_gather<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], nt, ctx->cic_blocks, scale,
+                                                      delta_out);
+    LAUNCHCHK();
+    return MG_OK;
+  }
   if (!ctx->cic) ACHK(dalloc(ctx, &ctx->cic, m));
   unsigned long long* acc = (unsigned long long*)ctx->cic;
   k_fill<unsigned long long><<<nblk(m), kBlock, 0, ctx->stream>>>(acc, m, 0ull);
   k_cic<<<nblk(np), kBlock, 0, ctx->stream>>>(n, np, pos, acc);
-  double scale = double(m) / double(np) / 4294967296.0;
   k_cic_finish<<<nblk(m), kBlock, 0, ctx->stream>>>(m, acc, scale, delta_out);
   LAUNCHCHK();
   return MG_OK;

@@ -96,6 +96,23 @@ def test_cic_matches_oracle(c1):
     d = mg.cic(torch.from_numpy(pos).to(DEV)).cpu().numpy()
     ref = oracle.cic(32, pos.astype(np.float64))
     assert np.max(np.abs(d - ref)) <= 1e-6 * (1 + np.max(np.abs(ref)))
+    # a clump: 20000 particles inside one cell plus a uniform background
+    clump = np.concatenate([rng.uniform(0, 32, (3000, 3)),
+                            5.2 + 0.6 * rng.random((20000, 3))]).astype(np.float32)
+    d = mg.cic(torch.from_numpy(clump).to(DEV)).cpu().numpy()
+    ref = oracle.cic(32, clump.astype(np.float64))
+    assert np.max(np.abs(d - ref)) <= 1e-6 * (1 + np.max(np.abs(ref)))
+    mg.close()
+
+
+def test_cic_direct_path_matches_oracle():
+    """n not divisible by the 16-cell tile: the direct atomic kernel."""
+    n = 24
+    mg = api.Context(n, device=DEV)
+    pos = synthetic.zeldovich_positions(n, 12, seed=7, dtype=np.float32)
+    d = mg.cic(torch.from_numpy(pos).to(DEV)).cpu().numpy()
+    ref = oracle.cic(n, pos.astype(np.float64))
+    assert np.max(np.abs(d - ref)) <= 1e-6 * (1 + np.max(np.abs(ref)))
     mg.close()
 
 
