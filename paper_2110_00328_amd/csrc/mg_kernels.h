@@ -115,48 +115,76 @@ struct Vec<double> {
   static constexpr int V = 2;
   using type = double2;
 };
+// N consecutive elements in 16-byte (or, for 2 floats, 8-byte) accesses;
+// p must be aligned to the access size.
+template <typename T, int N>
+__device__ __forceinline__ void ldn(const T* __restrict__ p, T* out) {
+  if constexpr (N * sizeof(T) == 8 && sizeof(T) == 4) {
+    float2 v = *reinterpret_cast<const float2*>(p);
+    out[0] = v.x; out[1] = v.y;
+  } else {
+    using VT = typename Vec<T>::type;
+    constexpr int P = Vec<T>::V;
+#pragma unroll
+    for (int c = 0; c < N / P; ++c) {
+      VT v = *reinterpret_cast<const VT*>(p + c * P);
+      if constexpr (P == 4) {
+        out[4 * c] = v.x; out[4 * c + 1] = v.y; out[4 * c + 2] = v.z; out[4 * c + 3] = v.w;
+      } else {
+        out[2 * c] = v.x; out[2 * c + 1] = v.y;
+      }
+    }
+  }
+}
+template <typename T, int N>
+__device__ __forceinline__ void stn(T* __restrict__ p, const T* in) {
+  if constexpr (N * sizeof(T) == 8 && sizeof(T) == 4) {
+    float2 v;
+    v.x = in[0]; v.y = in[1];
+    *reinterpret_cast<float2*>(p) = v;
+  } else {
+    using VT = typename Vec<T>::type;
+    constexpr int P = Vec<T>::V;
+#pragma unroll
+    for (int c = 0; c < N / P; ++c) {
+      VT v;
+      if constexpr (P == 4) {
+        v.x = in[4 * c]; v.y = in[4 * c + 1]; v.z = in[4 * c + 2]; v.w = in[4 * c + 3];
+      } else {
+        v.x = in[2 * c]; v.y = in[2 * c + 1];
+      }
+      *reinterpret_cast<VT*>(p + c * P) = v;
+    }
+  }
+}
 template <typename T>
 __device__ __forceinline__ void ldv(const T* __restrict__ p, T* out) {
-  using VT = typename Vec<T>::type;
-  VT v = *reinterpret_cast<const VT*>(p);
-  if constexpr (Vec<T>::V == 4) {
-    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
-  } else {
-    out[0] = v.x; out[1] = v.y;
-  }
+  ldn<T, Vec<T>::V>(p, out);
 }
 template <typename T>
 __device__ __forceinline__ void stv(T* __restrict__ p, const T* in) {
-  using VT = typename Vec<T>::type;
-  VT v;
-  if constexpr (Vec<T>::V == 4) {
-    v.x = in[0]; v.y = in[1]; v.z = in[2]; v.w = in[3];
-  } else {
-    v.x = in[0]; v.y = in[1];
-  }
-  *reinterpret_cast<VT*>(p) = v;
+  stn<T, Vec<T>::V>(p, in);
 }
 // Neighbour sums of the V cells (ih0 .. ih0+V-1, j, k) of colour c from the
 // other colour's array o; s = (j + k + c) & 1.  Same summation order as nbsum.
-template <typename T>
+template <typename T, int V = Vec<T>::V>
 __device__ __forceinline__ void nbsum_vec(const Lev& L, const T* __restrict__ o, int ih0, int j,
                                           int k, int s, T* sum) {
-  constexpr int V = Vec<T>::V;
   int jm = (j == 0) ? L.n - 1 : j - 1, jp = (j == L.n - 1) ? 0 : j + 1;
   int km = (k == 0) ? L.n - 1 : k - 1, kp = (k == L.n - 1) ? 0 : k + 1;
   uint32_t r = prow(L, j, k);
   T xv[V + 1], ym[V], yp[V], zm[V], zp[V];
   if (s) {
-    ldv<T>(o + r + ih0, xv);
+    ldn<T, V>(o + r + ih0, xv);
     xv[V] = o[r + (ih0 + V == L.nh ? 0 : ih0 + V)];
   } else {
-    ldv<T>(o + r + ih0, xv + 1);
+    ldn<T, V>(o + r + ih0, xv + 1);
     xv[0] = o[r + (ih0 == 0 ? L.nh - 1 : ih0 - 1)];
   }
-  ldv<T>(o + prow(L, jm, k) + ih0, ym);
-  ldv<T>(o + prow(L, jp, k) + ih0, yp);
-  ldv<T>(o + prow(L, j, km) + ih0, zm);
-  ldv<T>(o + prow(L, j, kp) + ih0, zp);
+  ldn<T, V>(o + prow(L, jm, k) + ih0, ym);
+  ldn<T, V>(o + prow(L, jp, k) + ih0, yp);
+  ldn<T, V>(o + prow(L, j, km) + ih0, zm);
+  ldn<T, V>(o + prow(L, j, kp) + ih0, zp);
 #pragma unroll
   for (int q = 0; q < V; ++q) sum[q] = (xv[q] + xv[q + 1]) + (ym[q] + yp[q]) + (zm[q] + zp[q]);
 }
@@ -620,14 +648,47 @@ __global__ __launch_bounds__(kBlock) void k_smooth_lin_v(Lev L, T* e, const T* d
   stv<T>(e + q0, out);
 }
 
-// FP64 outer step of the refined mode, both colours per thread:
-// d = F(w64), rho = -d, X = w64, e = 0; per-block sum of d^2.
+// Neighbour sums of w + e (the updated FP64 values, formed exactly as the
+// update w += double(e) stores them).
+template <typename TE, int V>
+__device__ __forceinline__ void nbsum2_vec(const Lev& L, const double* __restrict__ w,
+                                           const TE* __restrict__ e, int ih0, int j, int k,
+                                           int s, double* sum) {
+  int jm = (j == 0) ? L.n - 1 : j - 1, jp = (j == L.n - 1) ? 0 : j + 1;
+  int km = (k == 0) ? L.n - 1 : k - 1, kp = (k == L.n - 1) ? 0 : k + 1;
+  const uint32_t rows[5] = {prow(L, j, k), prow(L, jm, k), prow(L, jp, k), prow(L, j, km),
+                            prow(L, j, kp)};
+  double nv[5][V];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    TE ev[V];
+    ldn<double, V>(w + rows[q] + ih0, nv[q]);
+    ldn<TE, V>(e + rows[q] + ih0, ev);
+#pragma unroll
+    for (int t = 0; t < V; ++t) nv[q][t] += double(ev[t]);
+  }
+  uint32_t xi = s ? (ih0 + V == L.nh ? 0 : ih0 + V) : (ih0 == 0 ? L.nh - 1 : ih0 - 1);
+  double xe = w[rows[0] + xi] + double(e[rows[0] + xi]);
+  double xv[V + 1];
+#pragma unroll
+  for (int t = 0; t < V; ++t) xv[s ? t : t + 1] = nv[0][t];
+  xv[s ? V : 0] = xe;
+#pragma unroll
+  for (int q = 0; q < V; ++q)
+    sum[q] = (xv[q] + xv[q + 1]) + (nv[1][q] + nv[2][q]) + (nv[3][q] + nv[4][q]);
+}
+
+// Fused FP64 outer step of the refined mode: w_new = w + e (e may be null:
+// no update), d = F(w_new), rho = -d, X = w_new, e_zero = 0 (a different
+// buffer from e); per-block sum of d^2.
+constexpr int kVOuter = 4;  // cells per colour per thread in the outer kernels (nh % 4 == 0)
+
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_outer_residual_v(Lev L, const double* w,
-                                                             const float* dens, Consts C,
-                                                             float* rho, float* X, float* e,
-                                                             double* part) {
-  constexpr int V = Vec<double>::V;
+__global__ __launch_bounds__(kBlock) void k_outer_fused_v(Lev L, const double* w, const float* e,
+                                                          double* w_new, const float* dens,
+                                                          Consts C, float* rho, float* X,
+                                                          float* e_zero, double* part) {
+  constexpr int V = kVOuter;
   __shared__ double sh[32];
   uint32_t g4 = (uint32_t)gid();
   double acc = 0.0;
@@ -635,20 +696,87 @@ __global__ __launch_bounds__(kBlock) void k_outer_residual_v(Lev L, const double
     uint32_t g = g4 * V;
     int ih0, j, k;
     dec(g, L, ih0, j, k);
-#pragma unroll
+#pragma unroll 1
     for (int c = 0; c < 2; ++c) {
       uint32_t q0 = (uint32_t)c * (uint32_t)L.half + g;
+      int s = (j + k + c) & 1;
       double sum[V], vc[V];
-      nbsum_vec<double>(L, w + (1 - c) * L.half, ih0, j, k, (j + k + c) & 1, sum);
-      ldv<double>(w + q0, vc);
+      float dn[V], ro[V], xo[V], zo[V];
+      if (e) {
+        float ev[V];
+        nbsum2_vec<float, V>(L, w + (1 - c) * L.half, e + (1 - c) * L.half, ih0, j, k, s, sum);
+        ldn<double, V>(w + q0, vc);
+        ldn<float, V>(e + q0, ev);
+#pragma unroll
+        for (int q = 0; q < V; ++q) vc[q] += double(ev[q]);
+        stn<double, V>(w_new + q0, vc);
+      } else {
+        nbsum_vec<double, V>(L, w + (1 - c) * L.half, ih0, j, k, s, sum);
+        ldn<double, V>(w + q0, vc);
+      }
+      ldn<float, V>(dens + q0, dn);
 #pragma unroll
       for (int q = 0; q < V; ++q) {
-        double d = direct_resid<M, double>(C, 1.0, vc[q], sum[q], double(dens[q0 + q]), 0.0);
+        double d = direct_resid<M, double>(C, 1.0, vc[q], sum[q], double(dn[q]), 0.0);
         acc += d * d;
-        rho[q0 + q] = float(-d);
-        X[q0 + q] = float(vc[q]);
-        e[q0 + q] = 0.0f;
+        ro[q] = float(-d);
+        xo[q] = float(vc[q]);
+        zo[q] = 0.0f;
       }
+      stn<float, V>(rho + q0, ro);
+      stn<float, V>(X + q0, xo);
+      stn<float, V>(e_zero + q0, zo);
+    }
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Fused FP64 outer step of the adjoint: lam_new = lam + e (e may be null),
+// r = b - A lam_new -> r (inner precision), e_zero = 0; sum of r^2
+template <typename TO>
+__global__ __launch_bounds__(kBlock) void k_lin_outer_fused_v(Lev L, const double* lam,
+                                                              const TO* e, double* lam_new,
+                                                              const double* dg, const double* b,
+                                                              double kh2, TO* r, TO* e_zero,
+                                                              double* part) {
+  constexpr int V = kVOuter;
+  __shared__ double sh[32];
+  uint32_t g4 = (uint32_t)gid();
+  double acc = 0.0;
+  if (g4 < (uint32_t)(L.half / V)) {
+    uint32_t g = g4 * V;
+    int ih0, j, k;
+    dec(g, L, ih0, j, k);
+#pragma unroll 1
+    for (int c = 0; c < 2; ++c) {
+      uint32_t q0 = (uint32_t)c * (uint32_t)L.half + g;
+      int s = (j + k + c) & 1;
+      double sum[V], lc[V], dd[V], bb[V];
+      TO ro[V], zo[V];
+      if (e) {
+        TO ev[V];
+        nbsum2_vec<TO, V>(L, lam + (1 - c) * L.half, e + (1 - c) * L.half, ih0, j, k, s, sum);
+        ldn<double, V>(lam + q0, lc);
+        ldn<TO, V>(e + q0, ev);
+#pragma unroll
+        for (int q = 0; q < V; ++q) lc[q] += double(ev[q]);
+        stn<double, V>(lam_new + q0, lc);
+      } else {
+        nbsum_vec<double, V>(L, lam + (1 - c) * L.half, ih0, j, k, s, sum);
+        ldn<double, V>(lam + q0, lc);
+      }
+      ldn<double, V>(dg + q0, dd);
+      ldn<double, V>(b + q0, bb);
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        double d = bb[q] - (kh2 * (6.0 * lc[q] - sum[q]) + dd[q] * lc[q]);
+        acc += d * d;
+        ro[q] = TO(d);
+        zo[q] = TO(0);
+      }
+      stn<TO, V>(r + q0, ro);
+      stn<TO, V>(e_zero + q0, zo);
     }
   }
   double t = block_sum(acc, sh);
@@ -686,39 +814,191 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm_v(Lev L, const double* v,
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// FP64 outer step of the adjoint, both colours per thread: r = b - A lam ->
-// r (inner precision), e = 0, per-block sum of r^2
-template <typename TO>
-__global__ __launch_bounds__(kBlock) void k_lin_outer_v(Lev L, const double* lam, const double* dg,
-                                                        const double* b, double kh2, TO* r,
-                                                        TO* e, double* part) {
-  constexpr int V = Vec<double>::V;
-  __shared__ double sh[32];
+// ---------------------------------------------------------------------------
+// Vectorised transfers: V consecutive coarse cells (I0 .. I0+V-1, J, K) per
+// thread, I0 % V == 0 (requires the coarse side % V == 0).  Their children
+// are the fine packed cells ih = I0 .. I0+V-1 of both colours in the four
+// rows (2J+b, 2K+d), read and written with 16-byte accesses.
+// ---------------------------------------------------------------------------
+// v^h += P c (27/9/3/1 trilinear, separable over the coarse neighbourhood)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_v(Lev Lf, Lev Lc, T* __restrict__ v,
+                                                      const T* __restrict__ c) {
+  constexpr int V = Vec<T>::V;
   uint32_t g4 = (uint32_t)gid();
-  double acc = 0.0;
-  if (g4 < (uint32_t)(L.half / V)) {
-    uint32_t g = g4 * V;
-    int ih0, j, k;
-    dec(g, L, ih0, j, k);
+  if (g4 >= (uint32_t)(2 * Lc.half / V)) return;
+  int I0, J, K;
+  dec_nat(g4 * V, Lc, I0, J, K);
+  const int nc = Lc.n;
+  const int Js[3] = {J == 0 ? nc - 1 : J - 1, J, J + 1 == nc ? 0 : J + 1};
+  const int Ks[3] = {K == 0 ? nc - 1 : K - 1, K, K + 1 == nc ? 0 : K + 1};
+  // x pass: ax[d][b][q][x] for coarse cell I0+q, child x
+  T ax[3][3][V][2];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      uint32_t q0 = (uint32_t)c * (uint32_t)L.half + g;
-      double sum[V], lc[V], dd[V], bb[V];
-      nbsum_vec<double>(L, lam + (1 - c) * L.half, ih0, j, k, (j + k + c) & 1, sum);
-      ldv<double>(lam + q0, lc);
-      ldv<double>(dg + q0, dd);
-      ldv<double>(b + q0, bb);
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      T cx[V + 2];
+#pragma unroll
+      for (int q = 0; q < V + 2; ++q) {
+        int I = I0 - 1 + q;
+        I = I < 0 ? I + nc : (I >= nc ? I - nc : I);
+        cx[q] = c[pk_of(Lc, I, Js[b], Ks[d])];
+      }
 #pragma unroll
       for (int q = 0; q < V; ++q) {
-        double d = bb[q] - (kh2 * (6.0 * lc[q] - sum[q]) + dd[q] * lc[q]);
-        acc += d * d;
-        r[q0 + q] = TO(d);
-        e[q0 + q] = TO(0);
+        ax[d][b][q][0] = T(0.75) * cx[q + 1] + T(0.25) * cx[q];
+        ax[d][b][q][1] = T(0.75) * cx[q + 1] + T(0.25) * cx[q + 2];
       }
     }
+#pragma unroll
+  for (int z = 0; z < 2; ++z)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int j = 2 * J + y, k = 2 * K + z;
+      const uint32_t row = prow(Lf, j, k) + (uint32_t)I0;
+#pragma unroll
+      for (int col = 0; col < 2; ++col) {
+        const int x = (col + j + k) & 1;  // child parity of this colour in the row
+        T* dst = v + (uint32_t)col * (uint32_t)Lf.half + row;
+        T cur[V];
+        ldv<T>(dst, cur);
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          T ay[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            ay[d] = T(0.75) * ax[d][1][q][x] + T(0.25) * ax[d][y ? 2 : 0][q][x];
+          cur[q] += T(0.75) * ay[1] + T(0.25) * ay[z ? 2 : 0];
+        }
+        stv<T>(dst, cur);
+      }
+    }
+}
+
+// correction form: Re -> eH and eR, R(G(e) - rho) -> rhoH, optionally R X -> XH
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_v(
+    Lev Lf, Lev Lc, const float* __restrict__ e, const float* __restrict__ X,
+    const float* __restrict__ dens, const float* __restrict__ rho, float h2, float* eH, float* eR,
+    float* rhoH, float* XH, Consts C) {
+  constexpr int V = Vec<float>::V;
+  uint32_t g4 = (uint32_t)gid();
+  if (g4 >= (uint32_t)(2 * Lc.half / V)) return;
+  int I0, J, K;
+  dec_nat(g4 * V, Lc, I0, J, K);
+  float se[V] = {0, 0, 0, 0}, sd[V] = {0, 0, 0, 0}, sx[V] = {0, 0, 0, 0};
+#pragma unroll 1
+  for (int d = 0; d < 2; ++d)
+#pragma unroll 1
+    for (int b = 0; b < 2; ++b) {
+      const int j = 2 * J + b, k = 2 * K + d;
+#pragma unroll 1
+      for (int col = 0; col < 2; ++col) {
+        const uint32_t q0 = (uint32_t)col * (uint32_t)Lf.half + prow(Lf, j, k) + (uint32_t)I0;
+        float sum[V], ec[V], x[V], r[V], dc[V] = {0, 0, 0, 0};
+        nbsum_vec<float>(Lf, e + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
+        ldv<float>(e + q0, ec);
+        ldv<float>(X + q0, x);
+        ldv<float>(rho + q0, r);
+        if (M != FR) ldv<float>(dens + q0, dc);
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          se[q] += ec[q];
+          sx[q] += x[q];
+          sd[q] += corr_G<M>(C, h2, ec[q], sum[q], x[q], dc[q]) - r[q];
+        }
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    uint32_t pc = pk_of(Lc, I0 + q, J, K);
+    float re = se[q] * 0.125f;
+    eH[pc] = re;
+    eR[pc] = re;
+    rhoH[pc] = sd[q] * 0.125f;
+    if (XH) XH[pc] = sx[q] * 0.125f;
   }
-  double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// direct form: R v -> Rv and vinit, R(L(v) - S) -> Sd
+template <int M, typename TD>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict_direct_v(
+    Lev Lf, Lev Lc, const double* __restrict__ v, const TD* __restrict__ dens,
+    const double* __restrict__ S, double h2, double* Rv, double* vinit, double* Sd, Consts C) {
+  constexpr int V = Vec<double>::V;
+  uint32_t g4 = (uint32_t)gid();
+  if (g4 >= (uint32_t)(2 * Lc.half / V)) return;
+  int I0, J, K;
+  dec_nat(g4 * V, Lc, I0, J, K);
+  double sv[V] = {0, 0}, sd[V] = {0, 0};
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int j = 2 * J + b, k = 2 * K + d;
+#pragma unroll
+      for (int col = 0; col < 2; ++col) {
+        const uint32_t q0 = (uint32_t)col * (uint32_t)Lf.half + prow(Lf, j, k) + (uint32_t)I0;
+        double sum[V], vc[V], sc[V] = {0, 0};
+        nbsum_vec<double>(Lf, v + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
+        ldv<double>(v + q0, vc);
+        if (S) ldv<double>(S + q0, sc);
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          sv[q] += vc[q];
+          sd[q] += direct_resid<M, double>(C, h2, vc[q], sum[q], double(dens[q0 + q]), sc[q]);
+        }
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    uint32_t pc = pk_of(Lc, I0 + q, J, K);
+    double rv = sv[q] * 0.125;
+    Rv[pc] = rv;
+    vinit[pc] = rv;
+    Sd[pc] = sd[q] * 0.125;
+  }
+}
+
+// linear: rH = R(r - A e), eH = 0
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lin_resid_restrict_v(Lev Lf, Lev Lc,
+                                                                 const T* __restrict__ e,
+                                                                 const T* __restrict__ dg,
+                                                                 const T* __restrict__ r, T kh2,
+                                                                 T* rH, T* eH) {
+  constexpr int V = Vec<T>::V;
+  uint32_t g4 = (uint32_t)gid();
+  if (g4 >= (uint32_t)(2 * Lc.half / V)) return;
+  int I0, J, K;
+  dec_nat(g4 * V, Lc, I0, J, K);
+  T sd[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) sd[q] = T(0);
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int j = 2 * J + b, k = 2 * K + d;
+#pragma unroll
+      for (int col = 0; col < 2; ++col) {
+        const uint32_t q0 = (uint32_t)col * (uint32_t)Lf.half + prow(Lf, j, k) + (uint32_t)I0;
+        T sum[V], ec[V], dd[V], rr[V];
+        nbsum_vec<T>(Lf, e + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
+        ldv<T>(e + q0, ec);
+        ldv<T>(dg + q0, dd);
+        ldv<T>(r + q0, rr);
+#pragma unroll
+        for (int q = 0; q < V; ++q) sd[q] += rr[q] - (kh2 * (T(6) * ec[q] - sum[q]) + dd[q] * ec[q]);
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    uint32_t pc = pk_of(Lc, I0 + q, J, K);
+    rH[pc] = sd[q] * T(0.125);
+    eH[pc] = T(0);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -33,7 +33,9 @@ struct Work64 {  // FP64 direct mode
   float* dens0 = nullptr;      // finest level, packed float
 };
 struct Work32 {  // FP32 correction mode
-  double* w = nullptr;         // FP64 master, packed
+  double* w = nullptr;         // FP64 master, packed (current)
+  double* wbuf[2] = {};        // ping-pong pair for the fused update
+  float* ebuf[2] = {};         // ping-pong pair for the level-0 correction
   float* e[kMaxLev] = {};
   float* X[kMaxLev] = {};
   float* rho[kMaxLev] = {};
@@ -42,6 +44,7 @@ struct Work32 {  // FP32 correction mode
 };
 template <typename T>
 struct WorkLin {  // adjoint linear multigrid in precision T
+  T* ebuf[2] = {};  // ping-pong pair for the level-0 correction
   T* e[kMaxLev] = {};
   T* r[kMaxLev] = {};
   T* dg[kMaxLev] = {};
@@ -51,7 +54,8 @@ struct WorkAdj {
   float* dens = nullptr;  // packed float
   double* dg = nullptr;   // FP64 diagonal, packed
   double* b = nullptr;    // right-hand side s * dL/dv, packed
-  double* lam = nullptr;  // FP64 solution, packed
+  double* lam = nullptr;  // FP64 solution, packed (current)
+  double* lambuf[2] = {}; // ping-pong pair for the fused update
   WorkLin<float> w32;
   WorkLin<double> w64;
   bool have32 = false, have64 = false;
@@ -183,10 +187,14 @@ int ensure64(mg_ctx* ctx) {
 int ensure32(mg_ctx* ctx) {
   if (ctx->have32) return MG_OK;
   Work32& W = ctx->w32;
-  ACHK(dalloc(ctx, &W.w, cells(ctx->L[0])));
+  ACHK(dalloc(ctx, &W.wbuf[0], cells(ctx->L[0])));
+  ACHK(dalloc(ctx, &W.wbuf[1], cells(ctx->L[0])));
+  ACHK(dalloc(ctx, &W.ebuf[1], cells(ctx->L[0])));
+  W.w = W.wbuf[0];
   for (int l = 0; l < ctx->nlev; ++l) {
     int64_t m = cells(ctx->L[l]);
     ACHK(dalloc(ctx, &W.e[l], m));
+    if (l == 0) W.ebuf[0] = W.e[0];
     ACHK(dalloc(ctx, &W.X[l], m));
     ACHK(dalloc(ctx, &W.rho[l], m));
     ACHK(dalloc(ctx, &W.dens[l], m));
@@ -204,6 +212,8 @@ int ensure_lin(mg_ctx* ctx, WorkLin<T>& W) {
     ACHK(dalloc(ctx, &W.r[l], m));
     if (l > 0 || sizeof(T) == 4) ACHK(dalloc(ctx, &W.dg[l], m));
   }
+  W.ebuf[0] = W.e[0];
+  ACHK(dalloc(ctx, &W.ebuf[1], cells(ctx->L[0])));
   return MG_OK;
 }
 
@@ -215,7 +225,9 @@ int ensure_adj(mg_ctx* ctx, int precision) {
     ACHK(dalloc(ctx, &A.dens, m));
     ACHK(dalloc(ctx, &A.dg, m));
     ACHK(dalloc(ctx, &A.b, m));
-    ACHK(dalloc(ctx, &A.lam, m));
+    ACHK(dalloc(ctx, &A.lambuf[0], m));
+    ACHK(dalloc(ctx, &A.lambuf[1], m));
+    A.lam = A.lambuf[0];
     ctx->haveAdj = true;
   }
   if (precision == MG_FP32_REFINED && !A.have32) {
@@ -454,9 +466,17 @@ int cycle64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   const Lev& Lf = ctx->L[l];
   const Lev& Lc = ctx->L[l + 1];
   ACHK(smooth64<M>(ctx, C, l, o->nu_pre));
-  if (l == 0)
+  const bool vec = Lc.n % Vec<double>::V == 0;
+  const int64_t ncv = cells(Lc) / Vec<double>::V;
+  if (l == 0 && vec)
+    k_resid_restrict_direct_v<M, float><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, W.v[0], W.dens0, (const double*)nullptr, 1.0, W.Rv[1], W.v[1], W.S[1], C);
+  else if (l == 0)
     k_resid_restrict_direct<M, double, float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.v[0], W.dens0, (const double*)nullptr, 1.0, W.Rv[1], W.v[1], W.S[1], C);
+  else if (vec)
+    k_resid_restrict_direct_v<M, double><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, W.v[l], W.dens[l], W.S[l], lev_h2(l), W.Rv[l + 1], W.v[l + 1], W.S[l + 1], C);
   else
     k_resid_restrict_direct<M, double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.v[l], W.dens[l], W.S[l], lev_h2(l), W.Rv[l + 1], W.v[l + 1], W.S[l + 1], C);
@@ -474,8 +494,11 @@ int cycle64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   }
   k_coarse_diff<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(cells(Lc), W.v[l + 1],
                                                                        W.Rv[l + 1]);
-  k_prolong_block<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.v[l],
-                                                                         W.Rv[l + 1]);
+  if (vec)
+    k_prolong_v<double><<<nblk(ncv), kBlock, 0, ctx->stream>>>(Lf, Lc, W.v[l], W.Rv[l + 1]);
+  else
+    k_prolong_block<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.v[l],
+                                                                           W.Rv[l + 1]);
   LAUNCHCHK();
   return smooth64<M>(ctx, C, l, o->nu_post);
 }
@@ -621,9 +644,16 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   const Lev& Lf = ctx->L[l];
   const Lev& Lc = ctx->L[l + 1];
   ACHK(smooth32<M>(ctx, C, l, o->nu_pre));
-  k_resid_restrict_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
-      Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
-      W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C);
+  const bool vec = Lc.n % Vec<float>::V == 0;
+  const int64_t ncv = cells(Lc) / Vec<float>::V;
+  if (vec)
+    k_resid_restrict_corr_v<M><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
+        W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C);
+  else
+    k_resid_restrict_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
+        W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C);
   k_coarse_src_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
       Lc, W.eR[l + 1], W.X[l + 1], W.dens[l + 1], W.rho[l + 1], float(lev_h2(l + 1)), C);
   LAUNCHCHK();
@@ -638,8 +668,11 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   }
   k_coarse_diff<float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(cells(Lc), W.e[l + 1],
                                                                       W.eR[l + 1]);
-  k_prolong_block<float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l],
-                                                                        W.eR[l + 1]);
+  if (vec)
+    k_prolong_v<float><<<nblk(ncv), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.eR[l + 1]);
+  else
+    k_prolong_block<float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l],
+                                                                          W.eR[l + 1]);
   LAUNCHCHK();
   return smooth32<M>(ctx, C, l, o->nu_post);
 }
@@ -656,6 +689,9 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
     k_restrict<float, float><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
         ctx->L[l], ctx->L[l + 1], W.dens[l], W.dens[l + 1]);
   double sgn = (C.model == FR) ? -1.0 : 1.0;
+  int cur = 0, eb = 0;  // current master buffer, current level-0 correction buffer
+  W.w = W.wbuf[cur];
+  W.e[0] = W.ebuf[eb];
   if (field_in)
     k_pack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, field_in, W.w, sgn);
   else
@@ -665,12 +701,24 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   ACHK(bg_rms(ctx, C, delta, &eps_bg));
   int outer = 0, rc = MG_OK, vc = 0, k_prev = 0;
   double rel = 0.0, rel_prev = -1.0;
+  const bool fused = L0.nh % kVOuter == 0;
+  const float* pending = nullptr;  // correction not yet added to the master
   for (;;) {
     int64_t nparts;
-    if (L0.nh % Vec<double>::V == 0) {
-      nparts = nblk(L0.half / Vec<double>::V);
-      k_outer_residual_v<M><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-          L0, W.w, W.dens[0], C, W.rho[0], W.X[0], W.e[0], ctx->part);
+    if (fused) {
+      // w_new = w + pending, residual at w_new, next correction buffer zeroed
+      nparts = nblk(L0.half / kVOuter);
+      double* wn = pending ? W.wbuf[1 - cur] : W.w;
+      float* ez = W.ebuf[pending ? 1 - eb : eb];
+      k_outer_fused_v<M><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+          L0, W.w, pending, wn, W.dens[0], C, W.rho[0], W.X[0], ez, ctx->part);
+      if (pending) {
+        cur = 1 - cur;
+        eb = 1 - eb;
+        W.w = W.wbuf[cur];
+        W.e[0] = W.ebuf[eb];
+        pending = nullptr;
+      }
     } else {
       nparts = nblk(m);
       k_outer_residual<M><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
@@ -695,8 +743,12 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
     vc += k;
     rel_prev = rel;
     k_prev = k;
-    k_outer_update<<<nblk(m), kBlock, 0, ctx->stream>>>(m, W.w, W.e[0]);
-    LAUNCHCHK();
+    if (fused) {
+      pending = W.e[0];  // added by the next fused residual
+    } else {
+      k_outer_update<<<nblk(m), kBlock, 0, ctx->stream>>>(m, W.w, W.e[0]);
+      LAUNCHCHK();
+    }
     ++outer;
   }
   k_unpack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, W.w, field_out, sgn);
@@ -775,9 +827,14 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
   }
   const Lev& Lc = ctx->L[l + 1];
   smooth(o->nu_pre);
-  k_lin_resid_restrict<T><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.dg[l],
-                                                                        W.r[l], kh2, W.r[l + 1],
-                                                                        W.e[l + 1]);
+  const bool cvec = Lc.n % Vec<T>::V == 0;
+  const int64_t ncv = cells(Lc) / Vec<T>::V;
+  if (cvec)
+    k_lin_resid_restrict_v<T><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, W.e[l], W.dg[l], W.r[l], kh2, W.r[l + 1], W.e[l + 1]);
+  else
+    k_lin_resid_restrict<T><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, W.e[l], W.dg[l], W.r[l], kh2, W.r[l + 1], W.e[l + 1]);
   LAUNCHCHK();
   if (type == MG_CYCLE_V) {
     ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_V));
@@ -788,7 +845,10 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
     ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_F));
     ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_V));
   }
-  k_prolong_block<T><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1]);
+  if (cvec)
+    k_prolong_v<T><<<nblk(ncv), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1]);
+  else
+    k_prolong_block<T><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1]);
   smooth(o->nu_post);
   LAUNCHCHK();
   return MG_OK;
@@ -809,6 +869,10 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
   k_pack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, grad_field, A.b,
                                                               lin_sign(C) * sgn_field);
   k_lin_setup<M><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, A.v, A.dens, C, A.dg);
+  int cur = 0, eb = 0;
+  A.lam = A.lambuf[cur];
+  if (A.have32) A.w32.e[0] = A.w32.ebuf[eb];
+  if (A.have64) A.w64.e[0] = A.w64.ebuf[eb];
   k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(A.lam, m, 0.0);
   LAUNCHCHK();
   const bool f32 = o->precision == MG_FP32_REFINED;
@@ -832,18 +896,32 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
   double kap = lin_kap(C);
   int outer = 0, rc = MG_OK, vc = 0, k_prev = 0;
   double rel = 0.0, rel_prev = -1.0;
+  const bool vec = L0.nh % kVOuter == 0;
+  const void* pending = nullptr;  // correction not yet added to lam
   for (;;) {
-    const bool vec = L0.nh % Vec<double>::V == 0;
-    int64_t nparts = vec ? nblk(L0.half / Vec<double>::V) : nblk(m);
-    if (f32 && vec)
-      k_lin_outer_v<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-          L0, A.lam, A.dg, A.b, kap, A.w32.r[0], A.w32.e[0], ctx->part);
-    else if (f32)
+    int64_t nparts = vec ? nblk(L0.half / kVOuter) : nblk(m);
+    if (vec) {
+      double* ln = pending ? A.lambuf[1 - cur] : A.lam;
+      int ez = pending ? 1 - eb : eb;
+      if (f32)
+        k_lin_outer_fused_v<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+            L0, A.lam, (const float*)pending, ln, A.dg, A.b, kap, A.w32.r[0], A.w32.ebuf[ez],
+            ctx->part);
+      else
+        k_lin_outer_fused_v<double><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+            L0, A.lam, (const double*)pending, ln, A.dg, A.b, kap, A.w64.r[0], A.w64.ebuf[ez],
+            ctx->part);
+      if (pending) {
+        cur = 1 - cur;
+        eb = 1 - eb;
+        A.lam = A.lambuf[cur];
+        if (f32) A.w32.e[0] = A.w32.ebuf[eb];
+        else A.w64.e[0] = A.w64.ebuf[eb];
+        pending = nullptr;
+      }
+    } else if (f32)
       k_lin_outer<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
           L0, A.lam, A.dg, A.b, kap, A.w32.r[0], A.w32.e[0], ctx->part);
-    else if (vec)
-      k_lin_outer_v<double><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-          L0, A.lam, A.dg, A.b, kap, A.w64.r[0], A.w64.e[0], ctx->part);
     else
       k_lin_outer<double><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
           L0, A.lam, A.dg, A.b, kap, A.w64.r[0], A.w64.e[0], ctx->part);
@@ -865,10 +943,12 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
     int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol);
     if (f32) {
       for (int it = 0; it < k; ++it) ACHK(lin_cycle<float>(ctx, A.w32, kap, o, 0, o->cycle));
-      k_axpy_to64<float><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w32.e[0]);
+      if (vec) pending = A.w32.e[0];
+      else k_axpy_to64<float><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w32.e[0]);
     } else {
       for (int it = 0; it < k; ++it) ACHK(lin_cycle<double>(ctx, A.w64, kap, o, 0, o->cycle));
-      k_axpy_to64<double><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w64.e[0]);
+      if (vec) pending = A.w64.e[0];
+      else k_axpy_to64<double><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w64.e[0]);
     }
     vc += k;
     rel_prev = rel;
@@ -1466,8 +1546,12 @@ int mg_prolong_add(mg_ctx* ctx, const double* coarse, double* fine) {
   const Lev& Lc = ctx->L[1];
   k_pack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, fine, ctx->w64.v[0], 1.0);
   k_pack<double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lc, coarse, ctx->w64.v[1], 1.0);
-  k_prolong_block<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, ctx->w64.v[0],
-                                                                         ctx->w64.v[1]);
+  if (Lc.n % Vec<double>::V == 0)
+    k_prolong_v<double><<<nblk(cells(Lc) / Vec<double>::V), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, ctx->w64.v[0], ctx->w64.v[1]);
+  else
+    k_prolong_block<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, ctx->w64.v[0],
+                                                                           ctx->w64.v[1]);
   k_unpack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, ctx->w64.v[0], fine,
                                                                          1.0);
   LAUNCHCHK();
