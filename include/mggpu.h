@@ -166,16 +166,26 @@ int mg_relax_halfsweep(mg_ctx *ctx, int model, const mg_model_params *params,
 int mg_restrict(mg_ctx *ctx, const double *fine, double *coarse);
 int mg_prolong_add(mg_ctx *ctx, const double *coarse, double *fine);
 
-/* Many independent boxes of different n and model in one batched solve
- * (MPI over realisations in the paper, Sec. 3.1).  Each box uses its own
- * context-free workspace inside ctx; see mg_box_desc. */
+/* Many independent boxes of different n and model in one persistent launch
+ * (the paper farms independent realisations out over MPI, Sec. 3.1).  The
+ * launch never has more workgroups than can be resident; each workgroup
+ * takes the next box from an atomic ticket and runs that box's whole
+ * FP32-refined solve (the scheme of mg_solve with MG_FP32_REFINED), then its
+ * force if requested.  Workspace for all boxes lives in ctx (its n is not
+ * used).  The tile shape (workgroup size; 1 or 4 cells per thread) comes
+ * from mg_batched_tune, from the cache file $MGGPU_TUNE_CACHE (default
+ * $HOME/.mggpu_tune.json) keyed by the batch's (n, model) set, or is tuned
+ * on first use.  opts->precision must be MG_FP32_REFINED.  Returns MG_OK
+ * when every box converged, else MG_ENAN / MG_ENOCONV (per-box status in
+ * per_box, which may be NULL). */
 typedef struct {
-  int n;                   /* grid size of this box (even, >= 8) */
+  int n;                   /* grid size of this box (even, 8 <= n <= 1024) */
   int model;               /* MG_FR / MG_SYMMETRON / MG_CQ */
   mg_model_params params;
   const float *delta;      /* n^3 device floats */
-  double *field;           /* n^3 device doubles: initial guess in (NaN-free), solution out */
+  double *field;           /* n^3 device doubles: solution out (and guess in) */
   float *force;            /* [3][n^3] device floats, or NULL */
+  int field_in;            /* 1: field holds the initial guess; 0: background */
 } mg_box_desc;
 
 /* Kernel timing with HIP events recorded on the context's stream around
@@ -190,6 +200,15 @@ int mg_prof_read(mg_ctx *ctx, int kernel_class, double *total_ms, int64_t *launc
 
 int mg_solve_batched(mg_ctx *ctx, int n_box, const mg_box_desc *boxes,
                      const mg_solver_opts *opts, double tol, mg_stats *per_box);
+
+/* Autotuner of the batched launch: times one outer step (2 FP32 cycles) of
+ * the given batch for each workgroup size in {256, 512, 1024} and 1 or 4
+ * cells per thread, keeps the fastest for this context and writes it to the
+ * cache file.  Overwrites nothing the caller owns. */
+int mg_batched_tune(mg_ctx *ctx, int n_box, const mg_box_desc *boxes,
+                    const mg_solver_opts *opts, int *block_out, int *vec_out);
+/* Tile shape the last batched call used (0, -1 before any). */
+int mg_batched_config(const mg_ctx *ctx, int *block, int *vec);
 
 #ifdef __cplusplus
 }

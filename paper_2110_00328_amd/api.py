@@ -187,6 +187,48 @@ class Context:
                                               _p(grad_out), _p(loss_out)))
         return loss_out, grad_out
 
+    # -- batched boxes ------------------------------------------------------
+    def _box_array(self, boxes):
+        arr = (L.BoxDesc * len(boxes))()
+        for q, b in enumerate(boxes):
+            n = int(b["n"])
+            _need(b["delta"], torch.float32, (n, n, n), f"boxes[{q}].delta")
+            _need(b["field"], torch.float64, (n, n, n), f"boxes[{q}].field")
+            force = b.get("force")
+            if force is not None:
+                _need(force, torch.float32, (3, n, n, n), f"boxes[{q}].force")
+            arr[q].n = n
+            arr[q].model = model_id(b["model"])
+            arr[q].params = b["params"]
+            arr[q].delta = b["delta"].data_ptr()
+            arr[q].field = b["field"].data_ptr()
+            arr[q].force = force.data_ptr() if force is not None else None
+            arr[q].field_in = 1 if b.get("field_in") else 0
+        return arr
+
+    def solve_batched(self, boxes, tol=1e-6, opts=None, allow_noconv=False):
+        """boxes: list of dicts (n, model, params, delta, field[, force, field_in]).
+        Returns the per-box stats."""
+        arr = self._box_array(boxes)
+        opts = opts if opts is not None else solver_opts()
+        st = (L.Stats * len(boxes))()
+        rc = self.lib.mg_solve_batched(self.ptr, len(boxes), arr, ctypes.byref(opts), tol, st)
+        self._check(rc, allow=(L.MG_ENOCONV,) if allow_noconv else ())
+        return list(st)
+
+    def batched_tune(self, boxes, opts=None):
+        arr = self._box_array(boxes)
+        opts = opts if opts is not None else solver_opts()
+        blk, vec = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(self.lib.mg_batched_tune(self.ptr, len(boxes), arr, ctypes.byref(opts),
+                                             ctypes.byref(blk), ctypes.byref(vec)))
+        return blk.value, vec.value
+
+    def batched_config(self):
+        blk, vec = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(self.lib.mg_batched_config(self.ptr, ctypes.byref(blk), ctypes.byref(vec)))
+        return blk.value, vec.value
+
     # -- kernel timing ------------------------------------------------------
     def prof_enable(self, on=True):
         self._check(self.lib.mg_prof_enable(self.ptr, 1 if on else 0))

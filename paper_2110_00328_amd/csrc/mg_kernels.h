@@ -605,12 +605,12 @@ __global__ __launch_bounds__(kBlock) void k_smooth_direct_v(Lev L, double* v, co
 }
 
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_smooth_corr_v(Lev L, float* e, const float* X,
-                                                          const float* dens, const float* rho,
-                                                          int colour, float h2, Consts C) {
+__device__ __forceinline__ void op_smooth_corr_v(const Lev& L, float* __restrict__ e,
+                                                 const float* __restrict__ X,
+                                                 const float* __restrict__ dens,
+                                                 const float* __restrict__ rho, int colour,
+                                                 float h2, const Consts& C, uint32_t g4) {
   constexpr int V = Vec<float>::V;
-  uint32_t g4 = (uint32_t)gid();
-  if (g4 >= (uint32_t)(L.half / V)) return;
   uint32_t g = g4 * V;
   int ih0, j, k;
   dec(g, L, ih0, j, k);
@@ -626,6 +626,14 @@ __global__ __launch_bounds__(kBlock) void k_smooth_corr_v(Lev L, float* e, const
 #pragma unroll
   for (int q = 0; q < V; ++q) out[q] = corr_update<M>(C, h2, eo[q], sum[q], x[q], dc[q], r[q]);
   stv<float>(own + g, out);
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_smooth_corr_v(Lev L, float* e, const float* X,
+                                                          const float* dens, const float* rho,
+                                                          int colour, float h2, Consts C) {
+  uint32_t g4 = (uint32_t)gid();
+  if (g4 < (uint32_t)(L.half / Vec<float>::V))
+    op_smooth_corr_v<M>(L, e, X, dens, rho, colour, h2, C, g4);
 }
 
 template <typename T>
@@ -822,11 +830,9 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm_v(Lev L, const double* v,
 // ---------------------------------------------------------------------------
 // v^h += P c (27/9/3/1 trilinear, separable over the coarse neighbourhood)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong_v(Lev Lf, Lev Lc, T* __restrict__ v,
-                                                      const T* __restrict__ c) {
+__device__ __forceinline__ void op_prolong_v(const Lev& Lf, const Lev& Lc, T* __restrict__ v,
+                                             const T* __restrict__ c, uint32_t g4) {
   constexpr int V = Vec<T>::V;
-  uint32_t g4 = (uint32_t)gid();
-  if (g4 >= (uint32_t)(2 * Lc.half / V)) return;
   int I0, J, K;
   dec_nat(g4 * V, Lc, I0, J, K);
   const int nc = Lc.n;
@@ -875,16 +881,20 @@ __global__ __launch_bounds__(kBlock) void k_prolong_v(Lev Lf, Lev Lc, T* __restr
       }
     }
 }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_v(Lev Lf, Lev Lc, T* __restrict__ v,
+                                                      const T* __restrict__ c) {
+  uint32_t g4 = (uint32_t)gid();
+  if (g4 < (uint32_t)(2 * Lc.half / Vec<T>::V)) op_prolong_v<T>(Lf, Lc, v, c, g4);
+}
 
 // correction form: Re -> eH and eR, R(G(e) - rho) -> rhoH, optionally R X -> XH
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_v(
-    Lev Lf, Lev Lc, const float* __restrict__ e, const float* __restrict__ X,
+__device__ __forceinline__ void op_resid_restrict_corr_v(
+    const Lev& Lf, const Lev& Lc, const float* __restrict__ e, const float* __restrict__ X,
     const float* __restrict__ dens, const float* __restrict__ rho, float h2, float* eH, float* eR,
-    float* rhoH, float* XH, Consts C) {
+    float* rhoH, float* XH, const Consts& C, uint32_t g4) {
   constexpr int V = Vec<float>::V;
-  uint32_t g4 = (uint32_t)gid();
-  if (g4 >= (uint32_t)(2 * Lc.half / V)) return;
   int I0, J, K;
   dec_nat(g4 * V, Lc, I0, J, K);
   float se[V] = {0, 0, 0, 0}, sd[V] = {0, 0, 0, 0}, sx[V] = {0, 0, 0, 0};
@@ -919,6 +929,15 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_v(
     rhoH[pc] = sd[q] * 0.125f;
     if (XH) XH[pc] = sx[q] * 0.125f;
   }
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_v(
+    Lev Lf, Lev Lc, const float* __restrict__ e, const float* __restrict__ X,
+    const float* __restrict__ dens, const float* __restrict__ rho, float h2, float* eH, float* eR,
+    float* rhoH, float* XH, Consts C) {
+  uint32_t g4 = (uint32_t)gid();
+  if (g4 < (uint32_t)(2 * Lc.half / Vec<float>::V))
+    op_resid_restrict_corr_v<M>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, g4);
 }
 
 // direct form: R v -> Rv and vinit, R(L(v) - S) -> Sd

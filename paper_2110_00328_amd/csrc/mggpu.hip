@@ -14,6 +14,13 @@
 #include <string>
 #include <vector>
 
+#include <algorithm>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "mg_batched.h"
 #include "mg_kernels.h"
 #include "mggpu.h"
 
@@ -84,6 +91,15 @@ struct mg_ctx {
   int64_t cic_np = 0;
   unsigned long long* cic_blocks = nullptr;  // per-tile private 17^3 blocks
   uint32_t* cic_cnt = nullptr;  // counts, offsets, cursors per tile
+  // batched solves
+  void* bpool = nullptr;
+  size_t bpool_bytes = 0;
+  BoxDev* bdev = nullptr;
+  BoxOut* bout = nullptr;
+  unsigned* bticket = nullptr;
+  int bcap = 0;
+  int bblock = 0, bvec = -1;  // last tile shape used
+  std::string bkey;
   double* nat64 = nullptr;     // natural-layout scratch (debug entry points)
   std::vector<void*> allocs;
   // event timing of the finest-level smoothers
@@ -1323,6 +1339,10 @@ void mg_ctx_destroy(mg_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->bpool) (void)hipFree(ctx->bpool);
+  if (ctx->bdev) (void)hipFree(ctx->bdev);
+  if (ctx->bout) (void)hipFree(ctx->bout);
+  if (ctx->bticket) (void)hipFree(ctx->bticket);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->hscal) (void)hipHostFree(ctx->hscal);
   delete ctx;
@@ -1584,15 +1604,307 @@ int mg_prof_read(mg_ctx* ctx, int cls, double* total_ms, int64_t* launches) {
   return MG_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched solves: descriptors, workspace, tile-shape tuning
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kTileBlocks[3] = {256, 512, 1024};
+
+// level pyramid of one box (same rule as the context's)
+int box_levels(int n, Lev* L) {
+  int m = n, l = 0;
+  for (;;) {
+    L[l].n = m;
+    L[l].nh = m / 2;
+    L[l].half = (int64_t)m * m * m / 2;
+    L[l].dnh = FastDiv::make((uint32_t)(m / 2));
+    L[l].dn = FastDiv::make((uint32_t)m);
+    ++l;
+    if (!(m / 2 >= 4 && ((m / 2) % 2) == 0) || l >= kMaxLevB) break;
+    m /= 2;
+  }
+  return l;
+}
+
+size_t box_bytes(const Lev* L, int nlev) {
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t t = up(8 * (size_t)(2 * L[0].half));
+  for (int l = 0; l < nlev; ++l) t += (l > 0 ? 5 : 4) * up(4 * (size_t)(2 * L[l].half));
+  return t;
+}
+
+// Builds and uploads the descriptors; allocates the workspace pool.
+int batch_setup(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver_opts* o, double tol,
+                bool trial, int vec, std::vector<BoxDev>& host) {
+  host.assign(nb, BoxDev());
+  size_t total = 0;
+  for (int b = 0; b < nb; ++b) {
+    BoxDev& B = host[b];
+    memset(&B, 0, sizeof B);
+    const mg_box_desc& D = boxes[b];
+    if (D.n < 8 || (D.n & 1) || D.n > 1024 || !D.delta || !D.field)
+      return fail(ctx, MG_EINVAL, "mg_solve_batched: box " + std::to_string(b) +
+                                      " needs even 8 <= n <= 1024 and delta/field");
+    ACHK(make_consts(ctx, D.model, &D.params, D.n, &B.C));
+    B.model = D.model;
+    B.nlev = box_levels(D.n, B.L);
+    for (int l = 0; l < B.nlev; ++l) B.h2[l] = float(lev_h2(l));
+    std::vector<Op> ops;
+    gen_prog(ops, 0, B.nlev - 1, o->cycle, o->nu_pre, o->nu_post);
+    if ((int)ops.size() > kMaxOpsB) return fail(ctx, MG_EINVAL, "cycle program too long");
+    B.nops = (int)ops.size();
+    for (size_t q = 0; q < ops.size(); ++q) B.op[q] = ops[q];
+    B.vec = vec;
+    B.nu1 = o->nu_pre;
+    B.nu2 = o->nu_post;
+    B.fixed_inner = trial ? 2 : o->inner_cycles;
+    B.max_outer = trial ? 1 : o->max_cycles;
+    B.coarse_sweeps = o->coarse_sweeps > 0 ? o->coarse_sweeps : 24;
+    B.use_field_in = D.field_in ? 1 : 0;
+    B.trial = trial ? 1 : 0;
+    B.tol = trial ? 1e-300 : tol;
+    B.delta = D.delta;
+    B.field = D.field;
+    B.force = D.force;
+    total += box_bytes(B.L, B.nlev);
+  }
+  if (total > ctx->bpool_bytes) {
+    if (ctx->bpool) (void)hipFree(ctx->bpool);
+    ctx->bpool = nullptr;
+    ctx->bpool_bytes = 0;
+    HIPCHK(hipMalloc(&ctx->bpool, total));
+    ctx->bpool_bytes = total;
+  }
+  if (nb > ctx->bcap) {
+    if (ctx->bdev) (void)hipFree(ctx->bdev);
+    if (ctx->bout) (void)hipFree(ctx->bout);
+    ctx->bdev = nullptr;
+    ctx->bout = nullptr;
+    HIPCHK(hipMalloc((void**)&ctx->bdev, sizeof(BoxDev) * nb));
+    HIPCHK(hipMalloc((void**)&ctx->bout, sizeof(BoxOut) * nb));
+    ctx->bcap = nb;
+  }
+  if (!ctx->bticket) HIPCHK(hipMalloc((void**)&ctx->bticket, 256));
+  char* base = (char*)ctx->bpool;
+  auto take = [&](size_t bytes) {
+    char* p = base;
+    base += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  for (int b = 0; b < nb; ++b) {
+    BoxDev& B = host[b];
+    B.w = (double*)take(8 * (size_t)(2 * B.L[0].half));
+    for (int l = 0; l < B.nlev; ++l) {
+      size_t bytes = 4 * (size_t)(2 * B.L[l].half);
+      B.e[l] = (float*)take(bytes);
+      B.X[l] = (float*)take(bytes);
+      B.rho[l] = (float*)take(bytes);
+      B.dens[l] = (float*)take(bytes);
+      if (l > 0) B.eR[l] = (float*)take(bytes);
+    }
+  }
+  HIPCHK(hipMemcpyAsync(ctx->bdev, host.data(), sizeof(BoxDev) * nb, hipMemcpyHostToDevice,
+                        ctx->stream));
+  return MG_OK;
+}
+
+template <int BS>
+int batch_launch_bs(mg_ctx* ctx, int nb) {
+  int dev = 0, per_cu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<BS>, BS, 0));
+  if (per_cu < 1) return fail(ctx, MG_EHIP, "batched kernel cannot be resident");
+  int grid = std::min(nb, per_cu * prop.multiProcessorCount);  // never more than resident
+  k_fill<unsigned><<<1, 64, 0, ctx->stream>>>(ctx->bticket, 1, 0u);
+  k_batched<BS><<<grid, BS, 0, ctx->stream>>>(ctx->bdev, nb, ctx->bout, ctx->bticket);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int batch_launch(mg_ctx* ctx, int nb, int block) {
+  if (block == 256) return batch_launch_bs<256>(ctx, nb);
+  if (block == 512) return batch_launch_bs<512>(ctx, nb);
+  return batch_launch_bs<1024>(ctx, nb);
+}
+
+std::string batch_key(int nb, const mg_box_desc* boxes, const mg_solver_opts* o) {
+  std::vector<std::string> parts;
+  for (int b = 0; b < nb; ++b)
+    parts.push_back(std::to_string(boxes[b].n) + (boxes[b].model == MG_FR ? "f" :
+                                                  boxes[b].model == MG_SYMMETRON ? "s" : "q"));
+  std::sort(parts.begin(), parts.end());
+  parts.erase(std::unique(parts.begin(), parts.end()), parts.end());
+  std::string k = "batched:";
+  for (auto& p : parts) k += p + ",";
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    k += std::string(":") + prop.gcnArchName;
+  k += ":V(" + std::to_string(o->nu_pre) + "," + std::to_string(o->nu_post) + ")c" +
+       std::to_string(o->cycle);
+  return k;
+}
+
+std::string cache_path() {
+  const char* e = getenv("MGGPU_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* h = getenv("HOME");
+  return std::string(h && *h ? h : "/tmp") + "/.mggpu_tune.json";
+}
+
+// cache file: one JSON object, "key": [block, vec, ms] per line
+bool cache_lookup(const std::string& key, int* block, int* vec) {
+  std::ifstream f(cache_path());
+  if (!f) return false;
+  std::string line;
+  std::string q = "\"" + key + "\":";
+  while (std::getline(f, line)) {
+    size_t p = line.find(q);
+    if (p == std::string::npos) continue;
+    int b = 0, v = 0;
+    if (sscanf(line.c_str() + p + q.size(), " [%d, %d", &b, &v) == 2 &&
+        (b == 256 || b == 512 || b == 1024) && (v == 0 || v == 1)) {
+      *block = b;
+      *vec = v;
+      return true;
+    }
+  }
+  return false;
+}
+
+void cache_store(const std::string& key, int block, int vec, double ms) {
+  std::map<std::string, std::string> ent;
+  {
+    std::ifstream f(cache_path());
+    std::string line;
+    while (f && std::getline(f, line)) {
+      size_t a = line.find('"'), b = line.find("\":");
+      if (a == std::string::npos || b == std::string::npos || b <= a) continue;
+      size_t c = line.find('[', b), d = line.find(']', b);
+      if (c == std::string::npos || d == std::string::npos) continue;
+      ent[line.substr(a + 1, b - a - 1)] = line.substr(c, d - c + 1);
+    }
+  }
+  std::ostringstream v;
+  v << "[" << block << ", " << vec << ", " << ms << "]";
+  ent[key] = v.str();
+  std::string tmp = cache_path() + ".tmp";
+  std::ofstream f(tmp);
+  if (!f) return;
+  f << "{\n";
+  size_t i = 0;
+  for (auto& kv : ent) f << "  \"" << kv.first << "\": " << kv.second << (++i < ent.size() ? ",\n" : "\n");
+  f << "}\n";
+  f.close();
+  (void)rename(tmp.c_str(), cache_path().c_str());
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_batched_tune(mg_ctx* ctx, int n_box, const mg_box_desc* boxes, const mg_solver_opts* opts,
+                    int* block_out, int* vec_out) {
+  if (!ctx) return MG_EINVAL;
+  ACHK(check_opts(ctx, opts));
+  if (n_box < 1 || !boxes) return fail(ctx, MG_EINVAL, "mg_batched_tune: no boxes");
+  // time one outer step (2 FP32 cycles) of the whole batch per candidate
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  double best = 1e300;
+  int bb = 1024, bv = 1;
+  std::vector<BoxDev> host;
+  for (int vec = 0; vec < 2; ++vec) {
+    ACHK(batch_setup(ctx, n_box, boxes, opts, 1e-300, true, vec, host));
+    for (int ci = 0; ci < 3; ++ci) {
+      int blk = kTileBlocks[ci];
+      ACHK(batch_launch(ctx, n_box, blk));  // warm-up
+      HIPCHK(hipEventRecord(t0, ctx->stream));
+      ACHK(batch_launch(ctx, n_box, blk));
+      HIPCHK(hipEventRecord(t1, ctx->stream));
+      HIPCHK(hipEventSynchronize(t1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+      if (ms < best) {
+        best = ms;
+        bb = blk;
+        bv = vec;
+      }
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  std::string key = batch_key(n_box, boxes, opts);
+  cache_store(key, bb, bv, best);
+  ctx->bkey = key;
+  ctx->bblock = bb;
+  ctx->bvec = bv;
+  if (block_out) *block_out = bb;
+  if (vec_out) *vec_out = bv;
+  return MG_OK;
+}
+
 int mg_solve_batched(mg_ctx* ctx, int n_box, const mg_box_desc* boxes, const mg_solver_opts* opts,
                      double tol, mg_stats* per_box) {
   if (!ctx) return MG_EINVAL;
-  (void)n_box;
-  (void)boxes;
-  (void)opts;
-  (void)tol;
-  (void)per_box;
-  return fail(ctx, MG_EINVAL, "mg_solve_batched: not available in this build");
+  auto t0 = std::chrono::steady_clock::now();
+  ACHK(check_opts(ctx, opts));
+  if (n_box < 1 || !boxes) return fail(ctx, MG_EINVAL, "mg_solve_batched: no boxes");
+  if (!(tol > 0.0)) return fail(ctx, MG_EINVAL, "mg_solve_batched: tol must be > 0");
+  if (opts->precision != MG_FP32_REFINED)
+    return fail(ctx, MG_EINVAL, "mg_solve_batched: runs the FP32-refined scheme");
+  // tile shape: this context's last tuning for the same batch shape, else the
+  // cache file, else tune now
+  std::string key = batch_key(n_box, boxes, opts);
+  int blk = 0, vec = -1;
+  if (ctx->bkey == key && ctx->bblock > 0) {
+    blk = ctx->bblock;
+    vec = ctx->bvec;
+  } else if (cache_lookup(key, &blk, &vec)) {
+    ctx->bkey = key;
+    ctx->bblock = blk;
+    ctx->bvec = vec;
+  } else {
+    ACHK(mg_batched_tune(ctx, n_box, boxes, opts, &blk, &vec));
+  }
+  std::vector<BoxDev> host;
+  ACHK(batch_setup(ctx, n_box, boxes, opts, tol, false, vec, host));
+  ACHK(batch_launch(ctx, n_box, blk));
+  std::vector<BoxOut> outs(n_box);
+  HIPCHK(hipMemcpyAsync(outs.data(), ctx->bout, sizeof(BoxOut) * n_box, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  int rc = MG_OK;
+  for (int b = 0; b < n_box; ++b) {
+    if (outs[b].status == MG_ENAN) rc = MG_ENAN;
+    else if (outs[b].status == MG_ENOCONV && rc == MG_OK) rc = MG_ENOCONV;
+    if (per_box) {
+      memset(&per_box[b], 0, sizeof(mg_stats));
+      per_box[b].cycles = outs[b].outer;
+      per_box[b].vcycles = outs[b].vcycles;
+      per_box[b].status = outs[b].status;
+      per_box[b].rel_resid = outs[b].rel;
+      per_box[b].ms_total = ms;
+    }
+  }
+  if (rc != MG_OK)
+    ctx->err = rc == MG_ENAN ? "mg_solve_batched: non-finite residual in a box"
+                             : "mg_solve_batched: a box reached max_cycles";
+  return rc;
+}
+
+int mg_batched_config(const mg_ctx* ctx, int* block, int* vec) {
+  if (!ctx || !block || !vec) return MG_EINVAL;
+  *block = ctx->bblock;
+  *vec = ctx->bvec;
+  return MG_OK;
 }
 
 }  // extern "C"
