@@ -27,6 +27,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 FP32_SMOOTH_BYTES_PER_CELL = 16.0  # per updated cell: X, rho, other-colour e, write e
+# HBM bytes per finest-level launch of that kernel at 512^3, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (scaled x2.0 and x1.0 by a 1 GiB copy):
+# profiles/k_smooth_corr_v_fr512_hbm_traffic.md.  Set to None whenever the
+# kernel changes, until the counters are taken again.
+FP32_SMOOTH_TRAFFIC_512 = 1115.8e6
 
 
 def parse():
@@ -38,7 +43,9 @@ def parse():
     ap.add_argument("--fr0", type=float, default=1e-5)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=256)
+    ap.add_argument("--cpu-n", type=int, default=384)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the |f_R0|=1e-6, coupled-quintessence and batched legs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB FP32 device copy (counter calibration)")
     return ap.parse_args()
@@ -72,10 +79,118 @@ def cpu_baseline(n, fr0, tol):
                 seconds=dt)
 
 
+def _timed(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
+    """The other workloads the metric names, timed outside the main loop:
+    |f_R0| = 1e-6 forward+adjoint, coupled quintessence forward (FP32-refined
+    and FP64), and the 64-box batched sweep in one persistent launch against
+    the same boxes solved one after another."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_2110_00328_amd import api
+
+    dev = pos.device
+    out = {}
+    gforce = torch.empty_like(force)
+    gfield = torch.empty_like(field)
+    gdelta = torch.empty_like(field)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    mg.cic(pos, out=delta)
+    # f(R) |f_R0| = 1e-6: deeper screening, same pipeline
+    prm6 = api.model_params(float(n), fr0=1e-6)
+    leg = {}
+    for prec in ("fp32", "fp64"):
+        o = api.solver_opts(precision=prec)
+        st = {}
+
+        def fwd_adj():
+            _, s1 = mg.solve("fr", prm6, delta, out=field, tol=tol, opts=o)
+            mg.force("fr", prm6, field, out=force)
+            mg.loss_force_sq(force, cells, grad_out=gforce, loss_out=loss)
+            mg.force_adjoint("fr", prm6, field, gforce, out=gfield)
+            _, s2 = mg.solve_adjoint("fr", prm6, delta, field, gfield, out=gdelta, tol=tol, opts=o)
+            st.update(fwd_vcycles=s1.vcycles, adj_vcycles=s2.vcycles)
+
+        leg[prec + "_ms"] = _timed(fwd_adj, 2)
+        leg[prec + "_cycles"] = dict(st)
+    leg["fp64_over_fp32"] = leg["fp64_ms"] / leg["fp32_ms"]
+    out["fr0_1e-6_solve_adjoint"] = leg
+    # coupled quintessence (alpha=0.1, beta=-0.2; phibar=0.5 and lambda are stand-ins)
+    prmq = api.model_params(float(n))
+    leg = {}
+    for prec in ("fp32", "fp64"):
+        o = api.solver_opts(precision=prec)
+        st = {}
+
+        def fwd():
+            _, s1 = mg.solve("cq", prmq, delta, out=field, tol=tol, opts=o)
+            mg.force("cq", prmq, field, out=force)
+            st.update(vcycles=s1.vcycles, rel=s1.rel_resid)
+
+        leg[prec + "_ms"] = _timed(fwd, 2)
+        leg[prec + "_cycles"] = dict(st)
+    leg["fp64_over_fp32"] = leg["fp64_ms"] / leg["fp32_ms"]
+    out["cq_solve_force"] = leg
+    # 64 boxes of 64^3 / 96^3 / 128^3, f(R) with log-uniform |f_R0| and symmetron
+    spec = synthetic.c4_boxes()
+    boxes = []
+    for b in spec:
+        nb = b["n"]
+        prm = api.model_params(b["box"], **b["params"])
+        boxes.append(dict(n=nb, model=b["model"], params=prm,
+                          delta=torch.from_numpy(b["delta"].astype(np.float32)).to(dev),
+                          field=torch.empty((nb, nb, nb), dtype=torch.float64, device=dev),
+                          force=torch.empty((3, nb, nb, nb), dtype=torch.float32, device=dev)))
+    cells_total = sum(b["n"] ** 3 for b in boxes)
+    o = api.solver_opts(precision="fp32")
+    bctx = api.Context(boxes[0]["n"], device=dev)
+    os.environ.setdefault("MGGPU_TUNE_CACHE", os.path.join(tempfile.mkdtemp(), "tune.json"))
+    t0 = time.perf_counter()
+    bctx.batched_tune(boxes, opts=o)
+    tune_ms = (time.perf_counter() - t0) * 1e3
+    stats = []
+    b_ms = _timed(lambda: stats.__setitem__(slice(None), bctx.solve_batched(boxes, tol=tol, opts=o)),
+                  3)
+    blk, vec = bctx.batched_config()
+    bctx.close()
+    singles = {nb: api.Context(nb, device=dev) for nb in (64, 96, 128)}
+
+    def one_by_one():
+        for b in boxes:
+            c = singles[b["n"]]
+            c.solve(b["model"], b["params"], b["delta"], out=b["field"], tol=tol, opts=o)
+            c.force(b["model"], b["params"], b["field"], out=b["force"])
+
+    s_ms = _timed(one_by_one, 2)
+    for c in singles.values():
+        c.close()
+    out["batched_c4"] = dict(
+        boxes=len(boxes), cells=cells_total, ms=b_ms, boxes_per_s=len(boxes) / (b_ms * 1e-3),
+        cells_per_s=cells_total / (b_ms * 1e-3), block=blk, cells_per_thread=4 if vec else 1,
+        tune_ms=tune_ms, max_rel_resid=max(s.rel_resid for s in stats),
+        outer_steps=[int(min(s.cycles for s in stats)), int(max(s.cycles for s in stats))],
+        one_by_one_ms=s_ms, batched_speedup=s_ms / b_ms)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -145,6 +260,8 @@ def main():
         torch.cuda.synchronize()
         fp64_ms = (time.perf_counter() - t1) * 1e3
 
+    extra = {} if a.no_extra else extra_legs(a, mg, pos, delta, field, force, cells, n, tol)
+
     avg = sm_ms / max(sm_n, 1)
     bytes_per_launch = FP32_SMOOTH_BYTES_PER_CELL * (m / 2)
     achieved = bytes_per_launch / (avg * 1e-3) / 1e9 if sm_n else None
@@ -169,8 +286,11 @@ def main():
         "fp64_ms_per_step": fp64_ms,
         "fp64_over_fp32": (fp64_ms / ms) if fp64_ms else None,
         "phases": info,
+        **extra,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": FP32_SMOOTH_TRAFFIC_512 if n == 512 else None,
+                     "traffic_unit": "bytes per launch (HBM, counted)",
                      "kernel": "k_smooth_corr<FR> (finest-level FP32 half-sweep)",
                      "avg_launch_ms": avg, "launches": sm_n,
                      "algorithmic_bytes_per_launch": bytes_per_launch},

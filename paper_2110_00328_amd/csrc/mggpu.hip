@@ -274,7 +274,7 @@ int make_consts(mg_ctx* ctx, int model, const mg_model_params* P, int n, Consts*
   C.ct2 = ct * ct;
   C.om_a = om / a;
   if (model == MG_FR) {
-    if (P->fr_n != 1) return fail(ctx, MG_EINVAL, "f(R): this build solves n = 1");
+    if (P->fr_n != 1) return fail(ctx, MG_EINVAL, "f(R): the library solves n = 1");
     if (!(P->fr_fr0_abs > 0.0)) return fail(ctx, MG_EINVAL, "f(R): |f_R0| must be > 0");
     // R-bar(a)/H0^2 = 3 (Om a^-3 + 4 OL); K = R-bar a^2 / 3
     double ra = om / (a * a * a) + 4.0 * ol;
