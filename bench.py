@@ -165,7 +165,7 @@ def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
     stats = []
     b_ms = _timed(lambda: stats.__setitem__(slice(None), bctx.solve_batched(boxes, tol=tol, opts=o)),
                   3)
-    blk, vec = bctx.batched_config()
+    blk, vec, teams = bctx.batched_config()
     bctx.close()
     singles = {nb: api.Context(nb, device=dev) for nb in (64, 96, 128)}
 
@@ -181,6 +181,7 @@ def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
     out["batched_c4"] = dict(
         boxes=len(boxes), cells=cells_total, ms=b_ms, boxes_per_s=len(boxes) / (b_ms * 1e-3),
         cells_per_s=cells_total / (b_ms * 1e-3), block=blk, cells_per_thread=4 if vec else 1,
+        teams="one sized team per box" if teams else "single-workgroup teams",
         tune_ms=tune_ms, max_rel_resid=max(s.rel_resid for s in stats),
         outer_steps=[int(min(s.cycles for s in stats)), int(max(s.cycles for s in stats))],
         one_by_one_ms=s_ms, batched_speedup=s_ms / b_ms)

@@ -167,17 +167,23 @@ int mg_restrict(mg_ctx *ctx, const double *fine, double *coarse);
 int mg_prolong_add(mg_ctx *ctx, const double *coarse, double *fine);
 
 /* Many independent boxes of different n and model in one persistent launch
- * (the paper farms independent realisations out over MPI, Sec. 3.1).  The
- * launch never has more workgroups than can be resident; each workgroup
- * takes the next box from an atomic ticket and runs that box's whole
- * FP32-refined solve (the scheme of mg_solve with MG_FP32_REFINED), then its
- * force if requested.  Workspace for all boxes lives in ctx (its n is not
- * used).  The tile shape (workgroup size; 1 or 4 cells per thread) comes
- * from mg_batched_tune, from the cache file $MGGPU_TUNE_CACHE (default
- * $HOME/.mggpu_tune.json) keyed by the batch's (n, model) set, or is tuned
- * on first use.  opts->precision must be MG_FP32_REFINED.  Returns MG_OK
- * when every box converged, else MG_ENAN / MG_ENOCONV (per-box status in
- * per_box, which may be NULL). */
+ * (the paper runs independent realisations side by side over MPI, Sec. 3.1).
+ * The launch is cooperative and never has more workgroups than can be
+ * resident.  Each box is run by a team of workgroups: either one team per
+ * box, sized by its cell count (a big box gets several workgroups, a small
+ * one a single workgroup; levels of n <= 16 run on one workgroup of the
+ * team), or single-workgroup teams each running a longest-first list of
+ * boxes.  A team runs its box's whole FP32-refined solve (the scheme of
+ * mg_solve with MG_FP32_REFINED), then its force if requested.  Team
+ * barriers wait for a bounded time; if one times out every workgroup leaves
+ * and the call returns MG_EHIP.  Workspace for all boxes lives in ctx (its n
+ * is not used).  The tile shape (workgroup size; 1 or 4 cells per thread;
+ * team split) comes from mg_batched_set_config if pinned, else from the last
+ * tuning of this context for the same multiset of (n, model), else from the
+ * cache file $MGGPU_TUNE_CACHE (default $HOME/.mggpu_tune.json), else
+ * mg_batched_tune runs first.  opts->precision must be MG_FP32_REFINED.
+ * Returns MG_OK when every box converged, else MG_ENAN / MG_ENOCONV
+ * (per-box status in per_box, which may be NULL). */
 typedef struct {
   int n;                   /* grid size of this box (even, 8 <= n <= 1024) */
   int model;               /* MG_FR / MG_SYMMETRON / MG_CQ */
@@ -202,13 +208,18 @@ int mg_solve_batched(mg_ctx *ctx, int n_box, const mg_box_desc *boxes,
                      const mg_solver_opts *opts, double tol, mg_stats *per_box);
 
 /* Autotuner of the batched launch: times one outer step (2 FP32 cycles) of
- * the given batch for each workgroup size in {256, 512, 1024} and 1 or 4
- * cells per thread, keeps the fastest for this context and writes it to the
- * cache file.  Overwrites nothing the caller owns. */
+ * the given batch for each workgroup size in {256, 512, 1024}, 1 or 4 cells
+ * per thread, and both team splits; keeps the fastest for this context and
+ * writes it to the cache file.  Overwrites nothing the caller owns. */
 int mg_batched_tune(mg_ctx *ctx, int n_box, const mg_box_desc *boxes,
                     const mg_solver_opts *opts, int *block_out, int *vec_out);
-/* Tile shape the last batched call used (0, -1 before any). */
-int mg_batched_config(const mg_ctx *ctx, int *block, int *vec);
+/* Tile shape the last batched call used: workgroup size, vec (1: 4 cells per
+ * thread), teams (1: one sized team per box; 0: single-workgroup teams).
+ * (0, -1, -1) before any. */
+int mg_batched_config(const mg_ctx *ctx, int *block, int *vec, int *teams);
+/* Pins the tile shape for later batched calls (block 256/512/1024, vec 0/1,
+ * teams 0/1); block = 0 unpins.  MG_EINVAL on other values. */
+int mg_batched_set_config(mg_ctx *ctx, int block, int vec, int teams);
 
 #ifdef __cplusplus
 }

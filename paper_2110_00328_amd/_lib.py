@@ -20,7 +20,7 @@ EXPORTS = (
     "mg_solve", "mg_residual", "mg_force", "mg_force_adjoint", "mg_solve_adjoint",
     "mg_loss_force_sq", "mg_relax_halfsweep", "mg_restrict", "mg_prolong_add",
     "mg_solve_batched", "mg_prof_enable", "mg_prof_read", "mg_batched_tune",
-    "mg_batched_config",
+    "mg_batched_config", "mg_batched_set_config",
 )
 MG_PROF_SMOOTH32, MG_PROF_SMOOTH64, MG_PROF_LIN32, MG_PROF_LIN64 = 0, 1, 2, 3
 
@@ -111,7 +111,8 @@ def load():
         "mg_prof_enable": (ci, [vp, ci]),
         "mg_prof_read": (ci, [vp, ci, P(dbl), P(i64)]),
         "mg_batched_tune": (ci, [vp, ci, P(BoxDesc), P(SolverOpts), P(ci), P(ci)]),
-        "mg_batched_config": (ci, [vp, P(ci), P(ci)]),
+        "mg_batched_config": (ci, [vp, P(ci), P(ci), P(ci)]),
+        "mg_batched_set_config": (ci, [vp, ci, ci, ci]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

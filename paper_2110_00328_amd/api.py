@@ -225,9 +225,15 @@ class Context:
         return blk.value, vec.value
 
     def batched_config(self):
-        blk, vec = ctypes.c_int(0), ctypes.c_int(0)
-        self._check(self.lib.mg_batched_config(self.ptr, ctypes.byref(blk), ctypes.byref(vec)))
-        return blk.value, vec.value
+        """(workgroup size, 4 cells per thread?, one sized team per box?)"""
+        blk, vec, team = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        self._check(self.lib.mg_batched_config(self.ptr, ctypes.byref(blk), ctypes.byref(vec),
+                                               ctypes.byref(team)))
+        return blk.value, vec.value, team.value
+
+    def batched_set_config(self, block=0, vec=1, teams=1):
+        """Pin the batched tile shape (block=0 unpins)."""
+        self._check(self.lib.mg_batched_set_config(self.ptr, block, vec, teams))
 
     # -- kernel timing ------------------------------------------------------
     def prof_enable(self, on=True):

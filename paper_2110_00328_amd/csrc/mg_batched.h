@@ -1,14 +1,22 @@
 // mg_batched.h -- many independent boxes in one persistent launch.
 //
 // The paper runs independent realisations side by side (MPI over nodes,
-// Sec. 3.1); here a single launch takes a list of boxes of different sizes
-// and models.  The grid never exceeds the number of workgroups that can be
-// resident at once, and each workgroup repeatedly takes the next box from an
-// atomic ticket and runs that box's whole refined solve: FP64 outer
-// residuals, FP32 correction V-cycles over all of its levels (block-strided
-// level operations separated by __syncthreads), the coarsest-level solve,
-// and optionally the fifth force.  No workgroup ever waits for another, so
-// the launch cannot deadlock and every wave leaves once the tickets run out.
+// Sec. 3.1); here a single cooperative launch takes a list of boxes of
+// different sizes and models.  The grid is exactly the set of workgroups that
+// can be resident at once.  The host splits it into teams: a box gets a team
+// whose size follows its cell count (so a 128^3 box gets several workgroups
+// and a 64^3 box one), or, when there are more boxes than workgroups, teams of
+// one workgroup each run a static longest-first list of boxes.  A team runs
+// its box's whole FP32-refined solve -- FP64 outer residuals, FP32 correction
+// cycles over all levels, the coarsest-level solve -- then the fifth force.
+//
+// Inside a team, fine-level operations are split over the team's workgroups
+// and separated by team barriers; levels of n <= 16 are run by the team's
+// first workgroup alone.  A team barrier is an arrival counter in device
+// memory with a bounded wait: if any wait exceeds its spin limit the
+// workgroup raises a launch-wide abort flag, every workgroup leaves at its
+// next barrier or box, and the host reports an error.  So every wave always
+// reaches the end of the kernel.
 #pragma once
 #include "mg_kernels.h"
 
@@ -16,11 +24,14 @@ namespace mgg {
 
 constexpr int kMaxLevB = 8;
 constexpr int kMaxOpsB = 160;
+constexpr int kLeadN = 16;                 // levels of n <= 16 run on one workgroup
+constexpr unsigned kSpinLimit = 1u << 25;  // ~2 s of s_sleep(2) polls
 
 struct BoxDev {
   int model, nlev, vec, nops;
   int nu1, nu2, fixed_inner, max_outer, coarse_sweeps, use_field_in;
   int trial;  // tuning run: no outputs written
+  int pad0;
   double tol;
   Lev L[kMaxLevB];
   float h2[kMaxLevB];
@@ -42,7 +53,92 @@ struct BoxOut {
   double rel;
 };
 
-__device__ __forceinline__ int b_plan(int fixed, double rel, double rel_prev, int k_prev,
+// one team: `size` workgroups run boxes order[first .. first + count)
+struct TeamDev {
+  int size, first, count, part_off;
+};
+
+// A workgroup's view of its team.  `gtid`/`gnt` spread a loop over the team
+// (or over this workgroup alone for the one-workgroup view).  The counters of
+// barriers and reductions live in LDS (uniform per workgroup), so the view
+// itself is passed by value.
+struct Team {
+  unsigned* ctr;    // arrival counter (monotonic over the launch)
+  double* part;     // 2 x size reduction slots
+  int* abort;
+  int* s_ok;        // LDS: outcome of the last barrier
+  unsigned* s_gen;  // LDS: barriers passed (thread 0 only)
+  unsigned* s_red;  // LDS: reductions done (slot parity)
+  int size, rank;
+  uint32_t gtid, gnt;
+};
+
+__device__ __forceinline__ Team solo_view(Team T) {
+  T.size = 1;
+  T.rank = 0;
+  T.gtid = threadIdx.x;
+  T.gnt = blockDim.x;
+  return T;
+}
+
+// Team barrier: every thread releases its writes at device scope, one thread
+// arrives and waits (bounded), then acquires.  Returns false on abort.
+__device__ bool team_sync(const Team& T) {
+  if (T.size == 1) {
+    __syncthreads();
+    return true;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned gen = *T.s_gen + 1u;
+    *T.s_gen = gen;
+    atomicAdd(T.ctr, 1u);
+    const unsigned target = gen * (unsigned)T.size;
+    unsigned spins = 0;
+    int ok = 1;
+    while (__hip_atomic_load(T.ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(T.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          ++spins > kSpinLimit) {
+        ok = 0;
+        atomicExch(T.abort, 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    *T.s_ok = ok;
+  }
+  __syncthreads();
+  return *T.s_ok != 0;
+}
+
+// Sum of v over the team, same value (same summation order) in every
+// workgroup.  Returns false on abort.
+__device__ bool team_sum(const Team& T, double v, double* sh, double* out) {
+  double t = block_sum(v, sh);  // valid in thread 0
+  if (T.size == 1) {
+    __syncthreads();
+    if (threadIdx.x == 0) sh[16] = t;
+    __syncthreads();
+    *out = sh[16];
+    __syncthreads();
+    return true;
+  }
+  const unsigned r = *T.s_red;  // read by every thread before the barrier below
+  double* slot = T.part + (r & 1u) * (unsigned)T.size;
+  if (threadIdx.x == 0)
+    __hip_atomic_store(slot + T.rank, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!team_sync(T)) return false;
+  double s = 0.0;
+  for (int q = 0; q < T.size; ++q)
+    s += __hip_atomic_load(slot + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) *T.s_red = r + 1u;  // next reader passes a barrier first
+  *out = s;
+  return true;
+}
+
+__device__ __noinline__ int b_plan(int fixed, double rel, double rel_prev, int k_prev,
                                       double tol) {
   if (fixed > 0) return fixed;
   if (rel_prev <= 0.0 || k_prev <= 0 || !(rel < rel_prev)) return 2;
@@ -53,63 +149,63 @@ __device__ __forceinline__ int b_plan(int fixed, double rel, double rel_prev, in
 }
 
 template <int M>
-__device__ void b_smooth(const BoxDev& B, int l, int sweeps) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+__device__ __noinline__ bool b_smooth(const BoxDev& B, Team T, int l, int sweeps) {
   const Lev L = B.L[l];
   const bool vec = B.vec && (L.nh % 4) == 0;
   for (int it = 0; it < sweeps; ++it)
     for (int colour = 0; colour < 2; ++colour) {
       if (vec) {
-        for (uint32_t g4 = tid; g4 < (uint32_t)(L.half / 4); g4 += nt)
+        for (uint32_t g4 = T.gtid; g4 < (uint32_t)(L.half / 4); g4 += T.gnt)
           op_smooth_corr_v<M>(L, B.e[l], B.X[l], B.dens[l], B.rho[l], colour, B.h2[l], B.C, g4);
       } else {
-        for (int64_t g = tid; g < L.half; g += nt)
+        for (int64_t g = T.gtid; g < L.half; g += T.gnt)
           op_smooth_corr<M>(L, B.e[l], B.X[l], B.dens[l], B.rho[l], colour, B.h2[l], B.C, g);
       }
-      __syncthreads();
+      if (!team_sync(T)) return false;
     }
+  return true;
 }
 
 template <int M>
-__device__ void b_down(const BoxDev& B, int l, bool rx) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+__device__ __noinline__ bool b_down(const BoxDev& B, Team T, int l, bool rx) {
   const Lev Lf = B.L[l], Lc = B.L[l + 1];
   float* XH = rx ? B.X[l + 1] : nullptr;
   if (B.vec && (Lc.n % 4) == 0) {
-    for (uint32_t g4 = tid; g4 < (uint32_t)(2 * Lc.half / 4); g4 += nt)
+    for (uint32_t g4 = T.gtid; g4 < (uint32_t)(2 * Lc.half / 4); g4 += T.gnt)
       op_resid_restrict_corr_v<M>(Lf, Lc, B.e[l], B.X[l], B.dens[l], B.rho[l], B.h2[l],
                                   B.e[l + 1], B.eR[l + 1], B.rho[l + 1], XH, B.C, g4);
   } else {
-    for (int64_t g = tid; g < 2 * Lc.half; g += nt)
+    for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
       op_resid_restrict_corr<M>(Lf, Lc, B.e[l], B.X[l], B.dens[l], B.rho[l], B.h2[l], B.e[l + 1],
                                 B.eR[l + 1], B.rho[l + 1], XH, B.C, g);
   }
-  __syncthreads();
-  for (int64_t g = tid; g < 2 * Lc.half; g += nt)
+  if (!team_sync(T)) return false;
+  for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
     op_coarse_src_corr<M>(Lc, B.eR[l + 1], B.X[l + 1], B.dens[l + 1], B.rho[l + 1], B.h2[l + 1],
                           B.C, g);
-  __syncthreads();
+  return team_sync(T);
 }
 
-__device__ __forceinline__ void b_up(const BoxDev& B, int l) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+__device__ __noinline__ bool b_up(const BoxDev& B, Team T, int l) {
   const Lev Lf = B.L[l], Lc = B.L[l + 1];
-  for (int64_t g = tid; g < 2 * Lc.half; g += nt) B.eR[l + 1][g] = B.e[l + 1][g] - B.eR[l + 1][g];
-  __syncthreads();
+  for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
+    B.eR[l + 1][g] = B.e[l + 1][g] - B.eR[l + 1][g];
+  if (!team_sync(T)) return false;
   if (B.vec && (Lc.n % 4) == 0) {
-    for (uint32_t g4 = tid; g4 < (uint32_t)(2 * Lc.half / 4); g4 += nt)
+    for (uint32_t g4 = T.gtid; g4 < (uint32_t)(2 * Lc.half / 4); g4 += T.gnt)
       op_prolong_v<float>(Lf, Lc, B.e[l], B.eR[l + 1], g4);
   } else {
-    for (int64_t g = tid; g < 2 * Lc.half; g += nt)
+    for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
       op_prolong_block<float>(Lf, Lc, B.e[l], B.eR[l + 1], g);
   }
-  __syncthreads();
+  return team_sync(T);
 }
 
-// relax until the RMS residual has dropped by 1e-8 (checked every 4 sweeps);
-// coupled quintessence adds a Newton step on the uniform mode at each check
+// Coarsest level, one workgroup: relax until the RMS residual has dropped by
+// 1e-8 (checked every 4 sweeps); coupled quintessence adds a Newton step on
+// the uniform mode at each check.
 template <int M>
-__device__ void b_coarsest(const BoxDev& B, int l, double* sh) {
+__device__ __noinline__ void b_coarsest(const BoxDev& B, int l, double* sh) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const Lev L = B.L[l];
   double r0 = -1.0;
@@ -145,26 +241,51 @@ __device__ void b_coarsest(const BoxDev& B, int l, double* sh) {
   }
 }
 
-template <int M>
-__device__ void b_cycle(const BoxDev& B, bool rx, double* sh) {
-  for (int o = 0; o < B.nops; ++o) {
-    const Op op = B.op[o];
-    if (op.kind == OP_SMOOTH) b_smooth<M>(B, op.lev, op.count);
-    else if (op.kind == OP_DOWN) b_down<M>(B, op.lev, rx);
-    else if (op.kind == OP_UP) b_up(B, op.lev);
-    else b_coarsest<M>(B, op.lev, sh);
-  }
+__device__ __forceinline__ bool op_is_lead(const BoxDev& B, const Op& op) {
+  return op.kind == OP_COARSEST || B.L[op.lev].n <= kLeadN;
 }
 
 template <int M>
-__device__ void box_solve(const BoxDev& B, BoxOut* out, double* sh) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+__device__ bool b_run_op(const BoxDev& B, const Team& V, const Op& op, bool rx, double* sh) {
+  if (op.kind == OP_SMOOTH) return b_smooth<M>(B, V, op.lev, op.count);
+  if (op.kind == OP_DOWN) return b_down<M>(B, V, op.lev, rx);
+  if (op.kind == OP_UP) return b_up(B, V, op.lev);
+  b_coarsest<M>(B, op.lev, sh);
+  return true;
+}
+
+// One cycle.  Operations on small levels run on the team's first workgroup
+// (the others skip them); a team barrier separates them from team-wide ones.
+template <int M>
+__device__ __noinline__ bool b_cycle(const BoxDev& B, Team T, bool rx, double* sh) {
+  bool prev_lead = false;
+  for (int o = 0; o < B.nops; ++o) {
+    const Op op = B.op[o];
+    if (T.size > 1 && op_is_lead(B, op)) {
+      if (T.rank == 0) {
+        Team S = solo_view(T);
+        b_run_op<M>(B, S, op, rx, sh);
+      }
+      prev_lead = true;
+    } else {
+      if (prev_lead && !team_sync(T)) return false;
+      if (!b_run_op<M>(B, T, op, rx, sh)) return false;
+      prev_lead = false;
+    }
+  }
+  if (prev_lead) return team_sync(T);
+  return true;
+}
+
+// natural -> packed inputs; returns the squared background residual summed
+// over the team in *bsq_out
+template <int M>
+__device__ __noinline__ bool b_pack(const BoxDev& B, Team T, double* sh, double* bsq_out) {
   const Lev L0 = B.L[0];
   const int64_t m = 2 * L0.half;
   const double sgn = (M == FR) ? -1.0 : 1.0;
-  // natural -> packed inputs; background residual
   double bsq = 0.0;
-  for (int64_t g = tid; g < m; g += nt) {
+  for (int64_t g = T.gtid; g < m; g += T.gnt) {
     int i, j, k;
     dec_nat(g, L0, i, j, k);
     uint32_t pk = pk_of(L0, i, j, k);
@@ -174,73 +295,61 @@ __device__ void box_solve(const BoxDev& B, BoxOut* out, double* sh) {
     double t = B.C.bg_coef * double(d);
     bsq += t * t;
   }
-  double eps_bg = sqrt(block_sum_all(bsq, sh) / double(m));
-  if (!(eps_bg > 0.0)) eps_bg = 1.0;
+  if (!team_sum(T, bsq, sh, bsq_out)) return false;
   if (M != FR) {
     for (int l = 0; l + 1 < B.nlev; ++l) {
-      for (int64_t g = tid; g < 2 * B.L[l + 1].half; g += nt)
+      for (int64_t g = T.gtid; g < 2 * B.L[l + 1].half; g += T.gnt)
         op_restrict<float, float>(B.L[l], B.L[l + 1], B.dens[l], B.dens[l + 1], g);
-      __syncthreads();
+      if (!team_sync(T)) return false;
     }
   }
-  int outer = 0, vc = 0, k_prev = 0, status = 0;
-  double rel = 0.0, rel_prev = -1.0;
-  for (;;) {
-    // FP64 residual of the master; correction problem for the next step
-    double acc = 0.0;
-    for (int64_t g = tid; g < m; g += nt) {
-      double d = cell_resid_direct<M, double, float>(L0, B.w, B.dens[0], (const double*)nullptr,
-                                                     1.0, B.C, g);
-      acc += d * d;
-      B.rho[0][g] = float(-d);
-      B.X[0][g] = float(B.w[g]);
-      B.e[0][g] = 0.0f;
-    }
-    rel = sqrt(block_sum_all(acc, sh) / double(m)) / eps_bg;
-    if (!isfinite(rel)) {
-      status = -3;
-      break;
-    }
-    if (rel <= B.tol) break;
-    if (outer >= B.max_outer) {
-      status = -2;
-      break;
-    }
-    int kc = b_plan(B.fixed_inner, rel, rel_prev, k_prev, B.tol);
-    for (int it = 0; it < kc; ++it) b_cycle<M>(B, it == 0, sh);
-    for (int64_t g = tid; g < m; g += nt) B.w[g] += double(B.e[0][g]);
-    __syncthreads();
-    vc += kc;
-    rel_prev = rel;
-    k_prev = kc;
-    ++outer;
+  return true;
+}
+
+// w += e (when add), then the FP64 residual of w and the FP32 correction
+// problem for the next step; squared residual summed over the team
+template <int M>
+__device__ __noinline__ bool b_outer(const BoxDev& B, Team T, bool add, double* sh,
+                                     double* sq_out) {
+  const Lev L0 = B.L[0];
+  const int64_t m = 2 * L0.half;
+  if (add) {
+    for (int64_t g = T.gtid; g < m; g += T.gnt) B.w[g] += double(B.e[0][g]);
+    if (!team_sync(T)) return false;
   }
-  if (B.trial) {
-    if (tid == 0) {
-      out->outer = outer;
-      out->vcycles = vc;
-      out->status = status;
-      out->rel = rel;
-    }
-    __syncthreads();
-    return;
+  double acc = 0.0;
+  for (int64_t g = T.gtid; g < m; g += T.gnt) {
+    double d = cell_resid_direct<M, double, float>(L0, B.w, B.dens[0], (const double*)nullptr,
+                                                   1.0, B.C, g);
+    acc += d * d;
+    B.rho[0][g] = float(-d);
+    B.X[0][g] = float(B.w[g]);
+    B.e[0][g] = 0.0f;
   }
-  // packed -> natural solution, then the force from it
-  for (int64_t g = tid; g < m; g += nt) {
+  return team_sum(T, acc, sh, sq_out);
+}
+
+// packed -> natural solution, then the fifth force from it
+template <int M>
+__device__ __noinline__ bool b_finish(const BoxDev& B, Team T) {
+  const Lev L0 = B.L[0];
+  const int64_t m = 2 * L0.half;
+  const double sgn = (M == FR) ? -1.0 : 1.0;
+  for (int64_t g = T.gtid; g < m; g += T.gnt) {
     int i, j, k;
     dec_nat(g, L0, i, j, k);
     B.field[g] = sgn * B.w[pk_of(L0, i, j, k)];
   }
-  __syncthreads();
+  if (!team_sync(T)) return false;
   if (B.force) {
     const int n = L0.n;
-    for (int64_t g = tid; g < m; g += nt) {
+    const double* f = B.field;
+    for (int64_t g = T.gtid; g < m; g += T.gnt) {
       int i, j, k;
       dec_nat(g, L0, i, j, k);
       int ip = i + 1 == n ? 0 : i + 1, im = i == 0 ? n - 1 : i - 1;
       int jp = j + 1 == n ? 0 : j + 1, jm = j == 0 ? n - 1 : j - 1;
       int kp = k + 1 == n ? 0 : k + 1, km = k == 0 ? n - 1 : k - 1;
-      const double* f = B.field;
       auto phi = [&](double v) {
         return M == FR ? -B.C.phi5 * v : (M == SYM ? B.C.phi5 * v * v : B.C.phi5 * v);
       };
@@ -252,31 +361,97 @@ __device__ void box_solve(const BoxDev& B, BoxOut* out, double* sh) {
                                          phi(f[((int64_t)km * n + j) * n + i])));
     }
   }
-  if (tid == 0) {
+  return true;
+}
+
+// One box on one team: pack, outer FP64 steps with FP32 correction cycles,
+// then the outputs.  false = aborted.
+template <int M>
+__device__ __noinline__ bool box_solve(const BoxDev& B, Team T, BoxOut* out, double* sh) {
+  const double m = 2.0 * double(B.L[0].half);
+  double tot = 0.0;
+  if (!b_pack<M>(B, T, sh, &tot)) return false;
+  double eps_bg = sqrt(tot / m);
+  if (!(eps_bg > 0.0)) eps_bg = 1.0;
+  int outer = 0, vc = 0, k_prev = 0, status = 0;
+  double rel = 0.0, rel_prev = -1.0;
+  for (;;) {
+    if (!b_outer<M>(B, T, outer > 0, sh, &tot)) return false;
+    rel = sqrt(tot / m) / eps_bg;
+    if (!isfinite(rel)) {
+      status = -3;
+      break;
+    }
+    if (rel <= B.tol) break;
+    if (outer >= B.max_outer) {
+      status = -2;
+      break;
+    }
+    int kc = b_plan(B.fixed_inner, rel, rel_prev, k_prev, B.tol);
+    for (int it = 0; it < kc; ++it)
+      if (!b_cycle<M>(B, T, it == 0, sh)) return false;
+    vc += kc;
+    rel_prev = rel;
+    k_prev = kc;
+    ++outer;
+  }
+  if (!B.trial && !b_finish<M>(B, T)) return false;
+  if (T.rank == 0 && threadIdx.x == 0) {
     out->outer = outer;
     out->vcycles = vc;
     out->status = status;
     out->rel = rel;
   }
-  __syncthreads();
+  // the team's workspace may be reused by its next box
+  return team_sync(T);
 }
 
-// The persistent launch: grid <= resident workgroups, boxes taken by ticket.
+// The persistent cooperative launch: wg[b] = (team, rank) of workgroup b
+// (team < 0: idle).  Each team runs its list of boxes.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_batched(const BoxDev* __restrict__ boxes, int nbox,
-                                                BoxOut* __restrict__ outs, unsigned* ticket) {
+__global__ __launch_bounds__(BS) void k_batched(const BoxDev* __restrict__ boxes,
+                                                const int* __restrict__ order,
+                                                const TeamDev* __restrict__ teams,
+                                                const int2* __restrict__ wg,
+                                                BoxOut* __restrict__ outs, unsigned* ctr,
+                                                double* parts, int* abort) {
   __shared__ double sh[32];
-  __shared__ int bid;
-  for (;;) {
-    if (threadIdx.x == 0) bid = (int)atomicAdd(ticket, 1u);
+  __shared__ int s_ok;
+  __shared__ unsigned s_gen, s_red;
+  const int2 me = wg[blockIdx.x];
+  if (me.x < 0) return;
+  const TeamDev TD = teams[me.x];
+  if (threadIdx.x == 0) {
+    s_gen = 0u;
+    s_red = 0u;
+  }
+  __syncthreads();
+  Team T;
+  T.ctr = ctr + me.x;
+  T.part = parts + TD.part_off;
+  T.abort = abort;
+  T.s_ok = &s_ok;
+  T.s_gen = &s_gen;
+  T.s_red = &s_red;
+  T.size = TD.size;
+  T.rank = me.y;
+  T.gtid = (uint32_t)me.y * blockDim.x + threadIdx.x;
+  T.gnt = (uint32_t)TD.size * blockDim.x;
+  for (int q = 0; q < TD.count; ++q) {
+    // leave once any workgroup has aborted (same decision for the whole workgroup)
+    if (threadIdx.x == 0)
+      s_ok = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
     __syncthreads();
-    const int b = bid;
+    const bool go = s_ok != 0;
     __syncthreads();
-    if (b >= nbox) break;
+    if (!go) break;
+    const int b = order[TD.first + q];
     const BoxDev& B = boxes[b];
-    if (B.model == FR) box_solve<FR>(B, outs + b, sh);
-    else if (B.model == SYM) box_solve<SYM>(B, outs + b, sh);
-    else box_solve<CQ>(B, outs + b, sh);
+    bool ok;
+    if (B.model == FR) ok = box_solve<FR>(B, T, outs + b, sh);
+    else if (B.model == SYM) ok = box_solve<SYM>(B, T, outs + b, sh);
+    else ok = box_solve<CQ>(B, T, outs + b, sh);
+    if (!ok) break;
   }
 }
 

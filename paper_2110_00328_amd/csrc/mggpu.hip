@@ -96,9 +96,17 @@ struct mg_ctx {
   size_t bpool_bytes = 0;
   BoxDev* bdev = nullptr;
   BoxOut* bout = nullptr;
-  unsigned* bticket = nullptr;
   int bcap = 0;
-  int bblock = 0, bvec = -1;  // last tile shape used
+  // team plan of the batched launch (device copies) and its sync state
+  int* border = nullptr;
+  TeamDev* bteams = nullptr;
+  int2* bwg = nullptr;
+  unsigned* bctr = nullptr;
+  double* bparts = nullptr;
+  int* babort = nullptr;
+  int bplan_cap = 0;  // capacity (entries) of border/bteams/bwg/bctr; bparts holds 2x
+  int bblock = 0, bvec = -1, bteam = -1;  // last tile shape used
+  bool bpinned = false;                    // shape fixed by mg_batched_set_config
   std::string bkey;
   double* nat64 = nullptr;     // natural-layout scratch (debug entry points)
   std::vector<void*> allocs;
@@ -1342,7 +1350,9 @@ void mg_ctx_destroy(mg_ctx* ctx) {
   if (ctx->bpool) (void)hipFree(ctx->bpool);
   if (ctx->bdev) (void)hipFree(ctx->bdev);
   if (ctx->bout) (void)hipFree(ctx->bout);
-  if (ctx->bticket) (void)hipFree(ctx->bticket);
+  for (void* p : {(void*)ctx->border, (void*)ctx->bteams, (void*)ctx->bwg, (void*)ctx->bctr,
+                  (void*)ctx->bparts, (void*)ctx->babort})
+    if (p) (void)hipFree(p);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->hscal) (void)hipHostFree(ctx->hscal);
   delete ctx;
@@ -1687,7 +1697,6 @@ int batch_setup(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver_o
     HIPCHK(hipMalloc((void**)&ctx->bout, sizeof(BoxOut) * nb));
     ctx->bcap = nb;
   }
-  if (!ctx->bticket) HIPCHK(hipMalloc((void**)&ctx->bticket, 256));
   char* base = (char*)ctx->bpool;
   auto take = [&](size_t bytes) {
     char* p = base;
@@ -1711,25 +1720,151 @@ int batch_setup(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver_o
   return MG_OK;
 }
 
+// Team plan for a grid of G resident workgroups.  team_mode 1: one team per
+// box (when boxes <= G) with sizes that balance cells per workgroup, capped
+// so that a workgroup keeps at least 32768 fine cells; team_mode 0 (or more
+// boxes than workgroups): single-workgroup teams with a longest-first static
+// list of boxes each.
+struct BatchPlan {
+  std::vector<int> order;
+  std::vector<TeamDev> teams;
+  std::vector<int2> wg;
+  int parts = 0;
+};
+
+void plan_teams(const std::vector<BoxDev>& host, int G, int team_mode, BatchPlan& P) {
+  const int nb = (int)host.size();
+  std::vector<double> cost(nb);
+  for (int b = 0; b < nb; ++b) cost[b] = double(host[b].L[0].half) * 2.0;
+  P.order.clear();
+  P.teams.clear();
+  P.wg.clear();
+  if (team_mode == 1 && nb <= G) {
+    std::vector<int> t(nb, 1), cap(nb);
+    for (int b = 0; b < nb; ++b) cap[b] = (int)std::max<double>(1.0, std::floor(cost[b] / 32768.0));
+    int left = G - nb;
+    while (left > 0) {
+      int best = -1;
+      double bc = 0.0;
+      for (int b = 0; b < nb; ++b)
+        if (t[b] < cap[b] && cost[b] / t[b] > bc) {
+          bc = cost[b] / t[b];
+          best = b;
+        }
+      if (best < 0) break;
+      ++t[best];
+      --left;
+    }
+    for (int b = 0; b < nb; ++b) {
+      P.order.push_back(b);
+      P.teams.push_back(TeamDev{t[b], b, 1, 0});
+    }
+  } else {
+    const int nt = std::min(nb, G);
+    std::vector<int> idx(nb);
+    for (int b = 0; b < nb; ++b) idx[b] = b;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    std::vector<double> load(nt, 0.0);
+    std::vector<std::vector<int>> lists(nt);
+    for (int b : idx) {
+      int best = 0;
+      for (int q = 1; q < nt; ++q)
+        if (load[q] < load[best]) best = q;
+      load[best] += cost[b];
+      lists[best].push_back(b);
+    }
+    for (int q = 0; q < nt; ++q) {
+      P.teams.push_back(TeamDev{1, (int)P.order.size(), (int)lists[q].size(), 0});
+      for (int b : lists[q]) P.order.push_back(b);
+    }
+  }
+  P.parts = 0;
+  for (int q = 0; q < (int)P.teams.size(); ++q) {
+    P.teams[q].part_off = P.parts;
+    P.parts += 2 * P.teams[q].size;
+    for (int r = 0; r < P.teams[q].size; ++r) P.wg.push_back(make_int2(q, r));
+  }
+}
+
 template <int BS>
-int batch_launch_bs(mg_ctx* ctx, int nb) {
-  int dev = 0, per_cu = 0;
+int batch_launch_bs(mg_ctx* ctx, const std::vector<BoxDev>& host, int team_mode, int* grid_out) {
+  const int nb = (int)host.size();
+  int dev = 0, per_cu = 0, coop = 0;
   HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  if (!coop) return fail(ctx, MG_EHIP, "batched solve needs cooperative launch support");
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, dev));
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<BS>, BS, 0));
   if (per_cu < 1) return fail(ctx, MG_EHIP, "batched kernel cannot be resident");
-  int grid = std::min(nb, per_cu * prop.multiProcessorCount);  // never more than resident
-  k_fill<unsigned><<<1, 64, 0, ctx->stream>>>(ctx->bticket, 1, 0u);
-  k_batched<BS><<<grid, BS, 0, ctx->stream>>>(ctx->bdev, nb, ctx->bout, ctx->bticket);
+  const int G = per_cu * prop.multiProcessorCount;
+  BatchPlan P;
+  plan_teams(host, G, team_mode, P);
+  const int grid = (int)P.wg.size();
+  if (grid < 1 || grid > G) return fail(ctx, MG_EHIP, "batched plan does not fit the device");
+  const int need = std::max(std::max((int)P.order.size(), (int)P.teams.size()), grid);
+  if (need > ctx->bplan_cap || P.parts > 2 * ctx->bplan_cap) {
+    for (void** p : {(void**)&ctx->border, (void**)&ctx->bteams, (void**)&ctx->bwg,
+                     (void**)&ctx->bctr, (void**)&ctx->bparts}) {
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+    }
+    ctx->bplan_cap = 0;
+    const int cap = std::max(need, (P.parts + 1) / 2);
+    HIPCHK(hipMalloc((void**)&ctx->border, sizeof(int) * cap));
+    HIPCHK(hipMalloc((void**)&ctx->bteams, sizeof(TeamDev) * cap));
+    HIPCHK(hipMalloc((void**)&ctx->bwg, sizeof(int2) * cap));
+    HIPCHK(hipMalloc((void**)&ctx->bctr, sizeof(unsigned) * cap));
+    HIPCHK(hipMalloc((void**)&ctx->bparts, sizeof(double) * 2 * cap));
+    ctx->bplan_cap = cap;
+  }
+  if (!ctx->babort) HIPCHK(hipMalloc((void**)&ctx->babort, 256));
+  HIPCHK(hipMemcpyAsync(ctx->border, P.order.data(), sizeof(int) * P.order.size(),
+                        hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->bteams, P.teams.data(), sizeof(TeamDev) * P.teams.size(),
+                        hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->bwg, P.wg.data(), sizeof(int2) * P.wg.size(), hipMemcpyHostToDevice,
+                        ctx->stream));
+  k_fill<unsigned><<<nblk((int64_t)P.teams.size()), kBlock, 0, ctx->stream>>>(
+      ctx->bctr, (int64_t)P.teams.size(), 0u);
+  k_fill<int><<<1, kBlock, 0, ctx->stream>>>(ctx->babort, 1, 0);
   LAUNCHCHK();
+  // the host copies of the plan must outlive the asynchronous uploads
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const BoxDev* a0 = ctx->bdev;
+  const int* a1 = ctx->border;
+  const TeamDev* a2 = ctx->bteams;
+  const int2* a3 = ctx->bwg;
+  BoxOut* a4 = ctx->bout;
+  unsigned* a5 = ctx->bctr;
+  double* a6 = ctx->bparts;
+  int* a7 = ctx->babort;
+  void* args[] = {(void*)&a0, (void*)&a1, (void*)&a2, (void*)&a3,
+                  (void*)&a4, (void*)&a5, (void*)&a6, (void*)&a7};
+  HIPCHK(hipLaunchCooperativeKernel((const void*)k_batched<BS>, dim3(grid), dim3(BS), args, 0,
+                                    ctx->stream));
+  if (grid_out) *grid_out = grid;
+  (void)nb;
   return MG_OK;
 }
 
-int batch_launch(mg_ctx* ctx, int nb, int block) {
-  if (block == 256) return batch_launch_bs<256>(ctx, nb);
-  if (block == 512) return batch_launch_bs<512>(ctx, nb);
-  return batch_launch_bs<1024>(ctx, nb);
+int batch_launch(mg_ctx* ctx, const std::vector<BoxDev>& host, int block, int team_mode) {
+  if (block == 256) return batch_launch_bs<256>(ctx, host, team_mode, nullptr);
+  if (block == 512) return batch_launch_bs<512>(ctx, host, team_mode, nullptr);
+  return batch_launch_bs<1024>(ctx, host, team_mode, nullptr);
+}
+
+// outputs of the last launch; MG_EHIP if a team barrier timed out
+int batch_collect(mg_ctx* ctx, int nb, std::vector<BoxOut>& outs) {
+  outs.resize(nb);
+  int abort_flag = 0;
+  HIPCHK(hipMemcpyAsync(outs.data(), ctx->bout, sizeof(BoxOut) * nb, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipMemcpyAsync(&abort_flag, ctx->babort, sizeof(int), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (abort_flag) return fail(ctx, MG_EHIP, "batched solve: a team barrier timed out");
+  return MG_OK;
 }
 
 std::string batch_key(int nb, const mg_box_desc* boxes, const mg_solver_opts* o) {
@@ -1738,9 +1873,14 @@ std::string batch_key(int nb, const mg_box_desc* boxes, const mg_solver_opts* o)
     parts.push_back(std::to_string(boxes[b].n) + (boxes[b].model == MG_FR ? "f" :
                                                   boxes[b].model == MG_SYMMETRON ? "s" : "q"));
   std::sort(parts.begin(), parts.end());
-  parts.erase(std::unique(parts.begin(), parts.end()), parts.end());
-  std::string k = "batched:";
-  for (auto& p : parts) k += p + ",";
+  // the multiset of (n, model): counts matter for the team split
+  std::string k = "batched2:";
+  for (size_t q = 0; q < parts.size();) {
+    size_t r = q;
+    while (r < parts.size() && parts[r] == parts[q]) ++r;
+    k += parts[q] + "x" + std::to_string(r - q) + ",";
+    q = r;
+  }
   int dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
@@ -1757,8 +1897,8 @@ std::string cache_path() {
   return std::string(h && *h ? h : "/tmp") + "/.mggpu_tune.json";
 }
 
-// cache file: one JSON object, "key": [block, vec, ms] per line
-bool cache_lookup(const std::string& key, int* block, int* vec) {
+// cache file: one JSON object, "key": [block, vec, team, ms] per line
+bool cache_lookup(const std::string& key, int* block, int* vec, int* team) {
   std::ifstream f(cache_path());
   if (!f) return false;
   std::string line;
@@ -1766,18 +1906,19 @@ bool cache_lookup(const std::string& key, int* block, int* vec) {
   while (std::getline(f, line)) {
     size_t p = line.find(q);
     if (p == std::string::npos) continue;
-    int b = 0, v = 0;
-    if (sscanf(line.c_str() + p + q.size(), " [%d, %d", &b, &v) == 2 &&
-        (b == 256 || b == 512 || b == 1024) && (v == 0 || v == 1)) {
+    int b = 0, v = 0, t = 0;
+    if (sscanf(line.c_str() + p + q.size(), " [%d, %d, %d", &b, &v, &t) == 3 &&
+        (b == 256 || b == 512 || b == 1024) && (v == 0 || v == 1) && (t == 0 || t == 1)) {
       *block = b;
       *vec = v;
+      *team = t;
       return true;
     }
   }
   return false;
 }
 
-void cache_store(const std::string& key, int block, int vec, double ms) {
+void cache_store(const std::string& key, int block, int vec, int team, double ms) {
   std::map<std::string, std::string> ent;
   {
     std::ifstream f(cache_path());
@@ -1791,7 +1932,7 @@ void cache_store(const std::string& key, int block, int vec, double ms) {
     }
   }
   std::ostringstream v;
-  v << "[" << block << ", " << vec << ", " << ms << "]";
+  v << "[" << block << ", " << vec << ", " << team << ", " << ms << "]";
   ent[key] = v.str();
   std::string tmp = cache_path() + ".tmp";
   std::ofstream f(tmp);
@@ -1818,33 +1959,45 @@ int mg_batched_tune(mg_ctx* ctx, int n_box, const mg_box_desc* boxes, const mg_s
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
   double best = 1e300;
-  int bb = 1024, bv = 1;
+  int bb = 1024, bv = 1, bt = 1;
   std::vector<BoxDev> host;
-  for (int vec = 0; vec < 2; ++vec) {
-    ACHK(batch_setup(ctx, n_box, boxes, opts, 1e-300, true, vec, host));
-    for (int ci = 0; ci < 3; ++ci) {
-      int blk = kTileBlocks[ci];
-      ACHK(batch_launch(ctx, n_box, blk));  // warm-up
-      HIPCHK(hipEventRecord(t0, ctx->stream));
-      ACHK(batch_launch(ctx, n_box, blk));
-      HIPCHK(hipEventRecord(t1, ctx->stream));
-      HIPCHK(hipEventSynchronize(t1));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, t0, t1));
-      if (ms < best) {
-        best = ms;
-        bb = blk;
-        bv = vec;
+  std::vector<BoxOut> outs;
+  int rc = MG_OK;
+  for (int vec = 0; vec < 2 && rc == MG_OK; ++vec) {
+    rc = batch_setup(ctx, n_box, boxes, opts, 1e-300, true, vec, host);
+    for (int team = 0; team < 2 && rc == MG_OK; ++team)
+      for (int ci = 0; ci < 3 && rc == MG_OK; ++ci) {
+        const int blk = kTileBlocks[ci];
+        rc = batch_launch(ctx, host, blk, team);  // warm-up
+        if (rc == MG_OK) rc = batch_collect(ctx, n_box, outs);
+        if (rc != MG_OK) break;
+        HIPCHK(hipEventRecord(t0, ctx->stream));
+        rc = batch_launch(ctx, host, blk, team);
+        if (rc != MG_OK) break;
+        HIPCHK(hipEventRecord(t1, ctx->stream));
+        HIPCHK(hipEventSynchronize(t1));
+        rc = batch_collect(ctx, n_box, outs);
+        if (rc != MG_OK) break;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+        if (ms < best) {
+          best = ms;
+          bb = blk;
+          bv = vec;
+          bt = team;
+        }
       }
-    }
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
+  if (rc != MG_OK) return rc;
   std::string key = batch_key(n_box, boxes, opts);
-  cache_store(key, bb, bv, best);
+  cache_store(key, bb, bv, bt, best);
   ctx->bkey = key;
+  ctx->bpinned = false;
   ctx->bblock = bb;
   ctx->bvec = bv;
+  ctx->bteam = bt;
   if (block_out) *block_out = bb;
   if (vec_out) *vec_out = bv;
   return MG_OK;
@@ -1862,24 +2015,25 @@ int mg_solve_batched(mg_ctx* ctx, int n_box, const mg_box_desc* boxes, const mg_
   // tile shape: this context's last tuning for the same batch shape, else the
   // cache file, else tune now
   std::string key = batch_key(n_box, boxes, opts);
-  int blk = 0, vec = -1;
-  if (ctx->bkey == key && ctx->bblock > 0) {
+  int blk = 0, vec = -1, team = -1;
+  if (ctx->bpinned || (ctx->bkey == key && ctx->bblock > 0)) {
     blk = ctx->bblock;
     vec = ctx->bvec;
-  } else if (cache_lookup(key, &blk, &vec)) {
+    team = ctx->bteam;
+  } else if (cache_lookup(key, &blk, &vec, &team)) {
     ctx->bkey = key;
     ctx->bblock = blk;
     ctx->bvec = vec;
+    ctx->bteam = team;
   } else {
     ACHK(mg_batched_tune(ctx, n_box, boxes, opts, &blk, &vec));
+    team = ctx->bteam;
   }
   std::vector<BoxDev> host;
   ACHK(batch_setup(ctx, n_box, boxes, opts, tol, false, vec, host));
-  ACHK(batch_launch(ctx, n_box, blk));
-  std::vector<BoxOut> outs(n_box);
-  HIPCHK(hipMemcpyAsync(outs.data(), ctx->bout, sizeof(BoxOut) * n_box, hipMemcpyDeviceToHost,
-                        ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ACHK(batch_launch(ctx, host, blk, team));
+  std::vector<BoxOut> outs;
+  ACHK(batch_collect(ctx, n_box, outs));
   double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   int rc = MG_OK;
   for (int b = 0; b < n_box; ++b) {
@@ -1900,10 +2054,31 @@ int mg_solve_batched(mg_ctx* ctx, int n_box, const mg_box_desc* boxes, const mg_
   return rc;
 }
 
-int mg_batched_config(const mg_ctx* ctx, int* block, int* vec) {
-  if (!ctx || !block || !vec) return MG_EINVAL;
+int mg_batched_config(const mg_ctx* ctx, int* block, int* vec, int* teams) {
+  if (!ctx || !block || !vec || !teams) return MG_EINVAL;
   *block = ctx->bblock;
   *vec = ctx->bvec;
+  *teams = ctx->bteam;
+  return MG_OK;
+}
+
+int mg_batched_set_config(mg_ctx* ctx, int block, int vec, int teams) {
+  if (!ctx) return MG_EINVAL;
+  if (block == 0) {
+    ctx->bpinned = false;
+    ctx->bkey.clear();
+    ctx->bblock = 0;
+    ctx->bvec = -1;
+    ctx->bteam = -1;
+    return MG_OK;
+  }
+  if ((block != 256 && block != 512 && block != 1024) || (vec != 0 && vec != 1) ||
+      (teams != 0 && teams != 1))
+    return fail(ctx, MG_EINVAL, "mg_batched_set_config: block 256/512/1024, vec 0/1, teams 0/1");
+  ctx->bpinned = true;
+  ctx->bblock = block;
+  ctx->bvec = vec;
+  ctx->bteam = teams;
   return MG_OK;
 }
 

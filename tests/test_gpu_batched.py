@@ -46,10 +46,10 @@ def test_batched_matches_single_box_solves(tmp_path, monkeypatch):
     tol = 1e-8
     opts = api.solver_opts(precision="fp32")
     stats = mg.solve_batched(boxes, tol=tol, opts=opts)
-    blk, vec = mg.batched_config()
-    assert blk in (256, 512, 1024) and vec in (0, 1)
+    blk, vec, teams = mg.batched_config()
+    assert blk in (256, 512, 1024) and vec in (0, 1) and teams in (0, 1)
     cache = json.load(open(tmp_path / "tune.json"))
-    assert any(v[0] == blk and v[1] == vec for v in cache.values())
+    assert any(v[:3] == [blk, vec, teams] for v in cache.values())
     for q, (b, st) in enumerate(zip(boxes, stats)):
         assert st.status == 0 and st.rel_resid <= tol, (q, st.status, st.rel_resid)
         single = api.Context(b["n"], device=DEV)
@@ -80,4 +80,64 @@ def test_batched_matches_single_box_solves(tmp_path, monkeypatch):
         b["field_in"] = 1
     stats2 = mg.solve_batched(boxes, tol=tol, opts=opts)
     assert all(s.cycles == 0 for s in stats2)
+    mg.close()
+
+
+def _big_boxes():
+    spec = [(128, "fr", 1e-5), (96, "sym", 1.5), (64, "fr", 1e-6), (48, "cq", None)]
+    out = []
+    for q, (n, model, par) in enumerate(spec):
+        d = synthetic.lognormal_delta(n, 950 + q, sigma_delta=2.0).astype(np.float32)
+        if model == "fr":
+            prm = api.model_params(float(n), fr0=par)
+        elif model == "sym":
+            prm = api.model_params(float(n), a_star=0.5, xi=1.0 / CH, beta_star=par)
+        else:
+            prm = api.model_params(float(n))
+        out.append(dict(n=n, model=model, params=prm, delta=torch.from_numpy(d).to(DEV),
+                        field=torch.zeros((n, n, n), dtype=torch.float64, device=DEV),
+                        force=torch.zeros((3, n, n, n), dtype=torch.float32, device=DEV)))
+    return out
+
+
+@pytest.mark.parametrize("shape", [(1024, 1, 1), (256, 1, 1), (512, 0, 1), (1024, 1, 0)])
+def test_batched_team_splits_match_single_box_solves(shape):
+    """Boxes big enough to be split over many workgroups (teams of up to 64
+    workgroups for 128^3), for pinned tile shapes of both team splits."""
+    boxes = _big_boxes()
+    mg = api.Context(16, device=DEV)
+    mg.batched_set_config(*shape)
+    tol = 1e-8
+    opts = api.solver_opts(precision="fp32")
+    print(f"shape {shape}", flush=True)
+    stats = mg.solve_batched(boxes, tol=tol, opts=opts)
+    assert mg.batched_config() == shape
+    for q, (b, st) in enumerate(zip(boxes, stats)):
+        assert st.status == 0 and st.rel_resid <= tol, (q, st.status, st.rel_resid)
+        single = api.Context(b["n"], device=DEV)
+        f1, _ = single.solve(b["model"], b["params"], b["delta"], tol=tol, opts=opts)
+        g1 = single.force(b["model"], b["params"], f1)
+        x, ref = b["field"].cpu().numpy(), f1.cpu().numpy()
+        if b["model"] == "cq":
+            x, ref = x - x.mean(), ref - ref.mean()
+            bg = 0.0
+        else:
+            bg = ref.mean()
+        err = np.linalg.norm(x - ref) / np.linalg.norm(ref - bg)
+        gerr = (np.linalg.norm((b["force"] - g1).cpu().numpy()) /
+                np.linalg.norm(g1.cpu().numpy()))
+        print(f"  box {q} n={b['n']} {b['model']}: outer={st.cycles} vc={st.vcycles} "
+              f"rel={st.rel_resid:.1e} field_diff={err:.1e} force_diff={gerr:.1e}", flush=True)
+        assert err < 1e-6 and gerr < 1e-6
+        single.close()
+    mg.close()
+
+
+def test_batched_set_config_rejects_bad_shapes():
+    mg = api.Context(16, device=DEV)
+    with pytest.raises(api.MGError):
+        mg.batched_set_config(300, 1, 1)
+    with pytest.raises(api.MGError):
+        mg.batched_set_config(256, 2, 1)
+    mg.batched_set_config(0)
     mg.close()
