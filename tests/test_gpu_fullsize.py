@@ -1,0 +1,285 @@
+"""Full-size parity: the workloads the benchmark and the parity cases name,
+at their real sizes, against the FP64 CPU oracle.
+
+- 512^3 f(R) (|f_R0| = 1e-5 and 1e-6), the bench's pipeline and launch
+  configuration (CIC of 512^3 FP32 Zel'dovich particles, FP32-refined
+  V(1,1) to relative residual 1e-6): CIC against the oracle's CIC; field and
+  force against the oracle's solve of the oracle's own density to 1e-10; the
+  oracle's residual of the GPU field; the plain FP64 GPU solve beside it.
+- 512^3 coupled quintessence: the oracle's residual of the GPU field (a
+  property at any size) and FP32-refined against FP64 on the GPU.
+- 256^3 f(R) and symmetron on a lognormal field with 20 NFW-like clumps
+  (peak delta up to 1e4): field and force against the oracle.
+- 256^3 f(R) adjoint of Loss = sum over 4096 cells of |F5|^2: against the
+  oracle's FP64 adjoint and against central finite differences of FP64 GPU
+  solves (h = 1e-4 on delta at 16 probe cells).
+- The autograd path (solve_force + backward) against the explicit adjoint
+  chain.
+
+Error metrics as in the other parity tests: field_err =
+||x - x_ora|| / ||x_ora - x_bg||, force_err = ||g - g_ora|| / ||g_ora||.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic
+from paper_2110_00328_amd import api
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+CH = oracle.C_OVER_H0
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_err(x, ref, bg=0.0):
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref - bg))
+
+
+@pytest.fixture(scope="module")
+def c3():
+    n = 512
+    t0 = time.perf_counter()
+    pos32 = synthetic.c3_positions(n)
+    say(f"c3 positions {time.perf_counter() - t0:.1f} s")
+    pos = torch.from_numpy(pos32).to(DEV)
+    mg = api.Context(n, device=DEV)
+    delta = mg.cic(pos)
+    t0 = time.perf_counter()
+    d_ora = oracle.cic(n, pos32.astype(np.float64))
+    say(f"oracle CIC {time.perf_counter() - t0:.1f} s")
+    d_gpu = delta.cpu().numpy()
+    err = np.max(np.abs(d_gpu - d_ora)) / np.max(np.abs(d_ora))
+    say(f"512^3 CIC max|diff|/max|delta| = {err:.2e}, sigma_delta = {d_ora.std():.3f}")
+    del pos
+    yield dict(n=n, mg=mg, delta=delta, d_ora=d_ora, cic_err=err)
+    mg.close()
+
+
+def test_c3_cic_matches_oracle(c3):
+    assert c3["cic_err"] < 1e-6
+
+
+@pytest.mark.parametrize("fr0", [1e-5, 1e-6])
+def test_c3_fr_solve_and_force_match_oracle(c3, fr0):
+    n, mg, delta = c3["n"], c3["mg"], c3["delta"]
+    P = oracle.params(oracle.FR, n, float(n), fr0=fr0)
+    prm = api.model_params(float(n), fr0=fr0)
+    t0 = time.perf_counter()
+    ref, cyc, rel_o, _ = oracle.solve(P, c3["d_ora"], tol=1e-10, max_cycles=100)
+    say(f"fr0={fr0:g}: oracle solve {time.perf_counter() - t0:.1f} s, {cyc} cycles, rel {rel_o:.1e}")
+    g_ref = oracle.force(P, ref)
+    bg = -oracle.background(P)
+    ref = -ref  # f_R
+    out = {}
+    for prec in ("fp32", "fp64"):
+        field, st = mg.solve("fr", prm, delta, tol=1e-6, opts=api.solver_opts(precision=prec))
+        g = mg.force("fr", prm, field).cpu().numpy().astype(np.float64)
+        x = field.cpu().numpy()
+        ferr, gerr = rel_err(x, ref, bg), rel_err(g, g_ref)
+        # the oracle's own relative residual of the GPU field (on the GPU's density)
+        r, _ = oracle.residual(P, delta.cpu().numpy().astype(np.float64), -x)
+        rel_by_oracle = np.sqrt(np.mean(r * r)) / oracle.background_resid_rms(
+            P, delta.cpu().numpy().astype(np.float64))
+        say(f"  {prec}: V-cycles={st.vcycles} rel={st.rel_resid:.2e} oracle-rel={rel_by_oracle:.2e} "
+            f"field_err={ferr:.2e} force_err={gerr:.2e}")
+        out[prec] = (ferr, gerr, rel_by_oracle, st.rel_resid)
+    for prec, (ferr, gerr, rel_o2, rel_g) in out.items():
+        assert rel_o2 <= 1e-6 and abs(rel_o2 - rel_g) <= 1e-3 * rel_g + 1e-12
+        assert ferr < 1e-5 and gerr < 1e-5
+
+
+def test_c3_cq_residual_by_oracle_and_fp32_vs_fp64(c3):
+    n, mg, delta = c3["n"], c3["mg"], c3["delta"]
+    P = oracle.params(oracle.CQ, n, float(n))
+    prm = api.model_params(float(n))
+    d64 = delta.cpu().numpy().astype(np.float64)
+    eps_bg = oracle.background_resid_rms(P, d64)
+    fields = {}
+    for prec in ("fp32", "fp64"):
+        field, st = mg.solve("cq", prm, delta, tol=1e-6, opts=api.solver_opts(precision=prec))
+        x = field.cpu().numpy()
+        r, _ = oracle.residual(P, d64, x)
+        rel_o = np.sqrt(np.mean(r * r)) / eps_bg
+        say(f"  cq {prec}: V-cycles={st.vcycles} rel={st.rel_resid:.2e} oracle-rel={rel_o:.2e}")
+        assert rel_o <= 1e-6 and abs(rel_o - st.rel_resid) <= 1e-3 * st.rel_resid + 1e-12
+        fields[prec] = x
+    a, b = fields["fp32"], fields["fp64"]
+    err = rel_err(a - a.mean(), b - b.mean())
+    say(f"  cq fp32 vs fp64 (uniform mode removed): {err:.2e}")
+    assert err < 1e-5
+
+
+@pytest.fixture(scope="module")
+def c2():
+    n = 256
+    d = synthetic.c2_delta(n).astype(np.float32)
+    say(f"c2 delta: sigma={d.std():.2f} max={d.max():.3g}")
+    mg = api.Context(n, device=DEV)
+    yield dict(n=n, d32=d, delta=torch.from_numpy(d).to(DEV), mg=mg)
+    mg.close()
+
+
+@pytest.mark.parametrize("model", ["fr", "sym"])
+def test_c2_fp32_solve_and_force_match_oracle(c2, model):
+    n, mg = c2["n"], c2["mg"]
+    if model == "fr":
+        P = oracle.params(oracle.FR, n, float(n), fr0=1e-5)
+        prm = api.model_params(float(n), fr0=1e-5)
+    else:
+        kw = dict(a_star=0.5, xi=1.0 / CH, beta_star=1.0)
+        P = oracle.params(oracle.SYM, n, float(n), **kw)
+        prm = api.model_params(float(n), **kw)
+    d64 = c2["d32"].astype(np.float64)
+    t0 = time.perf_counter()
+    ref, cyc, rel_o, _ = oracle.solve(P, d64, tol=1e-10, max_cycles=200)
+    say(f"{model}: oracle {time.perf_counter() - t0:.1f} s, {cyc} cycles, rel {rel_o:.1e}")
+    g_ref = oracle.force(P, ref)
+    sgn = -1.0 if model == "fr" else 1.0
+    bg = sgn * oracle.background(P)
+    for tol in (1e-6, 1e-8):
+        field, st = mg.solve(model, prm, c2["delta"], tol=tol, opts=api.solver_opts(precision="fp32"))
+        g = mg.force(model, prm, field).cpu().numpy().astype(np.float64)
+        ferr = rel_err(field.cpu().numpy(), sgn * ref, bg)
+        gerr = rel_err(g, g_ref)
+        say(f"  tol {tol:g}: V-cycles={st.vcycles} rel={st.rel_resid:.2e} field_err={ferr:.2e} "
+            f"force_err={gerr:.2e}")
+        # the stated 1e-5 at the configured tolerance; 1e-6 when driven to 1e-8
+        assert ferr < (1e-5 if tol == 1e-6 else 1e-6) and gerr < (1e-5 if tol == 1e-6 else 1e-6)
+
+
+@pytest.fixture(scope="module")
+def c5():
+    n = 256
+    d = synthetic.c5_delta(n).astype(np.float32)
+    cells = synthetic.c5_loss_cells(n)
+    mg = api.Context(n, device=DEV)
+    P = oracle.params(oracle.FR, n, float(n), fr0=1e-5)
+    prm = api.model_params(float(n), fr0=1e-5)
+    yield dict(n=n, d32=d, delta=torch.from_numpy(d).to(DEV), cells=cells,
+               cells_t=torch.from_numpy(cells).to(DEV), mg=mg, P=P, prm=prm)
+    mg.close()
+
+
+def _loss64(mg, prm, field, cells_t):
+    """Loss in FP64 from an FP64 field (central differences of Phi5 = -c~^2 f_R / 2)."""
+    n = field.shape[0]
+    ct = n * CH / float(n)  # c~ for 1 Mpc/h cells
+    phi = -0.5 * ct * ct * field
+    g = []
+    for ax in (2, 1, 0):  # x, y, z
+        g.append(-0.5 * (torch.roll(phi, -1, dims=ax) - torch.roll(phi, 1, dims=ax)))
+    g = torch.stack(g).reshape(3, -1)[:, cells_t]
+    return float((g * g).sum()), g
+
+
+def test_c5_adjoint_matches_oracle_and_finite_differences(c5):
+    n, mg, P, prm = c5["n"], c5["mg"], c5["P"], c5["prm"]
+    cells_t = c5["cells_t"]
+    # forward (FP32-refined, as the bench) and the adjoint chain on the GPU
+    field, _ = mg.solve("fr", prm, c5["delta"], tol=1e-10, opts=api.solver_opts(precision="fp32"))
+    force = mg.force("fr", prm, field)
+    loss, gforce = mg.loss_force_sq(force, cells_t)
+    gfield = mg.force_adjoint("fr", prm, field, gforce)
+    gd32, st32 = mg.solve_adjoint("fr", prm, c5["delta"], field, gfield, tol=1e-8,
+                                  opts=api.solver_opts(precision="fp32"))
+    gd64, st64 = mg.solve_adjoint("fr", prm, c5["delta"], field, gfield, tol=1e-11,
+                                  opts=api.solver_opts(precision="fp64"))
+    gd32, gd64 = gd32.cpu().numpy(), gd64.cpu().numpy()
+    # oracle: its own solve and adjoint of the same loss
+    d64 = c5["d32"].astype(np.float64)
+    t0 = time.perf_counter()
+    ref, _, _, _ = oracle.solve(P, d64, tol=1e-12, max_cycles=200)
+    g_ora = oracle.force(P, ref).reshape(3, -1)
+    gf = np.zeros_like(g_ora)
+    gf[:, c5["cells"]] = 2.0 * g_ora[:, c5["cells"]]
+    gv = oracle.force_adjoint(P, ref, gf.reshape(3, n, n, n))
+    gd_ora, _, _ = oracle.adjoint(P, d64, ref, gv, tol=1e-12)
+    say(f"oracle solve + adjoint {time.perf_counter() - t0:.1f} s")
+    e32, e64 = rel_err(gd32, gd_ora), rel_err(gd64, gd_ora)
+    say(f"adjoint vs oracle: fp32 {e32:.2e} ({st32.vcycles} cycles), fp64 {e64:.2e}")
+    assert e32 < 1e-5 and e64 < 1e-6
+    # central differences of FP64 GPU solves on delta at 16 probe cells
+    rng = np.random.default_rng(5006)
+    near = []
+    for c in c5["cells"][rng.choice(len(c5["cells"]), 8, replace=False)]:
+        k, j, i = np.unravel_index(c, (n, n, n))
+        near.append(np.ravel_multi_index((k, j, (i + 1) % n), (n, n, n)))
+    probes = np.array(near + list(rng.choice(n ** 3, 8, replace=False)))
+    o64 = api.solver_opts(precision="fp64")
+    base, _ = mg.solve("fr", prm, c5["delta"], tol=1e-13, opts=o64, allow_noconv=True)
+    # the FP64 adjoint of the FP64 loss
+    l0, g0 = _loss64(mg, prm, base, cells_t)
+    # the FP64 loss differentiates the library's own force
+    g_lib = mg.force("fr", prm, base).reshape(3, -1)[:, cells_t].double()
+    assert float((g_lib - g0).norm() / g0.norm()) < 1e-6
+    gfull = torch.zeros((3, n ** 3), dtype=torch.float64, device=DEV)
+    gfull[:, cells_t] = 2.0 * g0
+    gfa = mg.force_adjoint("fr", prm, base, gfull.reshape(3, n, n, n).float())
+    gda, _ = mg.solve_adjoint("fr", prm, c5["delta"], base, gfa, tol=1e-12, opts=o64,
+                              allow_noconv=True)
+    gda = gda.cpu().numpy().ravel()
+    h = 1e-4
+    # FD noise floor: the loss is known to about 1e-12 of itself (FP64 solves
+    # at their rounding floor), so a central difference carries ~1e-12 L / h
+    floor = 1e-12 * l0 / h
+    say(f"loss {l0:.6e}, FD noise floor {floor:.1e}")
+    worst = 0.0
+    d = c5["d32"].ravel().copy()
+    for c in probes:
+        dp, dm = d.copy(), d.copy()
+        dp[c] = np.float32(d[c] + h)
+        dm[c] = np.float32(d[c] - h)
+        step = float(dp[c]) - float(dm[c])
+        lp = _loss64(mg, prm, mg.solve("fr", prm, torch.from_numpy(dp.reshape(n, n, n)).to(DEV),
+                                       field_in=base, tol=1e-13, opts=o64,
+                                       allow_noconv=True)[0], cells_t)[0]
+        lm = _loss64(mg, prm, mg.solve("fr", prm, torch.from_numpy(dm.reshape(n, n, n)).to(DEV),
+                                       field_in=base, tol=1e-13, opts=o64,
+                                       allow_noconv=True)[0], cells_t)[0]
+        fd = (lp - lm) / step
+        e = abs(fd - gda[c]) / (1e-6 * abs(fd) + floor)
+        worst = max(worst, e)
+        say(f"  probe {c}: fd={fd:.6e} adjoint={gda[c]:.6e} |diff|/(1e-6|fd| + floor)={e:.2f}")
+    assert worst < 1.0
+
+
+def test_autograd_backward_matches_adjoint_chain():
+    n = 48
+    d = synthetic.lognormal_delta(n, 77, sigma_delta=1.5).astype(np.float32)
+    mg = api.Context(n, device=DEV)
+    prm = api.model_params(float(n), fr0=1e-5)
+    cells = torch.from_numpy(np.sort(np.random.default_rng(78).choice(n ** 3, 500,
+                                                                      replace=False))).to(DEV)
+    delta = torch.from_numpy(d).to(DEV).requires_grad_(True)
+    opts = api.solver_opts(precision="fp32")
+    field, force = api.solve_force(mg, "fr", prm, delta, tol=1e-10, opts=opts, adj_tol=1e-10)
+    loss = (force.reshape(3, -1)[:, cells] ** 2).sum()
+    loss.backward()
+    g_auto = delta.grad.double().cpu().numpy()
+    # explicit chain through the C ABI
+    f2, _ = mg.solve("fr", prm, delta.detach(), tol=1e-10, opts=opts)
+    F2 = mg.force("fr", prm, f2)
+    _, gF = mg.loss_force_sq(F2, cells)
+    gfield = mg.force_adjoint("fr", prm, f2, gF)
+    gd, _ = mg.solve_adjoint("fr", prm, delta.detach(), f2, gfield, tol=1e-10, opts=opts)
+    e = rel_err(g_auto, gd.cpu().numpy())
+    # and the oracle's adjoint of the same loss
+    P = oracle.params(oracle.FR, n, float(n), fr0=1e-5)
+    ref, _, _, _ = oracle.solve(P, d.astype(np.float64), tol=1e-12)
+    g_ora = oracle.force(P, ref).reshape(3, -1)
+    gf = np.zeros_like(g_ora)
+    cc = cells.cpu().numpy()
+    gf[:, cc] = 2.0 * g_ora[:, cc]
+    gv = oracle.force_adjoint(P, ref, gf.reshape(3, n, n, n))
+    gd_ora, _, _ = oracle.adjoint(P, d.astype(np.float64), ref, gv, tol=1e-12)
+    e_ora = rel_err(g_auto, gd_ora)
+    say(f"autograd vs explicit chain {e:.2e}, vs oracle {e_ora:.2e}")
+    assert e < 1e-6 and e_ora < 1e-5
+    mg.close()
