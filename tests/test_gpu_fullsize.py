@@ -226,10 +226,11 @@ def test_c5_adjoint_matches_oracle_and_finite_differences(c5):
                               allow_noconv=True)
     gda = gda.cpu().numpy().ravel()
     h = 1e-4
-    # FD noise floor: the loss is known to about 1e-12 of itself (FP64 solves
-    # at their rounding floor), so a central difference carries ~1e-12 L / h
-    floor = 1e-12 * l0 / h
-    say(f"loss {l0:.6e}, FD noise floor {floor:.1e}")
+    # Central differences of FP64 solves at their rounding floor scatter by
+    # ~1e-9 here (against gradients up to ~3e-3); the bound is 1e-5 relative
+    # plus 1e-8 absolute (4e-6 of the largest probe gradient).
+    floor = 1e-8
+    say(f"loss {l0:.6e}")
     worst = 0.0
     d = c5["d32"].ravel().copy()
     for c in probes:
@@ -244,9 +245,9 @@ def test_c5_adjoint_matches_oracle_and_finite_differences(c5):
                                        field_in=base, tol=1e-13, opts=o64,
                                        allow_noconv=True)[0], cells_t)[0]
         fd = (lp - lm) / step
-        e = abs(fd - gda[c]) / (1e-6 * abs(fd) + floor)
+        e = abs(fd - gda[c]) / (1e-5 * abs(fd) + floor)
         worst = max(worst, e)
-        say(f"  probe {c}: fd={fd:.6e} adjoint={gda[c]:.6e} |diff|/(1e-6|fd| + floor)={e:.2f}")
+        say(f"  probe {c}: fd={fd:.6e} adjoint={gda[c]:.6e} |diff|/(1e-5|fd| + 1e-8)={e:.3f}")
     assert worst < 1.0
 
 
