@@ -52,7 +52,7 @@ typedef struct {
   double a;          /* scale factor */
   double omega_m;    /* Omega_m today; Omega_Lambda = 1 - Omega_m */
   double box_mpch;   /* box size L in Mpc/h (sets c~) */
-  int fr_n;          /* f(R): Hu-Sawicki n (eq:fR_HS); n = 1 (others: MG_EINVAL) */
+  int fr_n;          /* f(R): Hu-Sawicki n (eq:fR_HS): 0, 1 or 2 */
   double fr_fr0_abs; /* f(R): |f_R0| > 0 */
   double sym_a_star; /* symmetron: a_* (< a) */
   double sym_xi;     /* symmetron: xi = H0/m_* (xi c/H0 = Compton length) */

@@ -24,11 +24,13 @@ enum { FR = 0, SYM = 1, CQ = 2 };
 struct Consts {
   int model;
   int cq_keep_exp;
+  int fr_n;        // Hu-Sawicki n in {0, 1, 2}
+  int pad_;
   double ct2;      // c~^2
   double om_a;     // Omega_m / a
   double K;        // R-bar(a) a^2 / 3 = Omega_m/a + 4 Omega_L a^2
   double wbar;     // |f_R(a)|
-  double wpow;     // wbar^{1/2} (n = 1)
+  double wpow;     // wbar^{1/(n+1)}
   double s_ratio;  // (a_*/a)^3
   double s_amp;    // a^2 / (2 xi^2)
   double ubar;     // sqrt(1 - (a_*/a)^3)
@@ -154,6 +156,49 @@ __device__ __forceinline__ double cubic_root_pos64(double p, double q) {
   return t;
 }
 
+// Unique positive root of u^2 + p u + q = 0 with q < 0 (eq:fR_quadratic_solns),
+// in the rationalised form when p > 0 so that nothing cancels.
+template <typename T>
+__device__ __forceinline__ T quad_root_pos(T p, T q) {
+  T sq = d_sqrt(p * p - T(4) * q);
+  return p > T(0) ? T(-2) * q / (p + sq) : T(0.5) * (sq - p);
+}
+
+// Unique positive root of u^4 + p u + q = 0 with q < 0 (eq:fR_quartic_solns).
+// The closed form loses all digits when |p| << |q|^{3/4}; instead Newton runs
+// from an upper bound: f is convex for u > 0, so the iterates fall
+// monotonically to the root.  Bounds: (-2q)^{1/4} always; -q/p when p > 0
+// (then f(-q/p) = (q/p)^4 > 0); max((-2q)^{1/4}, (-2p)^{1/3}) when p < 0.
+template <typename T>
+__device__ __forceinline__ T quart_root_pos(T p, T q) {
+  T u = d_sqrt(d_sqrt(T(-2) * q));
+  if (p > T(0)) {
+    T b = -q / p;
+    if (b < u) u = b;
+  } else if (p < T(0)) {
+    T b = d_cbrt(T(-2) * p);
+    if (b > u) u = b;
+  }
+  for (int it = 0; it < 64; ++it) {
+    T u3 = u * u * u;
+    T f = u3 * u + p * u + q;
+    T fp = T(4) * u3 + p;
+    if (!(fp > T(0))) break;
+    T un = u - f / fp;
+    if (!(un < u)) break;  // the monotone sequence has stopped
+    u = un;
+  }
+  return u;
+}
+
+// w^{-1/(n+1)} of the f(R) nonlinearity
+template <typename T>
+__device__ __forceinline__ T fr_inv_root(int n, T w) {
+  if (n == 1) return d_rsqrt(w);
+  if (n == 0) return T(1) / w;
+  return T(1) / d_cbrt(w);
+}
+
 // ---------------------------------------------------------------------------
 // direct form: v <- exact per-cell solution of L^h(v)_c = S_c
 // ---------------------------------------------------------------------------
@@ -161,14 +206,19 @@ __device__ __forceinline__ double cubic_root_pos64(double p, double q) {
 template <int M, typename T>
 __device__ __forceinline__ T direct_update(const Consts& C, T h2, T vc, T sum, T dc, T sc) {
   if constexpr (M == FR) {
-    // u^3 + p u + q = 0, w = u^2 (eq:fR_eom_codeunit, n = 1; S shifts p)
+    // u^{n+2} + p u + q = 0, w = u^{n+1} (eq:fR_eom_codeunit; S shifts p)
     T g = h2 / (T(6) * T(C.ct2));
     T p = g * (T(C.om_a) * dc + T(C.K) - sc) - sum / T(6);
     T q = -g * T(C.K) * T(C.wpow);
-    T u;
-    if constexpr (sizeof(T) == 8) u = cubic_root_pos64(p, q);
-    else u = cubic_root<T>(p, q);
-    return u * u;
+    if (C.fr_n == 1) {
+      T u;
+      if constexpr (sizeof(T) == 8) u = cubic_root_pos64(p, q);
+      else u = cubic_root<T>(p, q);
+      return u * u;
+    }
+    if (C.fr_n == 0) return quad_root_pos<T>(p, q);
+    T u = quart_root_pos<T>(p, q);
+    return u * u * u;
   } else if constexpr (M == SYM) {
     // u^3 + p u + q = 0 (eq:sym_cubic_eqn; S shifts q)
     T kap = T(C.ct2) / (T(C.s_amp) * h2);
@@ -200,7 +250,8 @@ template <int M, typename T>
 __device__ __forceinline__ T direct_resid(const Consts& C, T h2, T vc, T sum, T dc, T sc) {
   T lap = (sum - T(6) * vc) / h2;
   if constexpr (M == FR) {
-    return -T(C.ct2) * lap + T(C.om_a) * dc + T(C.K) - T(C.K) * T(C.wpow) * d_rsqrt(vc) - sc;
+    return -T(C.ct2) * lap + T(C.om_a) * dc + T(C.K) -
+           T(C.K) * T(C.wpow) * fr_inv_root<T>(C.fr_n, vc) - sc;
   } else if constexpr (M == SYM) {
     return T(C.ct2) * lap - T(C.s_amp) * (((T(1) + dc) * T(C.s_ratio) - T(1)) * vc + vc * vc * vc) - sc;
   } else {
@@ -219,12 +270,18 @@ __device__ __forceinline__ T direct_resid(const Consts& C, T h2, T vc, T sum, T 
 template <int M>
 __device__ __forceinline__ float corr_nl(const Consts& C, float e, float x, float dc) {
   if constexpr (M == FR) {
-    // K wbar^{1/2} [x^{-1/2} - (x+e)^{-1/2}] = A [1 - (1+t)^{-1/2}], t = e/x
-    //   = A t / (s (1 + s)), s = sqrt(1+t)
+    // K wbar^m [x^{-m} - (x+e)^{-m}] = A [1 - (1+t)^{-m}], m = 1/(n+1),
+    // t = e/x, A = K wbar^m x^{-m}; written without cancellation:
+    //   n = 0: A t/(1+t);  n = 1: A t/(s(1+s)), s = sqrt(1+t);
+    //   n = 2: A t/(c(c^2+c+1)), c = cbrt(1+t)
     float t = e / x;
-    float s = sqrtf(1.0f + t);
-    float A = C.f_kw * rsqrtf(x);
-    return A * t / (s * (1.0f + s));
+    if (C.fr_n == 1) {
+      float s = sqrtf(1.0f + t);
+      return C.f_kw * rsqrtf(x) * t / (s * (1.0f + s));
+    }
+    if (C.fr_n == 0) return C.f_kw / x * t / (1.0f + t);
+    float c = cbrtf(1.0f + t);
+    return C.f_kw / cbrtf(x) * t / (c * ((c + 1.0f) * c + 1.0f));
   } else if constexpr (M == SYM) {
     // -s_amp [ (rho a*^3/a^3 - 1 + 3x^2) e + 3x e^2 + e^3 ]
     float m = (1.0f + dc) * C.f_s_ratio - 1.0f + 3.0f * x * x;
@@ -255,28 +312,53 @@ template <int M>
 __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec_old, float sum,
                                              float x, float dc, float rho) {
   if constexpr (M == FR) {
-    // D x t + A [1 - (1+t)^{-1/2}] = R,  D = 6c^2/h^2, R = rho + c^2 sum / h^2
-    // s = sqrt(1+t):  s^3 + (beta - 1 - gamma) s - beta = 0,
+    // D x t + A [1 - (1+t)^{-m}] = R,  D = 6c^2/h^2, R = rho + c^2 sum / h^2,
+    // m = 1/(n+1).  With s = (1+t)^m:  s^{n+2} + (beta - 1 - gamma) s - beta = 0,
     //   beta = A / (D x), gamma = R / (D x);  sigma = s - 1 solves
-    //   sigma^3 + 3 sigma^2 + (2 + beta - gamma) sigma - gamma = 0.
+    //   (1+sigma)^{n+2} - 1 + (beta - 1 - gamma) sigma - gamma = 0,
+    //   whose linear coefficient is c1 = n + 1 + beta - gamma.
+    const int n = C.fr_n;
     float iD = h2 * (1.0f / 6.0f) / C.f_ct2;  // h^2 / (6 c^2), a level constant
     float ix = __frcp_rn(x);
-    float beta = C.f_kw * iD * ix * sqrtf(ix);
+    float xm = n == 1 ? ix * sqrtf(ix) : (n == 0 ? ix * ix : ix * cbrtf(ix));  // x^{-(m+1)}
+    float beta = C.f_kw * iD * xm;
     float gamma = (rho * iD + sum * (1.0f / 6.0f)) * ix;
-    float c1 = 2.0f + beta - gamma;
+    float c1 = float(n + 1) + beta - gamma;
     float sg;
     if (fabsf(gamma) < 1e-2f * c1) {
       sg = __fdividef(gamma, c1);  // small correction: linear guess, Newton below
-    } else {
+    } else if (n == 1) {
       sg = cubic_root_approx(beta - 1.0f - gamma, -beta) - 1.0f;
+    } else if (n == 0) {
+      sg = quad_root_pos<float>(beta - 1.0f - gamma, -beta) - 1.0f;
+    } else {
+      sg = quart_root_pos<float>(beta - 1.0f - gamma, -beta) - 1.0f;
+    }
+    if (n == 1) {
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        float f = ((sg + 3.0f) * sg + c1) * sg - gamma;
+        float fp = (3.0f * sg + 6.0f) * sg + c1;
+        sg -= __fdividef(f, fp);
+      }
+      return x * sg * (sg + 2.0f);
+    }
+    if (n == 0) {
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        float f = (sg + c1) * sg - gamma;
+        float fp = 2.0f * sg + c1;
+        sg -= __fdividef(f, fp);
+      }
+      return x * sg;
     }
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
-      float f = ((sg + 3.0f) * sg + c1) * sg - gamma;
-      float fp = (3.0f * sg + 6.0f) * sg + c1;
+      float f = (((sg + 4.0f) * sg + 6.0f) * sg + c1) * sg - gamma;
+      float fp = ((4.0f * sg + 12.0f) * sg + 12.0f) * sg + c1;
       sg -= __fdividef(f, fp);
     }
-    return x * sg * (sg + 2.0f);
+    return x * sg * ((sg + 3.0f) * sg + 3.0f);
   } else if constexpr (M == SYM) {
     // e^3 + 3x e^2 + P e + Q = 0, P = m + 6 kap, Q = rho/s_amp - kap sum,
     // m = (1+delta) a*^3/a^3 - 1 + 3x^2, kap = c^2/(s_amp h^2)
@@ -355,8 +437,10 @@ __host__ __device__ __forceinline__ double lin_sign(const Consts& C) {
 template <int M>
 __device__ __forceinline__ double lin_dg(const Consts& C, double v, double dc) {
   if constexpr (M == FR) {
-    // K wbar^{1/2} w^{-3/2} / 2
-    return 0.5 * C.K * C.wpow * pow(v, -1.5);
+    // m K wbar^m w^{-m-1}, m = 1/(n+1)
+    if (C.fr_n == 1) return 0.5 * C.K * C.wpow * pow(v, -1.5);
+    if (C.fr_n == 0) return C.K * C.wpow / (v * v);
+    return C.K * C.wpow / 3.0 * pow(v, -4.0 / 3.0);
   } else if constexpr (M == SYM) {
     return C.s_amp * (((1.0 + dc) * C.s_ratio - 1.0) + 3.0 * v * v);
   } else {

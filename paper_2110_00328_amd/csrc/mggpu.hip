@@ -282,14 +282,15 @@ int make_consts(mg_ctx* ctx, int model, const mg_model_params* P, int n, Consts*
   C.ct2 = ct * ct;
   C.om_a = om / a;
   if (model == MG_FR) {
-    if (P->fr_n != 1) return fail(ctx, MG_EINVAL, "f(R): the library solves n = 1");
+    if (P->fr_n < 0 || P->fr_n > 2) return fail(ctx, MG_EINVAL, "f(R): n must be 0, 1 or 2");
     if (!(P->fr_fr0_abs > 0.0)) return fail(ctx, MG_EINVAL, "f(R): |f_R0| must be > 0");
     // R-bar(a)/H0^2 = 3 (Om a^-3 + 4 OL); K = R-bar a^2 / 3
     double ra = om / (a * a * a) + 4.0 * ol;
     C.K = ra * a * a;
     double ratio = (om + 4.0 * ol) / ra;  // R-bar_0 / R-bar(a)
-    C.wbar = P->fr_fr0_abs * ratio * ratio;
-    C.wpow = sqrt(C.wbar);
+    C.fr_n = P->fr_n;
+    C.wbar = P->fr_fr0_abs * pow(ratio, double(P->fr_n + 1));
+    C.wpow = pow(C.wbar, 1.0 / double(P->fr_n + 1));
     C.phi5 = 0.5 * C.ct2;
     C.bg = C.wbar;
     C.bg_coef = C.om_a;

@@ -19,13 +19,16 @@ CH = oracle.C_OVER_H0
 
 def _boxes():
     spec = [(16, "fr", 1e-5), (24, "sym", 1.0), (32, "fr", 1e-6), (16, "sym", 0.7),
-            (24, "fr", 3e-5), (32, "cq", None), (40, "fr", 1e-5)]
+            (24, "fr", 3e-5), (32, "cq", None), (40, "fr", 1e-5), (24, "fr0", 1e-5),
+            (32, "fr2", 1e-5)]
     out = []
     for q, (n, model, par) in enumerate(spec):
         d = synthetic.lognormal_delta(n, 900 + q, sigma_delta=1.5).astype(np.float32)
-        if model == "fr":
-            prm = api.model_params(float(n), fr0=par)
-            P = oracle.params(oracle.FR, n, float(n), fr0=par)
+        if model.startswith("fr"):
+            fr_n = int(model[2:]) if len(model) > 2 else 1
+            model = "fr"
+            prm = api.model_params(float(n), fr0=par, fr_n=fr_n)
+            P = oracle.params(oracle.FR, n, float(n), fr0=par, fr_n=fr_n)
         elif model == "sym":
             prm = api.model_params(float(n), a_star=0.5, xi=1.0 / CH, beta_star=par)
             P = oracle.params(oracle.SYM, n, float(n), a_star=0.5, xi=1.0 / CH, beta_star=par)
@@ -67,7 +70,7 @@ def test_batched_matches_single_box_solves(tmp_path, monkeypatch):
         assert err < 1e-6 and gerr < 1e-6
         single.close()
     # two boxes against the oracle
-    for q in (0, 1):
+    for q in (0, 1, 7, 8):
         b = boxes[q]
         ref, _, _, _ = oracle.solve(b["P"], b["delta_np"].astype(np.float64), tol=1e-12)
         ref = -ref if b["model"] == "fr" else ref

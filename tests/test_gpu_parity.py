@@ -241,3 +241,65 @@ def test_adjoint_matches_oracle(model, prec):
     say(f"  outer={st.cycles} rel={st.rel_resid:.2e} grad_err={err:.2e}")
     assert err < (1e-8 if prec == "fp64" else 1e-5)
     mg.close()
+
+
+# --- f(R) with n = 0 and n = 2 (quadratic and quartic per-cell roots) ------
+def cfg_n(fr_n, n, box):
+    return (oracle.params(oracle.FR, n, box, fr_n=fr_n, fr0=1e-5),
+            api.model_params(box, fr_n=fr_n, fr0=1e-5))
+
+
+@pytest.mark.parametrize("fr_n", [0, 2])
+def test_fr_n_halfsweep_matches_oracle(fr_n):
+    n, box = 32, 32.0
+    say("halfsweep fr n =", fr_n)
+    P, prm = cfg_n(fr_n, n, box)
+    delta = lognormal(n, 13)
+    bg = oracle.background(P)
+    v0 = bg * np.random.default_rng(14).uniform(0.5, 1.5, (n, n, n))
+    mg = api.Context(n, device=DEV)
+    f = torch.from_numpy(-v0).to(DEV)
+    dd = torch.from_numpy(delta).to(DEV)
+    ref = v0.copy()
+    for colour in (0, 1, 0):
+        mg.relax_halfsweep("fr", prm, dd, f, colour)
+        ref = oracle.relax_colour(P, delta.astype(np.float64), ref, colour)
+        got = -f.cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref)), (fr_n, colour)
+    mg.close()
+
+
+@pytest.mark.parametrize("fr_n", [0, 2])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fr_n_solve_force_adjoint_match_oracle(fr_n, prec):
+    n, box = 40, 40.0  # 4 levels down to 10^3, ragged last block
+    say("fr n =", fr_n, prec)
+    P, prm = cfg_n(fr_n, n, box)
+    delta = lognormal(n, 43, sig=1.2)
+    d64 = delta.astype(np.float64)
+    ref, _, _, _ = oracle.solve(P, d64, tol=1e-13)
+    mg = api.Context(n, device=DEV)
+    tol = 1e-11 if prec == "fp64" else 1e-9
+    field, st = mg.solve("fr", prm, torch.from_numpy(delta).to(DEV), tol=tol,
+                         opts=api.solver_opts(precision=prec))
+    err = field_err("fr", field.cpu().numpy(), -ref, P)
+    g = mg.force("fr", prm, field).cpu().numpy().astype(np.float64)
+    g_ref = oracle.force(P, ref)
+    gerr = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    say(f"  solve: cycles={st.cycles} rel={st.rel_resid:.2e} field_err={err:.2e} force_err={gerr:.2e}")
+    lim = 1e-8 if prec == "fp64" else 1e-6
+    assert err < lim and gerr < max(lim, 1e-6)
+    # adjoint of a force loss at the oracle's solution
+    fref = torch.from_numpy(-ref).to(DEV)
+    cells = np.random.default_rng(44).choice(n ** 3, 400, replace=False)
+    _, gforce = mg.loss_force_sq(mg.force("fr", prm, fref), torch.from_numpy(cells).to(DEV))
+    gfield = mg.force_adjoint("fr", prm, fref, gforce)
+    gv_ora = oracle.force_adjoint(P, ref, gforce.cpu().numpy().astype(np.float64))
+    gd, sa = mg.solve_adjoint("fr", prm, torch.from_numpy(delta).to(DEV), fref, gfield,
+                              tol=1e-11 if prec == "fp64" else 1e-8,
+                              opts=api.solver_opts(precision=prec))
+    gd_ora, _, _ = oracle.adjoint(P, d64, ref, gv_ora, tol=1e-13)
+    aerr = np.linalg.norm(gd.cpu().numpy() - gd_ora) / np.linalg.norm(gd_ora)
+    say(f"  adjoint: outer={sa.cycles} rel={sa.rel_resid:.2e} grad_err={aerr:.2e}")
+    assert aerr < (1e-8 if prec == "fp64" else 1e-5)
+    mg.close()
