@@ -173,7 +173,8 @@ __device__ __noinline__ bool b_down(const BoxDev& B, Team T, int l, bool rx) {
   if (B.vec && (Lc.n % 4) == 0) {
     for (uint32_t g4 = T.gtid; g4 < (uint32_t)(2 * Lc.half / 4); g4 += T.gnt)
       op_resid_restrict_corr_v<M>(Lf, Lc, B.e[l], B.X[l], B.dens[l], B.rho[l], B.h2[l],
-                                  B.e[l + 1], B.eR[l + 1], B.rho[l + 1], XH, B.C, g4);
+                                  B.e[l + 1], B.eR[l + 1], B.rho[l + 1], XH, B.C,
+                                  (M != CQ && B.nu1 > 0) ? 1 : 0, g4);
   } else {
     for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
       op_resid_restrict_corr<M>(Lf, Lc, B.e[l], B.X[l], B.dens[l], B.rho[l], B.h2[l], B.e[l + 1],
@@ -186,15 +187,17 @@ __device__ __noinline__ bool b_down(const BoxDev& B, Team T, int l, bool rx) {
   return team_sync(T);
 }
 
+template <int M>
 __device__ __noinline__ bool b_up(const BoxDev& B, Team T, int l) {
   const Lev Lf = B.L[l], Lc = B.L[l + 1];
-  for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
-    B.eR[l + 1][g] = B.e[l + 1][g] - B.eR[l + 1][g];
-  if (!team_sync(T)) return false;
   if (B.vec && (Lc.n % 4) == 0) {
+    // e += P(e_H - R e) in one pass; colour 0 too only for CQ's Newton smoother
     for (uint32_t g4 = T.gtid; g4 < (uint32_t)(2 * Lc.half / 4); g4 += T.gnt)
-      op_prolong_v<float>(Lf, Lc, B.e[l], B.eR[l + 1], g4);
+      op_prolong_v<float, M == CQ ? 0 : 1>(Lf, Lc, B.e[l], B.e[l + 1], B.eR[l + 1], g4);
   } else {
+    for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
+      B.eR[l + 1][g] = B.e[l + 1][g] - B.eR[l + 1][g];
+    if (!team_sync(T)) return false;
     for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
       op_prolong_block<float>(Lf, Lc, B.e[l], B.eR[l + 1], g);
   }
@@ -249,7 +252,7 @@ template <int M>
 __device__ bool b_run_op(const BoxDev& B, const Team& V, const Op& op, bool rx, double* sh) {
   if (op.kind == OP_SMOOTH) return b_smooth<M>(B, V, op.lev, op.count);
   if (op.kind == OP_DOWN) return b_down<M>(B, V, op.lev, rx);
-  if (op.kind == OP_UP) return b_up(B, V, op.lev);
+  if (op.kind == OP_UP) return b_up<M>(B, V, op.lev);
   b_coarsest<M>(B, op.lev, sh);
   return true;
 }

@@ -266,6 +266,44 @@ __device__ __forceinline__ T direct_resid(const Consts& C, T h2, T vc, T sum, T 
 // ---------------------------------------------------------------------------
 // correction form (FP32): G(e)_c = F(x+e)_c - F(x)_c, solve G_c = rho_c
 // ---------------------------------------------------------------------------
+// expm1 and log1p for the tiny arguments of the correction form: the cubic
+// Taylor polynomial below |z| < 1e-3 (relative error < 5e-11), the library
+// function above.
+__device__ __forceinline__ float expm1_small(float z) {
+  return fabsf(z) < 1e-3f ? z * (1.0f + z * (0.5f + z * (1.0f / 6.0f))) : expm1f(z);
+}
+__device__ __forceinline__ float log1p_small(float z) {
+  return fabsf(z) < 1e-3f ? z * (1.0f - z * (0.5f - z * (1.0f / 3.0f))) : log1pf(z);
+}
+
+// Coupled quintessence (eq:csf_eom_code) per cell, correction form: the
+// change N(x+e) - N(x) of the non-Laplacian part, accurate relative to e, and
+// its derivative dN/dv at x+e.  With Y = phibar + x/c^2, u = e/(c^2 Y),
+// E1 = expm1(beta e/c^2), E2 = expm1(-(1+alpha) log1p(u)):
+//   N(x+e) - N(x) = -src exp(beta x/c^2)(1+delta) E1 + pot Y^{-(1+alpha)} E2
+//   dN/dv(x+e)    = -src (beta/c^2) exp(beta x/c^2)(1+E1)(1+delta)
+//                   - pot ((1+alpha)/c^2) Y^{-(2+alpha)} (1+E2)/(1+u)
+// The prefactors use the hardware exp/log (relative error ~1e-6, a scale
+// factor only); the differences use expm1_small / log1p_small.
+__device__ __forceinline__ void cq_corr_terms(const Consts& C, float x, float e, float dc,
+                                              float* dn, float* dnp) {
+  const float ict2 = 1.0f / C.f_ct2;
+  const float a1 = 1.0f + C.f_alpha;
+  const float Y = C.f_phibar + x * ict2;
+  const float PX = __expf(-a1 * __logf(Y));  // Y^{-(1+alpha)}
+  const float u = e * ict2 / Y;
+  const float E2 = expm1_small(-a1 * log1p_small(u));
+  float src = 0.0f, dsrc = 0.0f;
+  if (C.cq_keep_exp) {
+    const float ex = __expf(C.f_beta * x * ict2) * (1.0f + dc);
+    const float E1 = expm1_small(C.f_beta * e * ict2);
+    src = ex * E1;
+    dsrc = C.f_beta * ict2 * ex * (1.0f + E1);
+  }
+  *dn = -C.f_cq_src * src + C.f_cq_pot * PX * E2;
+  *dnp = -C.f_cq_src * dsrc - C.f_cq_pot * a1 * ict2 * (PX / Y) * (1.0f + E2) / (1.0f + u);
+}
+
 // Nonlinear part N(x+e) - N(x) of each model, accurate relative to e.
 template <int M>
 __device__ __forceinline__ float corr_nl(const Consts& C, float e, float x, float dc) {
@@ -287,12 +325,9 @@ __device__ __forceinline__ float corr_nl(const Consts& C, float e, float x, floa
     float m = (1.0f + dc) * C.f_s_ratio - 1.0f + 3.0f * x * x;
     return -C.f_s_amp * (m + (3.0f * x + e) * e) * e;
   } else {
-    float ct2 = C.f_ct2;
-    float ex = C.cq_keep_exp ? expf(C.f_beta * x / ct2) : 1.0f;
-    float src = C.cq_keep_exp ? ex * expm1f(C.f_beta * e / ct2) * (1.0f + dc) : 0.0f;
-    float Y = C.f_phibar + x / ct2;
-    float pot = powf(Y, -(1.0f + C.f_alpha)) * expm1f(-(1.0f + C.f_alpha) * log1pf(e / (ct2 * Y)));
-    return -C.f_cq_src * src + C.f_cq_pot * pot;
+    float dn, dnp;
+    cq_corr_terms(C, x, e, dc, &dn, &dnp);
+    return dn;
   }
 }
 
@@ -383,12 +418,10 @@ __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec
     return e;
   } else {
     // Newton-Gauss-Seidel (eq:relaxation_iteration) on the correction
-    float ct2 = C.f_ct2;
-    float G = corr_G<M>(C, h2, ec_old, sum, x, dc) - rho;
-    float ex = C.cq_keep_exp ? expf(C.f_beta * (x + ec_old) / ct2) : 0.0f;
-    float Y = C.f_phibar + (x + ec_old) / ct2;
-    float dG = -6.0f / h2 - C.f_cq_src * C.f_beta / ct2 * ex * (1.0f + dc) -
-               C.f_cq_pot * (1.0f + C.f_alpha) / ct2 * powf(Y, -(2.0f + C.f_alpha));
+    float dn, dnp;
+    cq_corr_terms(C, x, ec_old, dc, &dn, &dnp);
+    float G = (sum - 6.0f * ec_old) / h2 + dn - rho;
+    float dG = -6.0f / h2 + dnp;
     return ec_old - G / dG;
   }
 }
@@ -397,12 +430,10 @@ __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec
 // mode Newton step of the coarsest CQ level)
 template <int M>
 __device__ __forceinline__ float corr_diag(const Consts& C, float h2, float ec, float x, float dc) {
-  float ct2 = C.f_ct2;
   if constexpr (M == CQ) {
-    float ex = C.cq_keep_exp ? expf(C.f_beta * (x + ec) / ct2) : 0.0f;
-    float Y = C.f_phibar + (x + ec) / ct2;
-    return -6.0f / h2 - C.f_cq_src * C.f_beta / ct2 * ex * (1.0f + dc) -
-           C.f_cq_pot * (1.0f + C.f_alpha) / ct2 * powf(Y, -(2.0f + C.f_alpha));
+    float dn, dnp;
+    cq_corr_terms(C, x, ec, dc, &dn, &dnp);
+    return -6.0f / h2 + dnp;
   } else {
     return 1.0f;
   }

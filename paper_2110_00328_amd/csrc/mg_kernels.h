@@ -743,15 +743,19 @@ __global__ __launch_bounds__(kBlock) void k_outer_fused_v(Lev L, const double* w
 // Fused FP64 outer step of the adjoint: lam_new = lam + e (e may be null),
 // r = b - A lam_new -> r (inner precision), e_zero = 0; sum of r^2
 template <typename TO>
+// lam_new = lam + e + shift (a uniform shift; the Laplacian of a constant
+// vanishes, so only the diagonal term sees it).  part_sum (optional) gets the
+// partial sums of r itself.
 __global__ __launch_bounds__(kBlock) void k_lin_outer_fused_v(Lev L, const double* lam,
                                                               const TO* e, double* lam_new,
                                                               const double* dg, const double* b,
                                                               double kh2, TO* r, TO* e_zero,
-                                                              double* part) {
+                                                              double* part, double shift,
+                                                              double* part_sum) {
   constexpr int V = kVOuter;
   __shared__ double sh[32];
   uint32_t g4 = (uint32_t)gid();
-  double acc = 0.0;
+  double acc = 0.0, accs = 0.0;
   if (g4 < (uint32_t)(L.half / V)) {
     uint32_t g = g4 * V;
     int ih0, j, k;
@@ -768,7 +772,10 @@ __global__ __launch_bounds__(kBlock) void k_lin_outer_fused_v(Lev L, const doubl
         ldn<double, V>(lam + q0, lc);
         ldn<TO, V>(e + q0, ev);
 #pragma unroll
-        for (int q = 0; q < V; ++q) lc[q] += double(ev[q]);
+        for (int q = 0; q < V; ++q) {
+          lc[q] += double(ev[q]) + shift;
+          sum[q] += 6.0 * shift;
+        }
         stn<double, V>(lam_new + q0, lc);
       } else {
         nbsum_vec<double, V>(L, lam + (1 - c) * L.half, ih0, j, k, s, sum);
@@ -780,6 +787,7 @@ __global__ __launch_bounds__(kBlock) void k_lin_outer_fused_v(Lev L, const doubl
       for (int q = 0; q < V; ++q) {
         double d = bb[q] - (kh2 * (6.0 * lc[q] - sum[q]) + dd[q] * lc[q]);
         acc += d * d;
+        accs += d;
         ro[q] = TO(d);
         zo[q] = TO(0);
       }
@@ -789,6 +797,10 @@ __global__ __launch_bounds__(kBlock) void k_lin_outer_fused_v(Lev L, const doubl
   }
   double t = block_sum(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (part_sum) {
+    t = block_sum(accs, sh);
+    if (threadIdx.x == 0) part_sum[blockIdx.x] = t;
+  }
 }
 
 // residual norm of the finest level (FP64 direct form), both colours per thread
@@ -828,10 +840,15 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm_v(Lev L, const double* v,
 // are the fine packed cells ih = I0 .. I0+V-1 of both colours in the four
 // rows (2J+b, 2K+d), read and written with 16-byte accesses.
 // ---------------------------------------------------------------------------
-// v^h += P c (27/9/3/1 trilinear, separable over the coarse neighbourhood)
-template <typename T>
+// v^h += P (c - c2) (27/9/3/1 trilinear, separable over the coarse
+// neighbourhood; c2 may be null).  Only fine colours COL0..1 are written:
+// before a smoother that solves each cell exactly (f(R), symmetron, the
+// linear adjoint), the first post-smoothing half-sweep overwrites colour 0
+// without reading its old value, so its prolongation is not needed.
+template <typename T, int COL0>
 __device__ __forceinline__ void op_prolong_v(const Lev& Lf, const Lev& Lc, T* __restrict__ v,
-                                             const T* __restrict__ c, uint32_t g4) {
+                                             const T* __restrict__ c, const T* __restrict__ c2,
+                                             uint32_t g4) {
   constexpr int V = Vec<T>::V;
   int I0, J, K;
   dec_nat(g4 * V, Lc, I0, J, K);
@@ -845,11 +862,17 @@ __device__ __forceinline__ void op_prolong_v(const Lev& Lf, const Lev& Lc, T* __
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
       T cx[V + 2];
+      uint32_t pc[V + 2];
 #pragma unroll
       for (int q = 0; q < V + 2; ++q) {
         int I = I0 - 1 + q;
         I = I < 0 ? I + nc : (I >= nc ? I - nc : I);
-        cx[q] = c[pk_of(Lc, I, Js[b], Ks[d])];
+        pc[q] = pk_of(Lc, I, Js[b], Ks[d]);
+        cx[q] = c[pc[q]];
+      }
+      if (c2) {
+#pragma unroll
+        for (int q = 0; q < V + 2; ++q) cx[q] -= c2[pc[q]];
       }
 #pragma unroll
       for (int q = 0; q < V; ++q) {
@@ -864,7 +887,7 @@ __device__ __forceinline__ void op_prolong_v(const Lev& Lf, const Lev& Lc, T* __
       const int j = 2 * J + y, k = 2 * K + z;
       const uint32_t row = prow(Lf, j, k) + (uint32_t)I0;
 #pragma unroll
-      for (int col = 0; col < 2; ++col) {
+      for (int col = COL0; col < 2; ++col) {
         const int x = (col + j + k) & 1;  // child parity of this colour in the row
         T* dst = v + (uint32_t)col * (uint32_t)Lf.half + row;
         T cur[V];
@@ -881,19 +904,22 @@ __device__ __forceinline__ void op_prolong_v(const Lev& Lf, const Lev& Lc, T* __
       }
     }
 }
-template <typename T>
+template <typename T, int COL0>
 __global__ __launch_bounds__(kBlock) void k_prolong_v(Lev Lf, Lev Lc, T* __restrict__ v,
-                                                      const T* __restrict__ c) {
+                                                      const T* __restrict__ c,
+                                                      const T* __restrict__ c2) {
   uint32_t g4 = (uint32_t)gid();
-  if (g4 < (uint32_t)(2 * Lc.half / Vec<T>::V)) op_prolong_v<T>(Lf, Lc, v, c, g4);
+  if (g4 < (uint32_t)(2 * Lc.half / Vec<T>::V)) op_prolong_v<T, COL0>(Lf, Lc, v, c, c2, g4);
 }
 
-// correction form: Re -> eH and eR, R(G(e) - rho) -> rhoH, optionally R X -> XH
+// correction form: Re -> eH and eR, R(G(e) - rho) -> rhoH, optionally R X -> XH.
+// skip1: colour 1 was the last half-sweep of an exact per-cell smoother, so
+// its residual vanishes (to rounding) and is not recomputed.
 template <int M>
 __device__ __forceinline__ void op_resid_restrict_corr_v(
     const Lev& Lf, const Lev& Lc, const float* __restrict__ e, const float* __restrict__ X,
     const float* __restrict__ dens, const float* __restrict__ rho, float h2, float* eH, float* eR,
-    float* rhoH, float* XH, const Consts& C, uint32_t g4) {
+    float* rhoH, float* XH, const Consts& C, int skip1, uint32_t g4) {
   constexpr int V = Vec<float>::V;
   int I0, J, K;
   dec_nat(g4 * V, Lc, I0, J, K);
@@ -907,8 +933,18 @@ __device__ __forceinline__ void op_resid_restrict_corr_v(
       for (int col = 0; col < 2; ++col) {
         const uint32_t q0 = (uint32_t)col * (uint32_t)Lf.half + prow(Lf, j, k) + (uint32_t)I0;
         float sum[V], ec[V], x[V], r[V], dc[V] = {0, 0, 0, 0};
-        nbsum_vec<float>(Lf, e + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
         ldv<float>(e + q0, ec);
+        if (col == 1 && skip1) {
+#pragma unroll
+          for (int q = 0; q < V; ++q) se[q] += ec[q];
+          if (XH) {
+            ldv<float>(X + q0, x);
+#pragma unroll
+            for (int q = 0; q < V; ++q) sx[q] += x[q];
+          }
+          continue;
+        }
+        nbsum_vec<float>(Lf, e + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
         ldv<float>(X + q0, x);
         ldv<float>(rho + q0, r);
         if (M != FR) ldv<float>(dens + q0, dc);
@@ -934,17 +970,18 @@ template <int M>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_v(
     Lev Lf, Lev Lc, const float* __restrict__ e, const float* __restrict__ X,
     const float* __restrict__ dens, const float* __restrict__ rho, float h2, float* eH, float* eR,
-    float* rhoH, float* XH, Consts C) {
+    float* rhoH, float* XH, Consts C, int skip1) {
   uint32_t g4 = (uint32_t)gid();
   if (g4 < (uint32_t)(2 * Lc.half / Vec<float>::V))
-    op_resid_restrict_corr_v<M>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, g4);
+    op_resid_restrict_corr_v<M>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, skip1, g4);
 }
 
 // direct form: R v -> Rv and vinit, R(L(v) - S) -> Sd
 template <int M, typename TD>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict_direct_v(
     Lev Lf, Lev Lc, const double* __restrict__ v, const TD* __restrict__ dens,
-    const double* __restrict__ S, double h2, double* Rv, double* vinit, double* Sd, Consts C) {
+    const double* __restrict__ S, double h2, double* Rv, double* vinit, double* Sd, Consts C,
+    int skip1) {
   constexpr int V = Vec<double>::V;
   uint32_t g4 = (uint32_t)gid();
   if (g4 >= (uint32_t)(2 * Lc.half / V)) return;
@@ -960,8 +997,13 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_direct_v(
       for (int col = 0; col < 2; ++col) {
         const uint32_t q0 = (uint32_t)col * (uint32_t)Lf.half + prow(Lf, j, k) + (uint32_t)I0;
         double sum[V], vc[V], sc[V] = {0, 0};
-        nbsum_vec<double>(Lf, v + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
         ldv<double>(v + q0, vc);
+        if (col == 1 && skip1) {  // residual of the last exact half-sweep: zero
+#pragma unroll
+          for (int q = 0; q < V; ++q) sv[q] += vc[q];
+          continue;
+        }
+        nbsum_vec<double>(Lf, v + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
         if (S) ldv<double>(S + q0, sc);
 #pragma unroll
         for (int q = 0; q < V; ++q) {
@@ -986,7 +1028,7 @@ __global__ __launch_bounds__(kBlock) void k_lin_resid_restrict_v(Lev Lf, Lev Lc,
                                                                  const T* __restrict__ e,
                                                                  const T* __restrict__ dg,
                                                                  const T* __restrict__ r, T kh2,
-                                                                 T* rH, T* eH) {
+                                                                 T* rH, T* eH, int skip1) {
   constexpr int V = Vec<T>::V;
   uint32_t g4 = (uint32_t)gid();
   if (g4 >= (uint32_t)(2 * Lc.half / V)) return;
@@ -1000,8 +1042,8 @@ __global__ __launch_bounds__(kBlock) void k_lin_resid_restrict_v(Lev Lf, Lev Lc,
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int j = 2 * J + b, k = 2 * K + d;
-#pragma unroll
-      for (int col = 0; col < 2; ++col) {
+      // skip1: colour 1 was the last (exact) half-sweep, its residual is zero
+      for (int col = 0; col < 2 - skip1; ++col) {
         const uint32_t q0 = (uint32_t)col * (uint32_t)Lf.half + prow(Lf, j, k) + (uint32_t)I0;
         T sum[V], ec[V], dd[V], rr[V];
         nbsum_vec<T>(Lf, e + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
@@ -1164,7 +1206,7 @@ __global__ __launch_bounds__(kBlock) void k_lin_resid_restrict(Lev Lf, Lev Lc, c
 template <typename TO>
 __global__ __launch_bounds__(kBlock) void k_lin_outer(Lev L, const double* lam, const double* dg,
                                                       const double* b, double kh2, TO* r,
-                                                      TO* e, double* part) {
+                                                      TO* e, double* part, double* part_sum) {
   __shared__ double sh[32];
   int64_t g = gid();
   double d = 0.0;
@@ -1175,6 +1217,24 @@ __global__ __launch_bounds__(kBlock) void k_lin_outer(Lev L, const double* lam, 
   }
   double t = block_sum(d * d, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (part_sum) {
+    t = block_sum(d, sh);
+    if (threadIdx.x == 0) part_sum[blockIdx.x] = t;
+  }
+}
+// partial sums of a[g] * b[g] (b null: of a[g])
+template <typename TA>
+__global__ __launch_bounds__(kBlock) void k_dot(int64_t m, const TA* a, const double* b,
+                                                double* part) {
+  __shared__ double sh[32];
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double d = g < m ? double(a[g]) * (b ? b[g] : 1.0) : 0.0;
+  double t = block_sum(d, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+__global__ __launch_bounds__(kBlock) void k_add_const(int64_t m, double* y, double c) {
+  int64_t g = gid();
+  if (g < m) y[g] += c;
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sq_norm(int64_t m, const T* x, double* part) {

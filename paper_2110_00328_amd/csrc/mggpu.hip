@@ -83,6 +83,7 @@ struct mg_ctx {
   WorkAdj adj;
   double* part = nullptr;
   double* part2 = nullptr;
+  double* part3 = nullptr;     // second set of block partials (same capacity as part)
   int64_t part_cap = 0;
   double* scal = nullptr;      // device scalars
   double* hscal = nullptr;     // pinned host mirror
@@ -367,18 +368,19 @@ int plan_cycles(int fixed, double rel, double rel_prev, int k_prev, double tol) 
 // reductions to the host
 // ---------------------------------------------------------------------------
 // deterministic: fixed chunks summed by up to 256 blocks, then one block
-int sum_on_device(mg_ctx* ctx, int64_t nparts, double* dst) {
+int sum_on_device(mg_ctx* ctx, int64_t nparts, double* dst, const double* src = nullptr) {
   int64_t nb = (nparts + 2047) / 2048;
   if (nb > 256) nb = 256;
   int64_t chunk = (nparts + nb - 1) / nb;
-  k_sum_chunks<<<(unsigned)nb, 256, 0, ctx->stream>>>(ctx->part, nparts, chunk, ctx->part2);
+  k_sum_chunks<<<(unsigned)nb, 256, 0, ctx->stream>>>(src ? src : ctx->part, nparts, chunk,
+                                                      ctx->part2);
   k_sum_partials<<<1, 256, 0, ctx->stream>>>(ctx->part2, nb, dst, 0);
   LAUNCHCHK();
   return MG_OK;
 }
 
-int sum_to_host(mg_ctx* ctx, int64_t nparts, double* out) {
-  ACHK(sum_on_device(ctx, nparts, ctx->scal));
+int sum_to_host(mg_ctx* ctx, int64_t nparts, double* out, const double* src = nullptr) {
+  ACHK(sum_on_device(ctx, nparts, ctx->scal, src));
   HIPCHK(hipMemcpyAsync(ctx->hscal, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   *out = ctx->hscal[0];
@@ -493,15 +495,19 @@ int cycle64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   ACHK(smooth64<M>(ctx, C, l, o->nu_pre));
   const bool vec = Lc.n % Vec<double>::V == 0;
   const int64_t ncv = cells(Lc) / Vec<double>::V;
+  // f(R) and the symmetron solve each cell exactly: after a pre-smoothing
+  // sweep the colour updated last has zero residual
+  const int skip1 = (M != CQ && o->nu_pre > 0) ? 1 : 0;
   if (l == 0 && vec)
     k_resid_restrict_direct_v<M, float><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
-        Lf, Lc, W.v[0], W.dens0, (const double*)nullptr, 1.0, W.Rv[1], W.v[1], W.S[1], C);
+        Lf, Lc, W.v[0], W.dens0, (const double*)nullptr, 1.0, W.Rv[1], W.v[1], W.S[1], C, skip1);
   else if (l == 0)
     k_resid_restrict_direct<M, double, float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.v[0], W.dens0, (const double*)nullptr, 1.0, W.Rv[1], W.v[1], W.S[1], C);
   else if (vec)
     k_resid_restrict_direct_v<M, double><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
-        Lf, Lc, W.v[l], W.dens[l], W.S[l], lev_h2(l), W.Rv[l + 1], W.v[l + 1], W.S[l + 1], C);
+        Lf, Lc, W.v[l], W.dens[l], W.S[l], lev_h2(l), W.Rv[l + 1], W.v[l + 1], W.S[l + 1], C,
+        skip1);
   else
     k_resid_restrict_direct<M, double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.v[l], W.dens[l], W.S[l], lev_h2(l), W.Rv[l + 1], W.v[l + 1], W.S[l + 1], C);
@@ -517,13 +523,16 @@ int cycle64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
     ACHK(cycle64<M>(ctx, C, o, l + 1, MG_CYCLE_F));
     ACHK(cycle64<M>(ctx, C, o, l + 1, MG_CYCLE_V));
   }
-  k_coarse_diff<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(cells(Lc), W.v[l + 1],
-                                                                       W.Rv[l + 1]);
-  if (vec)
-    k_prolong_v<double><<<nblk(ncv), kBlock, 0, ctx->stream>>>(Lf, Lc, W.v[l], W.Rv[l + 1]);
-  else
+  if (vec) {
+    // v += P(v_H - R v); colour 0 only for the Newton (CQ) smoother
+    k_prolong_v<double, M == CQ ? 0 : 1><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, W.v[l], W.v[l + 1], W.Rv[l + 1]);
+  } else {
+    k_coarse_diff<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(cells(Lc), W.v[l + 1],
+                                                                         W.Rv[l + 1]);
     k_prolong_block<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.v[l],
                                                                            W.Rv[l + 1]);
+  }
   LAUNCHCHK();
   return smooth64<M>(ctx, C, l, o->nu_post);
 }
@@ -671,10 +680,13 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   ACHK(smooth32<M>(ctx, C, l, o->nu_pre));
   const bool vec = Lc.n % Vec<float>::V == 0;
   const int64_t ncv = cells(Lc) / Vec<float>::V;
+  // exact per-cell smoothers (f(R), symmetron): the colour swept last has
+  // zero residual
+  const int skip1 = (M != CQ && o->nu_pre > 0) ? 1 : 0;
   if (vec)
     k_resid_restrict_corr_v<M><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
-        W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C);
+        W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C, skip1);
   else
     k_resid_restrict_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
@@ -691,13 +703,16 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
     ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_F, rx));
     ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V, false));
   }
-  k_coarse_diff<float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(cells(Lc), W.e[l + 1],
-                                                                      W.eR[l + 1]);
-  if (vec)
-    k_prolong_v<float><<<nblk(ncv), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.eR[l + 1]);
-  else
+  if (vec) {
+    // e += P(e_H - R e); colour 0 too only for the Newton (CQ) smoother
+    k_prolong_v<float, M == CQ ? 0 : 1><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, W.e[l], W.e[l + 1], W.eR[l + 1]);
+  } else {
+    k_coarse_diff<float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(cells(Lc), W.e[l + 1],
+                                                                        W.eR[l + 1]);
     k_prolong_block<float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l],
                                                                           W.eR[l + 1]);
+  }
   LAUNCHCHK();
   return smooth32<M>(ctx, C, l, o->nu_post);
 }
@@ -854,9 +869,9 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
   smooth(o->nu_pre);
   const bool cvec = Lc.n % Vec<T>::V == 0;
   const int64_t ncv = cells(Lc) / Vec<T>::V;
-  if (cvec)
+  if (cvec)  // Gauss-Seidel on a linear system is exact per cell: skip colour 1
     k_lin_resid_restrict_v<T><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
-        Lf, Lc, W.e[l], W.dg[l], W.r[l], kh2, W.r[l + 1], W.e[l + 1]);
+        Lf, Lc, W.e[l], W.dg[l], W.r[l], kh2, W.r[l + 1], W.e[l + 1], o->nu_pre > 0 ? 1 : 0);
   else
     k_lin_resid_restrict<T><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.e[l], W.dg[l], W.r[l], kh2, W.r[l + 1], W.e[l + 1]);
@@ -871,7 +886,8 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
     ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_V));
   }
   if (cvec)
-    k_prolong_v<T><<<nblk(ncv), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1]);
+    k_prolong_v<T, 1><<<nblk(ncv), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1],
+                                                             (const T*)nullptr);
   else
     k_prolong_block<T><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1]);
   smooth(o->nu_post);
@@ -923,6 +939,19 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
   double rel = 0.0, rel_prev = -1.0;
   const bool vec = L0.nh % kVOuter == 0;
   const void* pending = nullptr;  // correction not yet added to lam
+  // Coupled quintessence: the constant vector is nearly a null vector of A
+  // (A 1 = dg, the tiny mass term), so rounding in the inner cycles leaves
+  // an inaccurate uniform mode.  Each outer step therefore adds the FP64
+  // Galerkin correction along 1, which zeroes sum(b - A lam) exactly:
+  //   lam += e + c,  c = (sum r - sum dg e) / sum dg.
+  const bool galerkin = C.model == CQ;
+  double sum_dg = 0.0, shift = 0.0, sum_r = 0.0;
+  if (galerkin) {
+    k_dot<double><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.dg, (const double*)nullptr, ctx->part3);
+    LAUNCHCHK();
+    ACHK(sum_to_host(ctx, nblk(m), &sum_dg, ctx->part3));
+  }
+  double* psum = galerkin && sum_dg > 0.0 ? ctx->part3 : nullptr;
   for (;;) {
     int64_t nparts = vec ? nblk(L0.half / kVOuter) : nblk(m);
     if (vec) {
@@ -931,11 +960,11 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
       if (f32)
         k_lin_outer_fused_v<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
             L0, A.lam, (const float*)pending, ln, A.dg, A.b, kap, A.w32.r[0], A.w32.ebuf[ez],
-            ctx->part);
+            ctx->part, shift, psum);
       else
         k_lin_outer_fused_v<double><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
             L0, A.lam, (const double*)pending, ln, A.dg, A.b, kap, A.w64.r[0], A.w64.ebuf[ez],
-            ctx->part);
+            ctx->part, shift, psum);
       if (pending) {
         cur = 1 - cur;
         eb = 1 - eb;
@@ -944,14 +973,19 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
         else A.w64.e[0] = A.w64.ebuf[eb];
         pending = nullptr;
       }
-    } else if (f32)
-      k_lin_outer<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-          L0, A.lam, A.dg, A.b, kap, A.w32.r[0], A.w32.e[0], ctx->part);
-    else
-      k_lin_outer<double><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-          L0, A.lam, A.dg, A.b, kap, A.w64.r[0], A.w64.e[0], ctx->part);
+    } else {
+      if (shift != 0.0) k_add_const<<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, shift);
+      if (f32)
+        k_lin_outer<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+            L0, A.lam, A.dg, A.b, kap, A.w32.r[0], A.w32.e[0], ctx->part, psum);
+      else
+        k_lin_outer<double><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+            L0, A.lam, A.dg, A.b, kap, A.w64.r[0], A.w64.e[0], ctx->part, psum);
+    }
+    shift = 0.0;
     LAUNCHCHK();
     double s;
+    if (psum) ACHK(sum_to_host(ctx, nparts, &sum_r, psum));
     ACHK(sum_to_host(ctx, nparts, &s));
     rel = sqrt(s) / bb;
     if (outer > 0 && st && outer - 1 < 64) st->resid_hist[outer - 1] = rel;
@@ -968,12 +1002,20 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
     int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol);
     if (f32) {
       for (int it = 0; it < k; ++it) ACHK(lin_cycle<float>(ctx, A.w32, kap, o, 0, o->cycle));
+      if (psum) k_dot<float><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.w32.e[0], A.dg, ctx->part3);
       if (vec) pending = A.w32.e[0];
       else k_axpy_to64<float><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w32.e[0]);
     } else {
       for (int it = 0; it < k; ++it) ACHK(lin_cycle<double>(ctx, A.w64, kap, o, 0, o->cycle));
+      if (psum) k_dot<double><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.w64.e[0], A.dg, ctx->part3);
       if (vec) pending = A.w64.e[0];
       else k_axpy_to64<double><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w64.e[0]);
+    }
+    if (psum) {
+      double dge;
+      LAUNCHCHK();
+      ACHK(sum_to_host(ctx, nblk(m), &dge, ctx->part3));
+      shift = (sum_r - dge) / sum_dg;
     }
     vc += k;
     rel_prev = rel;
@@ -1329,6 +1371,7 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
   ctx->part_cap = nblk((int64_t)n * n * n) + 16;
   int rc = dalloc(ctx, &ctx->part, ctx->part_cap);
   if (rc == MG_OK) rc = dalloc(ctx, &ctx->part2, 256);
+  if (rc == MG_OK) rc = dalloc(ctx, &ctx->part3, ctx->part_cap);
   if (rc == MG_OK) rc = dalloc(ctx, &ctx->scal, 16);
   if (rc == MG_OK) {
     void* h = nullptr;
@@ -1578,8 +1621,8 @@ int mg_prolong_add(mg_ctx* ctx, const double* coarse, double* fine) {
   k_pack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, fine, ctx->w64.v[0], 1.0);
   k_pack<double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lc, coarse, ctx->w64.v[1], 1.0);
   if (Lc.n % Vec<double>::V == 0)
-    k_prolong_v<double><<<nblk(cells(Lc) / Vec<double>::V), kBlock, 0, ctx->stream>>>(
-        Lf, Lc, ctx->w64.v[0], ctx->w64.v[1]);
+    k_prolong_v<double, 0><<<nblk(cells(Lc) / Vec<double>::V), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, ctx->w64.v[0], ctx->w64.v[1], (const double*)nullptr);
   else
     k_prolong_block<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, ctx->w64.v[0],
                                                                            ctx->w64.v[1]);
