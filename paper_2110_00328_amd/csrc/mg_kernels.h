@@ -604,12 +604,16 @@ __global__ __launch_bounds__(kBlock) void k_smooth_direct_v(Lev L, double* v, co
   stv<double>(own + g, out);
 }
 
+// fresh: first half-sweeps after an outer step, whose correction starts at
+// zero: the buffer is not cleared, the old values are taken as 0 instead
+// (colour 0: neighbours and own value; colour 1: own value).
 template <int M>
 __device__ __forceinline__ void op_smooth_corr_v(const Lev& L, float* __restrict__ e,
                                                  const float* __restrict__ X,
                                                  const float* __restrict__ dens,
                                                  const float* __restrict__ rho, int colour,
-                                                 float h2, const Consts& C, uint32_t g4) {
+                                                 float h2, const Consts& C, uint32_t g4,
+                                                 int fresh = 0) {
   constexpr int V = Vec<float>::V;
   uint32_t g = g4 * V;
   int ih0, j, k;
@@ -617,12 +621,12 @@ __device__ __forceinline__ void op_smooth_corr_v(const Lev& L, float* __restrict
   int s = (j + k + colour) & 1;
   float* own = e + colour * L.half;
   uint32_t q0 = (uint32_t)colour * (uint32_t)L.half + g;
-  float sum[V], x[V], r[V], dc[V] = {0, 0, 0, 0}, eo[V] = {0, 0, 0, 0}, out[V];
-  nbsum_vec<float>(L, e + (1 - colour) * L.half, ih0, j, k, s, sum);
+  float sum[V] = {0, 0, 0, 0}, x[V], r[V], dc[V] = {0, 0, 0, 0}, eo[V] = {0, 0, 0, 0}, out[V];
+  if (!(fresh && colour == 0)) nbsum_vec<float>(L, e + (1 - colour) * L.half, ih0, j, k, s, sum);
   ldv<float>(X + q0, x);
   ldv<float>(rho + q0, r);
   if (M != FR) ldv<float>(dens + q0, dc);
-  if (M == CQ) ldv<float>(own + g, eo);
+  if (M == CQ && !fresh) ldv<float>(own + g, eo);
 #pragma unroll
   for (int q = 0; q < V; ++q) out[q] = corr_update<M>(C, h2, eo[q], sum[q], x[q], dc[q], r[q]);
   stv<float>(own + g, out);
@@ -630,15 +634,17 @@ __device__ __forceinline__ void op_smooth_corr_v(const Lev& L, float* __restrict
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_smooth_corr_v(Lev L, float* e, const float* X,
                                                           const float* dens, const float* rho,
-                                                          int colour, float h2, Consts C) {
+                                                          int colour, float h2, Consts C,
+                                                          int fresh) {
   uint32_t g4 = (uint32_t)gid();
   if (g4 < (uint32_t)(L.half / Vec<float>::V))
-    op_smooth_corr_v<M>(L, e, X, dens, rho, colour, h2, C, g4);
+    op_smooth_corr_v<M>(L, e, X, dens, rho, colour, h2, C, g4, fresh);
 }
 
 template <typename T>
+// fresh (colour 0 only): the correction starts at zero, neighbours are 0
 __global__ __launch_bounds__(kBlock) void k_smooth_lin_v(Lev L, T* e, const T* dg, const T* r,
-                                                         int colour, T kh2) {
+                                                         int colour, T kh2, int fresh) {
   constexpr int V = Vec<T>::V;
   uint32_t g4 = (uint32_t)gid();
   if (g4 >= (uint32_t)(L.half / V)) return;
@@ -648,7 +654,12 @@ __global__ __launch_bounds__(kBlock) void k_smooth_lin_v(Lev L, T* e, const T* d
   int s = (j + k + colour) & 1;
   uint32_t q0 = (uint32_t)colour * (uint32_t)L.half + g;
   T sum[V], d[V], rr[V], out[V];
-  nbsum_vec<T>(L, e + (1 - colour) * L.half, ih0, j, k, s, sum);
+  if (fresh && colour == 0) {
+#pragma unroll
+    for (int q = 0; q < V; ++q) sum[q] = T(0);
+  } else {
+    nbsum_vec<T>(L, e + (1 - colour) * L.half, ih0, j, k, s, sum);
+  }
   ldv<T>(dg + q0, d);
   ldv<T>(r + q0, rr);
 #pragma unroll
@@ -738,6 +749,207 @@ __global__ __launch_bounds__(kBlock) void k_outer_fused_v(Lev L, const double* w
   }
   double t = block_sum(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// ---------------------------------------------------------------------------
+// k-marching versions of the FP64 outer steps.  A block owns kBlock groups of
+// V consecutive packed cells of one plane (both colours) and walks kt planes
+// upwards, keeping its own columns of planes k-1, k, k+1 in registers, so the
+// z-neighbours are read from HBM once; the in-plane neighbours (rows j +- 1,
+// the row's edge cell) are recent lines of the neighbouring threads and come
+// from L1/L2.  Consecutive blocks take neighbouring chunks of the same planes.
+// Same per-cell arithmetic and neighbour summation order as the kernels above.
+// ---------------------------------------------------------------------------
+constexpr int kMarchKT = 16;
+
+struct MarchPos {
+  int j, jm, jp, ih0, k0, k1;
+  bool ok;
+};
+__device__ __forceinline__ MarchPos march_pos(const Lev& L, int kt, int V) {
+  MarchPos P;
+  const uint32_t ngrp = (uint32_t)L.n * (uint32_t)L.nh / (uint32_t)V;
+  const uint32_t nchunk = (ngrp + kBlock - 1) / kBlock;
+  const uint32_t b = (uint32_t)xcd_block();
+  const uint32_t kb = b / nchunk, chunk = b - kb * nchunk;
+  const uint32_t grp = chunk * kBlock + threadIdx.x;
+  P.k0 = (int)kb * kt;
+  P.ok = grp < ngrp && P.k0 < L.n;
+  const uint32_t p = grp * (uint32_t)V;
+  const uint32_t jj = L.dnh.div(p);
+  P.j = (int)jj;
+  P.ih0 = (int)(p - jj * (uint32_t)L.nh);
+  P.jm = P.j == 0 ? L.n - 1 : P.j - 1;
+  P.jp = P.j == L.n - 1 ? 0 : P.j + 1;
+  P.k1 = P.k0 + kt < L.n ? P.k0 + kt : L.n;
+  return P;
+}
+// blocks of a march over a level
+__host__ __device__ inline unsigned march_blocks(const Lev& L, int kt, int V) {
+  unsigned ngrp = (unsigned)((uint64_t)L.n * (uint64_t)L.nh / (uint64_t)V);
+  unsigned nchunk = (ngrp + kBlock - 1) / kBlock;
+  return nchunk * (unsigned)((L.n + kt - 1) / kt);
+}
+// v = w + e (e may be null) of V packed cells of colour c in row (j, k)
+template <typename TE, int V>
+__device__ __forceinline__ void march_ld(const Lev& L, const double* __restrict__ w,
+                                         const TE* __restrict__ e, int c, int j, int k, int ih0,
+                                         double* out) {
+  const uint32_t q0 = (uint32_t)c * (uint32_t)L.half + prow(L, j, k) + (uint32_t)ih0;
+  ldn<double, V>(w + q0, out);
+  if (e) {
+    TE ev[V];
+    ldn<TE, V>(e + q0, ev);
+#pragma unroll
+    for (int t = 0; t < V; ++t) out[t] += double(ev[t]);
+  }
+}
+// neighbour sums of the V cells of colour c at plane k from the window
+// (planes k-1 and k+1 of the other colour) and the in-plane loads
+template <typename TE, int V>
+__device__ __forceinline__ void march_nbsum(const Lev& L, const double* __restrict__ w,
+                                            const TE* __restrict__ e, const MarchPos& P, int c,
+                                            int k, const double (*wo)[V], double* sum) {
+  const int o = 1 - c;
+  const int s = (P.j + k + c) & 1;
+  double ym[V], yp[V];
+  march_ld<TE, V>(L, w, e, o, P.jm, k, P.ih0, ym);
+  march_ld<TE, V>(L, w, e, o, P.jp, k, P.ih0, yp);
+  const uint32_t ro = (uint32_t)o * (uint32_t)L.half + prow(L, P.j, k);
+  const uint32_t xi = s ? (P.ih0 + V == L.nh ? 0 : P.ih0 + V) : (P.ih0 == 0 ? L.nh - 1 : P.ih0 - 1);
+  const double xe = w[ro + xi] + (e ? double(e[ro + xi]) : 0.0);
+  double xv[V + 1];
+#pragma unroll
+  for (int t = 0; t < V; ++t) xv[s ? t : t + 1] = wo[1][t];
+  xv[s ? V : 0] = xe;
+#pragma unroll
+  for (int q = 0; q < V; ++q)
+    sum[q] = (xv[q] + xv[q + 1]) + (ym[q] + yp[q]) + (wo[0][q] + wo[2][q]);
+}
+
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_outer_fused_kv(Lev L, const double* __restrict__ w,
+                                                           const float* __restrict__ e,
+                                                           double* __restrict__ w_new,
+                                                           const float* __restrict__ dens,
+                                                           Consts C, float* __restrict__ rho,
+                                                           float* __restrict__ X,
+                                                           float* __restrict__ e_zero,
+                                                           double* __restrict__ part, int kt) {
+  constexpr int V = kVOuter;
+  __shared__ double sh[32];
+  const MarchPos P = march_pos(L, kt, V);
+  double acc = 0.0;
+  if (P.ok) {
+    double win[2][3][V];  // [colour][plane k-1, k, k+1][cell]
+    const int km0 = P.k0 == 0 ? L.n - 1 : P.k0 - 1;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      march_ld<float, V>(L, w, e, c, P.j, km0, P.ih0, win[c][0]);
+      march_ld<float, V>(L, w, e, c, P.j, P.k0, P.ih0, win[c][1]);
+    }
+    for (int k = P.k0; k < P.k1; ++k) {
+      const int kp = k + 1 == L.n ? 0 : k + 1;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) march_ld<float, V>(L, w, e, c, P.j, kp, P.ih0, win[c][2]);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double sum[V];
+        march_nbsum<float, V>(L, w, e, P, c, k, win[1 - c], sum);
+        const uint32_t q0 = (uint32_t)c * (uint32_t)L.half + prow(L, P.j, k) + (uint32_t)P.ih0;
+        if (e) stn<double, V>(w_new + q0, win[c][1]);
+        float dn[V], ro[V], xo[V], zo[V];
+        ldn<float, V>(dens + q0, dn);
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          const double vc = win[c][1][q];
+          double d = direct_resid<M, double>(C, 1.0, vc, sum[q], double(dn[q]), 0.0);
+          acc += d * d;
+          ro[q] = float(-d);
+          xo[q] = float(vc);
+          zo[q] = 0.0f;
+        }
+        stn<float, V>(rho + q0, ro);
+        stn<float, V>(X + q0, xo);
+        if (e_zero) stn<float, V>(e_zero + q0, zo);
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          win[c][0][q] = win[c][1][q];
+          win[c][1][q] = win[c][2][q];
+        }
+    }
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// adjoint: lam_new = lam + e + shift, r = b - A lam_new, e_zero = 0;
+// partial sums of r^2 (and of r when part_sum is given)
+template <typename TO>
+__global__ __launch_bounds__(kBlock) void k_lin_outer_fused_kv(
+    Lev L, const double* __restrict__ lam, const TO* __restrict__ e, double* __restrict__ lam_new,
+    const double* __restrict__ dg, const double* __restrict__ b, double kh2, TO* __restrict__ r,
+    TO* __restrict__ e_zero, double* __restrict__ part, double shift, double* __restrict__ part_sum,
+    int kt) {
+  constexpr int V = kVOuter;
+  __shared__ double sh[32];
+  const MarchPos P = march_pos(L, kt, V);
+  double acc = 0.0, accs = 0.0;
+  if (P.ok) {
+    double win[2][3][V];
+    const int km0 = P.k0 == 0 ? L.n - 1 : P.k0 - 1;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      march_ld<TO, V>(L, lam, e, c, P.j, km0, P.ih0, win[c][0]);
+      march_ld<TO, V>(L, lam, e, c, P.j, P.k0, P.ih0, win[c][1]);
+    }
+    for (int k = P.k0; k < P.k1; ++k) {
+      const int kp = k + 1 == L.n ? 0 : k + 1;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) march_ld<TO, V>(L, lam, e, c, P.j, kp, P.ih0, win[c][2]);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double sum[V], lc[V], dd[V], bb[V];
+        march_nbsum<TO, V>(L, lam, e, P, c, k, win[1 - c], sum);
+        const uint32_t q0 = (uint32_t)c * (uint32_t)L.half + prow(L, P.j, k) + (uint32_t)P.ih0;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          lc[q] = win[c][1][q] + shift;
+          sum[q] += 6.0 * shift;
+        }
+        if (e) stn<double, V>(lam_new + q0, lc);
+        ldn<double, V>(dg + q0, dd);
+        ldn<double, V>(b + q0, bb);
+        TO ro[V], zo[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          double d = bb[q] - (kh2 * (6.0 * lc[q] - sum[q]) + dd[q] * lc[q]);
+          acc += d * d;
+          accs += d;
+          ro[q] = TO(d);
+          zo[q] = TO(0);
+        }
+        stn<TO, V>(r + q0, ro);
+        if (e_zero) stn<TO, V>(e_zero + q0, zo);
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          win[c][0][q] = win[c][1][q];
+          win[c][1][q] = win[c][2][q];
+        }
+    }
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (part_sum) {
+    t = block_sum(accs, sh);
+    if (threadIdx.x == 0) part_sum[blockIdx.x] = t;
+  }
 }
 
 // Fused FP64 outer step of the adjoint: lam_new = lam + e (e may be null),

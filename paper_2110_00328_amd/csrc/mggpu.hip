@@ -627,18 +627,22 @@ int solve64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
 // FP32 correction multigrid inside an FP64 outer loop
 // ---------------------------------------------------------------------------
 template <int M>
-int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps) {
+// fresh: the correction buffer was not cleared; the first sweep takes it as 0
+int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps, bool fresh = false) {
   Work32& W = ctx->w32;
   const Lev& L = ctx->L[l];
   const bool vec = (L.nh % Vec<float>::V) == 0;
   const int64_t nv = L.half / Vec<float>::V;
   for (int s = 0; s < sweeps; ++s)
     for (int colour = 0; colour < 2; ++colour) {
-      int q = l == 0 ? prof_begin(ctx, MG_PROF_SMOOTH32) : -1;
+      // timed class: full half-sweeps of the finest level (a fresh colour-0
+      // half-sweep reads no neighbours and is left out)
+      const bool light = fresh && s == 0 && colour == 0;
+      int q = (l == 0 && !light) ? prof_begin(ctx, MG_PROF_SMOOTH32) : -1;
       if (vec)
-        k_smooth_corr_v<M><<<nblk(nv), kBlock, 0, ctx->stream>>>(L, W.e[l], W.X[l], W.dens[l],
-                                                                 W.rho[l], colour,
-                                                                 float(lev_h2(l)), C);
+        k_smooth_corr_v<M><<<nblk(nv), kBlock, 0, ctx->stream>>>(
+            L, W.e[l], W.X[l], W.dens[l], W.rho[l], colour, float(lev_h2(l)), C,
+            (fresh && s == 0) ? 1 : 0);
       else
         k_smooth_corr<M><<<nblk(L.half), kBlock, 0, ctx->stream>>>(L, W.e[l], W.X[l], W.dens[l],
                                                                    W.rho[l], colour,
@@ -652,7 +656,8 @@ int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps) {
 // rx: restrict the linearisation point X on the way down (first cycle of
 // an outer step)
 template <int M>
-int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int type, bool rx) {
+int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int type, bool rx,
+            bool fresh = false) {
   Work32& W = ctx->w32;
   if (l >= ctx->fused_from) {
     FusedCorr F;
@@ -674,10 +679,10 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
     LAUNCHCHK();
     return MG_OK;
   }
-  if (l == ctx->nlev - 1) return smooth32<M>(ctx, C, l, o->nu_pre + o->nu_post);
+  if (l == ctx->nlev - 1) return smooth32<M>(ctx, C, l, o->nu_pre + o->nu_post, fresh);
   const Lev& Lf = ctx->L[l];
   const Lev& Lc = ctx->L[l + 1];
-  ACHK(smooth32<M>(ctx, C, l, o->nu_pre));
+  ACHK(smooth32<M>(ctx, C, l, o->nu_pre, fresh));
   const bool vec = Lc.n % Vec<float>::V == 0;
   const int64_t ncv = cells(Lc) / Vec<float>::V;
   // exact per-cell smoothers (f(R), symmetron): the colour swept last has
@@ -742,16 +747,20 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   int outer = 0, rc = MG_OK, vc = 0, k_prev = 0;
   double rel = 0.0, rel_prev = -1.0;
   const bool fused = L0.nh % kVOuter == 0;
+  // the first pre-smoothing sweep of each outer step treats the correction
+  // as zero, so the buffer need not be cleared (not when level 0 is relaxed
+  // by the single-block kernel, which reads it, or without pre-smoothing)
+  const bool fresh = fused && o->nu_pre > 0 && ctx->fused_from > 0;
   const float* pending = nullptr;  // correction not yet added to the master
   for (;;) {
     int64_t nparts;
     if (fused) {
       // w_new = w + pending, residual at w_new, next correction buffer zeroed
-      nparts = nblk(L0.half / kVOuter);
+      nparts = march_blocks(L0, kMarchKT, kVOuter);
       double* wn = pending ? W.wbuf[1 - cur] : W.w;
-      float* ez = W.ebuf[pending ? 1 - eb : eb];
-      k_outer_fused_v<M><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-          L0, W.w, pending, wn, W.dens[0], C, W.rho[0], W.X[0], ez, ctx->part);
+      float* ez = fresh ? nullptr : W.ebuf[pending ? 1 - eb : eb];
+      k_outer_fused_kv<M><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+          L0, W.w, pending, wn, W.dens[0], C, W.rho[0], W.X[0], ez, ctx->part, kMarchKT);
       if (pending) {
         cur = 1 - cur;
         eb = 1 - eb;
@@ -779,7 +788,8 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
       break;
     }
     int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol);
-    for (int it = 0; it < k; ++it) ACHK(cycle32<M>(ctx, C, o, 0, o->cycle, it == 0));
+    for (int it = 0; it < k; ++it)
+      ACHK(cycle32<M>(ctx, C, o, 0, o->cycle, it == 0, fresh && it == 0));
     vc += k;
     rel_prev = rel;
     k_prev = k;
@@ -824,7 +834,8 @@ __global__ __launch_bounds__(kBlock) void k_lin_final(Lev L, const double* v, co
 }
 
 template <typename T>
-int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, int l, int type) {
+int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, int l, int type,
+              bool fresh = false) {
   if (l >= ctx->fused_from) {
     FusedLin<T> F;
     memset(&F, 0, sizeof F);
@@ -847,13 +858,13 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
   T kh2 = T(kap / lev_h2(l));
   const bool vec = (Lf.nh % Vec<T>::V) == 0;
   const int64_t nv = Lf.half / Vec<T>::V;
-  auto smooth = [&](int sweeps) {
+  auto smooth = [&](int sweeps, bool first_fresh) {
     for (int s = 0; s < sweeps; ++s)
       for (int colour = 0; colour < 2; ++colour) {
         int q = l == 0 ? prof_begin(ctx, sizeof(T) == 4 ? MG_PROF_LIN32 : MG_PROF_LIN64) : -1;
         if (vec)
-          k_smooth_lin_v<T><<<nblk(nv), kBlock, 0, ctx->stream>>>(Lf, W.e[l], W.dg[l], W.r[l],
-                                                                  colour, kh2);
+          k_smooth_lin_v<T><<<nblk(nv), kBlock, 0, ctx->stream>>>(
+              Lf, W.e[l], W.dg[l], W.r[l], colour, kh2, (first_fresh && s == 0) ? 1 : 0);
         else
           k_smooth_lin<T><<<nblk(Lf.half), kBlock, 0, ctx->stream>>>(Lf, W.e[l], W.dg[l], W.r[l],
                                                                       colour, kh2);
@@ -861,12 +872,12 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
       }
   };
   if (l == ctx->nlev - 1) {
-    smooth(o->nu_pre + o->nu_post);
+    smooth(o->nu_pre + o->nu_post, fresh);
     LAUNCHCHK();
     return MG_OK;
   }
   const Lev& Lc = ctx->L[l + 1];
-  smooth(o->nu_pre);
+  smooth(o->nu_pre, fresh);
   const bool cvec = Lc.n % Vec<T>::V == 0;
   const int64_t ncv = cells(Lc) / Vec<T>::V;
   if (cvec)  // Gauss-Seidel on a linear system is exact per cell: skip colour 1
@@ -890,7 +901,7 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
                                                              (const T*)nullptr);
   else
     k_prolong_block<T><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1]);
-  smooth(o->nu_post);
+  smooth(o->nu_post, false);
   LAUNCHCHK();
   return MG_OK;
 }
@@ -952,19 +963,22 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
     ACHK(sum_to_host(ctx, nblk(m), &sum_dg, ctx->part3));
   }
   double* psum = galerkin && sum_dg > 0.0 ? ctx->part3 : nullptr;
+  // the first pre-smoothing sweep of each outer step takes the correction as
+  // zero, so the fused outer kernel need not clear it
+  const bool fresh = vec && o->nu_pre > 0 && ctx->fused_from > 0;
   for (;;) {
-    int64_t nparts = vec ? nblk(L0.half / kVOuter) : nblk(m);
+    int64_t nparts = vec ? march_blocks(L0, kMarchKT, kVOuter) : nblk(m);
     if (vec) {
       double* ln = pending ? A.lambuf[1 - cur] : A.lam;
       int ez = pending ? 1 - eb : eb;
       if (f32)
-        k_lin_outer_fused_v<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-            L0, A.lam, (const float*)pending, ln, A.dg, A.b, kap, A.w32.r[0], A.w32.ebuf[ez],
-            ctx->part, shift, psum);
+        k_lin_outer_fused_kv<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+            L0, A.lam, (const float*)pending, ln, A.dg, A.b, kap, A.w32.r[0],
+            fresh ? (float*)nullptr : A.w32.ebuf[ez], ctx->part, shift, psum, kMarchKT);
       else
-        k_lin_outer_fused_v<double><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-            L0, A.lam, (const double*)pending, ln, A.dg, A.b, kap, A.w64.r[0], A.w64.ebuf[ez],
-            ctx->part, shift, psum);
+        k_lin_outer_fused_kv<double><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+            L0, A.lam, (const double*)pending, ln, A.dg, A.b, kap, A.w64.r[0],
+            fresh ? (double*)nullptr : A.w64.ebuf[ez], ctx->part, shift, psum, kMarchKT);
       if (pending) {
         cur = 1 - cur;
         eb = 1 - eb;
@@ -1001,12 +1015,14 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
     // correction scheme on r = b - A lam (FP32 or FP64 inner cycles)
     int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol);
     if (f32) {
-      for (int it = 0; it < k; ++it) ACHK(lin_cycle<float>(ctx, A.w32, kap, o, 0, o->cycle));
+      for (int it = 0; it < k; ++it)
+        ACHK(lin_cycle<float>(ctx, A.w32, kap, o, 0, o->cycle, fresh && it == 0));
       if (psum) k_dot<float><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.w32.e[0], A.dg, ctx->part3);
       if (vec) pending = A.w32.e[0];
       else k_axpy_to64<float><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w32.e[0]);
     } else {
-      for (int it = 0; it < k; ++it) ACHK(lin_cycle<double>(ctx, A.w64, kap, o, 0, o->cycle));
+      for (int it = 0; it < k; ++it)
+        ACHK(lin_cycle<double>(ctx, A.w64, kap, o, 0, o->cycle, fresh && it == 0));
       if (psum) k_dot<double><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.w64.e[0], A.dg, ctx->part3);
       if (vec) pending = A.w64.e[0];
       else k_axpy_to64<double><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.lam, A.w64.e[0]);
