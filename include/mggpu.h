@@ -71,10 +71,12 @@ typedef struct {
   int nu_post;      /* sweeps after the correction, >= 1 */
   int inner_cycles; /* cycles between FP64 residual checks (refined mode: FP32
                        cycles per outer step); 0 = automatic, from the measured
-                       contraction per cycle (1..4) */
+                       contraction per cycle (1..8) */
   int max_cycles;   /* cap on cycles (FP64) or outer steps (refined), 1..64 */
   int precision;    /* MG_FP64 / MG_FP32_REFINED */
-  int coarse_sweeps;/* cap on sweeps of the coarsest level (0 = default 24) */
+  int coarse_sweeps;/* cap on sweeps of the coarsest level (they stop once its
+                       residual has dropped by 1e-8); 0 = default: 24 for a
+                       coarsest level of n <= 8, else 2 n^2 */
 } mg_solver_opts;
 
 typedef struct {

@@ -145,7 +145,7 @@ __device__ __noinline__ int b_plan(int fixed, double rel, double rel_prev, int k
   double rho = pow(rel / rel_prev, 1.0 / k_prev);
   rho = rho < 0.01 ? 0.01 : (rho > 0.9 ? 0.9 : rho);
   int k = (int)ceil(1.05 * log(tol / rel) / log(rho));
-  return k < 1 ? 1 : (k > 4 ? 4 : k);
+  return k < 1 ? 1 : (k > 8 ? 8 : k);  // as the single-box planner
 }
 
 template <int M>

@@ -790,13 +790,19 @@ __host__ __device__ inline unsigned march_blocks(const Lev& L, int kt, int V) {
   unsigned nchunk = (ngrp + kBlock - 1) / kBlock;
   return nchunk * (unsigned)((L.n + kt - 1) / kt);
 }
-// v = w + e (e may be null) of V packed cells of colour c in row (j, k)
+// v = w + e (e may be null; w null: the uniform value wu) of V packed cells
+// of colour c in row (j, k)
 template <typename TE, int V>
 __device__ __forceinline__ void march_ld(const Lev& L, const double* __restrict__ w,
                                          const TE* __restrict__ e, int c, int j, int k, int ih0,
-                                         double* out) {
+                                         double* out, double wu) {
   const uint32_t q0 = (uint32_t)c * (uint32_t)L.half + prow(L, j, k) + (uint32_t)ih0;
-  ldn<double, V>(w + q0, out);
+  if (w) {
+    ldn<double, V>(w + q0, out);
+  } else {
+#pragma unroll
+    for (int t = 0; t < V; ++t) out[t] = wu;
+  }
   if (e) {
     TE ev[V];
     ldn<TE, V>(e + q0, ev);
@@ -809,15 +815,16 @@ __device__ __forceinline__ void march_ld(const Lev& L, const double* __restrict_
 template <typename TE, int V>
 __device__ __forceinline__ void march_nbsum(const Lev& L, const double* __restrict__ w,
                                             const TE* __restrict__ e, const MarchPos& P, int c,
-                                            int k, const double (*wo)[V], double* sum) {
+                                            int k, const double (*wo)[V], double* sum,
+                                            double wu) {
   const int o = 1 - c;
   const int s = (P.j + k + c) & 1;
   double ym[V], yp[V];
-  march_ld<TE, V>(L, w, e, o, P.jm, k, P.ih0, ym);
-  march_ld<TE, V>(L, w, e, o, P.jp, k, P.ih0, yp);
+  march_ld<TE, V>(L, w, e, o, P.jm, k, P.ih0, ym, wu);
+  march_ld<TE, V>(L, w, e, o, P.jp, k, P.ih0, yp, wu);
   const uint32_t ro = (uint32_t)o * (uint32_t)L.half + prow(L, P.j, k);
   const uint32_t xi = s ? (P.ih0 + V == L.nh ? 0 : P.ih0 + V) : (P.ih0 == 0 ? L.nh - 1 : P.ih0 - 1);
-  const double xe = w[ro + xi] + (e ? double(e[ro + xi]) : 0.0);
+  const double xe = (w ? w[ro + xi] : wu) + (e ? double(e[ro + xi]) : 0.0);
   double xv[V + 1];
 #pragma unroll
   for (int t = 0; t < V; ++t) xv[s ? t : t + 1] = wo[1][t];
@@ -843,19 +850,20 @@ __global__ __launch_bounds__(kBlock) void k_outer_fused_kv(Lev L, const double* 
   if (P.ok) {
     double win[2][3][V];  // [colour][plane k-1, k, k+1][cell]
     const int km0 = P.k0 == 0 ? L.n - 1 : P.k0 - 1;
+    const double wu = C.bg;  // w null: the master is the uniform background
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      march_ld<float, V>(L, w, e, c, P.j, km0, P.ih0, win[c][0]);
-      march_ld<float, V>(L, w, e, c, P.j, P.k0, P.ih0, win[c][1]);
+      march_ld<float, V>(L, w, e, c, P.j, km0, P.ih0, win[c][0], wu);
+      march_ld<float, V>(L, w, e, c, P.j, P.k0, P.ih0, win[c][1], wu);
     }
     for (int k = P.k0; k < P.k1; ++k) {
       const int kp = k + 1 == L.n ? 0 : k + 1;
 #pragma unroll
-      for (int c = 0; c < 2; ++c) march_ld<float, V>(L, w, e, c, P.j, kp, P.ih0, win[c][2]);
+      for (int c = 0; c < 2; ++c) march_ld<float, V>(L, w, e, c, P.j, kp, P.ih0, win[c][2], wu);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         double sum[V];
-        march_nbsum<float, V>(L, w, e, P, c, k, win[1 - c], sum);
+        march_nbsum<float, V>(L, w, e, P, c, k, win[1 - c], sum, wu);
         const uint32_t q0 = (uint32_t)c * (uint32_t)L.half + prow(L, P.j, k) + (uint32_t)P.ih0;
         if (e) stn<double, V>(w_new + q0, win[c][1]);
         float dn[V], ro[V], xo[V], zo[V];
@@ -902,18 +910,18 @@ __global__ __launch_bounds__(kBlock) void k_lin_outer_fused_kv(
     double win[2][3][V];
     const int km0 = P.k0 == 0 ? L.n - 1 : P.k0 - 1;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      march_ld<TO, V>(L, lam, e, c, P.j, km0, P.ih0, win[c][0]);
-      march_ld<TO, V>(L, lam, e, c, P.j, P.k0, P.ih0, win[c][1]);
+    for (int c = 0; c < 2; ++c) {  // lam null: lam = 0
+      march_ld<TO, V>(L, lam, e, c, P.j, km0, P.ih0, win[c][0], 0.0);
+      march_ld<TO, V>(L, lam, e, c, P.j, P.k0, P.ih0, win[c][1], 0.0);
     }
     for (int k = P.k0; k < P.k1; ++k) {
       const int kp = k + 1 == L.n ? 0 : k + 1;
 #pragma unroll
-      for (int c = 0; c < 2; ++c) march_ld<TO, V>(L, lam, e, c, P.j, kp, P.ih0, win[c][2]);
+      for (int c = 0; c < 2; ++c) march_ld<TO, V>(L, lam, e, c, P.j, kp, P.ih0, win[c][2], 0.0);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         double sum[V], lc[V], dd[V], bb[V];
-        march_nbsum<TO, V>(L, lam, e, P, c, k, win[1 - c], sum);
+        march_nbsum<TO, V>(L, lam, e, P, c, k, win[1 - c], sum, 0.0);
         const uint32_t q0 = (uint32_t)c * (uint32_t)L.half + prow(L, P.j, k) + (uint32_t)P.ih0;
 #pragma unroll
         for (int q = 0; q < V; ++q) {

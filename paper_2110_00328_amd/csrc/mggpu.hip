@@ -58,7 +58,6 @@ struct WorkLin {  // adjoint linear multigrid in precision T
 };
 struct WorkAdj {
   double* v = nullptr;    // forward field (solved variable), packed
-  float* dens = nullptr;  // packed float
   double* dg = nullptr;   // FP64 diagonal, packed
   double* b = nullptr;    // right-hand side s * dL/dv, packed
   double* lam = nullptr;  // FP64 solution, packed (current)
@@ -247,7 +246,6 @@ int ensure_adj(mg_ctx* ctx, int precision) {
   int64_t m = cells(ctx->L[0]);
   if (!ctx->haveAdj) {
     ACHK(dalloc(ctx, &A.v, m));
-    ACHK(dalloc(ctx, &A.dens, m));
     ACHK(dalloc(ctx, &A.dg, m));
     ACHK(dalloc(ctx, &A.b, m));
     ACHK(dalloc(ctx, &A.lambuf[0], m));
@@ -350,9 +348,26 @@ int check_opts(mg_ctx* ctx, const mg_solver_opts* o) {
 
 double lev_h2(int l) { return double(1u << l) * double(1u << l); }
 
+// Cap on Gauss-Seidel sweeps of the coarsest level (they stop early once the
+// RMS residual has dropped by 1e-8): 24 for the usual 4^3 / 6^3 / 8^3; a
+// larger coarsest level (n = odd * 2^l with a big odd factor) needs about
+// 2 n^2 sweeps, the slowest mode contracting by 1 - O(1/n^2) per sweep.
+int default_coarse_sweeps(int nc) { return nc <= 8 ? 24 : 2 * nc * nc; }
+
+// Sweeps per cycle of a grid that cannot be coarsened (n/2 odd or < 4):
+// it is its own coarsest level, relaxed without the early stop.
+int single_level_sweeps(const mg_ctx* ctx, const mg_solver_opts* o) {
+  int cap = o->coarse_sweeps > 0 ? o->coarse_sweeps : default_coarse_sweeps(ctx->L[0].n);
+  int nu = o->nu_pre + o->nu_post;
+  return cap > nu ? cap : nu;
+}
+
 // Cycles to run before the next residual check.  fixed > 0: that many.
 // Otherwise from the contraction per cycle seen so far: enough to reach
-// tol with 5% margin, between 1 and 4 (2 before anything is measured).
+// tol with 5% margin, between 1 and kMaxPlanned (2 before anything is
+// measured).  In the refined mode one check's FP32 cycles can reduce the
+// residual by up to ~1e-6 before FP32 rounding of the correction matters.
+constexpr int kMaxPlanned = 8;
 int plan_cycles(int fixed, double rel, double rel_prev, int k_prev, double tol) {
   if (fixed > 0) return fixed;
   if (rel_prev <= 0.0 || k_prev <= 0 || !(rel < rel_prev)) return 2;
@@ -361,7 +376,7 @@ int plan_cycles(int fixed, double rel, double rel_prev, int k_prev, double tol) 
   if (rho > 0.9) rho = 0.9;
   double need = 1.05 * log(tol / rel) / log(rho);
   int k = (int)ceil(need);
-  return k < 1 ? 1 : (k > 4 ? 4 : k);
+  return k < 1 ? 1 : (k > kMaxPlanned ? kMaxPlanned : k);
 }
 
 // ---------------------------------------------------------------------------
@@ -427,7 +442,8 @@ int make_prog(mg_ctx* ctx, int l, const mg_solver_opts* o, int type, FusedProg* 
   gen_prog(ops, l - f, ctx->nlev - 1 - f, type, o->nu_pre, o->nu_post);
   if ((int)ops.size() > kMaxOps) return fail(ctx, MG_EINVAL, "fused cycle program too long");
   P->nops = (int)ops.size();
-  P->coarse_sweeps = o->coarse_sweeps > 0 ? o->coarse_sweeps : 24;
+  P->coarse_sweeps =
+      o->coarse_sweeps > 0 ? o->coarse_sweeps : default_coarse_sweeps(ctx->L[ctx->nlev - 1].n);
   P->rx = rx;
   for (size_t q = 0; q < ops.size(); ++q) P->op[q] = ops[q];
   return MG_OK;
@@ -488,7 +504,7 @@ int cycle64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
     return MG_OK;
   }
   if (l == ctx->nlev - 1) {  // single-level grid: relax only
-    return smooth64<M>(ctx, C, l, o->nu_pre + o->nu_post);
+    return smooth64<M>(ctx, C, l, single_level_sweeps(ctx, o));
   }
   const Lev& Lf = ctx->L[l];
   const Lev& Lc = ctx->L[l + 1];
@@ -679,7 +695,7 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
     LAUNCHCHK();
     return MG_OK;
   }
-  if (l == ctx->nlev - 1) return smooth32<M>(ctx, C, l, o->nu_pre + o->nu_post, fresh);
+  if (l == ctx->nlev - 1) return smooth32<M>(ctx, C, l, single_level_sweeps(ctx, o), fresh);
   const Lev& Lf = ctx->L[l];
   const Lev& Lc = ctx->L[l + 1];
   ACHK(smooth32<M>(ctx, C, l, o->nu_pre, fresh));
@@ -730,23 +746,29 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   const Lev& L0 = ctx->L[0];
   int64_t m = cells(L0);
   k_pack<float, float><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, delta, W.dens[0], 1.0);
-  for (int l = 0; l + 1 < ctx->nlev; ++l)
-    k_restrict<float, float><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
-        ctx->L[l], ctx->L[l + 1], W.dens[l], W.dens[l + 1]);
+  // the f(R) correction operator does not involve the density below level 0
+  if (M != FR)
+    for (int l = 0; l + 1 < ctx->nlev; ++l)
+      k_restrict<float, float><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
+          ctx->L[l], ctx->L[l + 1], W.dens[l], W.dens[l + 1]);
   double sgn = (C.model == FR) ? -1.0 : 1.0;
   int cur = 0, eb = 0;  // current master buffer, current level-0 correction buffer
   W.w = W.wbuf[cur];
   W.e[0] = W.ebuf[eb];
+  const bool fused = L0.nh % kVOuter == 0;
+  // Starting from the uniform background, the first two outer kernels take
+  // the master as that constant instead of reading it; the first residual is
+  // then exactly the background residual whose RMS normalises rel.
+  const bool uni = fused && !field_in;
+  double eps_bg = 1.0;
   if (field_in)
     k_pack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, field_in, W.w, sgn);
-  else
+  else if (!uni)
     k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(W.w, m, C.bg);
   LAUNCHCHK();
-  double eps_bg;
-  ACHK(bg_rms(ctx, C, delta, &eps_bg));
+  if (!uni) ACHK(bg_rms(ctx, C, delta, &eps_bg));
   int outer = 0, rc = MG_OK, vc = 0, k_prev = 0;
   double rel = 0.0, rel_prev = -1.0;
-  const bool fused = L0.nh % kVOuter == 0;
   // the first pre-smoothing sweep of each outer step treats the correction
   // as zero, so the buffer need not be cleared (not when level 0 is relaxed
   // by the single-block kernel, which reads it, or without pre-smoothing)
@@ -759,8 +781,9 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
       nparts = march_blocks(L0, kMarchKT, kVOuter);
       double* wn = pending ? W.wbuf[1 - cur] : W.w;
       float* ez = fresh ? nullptr : W.ebuf[pending ? 1 - eb : eb];
+      const double* wsrc = (uni && outer <= 1) ? nullptr : W.w;
       k_outer_fused_kv<M><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-          L0, W.w, pending, wn, W.dens[0], C, W.rho[0], W.X[0], ez, ctx->part, kMarchKT);
+          L0, wsrc, pending, wn, W.dens[0], C, W.rho[0], W.X[0], ez, ctx->part, kMarchKT);
       if (pending) {
         cur = 1 - cur;
         eb = 1 - eb;
@@ -776,6 +799,10 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
     LAUNCHCHK();
     double s;
     ACHK(sum_to_host(ctx, nparts, &s));
+    if (uni && outer == 0) {
+      eps_bg = sqrt(s / double(m));
+      if (!(eps_bg > 0.0)) eps_bg = 1.0;
+    }
     rel = sqrt(s / double(m)) / eps_bg;
     if (outer > 0 && st && outer - 1 < 64) st->resid_hist[outer - 1] = rel;
     if (!std::isfinite(rel)) {
@@ -801,6 +828,8 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
     }
     ++outer;
   }
+  // stopped before any correction: the master is still the background
+  if (uni && outer == 0) k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(W.w, m, C.bg);
   k_unpack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, W.w, field_out, sgn);
   LAUNCHCHK();
   if (st) {
@@ -814,11 +843,35 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
 // ---------------------------------------------------------------------------
 // adjoint: linear multigrid on A lam = b, A = kap(6 - sum)/h^2 + dg
 // ---------------------------------------------------------------------------
+// The whole adjoint set-up in one pass over the natural cells: the solved
+// variable v = sgn field, the Jacobian diagonal dg (FP64, and FP32 when dg32
+// is given), the right-hand side b = bsign grad, packed; v itself only when
+// the final step needs it (v_out non-null); block partials of b^2.
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_lin_setup(Lev L, const double* v, const float* dens,
-                                                      Consts C, double* dg) {
+__global__ __launch_bounds__(kBlock) void k_lin_setup_nat(Lev L, const double* __restrict__ field,
+                                                          const float* __restrict__ delta,
+                                                          const double* __restrict__ grad,
+                                                          double sgn, double bsign, Consts C,
+                                                          double* v_out, double* dg, float* dg32,
+                                                          double* b, double* part) {
+  __shared__ double sh[32];
   int64_t g = gid();
-  if (g < 2 * L.half) dg[g] = lin_dg<M>(C, v[g], double(dens[g]));
+  double bb = 0.0;
+  if (g < 2 * L.half) {
+    int i, j, k;
+    dec_nat(g, L, i, j, k);
+    const uint32_t pk = pk_of(L, i, j, k);
+    const double v = sgn * field[g];
+    const double d = lin_dg<M>(C, v, double(delta[g]));
+    dg[pk] = d;
+    if (dg32) dg32[pk] = float(d);
+    if (v_out) v_out[pk] = v;
+    const double bv = bsign * grad[g];
+    b[pk] = bv;
+    bb = bv * bv;
+  }
+  double t = block_sum(bb, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_lin_final(Lev L, const double* v, const double* lam,
@@ -830,7 +883,8 @@ __global__ __launch_bounds__(kBlock) void k_lin_final(Lev L, const double* v, co
   int ih, j, k;
   dec(gg, L, ih, j, k);
   int i = 2 * ih + ((j + k + colour) & 1);
-  out_nat[((int64_t)k * L.n + j) * L.n + i] = -lin_dfd<M>(C, v[g]) * lam[g];
+  const double vv = M == FR ? 0.0 : v[g];  // the f(R) source derivative is constant
+  out_nat[((int64_t)k * L.n + j) * L.n + i] = -lin_dfd<M>(C, vv) * lam[g];
 }
 
 template <typename T>
@@ -872,7 +926,7 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
       }
   };
   if (l == ctx->nlev - 1) {
-    smooth(o->nu_pre + o->nu_post, fresh);
+    smooth(single_level_sweeps(ctx, o), fresh);
     LAUNCHCHK();
     return MG_OK;
   }
@@ -915,21 +969,26 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
   const Lev& L0 = ctx->L[0];
   int64_t m = cells(L0);
   double sgn_field = (C.model == FR) ? -1.0 : 1.0;
-  k_pack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, field, A.v, sgn_field);
-  k_pack<float, float><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, delta, A.dens, 1.0);
-  // b = s dL/dv, s = +1 (f(R)) / -1; dL/dv = sgn_field dL/dfield  ->  b = -dL/dfield
-  k_pack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, grad_field, A.b,
-                                                              lin_sign(C) * sgn_field);
-  k_lin_setup<M><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, A.v, A.dens, C, A.dg);
+  const bool f32 = o->precision == MG_FP32_REFINED;
+  const bool vec = L0.nh % kVOuter == 0;
   int cur = 0, eb = 0;
   A.lam = A.lambuf[cur];
   if (A.have32) A.w32.e[0] = A.w32.ebuf[eb];
   if (A.have64) A.w64.e[0] = A.w64.ebuf[eb];
-  k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(A.lam, m, 0.0);
+  // v, dg, b in one pass; b = s dL/dv, s = +1 (f(R)) / -1, and
+  // dL/dv = sgn_field dL/dfield.  v is kept only where dL/d(delta) needs it.
+  k_lin_setup_nat<M><<<nblk(m), kBlock, 0, ctx->stream>>>(
+      L0, field, delta, grad_field, sgn_field, lin_sign(C) * sgn_field, C,
+      M == FR ? (double*)nullptr : A.v, A.dg, f32 ? A.w32.dg[0] : (float*)nullptr, A.b,
+      ctx->part);
   LAUNCHCHK();
-  const bool f32 = o->precision == MG_FP32_REFINED;
+  double bb;
+  ACHK(sum_to_host(ctx, nblk(m), &bb));
+  bb = sqrt(bb);
+  if (!(bb > 0.0)) bb = 1.0;
+  // lam starts at 0: the fused outer kernels take it as 0 until written
+  if (!vec) k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(A.lam, m, 0.0);
   if (f32) {
-    k_cast<float><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.dg, A.w32.dg[0]);
     for (int l = 0; l + 1 < ctx->nlev; ++l)
       k_restrict<float, float><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
           ctx->L[l], ctx->L[l + 1], A.w32.dg[l], A.w32.dg[l + 1]);
@@ -939,16 +998,9 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
           ctx->L[l], ctx->L[l + 1], A.w64.dg[l], A.w64.dg[l + 1]);
   }
   LAUNCHCHK();
-  k_sq_norm<double><<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.b, ctx->part);
-  LAUNCHCHK();
-  double bb;
-  ACHK(sum_to_host(ctx, nblk(m), &bb));
-  bb = sqrt(bb);
-  if (!(bb > 0.0)) bb = 1.0;
   double kap = lin_kap(C);
   int outer = 0, rc = MG_OK, vc = 0, k_prev = 0;
   double rel = 0.0, rel_prev = -1.0;
-  const bool vec = L0.nh % kVOuter == 0;
   const void* pending = nullptr;  // correction not yet added to lam
   // Coupled quintessence: the constant vector is nearly a null vector of A
   // (A 1 = dg, the tiny mass term), so rounding in the inner cycles leaves
@@ -971,13 +1023,14 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
     if (vec) {
       double* ln = pending ? A.lambuf[1 - cur] : A.lam;
       int ez = pending ? 1 - eb : eb;
+      const double* lsrc = outer <= 1 ? nullptr : A.lam;  // null: lam = 0
       if (f32)
         k_lin_outer_fused_kv<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-            L0, A.lam, (const float*)pending, ln, A.dg, A.b, kap, A.w32.r[0],
+            L0, lsrc, (const float*)pending, ln, A.dg, A.b, kap, A.w32.r[0],
             fresh ? (float*)nullptr : A.w32.ebuf[ez], ctx->part, shift, psum, kMarchKT);
       else
         k_lin_outer_fused_kv<double><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-            L0, A.lam, (const double*)pending, ln, A.dg, A.b, kap, A.w64.r[0],
+            L0, lsrc, (const double*)pending, ln, A.dg, A.b, kap, A.w64.r[0],
             fresh ? (double*)nullptr : A.w64.ebuf[ez], ctx->part, shift, psum, kMarchKT);
       if (pending) {
         cur = 1 - cur;
@@ -1039,6 +1092,7 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
     LAUNCHCHK();
     ++outer;
   }
+  if (vec && outer == 0) k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(A.lam, m, 0.0);
   k_lin_final<M><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, A.v, A.lam, C, grad_delta);
   LAUNCHCHK();
   if (st) {
@@ -1090,6 +1144,65 @@ __global__ __launch_bounds__(kBlock) void k_force(Lev L, const double* __restric
   out[2 * m + g] = float(gz);
 }
 
+// The same force with a march in z: a thread owns 4 consecutive cells of a
+// row and walks kMarchKT planes, keeping Phi5 of planes k-1, k, k+1 in
+// registers (the field is read from HBM once); rows j +- 1 and the row's
+// edge cells come from L1/L2.  Requires n % 4 == 0.
+__global__ __launch_bounds__(kBlock) void k_force_kv(Lev L, const double* __restrict__ f, Consts C,
+                                                     float* __restrict__ out, int kt) {
+  constexpr int V = 4;
+  const int n = L.n;
+  const uint32_t ngrp = (uint32_t)n * (uint32_t)n / V;  // groups per plane
+  const uint32_t nchunk = (ngrp + kBlock - 1) / kBlock;
+  const uint32_t b = (uint32_t)xcd_block();
+  const uint32_t kb = b / nchunk, chunk = b - kb * nchunk;
+  const uint32_t grp = chunk * kBlock + threadIdx.x;
+  const int k0 = (int)kb * kt;
+  if (grp >= ngrp || k0 >= n) return;
+  const uint32_t p = grp * V;
+  const uint32_t jj = L.dn.div(p);
+  const int j = (int)jj, i0 = (int)(p - jj * (uint32_t)n);
+  const int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
+  const int im = i0 == 0 ? n - 1 : i0 - 1, ip = i0 + V == n ? 0 : i0 + V;
+  const int k1 = k0 + kt < n ? k0 + kt : n;
+  const int64_t m = 2 * L.half;
+  auto row = [&](int jr, int kr) { return ((int64_t)kr * n + jr) * n; };
+  auto ld = [&](int jr, int kr, double* ph) {
+    double v[V];
+    ldn<double, V>(f + row(jr, kr) + i0, v);
+#pragma unroll
+    for (int q = 0; q < V; ++q) ph[q] = phi5_of(C, v[q]);
+  };
+  double win[3][V];
+  ld(j, k0 == 0 ? n - 1 : k0 - 1, win[0]);
+  ld(j, k0, win[1]);
+  for (int k = k0; k < k1; ++k) {
+    ld(j, k + 1 == n ? 0 : k + 1, win[2]);
+    double ym[V], yp[V], xv[V + 2];
+    ld(jm, k, ym);
+    ld(jp, k, yp);
+    const int64_t r = row(j, k);
+    xv[0] = phi5_of(C, f[r + im]);
+    xv[V + 1] = phi5_of(C, f[r + ip]);
+#pragma unroll
+    for (int q = 0; q < V; ++q) xv[q + 1] = win[1][q];
+    float gx[V], gy[V], gz[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      gx[q] = float(-0.5 * (xv[q + 2] - xv[q]));
+      gy[q] = float(-0.5 * (yp[q] - ym[q]));
+      gz[q] = float(-0.5 * (win[2][q] - win[0][q]));
+    }
+    stn<float, V>(out + r + i0, gx);
+    stn<float, V>(out + m + r + i0, gy);
+    stn<float, V>(out + 2 * m + r + i0, gz);
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      win[0][q] = win[1][q];
+      win[1][q] = win[2][q];
+    }
+  }
+}
 __global__ __launch_bounds__(kBlock) void k_force_adjoint(Lev L, const double* __restrict__ f,
                                                           const float* __restrict__ gf, Consts C,
                                                           double* __restrict__ out) {
@@ -1380,8 +1493,11 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
       f = q;
       break;
     }
-  if (f > ctx->nlev - 1) f = ctx->nlev - 1;
-  if (f < 1) f = ctx->nlev;  // single level: nothing fused
+  if (f > ctx->nlev - 1) f = ctx->nlev - 1;  // the coarsest level is always solved
+  // Level 0 never runs in the single-block kernels (they expect the coarse
+  // levels' buffers); a grid that cannot be coarsened is relaxed by the
+  // level-0 smoother instead (single_level_sweeps).
+  if (f < 1) f = ctx->nlev;
   if (ctx->nlev - f > kMaxFused) f = ctx->nlev - kMaxFused;
   ctx->fused_from = f;
   ctx->part_cap = nblk((int64_t)n * n * n) + 16;
@@ -1511,8 +1627,15 @@ int mg_force(mg_ctx* ctx, int model, const mg_model_params* params, const double
   Consts C;
   ACHK(make_consts(ctx, model, params, ctx->n, &C));
   if (!field || !force_out) return fail(ctx, MG_EINVAL, "mg_force: NULL array");
-  int64_t m = (int64_t)ctx->n * ctx->n * ctx->n;
-  k_force<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], field, C, force_out);
+  const int n = ctx->n;
+  int64_t m = (int64_t)n * n * n;
+  if (n % 4 == 0) {
+    unsigned nchunk = (unsigned)(((int64_t)n * n / 4 + kBlock - 1) / kBlock);
+    unsigned nb = nchunk * (unsigned)((n + kMarchKT - 1) / kMarchKT);
+    k_force_kv<<<nb, kBlock, 0, ctx->stream>>>(ctx->L[0], field, C, force_out, kMarchKT);
+  } else {
+    k_force<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], field, C, force_out);
+  }
   LAUNCHCHK();
   return MG_OK;
 }
@@ -1732,7 +1855,8 @@ int batch_setup(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver_o
     B.nu2 = o->nu_post;
     B.fixed_inner = trial ? 2 : o->inner_cycles;
     B.max_outer = trial ? 1 : o->max_cycles;
-    B.coarse_sweeps = o->coarse_sweeps > 0 ? o->coarse_sweeps : 24;
+    B.coarse_sweeps =
+        o->coarse_sweeps > 0 ? o->coarse_sweeps : default_coarse_sweeps(B.L[B.nlev - 1].n);
     B.use_field_in = D.field_in ? 1 : 0;
     B.trial = trial ? 1 : 0;
     B.tol = trial ? 1e-300 : tol;

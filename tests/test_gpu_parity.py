@@ -303,3 +303,53 @@ def test_fr_n_solve_force_adjoint_match_oracle(fr_n, prec):
     say(f"  adjoint: outer={sa.cycles} rel={sa.rel_resid:.2e} grad_err={aerr:.2e}")
     assert aerr < (1e-8 if prec == "fp64" else 1e-5)
     mg.close()
+
+
+# --- initial guesses, uniform start, edge sizes ------------------------------
+@pytest.mark.parametrize("model", ["fr", "sym", "cq"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_initial_guess_independence(model, prec):
+    """The solution does not depend on the starting field (reading c8 #6):
+    from the background, from a perturbed background, and from the solution
+    itself (zero cycles)."""
+    n, box = 32, 32.0
+    say("initial guess", model, prec)
+    P, prm = cfg(model, n, box)
+    delta = torch.from_numpy(lognormal(n, 51)).to(DEV)
+    mg = api.Context(n, device=DEV)
+    o = api.solver_opts(precision=prec)
+    tol = 1e-10 if prec == "fp64" else 1e-9
+    f0, s0 = mg.solve(model, prm, delta, tol=tol, opts=o)
+    bg = to_field(model, oracle.background(P))
+    rng = np.random.default_rng(52)
+    if model == "cq":
+        guess = 1e-3 * rng.standard_normal((n, n, n))
+    else:
+        guess = bg * rng.uniform(0.8, 1.2, (n, n, n))
+    f1, s1 = mg.solve(model, prm, delta, field_in=torch.from_numpy(guess).to(DEV), tol=tol, opts=o)
+    err = field_err(model, f1.cpu().numpy(), f0.cpu().numpy(), P)
+    f2, s2 = mg.solve(model, prm, delta, field_in=f0.clone(), tol=tol, opts=o)
+    say(f"  from background {s0.cycles}, from perturbed {s1.cycles} (diff {err:.1e}), "
+        f"from solution {s2.cycles}")
+    assert s2.cycles == 0 and torch.equal(f2, f0)
+    assert err < (1e-7 if prec == "fp64" else 1e-6)
+    mg.close()
+
+
+@pytest.mark.parametrize("n", [8, 12, 18, 20, 36, 44])
+def test_edge_grid_sizes_match_oracle(n):
+    """Sizes off the fast paths: two levels (8 -> 4, 12 -> 6), a grid that
+    cannot be coarsened (18), scalar kernels with large coarsest levels
+    (20 -> 10, 36 -> 18, 44 -> 22)."""
+    say("edge size", n)
+    P, prm = cfg("fr", n, float(n))
+    delta = lognormal(n, 60 + n)
+    ref, _, _, _ = oracle.solve(P, delta.astype(np.float64), tol=1e-12, max_cycles=400)
+    mg = api.Context(n, device=DEV)
+    for prec in ("fp64", "fp32"):
+        field, st = mg.solve("fr", prm, torch.from_numpy(delta).to(DEV), tol=1e-10,
+                             opts=api.solver_opts(precision=prec))
+        err = field_err("fr", field.cpu().numpy(), -ref, P)
+        say(f"  {prec}: outer={st.cycles} rel={st.rel_resid:.1e} err={err:.1e}")
+        assert err < 1e-7
+    mg.close()
