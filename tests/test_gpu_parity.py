@@ -353,3 +353,30 @@ def test_edge_grid_sizes_match_oracle(n):
         say(f"  {prec}: outer={st.cycles} rel={st.rel_resid:.1e} err={err:.1e}")
         assert err < 1e-7
     mg.close()
+
+
+@pytest.mark.parametrize("cycle", ["F", "W"])
+@pytest.mark.parametrize("model", ["fr", "sym"])
+def test_f_and_w_cycles_match_oracle(cycle, model):
+    """F- and W-cycles (fig:multigrid_cycles) reach the same discrete solution,
+    in both precisions, and the fixed two-cycles-per-check mode (inner_cycles=2)
+    as well."""
+    n, box = 48, 48.0
+    say("cycle", cycle, model)
+    P, prm = cfg(model, n, box)
+    delta = lognormal(n, 71)
+    ref, _, _, _ = oracle.solve(P, delta.astype(np.float64), tol=1e-12)
+    mg = api.Context(n, device=DEV)
+    for prec in ("fp64", "fp32"):
+        for inner in (0, 2):
+            field, st = mg.solve(model, prm, torch.from_numpy(delta).to(DEV), tol=1e-10,
+                                 opts=api.solver_opts(cycle=cycle, precision=prec,
+                                                      inner_cycles=inner))
+            err = field_err(model, field.cpu().numpy(), to_field(model, ref), P)
+            say(f"  {prec} inner={inner}: checks={st.cycles} cycles={st.vcycles} err={err:.1e}")
+            assert err < 1e-7
+        gd, sa = mg.solve_adjoint(model, prm, torch.from_numpy(delta).to(DEV), field,
+                                  torch.ones((n, n, n), dtype=torch.float64, device=DEV),
+                                  tol=1e-10, opts=api.solver_opts(cycle=cycle, precision=prec))
+        assert sa.status == 0
+    mg.close()
