@@ -284,3 +284,46 @@ def test_autograd_backward_matches_adjoint_chain():
     say(f"autograd vs explicit chain {e:.2e}, vs oracle {e_ora:.2e}")
     assert e < 1e-6 and e_ora < 1e-5
     mg.close()
+
+
+def test_c5_1024_fp32_refined_adjoint_matches_fp64():
+    """The differentiable solve repeated at 1024^3 (lognormal, seed 5): the
+    FP32-refined forward + adjoint against the plain FP64 GPU path (no oracle
+    at this size).  Only the forward solution is kept for the backward pass;
+    the adjoint rebuilds its own level pyramid from it (the multigrid levels
+    are recomputed, not stored)."""
+    n = 1024
+    t0 = time.perf_counter()
+    d = synthetic.c5_delta(n).astype(np.float32)
+    cells = torch.from_numpy(synthetic.c5_loss_cells(n)).to(DEV)
+    say(f"1024^3 inputs {time.perf_counter() - t0:.1f} s")
+    delta = torch.from_numpy(d).to(DEV)
+    del d
+    mg = api.Context(n, device=DEV)
+    prm = api.model_params(float(n), fr0=1e-5)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        o = api.solver_opts(precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        field, st = mg.solve("fr", prm, delta, tol=1e-6, opts=o)
+        force = mg.force("fr", prm, field)
+        loss, gforce = mg.loss_force_sq(force, cells)
+        del force
+        gfield = mg.force_adjoint("fr", prm, field, gforce)
+        del gforce
+        gd, sa = mg.solve_adjoint("fr", prm, delta, field, gfield, tol=1e-6, opts=o)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        say(f"  {prec}: forward {st.vcycles} cycles (rel {st.rel_resid:.1e}), adjoint "
+            f"{sa.vcycles} cycles (rel {sa.rel_resid:.1e}), {ms:.0f} ms, "
+            f"HBM in use {torch.cuda.memory_allocated() / 2**30:.0f} GiB (tensors)")
+        out[prec] = (field.cpu().numpy(), gd.cpu().numpy(), float(loss))
+        del field, gfield, gd
+    f32, g32, l32 = out["fp32"]
+    f64, g64, l64 = out["fp64"]
+    ferr = rel_err(f32, f64, f64.mean())
+    gerr = rel_err(g32, g64)
+    say(f"  fp32 vs fp64: field {ferr:.2e}, dL/d(delta) {gerr:.2e}, loss {abs(l32 - l64) / l64:.1e}")
+    assert ferr < 1e-5 and gerr < 1e-5
+    mg.close()
