@@ -165,6 +165,47 @@ template <typename T>
 __device__ __forceinline__ void stv(T* __restrict__ p, const T* in) {
   stn<T, Vec<T>::V>(p, in);
 }
+template <typename T, int N>
+__device__ __forceinline__ void ldn_nt(const T* __restrict__ p, T* out);
+template <typename T, int N>
+__device__ __forceinline__ void stn_nt(T* __restrict__ p, const T* in);
+// Streaming (non-temporal) 16-byte accesses for data touched once per pass:
+// the cache hint keeps them from displacing lines that neighbouring threads
+// still reuse (the other colour's rows and planes).
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ void ldv_nt(const T* __restrict__ p, T* out) {
+  if constexpr (sizeof(T) == 4) {
+    nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+    out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+  } else {
+    nt_d2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+    out[0] = v[0]; out[1] = v[1];
+  }
+}
+template <typename T>
+__device__ __forceinline__ void stv_nt(T* __restrict__ p, const T* in) {
+  if constexpr (sizeof(T) == 4) {
+    nt_f4 v = {in[0], in[1], in[2], in[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<nt_f4*>(p));
+  } else {
+    nt_d2 v = {in[0], in[1]};
+    __builtin_nontemporal_store(v, reinterpret_cast<nt_d2*>(p));
+  }
+}
+template <typename T, int N>
+__device__ __forceinline__ void ldn_nt(const T* __restrict__ p, T* out) {
+  constexpr int P = Vec<T>::V;
+#pragma unroll
+  for (int c = 0; c < N / P; ++c) ldv_nt<T>(p + c * P, out + c * P);
+}
+template <typename T, int N>
+__device__ __forceinline__ void stn_nt(T* __restrict__ p, const T* in) {
+  constexpr int P = Vec<T>::V;
+#pragma unroll
+  for (int c = 0; c < N / P; ++c) stv_nt<T>(p + c * P, in + c * P);
+}
 // Neighbour sums of the V cells (ih0 .. ih0+V-1, j, k) of colour c from the
 // other colour's array o; s = (j + k + c) & 1.  Same summation order as nbsum.
 template <typename T, int V = Vec<T>::V>
@@ -623,13 +664,13 @@ __device__ __forceinline__ void op_smooth_corr_v(const Lev& L, float* __restrict
   uint32_t q0 = (uint32_t)colour * (uint32_t)L.half + g;
   float sum[V] = {0, 0, 0, 0}, x[V], r[V], dc[V] = {0, 0, 0, 0}, eo[V] = {0, 0, 0, 0}, out[V];
   if (!(fresh && colour == 0)) nbsum_vec<float>(L, e + (1 - colour) * L.half, ih0, j, k, s, sum);
-  ldv<float>(X + q0, x);
-  ldv<float>(rho + q0, r);
-  if (M != FR) ldv<float>(dens + q0, dc);
+  ldv_nt<float>(X + q0, x);
+  ldv_nt<float>(rho + q0, r);
+  if (M != FR) ldv_nt<float>(dens + q0, dc);
   if (M == CQ && !fresh) ldv<float>(own + g, eo);
 #pragma unroll
   for (int q = 0; q < V; ++q) out[q] = corr_update<M>(C, h2, eo[q], sum[q], x[q], dc[q], r[q]);
-  stv<float>(own + g, out);
+  stv_nt<float>(own + g, out);
 }
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_smooth_corr_v(Lev L, float* e, const float* X,
@@ -660,11 +701,11 @@ __global__ __launch_bounds__(kBlock) void k_smooth_lin_v(Lev L, T* e, const T* d
   } else {
     nbsum_vec<T>(L, e + (1 - colour) * L.half, ih0, j, k, s, sum);
   }
-  ldv<T>(dg + q0, d);
-  ldv<T>(r + q0, rr);
+  ldv_nt<T>(dg + q0, d);
+  ldv_nt<T>(r + q0, rr);
 #pragma unroll
   for (int q = 0; q < V; ++q) out[q] = (rr[q] + kh2 * sum[q]) / (T(6) * kh2 + d[q]);
-  stv<T>(e + q0, out);
+  stv_nt<T>(e + q0, out);
 }
 
 // Neighbour sums of w + e (the updated FP64 values, formed exactly as the
@@ -865,9 +906,9 @@ __global__ __launch_bounds__(kBlock) void k_outer_fused_kv(Lev L, const double* 
         double sum[V];
         march_nbsum<float, V>(L, w, e, P, c, k, win[1 - c], sum, wu);
         const uint32_t q0 = (uint32_t)c * (uint32_t)L.half + prow(L, P.j, k) + (uint32_t)P.ih0;
-        if (e) stn<double, V>(w_new + q0, win[c][1]);
+        if (e) stn_nt<double, V>(w_new + q0, win[c][1]);
         float dn[V], ro[V], xo[V], zo[V];
-        ldn<float, V>(dens + q0, dn);
+        ldn_nt<float, V>(dens + q0, dn);
 #pragma unroll
         for (int q = 0; q < V; ++q) {
           const double vc = win[c][1][q];
@@ -877,9 +918,9 @@ __global__ __launch_bounds__(kBlock) void k_outer_fused_kv(Lev L, const double* 
           xo[q] = float(vc);
           zo[q] = 0.0f;
         }
-        stn<float, V>(rho + q0, ro);
-        stn<float, V>(X + q0, xo);
-        if (e_zero) stn<float, V>(e_zero + q0, zo);
+        stn_nt<float, V>(rho + q0, ro);
+        stn_nt<float, V>(X + q0, xo);
+        if (e_zero) stn_nt<float, V>(e_zero + q0, zo);
       }
 #pragma unroll
       for (int c = 0; c < 2; ++c)
@@ -1111,7 +1152,7 @@ __device__ __forceinline__ void op_prolong_v(const Lev& Lf, const Lev& Lc, T* __
         const int x = (col + j + k) & 1;  // child parity of this colour in the row
         T* dst = v + (uint32_t)col * (uint32_t)Lf.half + row;
         T cur[V];
-        ldv<T>(dst, cur);
+        ldv_nt<T>(dst, cur);
 #pragma unroll
         for (int q = 0; q < V; ++q) {
           T ay[3];
@@ -1120,7 +1161,7 @@ __device__ __forceinline__ void op_prolong_v(const Lev& Lf, const Lev& Lc, T* __
             ay[d] = T(0.75) * ax[d][1][q][x] + T(0.25) * ax[d][y ? 2 : 0][q][x];
           cur[q] += T(0.75) * ay[1] + T(0.25) * ay[z ? 2 : 0];
         }
-        stv<T>(dst, cur);
+        stv_nt<T>(dst, cur);
       }
     }
 }
@@ -1158,16 +1199,16 @@ __device__ __forceinline__ void op_resid_restrict_corr_v(
 #pragma unroll
           for (int q = 0; q < V; ++q) se[q] += ec[q];
           if (XH) {
-            ldv<float>(X + q0, x);
+            ldv_nt<float>(X + q0, x);
 #pragma unroll
             for (int q = 0; q < V; ++q) sx[q] += x[q];
           }
           continue;
         }
         nbsum_vec<float>(Lf, e + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
-        ldv<float>(X + q0, x);
-        ldv<float>(rho + q0, r);
-        if (M != FR) ldv<float>(dens + q0, dc);
+        ldv_nt<float>(X + q0, x);
+        ldv_nt<float>(rho + q0, r);
+        if (M != FR) ldv_nt<float>(dens + q0, dc);
 #pragma unroll
         for (int q = 0; q < V; ++q) {
           se[q] += ec[q];
@@ -1268,8 +1309,8 @@ __global__ __launch_bounds__(kBlock) void k_lin_resid_restrict_v(Lev Lf, Lev Lc,
         T sum[V], ec[V], dd[V], rr[V];
         nbsum_vec<T>(Lf, e + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
         ldv<T>(e + q0, ec);
-        ldv<T>(dg + q0, dd);
-        ldv<T>(r + q0, rr);
+        ldv_nt<T>(dg + q0, dd);
+        ldv_nt<T>(r + q0, rr);
 #pragma unroll
         for (int q = 0; q < V; ++q) sd[q] += rr[q] - (kh2 * (T(6) * ec[q] - sum[q]) + dd[q] * ec[q]);
       }

@@ -1193,9 +1193,9 @@ __global__ __launch_bounds__(kBlock) void k_force_kv(Lev L, const double* __rest
       gy[q] = float(-0.5 * (yp[q] - ym[q]));
       gz[q] = float(-0.5 * (win[2][q] - win[0][q]));
     }
-    stn<float, V>(out + r + i0, gx);
-    stn<float, V>(out + m + r + i0, gy);
-    stn<float, V>(out + 2 * m + r + i0, gz);
+    stn_nt<float, V>(out + r + i0, gx);
+    stn_nt<float, V>(out + m + r + i0, gy);
+    stn_nt<float, V>(out + 2 * m + r + i0, gz);
 #pragma unroll
     for (int q = 0; q < V; ++q) {
       win[0][q] = win[1][q];
