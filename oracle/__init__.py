@@ -89,6 +89,9 @@ def lib():
         L.ora_adjoint.argtypes = [P, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
         L.ora_apply_jacobian.argtypes = [P, dp, dp, dp, dp]
         L.ora_force_adjoint.argtypes = [P, dp, dp, dp]
+        L.ora_interp.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, ctypes.c_int, dp]
+        L.ora_sym_friction.argtypes = [P, dp, dp, dp, ctypes.c_int64, dp]
+        L.ora_gradient.argtypes = [ctypes.c_int, dp, dp]
         _lib = L
     return _lib
 
@@ -275,3 +278,51 @@ def force_adjoint(P, v, gforce):
     out = np.empty_like(v)
     lib().ora_force_adjoint(ctypes.byref(P), _ptr(v), _ptr(gforce), _ptr(out))
     return out
+
+
+# --- the particle side after the fifth force --------------------------------
+def interp(n, pos, grid):
+    """CIC interpolation of a mesh field (ncomp, N, N, N) or (N, N, N) to
+    particles (np, 3); returns (np, ncomp) or (np,)."""
+    g = _f64(grid)
+    scalar = g.ndim == 3
+    g = g.reshape(1 if scalar else g.shape[0], -1)
+    pos = _f64(pos).reshape(-1, 3)
+    out = np.empty((pos.shape[0], g.shape[0]))
+    lib().ora_interp(n, pos.shape[0], _ptr(pos), _ptr(np.ascontiguousarray(g)), g.shape[0],
+                     _ptr(out))
+    return out[:, 0] if scalar else out
+
+
+def sym_friction(P, u, pos, mom):
+    """Symmetron friction force per particle (eq:F_x_codeunit)."""
+    pos = _f64(pos).reshape(-1, 3)
+    mom = _f64(mom).reshape(-1, 3)
+    out = np.empty_like(pos)
+    lib().ora_sym_friction(ctypes.byref(P), _ptr(_f64(u)), _ptr(pos), _ptr(mom), pos.shape[0],
+                           _ptr(out))
+    return out
+
+
+def gradient(phi):
+    """-grad phi by central differences, shape (3, N, N, N)."""
+    phi = _f64(phi)
+    out = np.empty((3,) + phi.shape)
+    lib().ora_gradient(phi.shape[0], _ptr(phi), _ptr(out))
+    return out
+
+
+def poisson_newton(P, delta):
+    """Newtonian potential of eq:GR_poisson_codeunit on the grid: the
+    zero-mean solution of (7-point Laplacian) Phi = (3/2) Omega_m a^-1 delta,
+    by FFT (numpy) with the discrete symbol -4 sum sin^2(pi m_i / N)."""
+    d = _f64(delta)
+    n = d.shape[0]
+    s = np.sin(np.pi * np.fft.fftfreq(n)) ** 2  # sin^2(pi m / N)
+    sr = np.sin(np.pi * np.fft.rfftfreq(n)) ** 2
+    k2 = 4.0 * (s[:, None, None] + s[None, :, None] + sr[None, None, :])
+    k2[0, 0, 0] = 1.0
+    src = 1.5 * P.omega_m / P.a * np.fft.rfftn(d)
+    phik = -src / k2
+    phik[0, 0, 0] = 0.0
+    return np.fft.irfftn(phik, s=d.shape)

@@ -623,6 +623,63 @@ void ora_cic(int n, int64_t np, const double *pos, double *delta) {
   for (size_t q = 0; q < m; ++q) delta[q] = delta[q] / mean - 1.0;
 }
 
+/* CIC interpolation of a mesh field to particles, the counterpart of the
+ * assignment above (same cells and weights, Sec. 3.1): grid holds ncomp
+ * components of n^3 values, out[p*ncomp + c] = sum_8 w grid[c][cell]. */
+void ora_interp(int n, int64_t np, const double *pos, const double *grid, int ncomp,
+                double *out) {
+  size_t m = (size_t)n * n * n;
+  for (int64_t p = 0; p < np; ++p) {
+    int i0[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+      double s = pos[3 * p + a] - 0.5;
+      double f = floor(s);
+      t[a] = s - f;
+      i0[a] = WRAP(((int)f % n + n) % n, n);
+    }
+    for (int c = 0; c < ncomp; ++c) out[p * ncomp + c] = 0.0;
+    for (int dk = 0; dk < 2; ++dk)
+      for (int dj = 0; dj < 2; ++dj)
+        for (int di = 0; di < 2; ++di) {
+          double w = (di ? t[0] : 1.0 - t[0]) * (dj ? t[1] : 1.0 - t[1]) *
+                     (dk ? t[2] : 1.0 - t[2]);
+          size_t cell = IDX(n, WRAP(i0[0] + di, n), WRAP(i0[1] + dj, n), WRAP(i0[2] + dk, n));
+          for (int c = 0; c < ncomp; ++c) out[p * ncomp + c] += w * grid[c * m + cell];
+        }
+  }
+}
+
+/* Symmetron friction term of eq:F_x_codeunit, as printed:
+ * F_x = -9 Omega_m beta_star^2 xi^2 sqrt(1 - (a_star / a)^3) a^-4 u(x_p) p_p, u
+ * CIC-interpolated from the solved field; mom and out are [np][3]. */
+void ora_sym_friction(const ora_params *P, const double *u, const double *pos,
+                      const double *mom, int64_t np, double *out) {
+  double ratio = pow(P->a_star / P->a, 3.0);
+  double coef = -9.0 * P->omega_m * P->beta_star * P->beta_star * P->xi * P->xi *
+                sqrt(1.0 - ratio) / pow(P->a, 4.0);
+  for (int64_t p = 0; p < np; ++p) {
+    double up;
+    ora_interp(P->n, 1, pos + 3 * p, u, 1, &up);
+    for (int a = 0; a < 3; ++a) out[3 * p + a] = coef * up * mom[3 * p + a];
+  }
+}
+
+/* -grad phi by central differences, out [3][n^3] (x, y, z) */
+void ora_gradient(int n, const double *phi, double *out) {
+  size_t m = (size_t)n * n * n;
+#pragma omp parallel for schedule(static)
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        size_t c = IDX(n, i, j, k);
+        out[c] = -0.5 * (phi[IDX(n, WRAP(i + 1, n), j, k)] - phi[IDX(n, WRAP(i - 1, n), j, k)]);
+        out[m + c] = -0.5 * (phi[IDX(n, i, WRAP(j + 1, n), k)] - phi[IDX(n, i, WRAP(j - 1, n), k)]);
+        out[2 * m + c] =
+            -0.5 * (phi[IDX(n, i, j, WRAP(k + 1, n))] - phi[IDX(n, i, j, WRAP(k - 1, n))]);
+      }
+}
+
 /* ------------------------------------------------------------------ */
 /* Adjoint                                                             */
 /* ------------------------------------------------------------------ */

@@ -1,0 +1,97 @@
+"""Oracle pins for the particle side after the fifth force: CIC
+interpolation to particles, the Newtonian FFT Poisson potential and its
+gradient, the symmetron friction term.
+
+Pins: interpolation is the exact transpose of the (separately pinned) CIC
+assignment; it reproduces cell values at cell centres, constants, and linear
+fields exactly.  The Poisson potential satisfies the 7-point discrete
+equation (checked by finite differences, not by the FFT), has zero mean, and
+matches the closed form for a single Fourier mode.  The friction term's
+coefficient is the printed expression of eq:F_x_codeunit (parity unpinned
+beyond that: the paper gives no worked value); its interpolation part is
+pinned through interp.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+OM = 0.3
+
+
+def test_interp_is_transpose_of_cic_assignment():
+    n, npart = 12, 3000
+    rng = np.random.default_rng(1)
+    pos = rng.uniform(0, n, (npart, 3))
+    F = rng.standard_normal((n, n, n))
+    count = (oracle.cic(n, pos) + 1.0) * npart / n ** 3  # sum of CIC weights per cell
+    lhs = oracle.interp(n, pos, F).sum()
+    rhs = np.sum(F * count)
+    assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(F * count))
+
+
+def test_interp_cell_centres_constants_and_linear_fields():
+    n = 10
+    rng = np.random.default_rng(2)
+    F = rng.standard_normal((3, n, n, n))
+    cells = rng.integers(0, n, (50, 3))
+    pos = cells + 0.5
+    got = oracle.interp(n, pos, F)
+    ref = F[:, cells[:, 2], cells[:, 1], cells[:, 0]].T
+    assert np.array_equal(got, ref)
+    const = np.full((n, n, n), 2.5)
+    assert np.allclose(oracle.interp(n, rng.uniform(0, n, (100, 3)), const), 2.5, rtol=0, atol=1e-14)
+    # a field linear in x is reproduced exactly away from the periodic seam
+    i = np.arange(n, dtype=float)
+    lin = np.broadcast_to(0.3 * (i + 0.5), (n, n, n)).copy()
+    p = rng.uniform(1.0, n - 1.0, (200, 3))
+    assert np.allclose(oracle.interp(n, p, lin), 0.3 * p[:, 0], rtol=0, atol=1e-13)
+
+
+def _lap(phi):
+    return sum(np.roll(phi, s, a) for a in range(3) for s in (1, -1)) - 6.0 * phi
+
+
+@pytest.mark.parametrize("a", [1.0, 0.5])
+def test_poisson_satisfies_discrete_equation_with_zero_mean(a):
+    n = 16
+    P = oracle.params(oracle.FR, n, float(n), a=a, omega_m=OM)
+    d = np.random.default_rng(3).standard_normal((n, n, n))
+    d -= d.mean()
+    phi = oracle.poisson_newton(P, d)
+    src = 1.5 * OM / a * d
+    assert np.abs(_lap(phi) - src).max() <= 1e-12 * np.abs(src).max()
+    assert abs(phi.mean()) < 1e-14
+
+
+def test_poisson_single_mode_closed_form():
+    n, m = 24, 3
+    P = oracle.params(oracle.FR, n, float(n), omega_m=OM)
+    x = np.arange(n)
+    d = np.broadcast_to(np.sin(2 * np.pi * m * x / n)[None, :, None], (n, n, n)).copy()  # y mode
+    phi = oracle.poisson_newton(P, d)
+    ref = -1.5 * OM * d / (4.0 * np.sin(np.pi * m / n) ** 2)
+    assert np.abs(phi - ref).max() <= 1e-13
+
+
+def test_gradient_of_sine_is_exact_central_difference():
+    n, m = 20, 2
+    x = np.arange(n)
+    s = np.sin(2 * np.pi * m * x / n)
+    phi = np.broadcast_to(s[:, None, None], (n, n, n)).copy()  # varies along z
+    g = oracle.gradient(phi)
+    ref = -np.sin(2 * np.pi * m / n) * np.cos(2 * np.pi * m * x / n)
+    assert np.abs(g[2] - ref[:, None, None]).max() < 1e-14
+    assert np.abs(g[0]).max() == 0.0 and np.abs(g[1]).max() == 0.0
+
+
+def test_friction_is_interpolated_field_times_momentum():
+    n = 8
+    P = oracle.params(oracle.SYM, n, float(n), a=1.0, a_star=0.5, xi=2e-3, beta_star=1.3)
+    rng = np.random.default_rng(4)
+    u = rng.uniform(0.5, 1.0, (n, n, n))
+    pos = rng.uniform(0, n, (40, 3))
+    mom = rng.standard_normal((40, 3))
+    f = oracle.sym_friction(P, u, pos, mom)
+    coef = -9 * OM * 1.3 ** 2 * 2e-3 ** 2 * np.sqrt(1 - 0.5 ** 3)
+    assert np.allclose(f, coef * oracle.interp(n, pos, u)[:, None] * mom, rtol=1e-14, atol=0)
