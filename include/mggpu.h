@@ -168,6 +168,37 @@ int mg_relax_halfsweep(mg_ctx *ctx, int model, const mg_model_params *params,
 int mg_restrict(mg_ctx *ctx, const double *fine, double *coarse);
 int mg_prolong_add(mg_ctx *ctx, const double *coarse, double *fine);
 
+/* ---- The particle side after the fifth force (a particle-mesh step) ---- */
+
+/* CIC interpolation of a mesh field to particles: the same cells and weights
+ * as cic_assign (Sec. 3.1), so it is that assignment's transpose.
+ * grid: ncomp (1..3) components of n^3 device floats, [ncomp][k][j][i];
+ * pos: [n_part][3] device floats in [0, n); out: [n_part][ncomp] device
+ * floats.  Weights and sums in FP64.  MG_EINVAL on bad sizes or NULL. */
+int mg_interp_to_particles(mg_ctx *ctx, const float *grid, int ncomp, const float *pos,
+                           int64_t n_part, float *out);
+/* The same for one FP64 field (n^3 doubles), out: n_part doubles. */
+int mg_interp_field_to_particles(mg_ctx *ctx, const double *field, const float *pos,
+                                 int64_t n_part, double *out);
+/* Newtonian potential of eq:GR_poisson_codeunit on the grid: the zero-mean
+ * solution of (7-point discrete Laplacian) Phi = (3/2) Omega_m a^-1 delta,
+ * exact by FFT in FP64 (rocFFT, opened at first use; MG_EHIP if absent).
+ * delta: n^3 device floats; phi_out: n^3 device doubles, natural layout.
+ * Uses params->a and params->omega_m only. */
+int mg_poisson_newton(mg_ctx *ctx, const mg_model_params *params, const float *delta,
+                      double *phi_out);
+/* -grad phi by central differences, (phi(c+e) - phi(c-e))/2 per axis, the
+ * Newtonian force of eq:F_N_codeunit without H0/a-dot.  phi: n^3 device
+ * doubles; force_out: [3][n^3] device floats (x, y, z). */
+int mg_gradient(mg_ctx *ctx, const double *phi, float *force_out);
+/* Symmetron friction term of eq:F_x_codeunit as printed:
+ * -9 Omega_m beta_*^2 xi^2 sqrt(1 - (a_* / a)^3) a^-4 u(x_p) p_p, with u the
+ * solved symmetron field (n^3 device doubles) CIC-interpolated to each
+ * particle.  pos, mom, out: [n_part][3] device floats.  MG_EINVAL unless
+ * 0 < a_* < a. */
+int mg_symmetron_friction(mg_ctx *ctx, const mg_model_params *params, const double *u_field,
+                          const float *pos, const float *mom, int64_t n_part, float *out);
+
 /* Many independent boxes of different n and model in one persistent launch
  * (the paper runs independent realisations side by side over MPI, Sec. 3.1).
  * The launch is cooperative and never has more workgroups than can be

@@ -325,4 +325,4 @@ def poisson_newton(P, delta):
     src = 1.5 * P.omega_m / P.a * np.fft.rfftn(d)
     phik = -src / k2
     phik[0, 0, 0] = 0.0
-    return np.fft.irfftn(phik, s=d.shape)
+    return np.fft.irfftn(phik, s=d.shape, axes=(0, 1, 2))

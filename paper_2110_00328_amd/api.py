@@ -187,6 +187,59 @@ class Context:
                                               _p(grad_out), _p(loss_out)))
         return loss_out, grad_out
 
+    # -- the particle side after the fifth force -----------------------------
+    def interp_to_particles(self, grid, pos, out=None):
+        """CIC interpolation of a float32 mesh field (ncomp, n, n, n) or
+        (n, n, n) to particles (n_part, 3)."""
+        scalar = grid.dim() == 3
+        ncomp = 1 if scalar else grid.shape[0]
+        shape = self._grid() if scalar else (ncomp,) + self._grid()
+        _need(grid, torch.float32, shape, "grid")
+        _need(pos, torch.float32, (pos.shape[0], 3), "pos")
+        if out is None:
+            out = torch.empty((pos.shape[0], ncomp), dtype=torch.float32, device=pos.device)
+        _need(out, torch.float32, (pos.shape[0], ncomp), "out")
+        self._check(self.lib.mg_interp_to_particles(self.ptr, _p(grid), ncomp, _p(pos),
+                                                    pos.shape[0], _p(out)))
+        return out[:, 0] if scalar else out
+
+    def interp_field_to_particles(self, field, pos, out=None):
+        _need(field, torch.float64, self._grid(), "field")
+        _need(pos, torch.float32, (pos.shape[0], 3), "pos")
+        if out is None:
+            out = torch.empty(pos.shape[0], dtype=torch.float64, device=pos.device)
+        self._check(self.lib.mg_interp_field_to_particles(self.ptr, _p(field), _p(pos),
+                                                          pos.shape[0], _p(out)))
+        return out
+
+    def poisson_newton(self, params, delta, out=None):
+        """Newtonian potential (zero mean) of the density contrast."""
+        _need(delta, torch.float32, self._grid(), "delta")
+        if out is None:
+            out = torch.empty(self._grid(), dtype=torch.float64, device=delta.device)
+        _need(out, torch.float64, self._grid(), "phi_out")
+        self._check(self.lib.mg_poisson_newton(self.ptr, ctypes.byref(params), _p(delta), _p(out)))
+        return out
+
+    def gradient(self, phi, out=None):
+        """-grad phi by central differences, (3, n, n, n) float32."""
+        _need(phi, torch.float64, self._grid(), "phi")
+        if out is None:
+            out = torch.empty((3,) + self._grid(), dtype=torch.float32, device=phi.device)
+        _need(out, torch.float32, (3,) + self._grid(), "force_out")
+        self._check(self.lib.mg_gradient(self.ptr, _p(phi), _p(out)))
+        return out
+
+    def symmetron_friction(self, params, u_field, pos, mom, out=None):
+        _need(u_field, torch.float64, self._grid(), "u_field")
+        _need(pos, torch.float32, (pos.shape[0], 3), "pos")
+        _need(mom, torch.float32, pos.shape, "mom")
+        if out is None:
+            out = torch.empty_like(mom)
+        self._check(self.lib.mg_symmetron_friction(self.ptr, ctypes.byref(params), _p(u_field),
+                                                   _p(pos), _p(mom), pos.shape[0], _p(out)))
+        return out
+
     # -- batched boxes ------------------------------------------------------
     def _box_array(self, boxes):
         arr = (L.BoxDesc * len(boxes))()

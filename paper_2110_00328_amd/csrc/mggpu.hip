@@ -18,7 +18,11 @@
 #include <cstdlib>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
+
+#include <dlfcn.h>
+#include <rocfft/rocfft.h>  // declarations only: the library is opened at first use
 
 #include "mg_batched.h"
 #include "mg_kernels.h"
@@ -109,6 +113,13 @@ struct mg_ctx {
   bool bpinned = false;                    // shape fixed by mg_batched_set_config
   std::string bkey;
   double* nat64 = nullptr;     // natural-layout scratch (debug entry points)
+  // Newtonian potential by FFT (rocFFT, FP64), created at first use
+  bool fft_ready = false;
+  rocfft_plan fft_fwd = nullptr, fft_inv = nullptr;
+  rocfft_execution_info fft_info = nullptr;
+  void* fft_work = nullptr;
+  size_t fft_work_bytes = 0;
+  double2* fft_c = nullptr;    // n * n * (n/2 + 1) complex
   std::vector<void*> allocs;
   // event timing of the finest-level smoothers
   bool prof = false;
@@ -263,6 +274,64 @@ int ensure_adj(mg_ctx* ctx, int precision) {
     A.have64 = true;
   }
   return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// rocFFT, opened by full path at first use so that it binds to the same HIP
+// runtime as this library (a process may hold other copies of it)
+// ---------------------------------------------------------------------------
+struct RocfftApi {
+  void* h = nullptr;
+  decltype(&rocfft_setup) setup = nullptr;
+  decltype(&rocfft_plan_create) plan_create = nullptr;
+  decltype(&rocfft_plan_get_work_buffer_size) work_size = nullptr;
+  decltype(&rocfft_execution_info_create) info_create = nullptr;
+  decltype(&rocfft_execution_info_set_work_buffer) info_set_work = nullptr;
+  decltype(&rocfft_execution_info_set_stream) info_set_stream = nullptr;
+  decltype(&rocfft_execute) execute = nullptr;
+  decltype(&rocfft_plan_destroy) plan_destroy = nullptr;
+  decltype(&rocfft_execution_info_destroy) info_destroy = nullptr;
+};
+
+const RocfftApi* rocfft_api(std::string* err) {
+  static RocfftApi A;
+  static bool tried = false;
+  static std::string why;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!tried) {
+    tried = true;
+    const char* root = getenv("ROCM_PATH");
+    std::string path = std::string(root && *root ? root : "/opt/rocm") + "/lib/librocfft.so.0";
+    A.h = dlopen(path.c_str(), RTLD_NOW | RTLD_LOCAL);
+    if (!A.h) {
+      why = "cannot open " + path;
+    } else {
+      bool ok = true;
+      auto get = [&](auto& f, const char* name) {
+        f = reinterpret_cast<std::remove_reference_t<decltype(f)>>(dlsym(A.h, name));
+        ok = ok && f != nullptr;
+      };
+      get(A.setup, "rocfft_setup");
+      get(A.plan_create, "rocfft_plan_create");
+      get(A.work_size, "rocfft_plan_get_work_buffer_size");
+      get(A.info_create, "rocfft_execution_info_create");
+      get(A.info_set_work, "rocfft_execution_info_set_work_buffer");
+      get(A.info_set_stream, "rocfft_execution_info_set_stream");
+      get(A.execute, "rocfft_execute");
+      get(A.plan_destroy, "rocfft_plan_destroy");
+      get(A.info_destroy, "rocfft_execution_info_destroy");
+      if (!ok || A.setup() != rocfft_status_success) {
+        why = "rocFFT symbols or setup failed";
+        A.h = nullptr;
+      }
+    }
+  }
+  if (!A.h) {
+    *err = why;
+    return nullptr;
+  }
+  return &A;
 }
 
 // ---------------------------------------------------------------------------
@@ -1306,10 +1375,10 @@ __device__ __forceinline__ CicCell cic_cell(int n, const float* __restrict__ pos
   CicCell c;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float x = pos[3 * p + a];
-    float s = x - 0.5f;
-    float fl = floorf(s);
-    c.t[a] = double(s - fl);
+    // in double the offset and the fraction are exact for any float position
+    const double s = double(pos[3 * p + a]) - 0.5;
+    const double fl = floor(s);
+    c.t[a] = s - fl;
     int q = (int)fl;
     q %= n;
     if (q < 0) q += n;
@@ -1531,6 +1600,15 @@ void mg_ctx_destroy(mg_ctx* ctx) {
     if (p) (void)hipFree(p);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->hscal) (void)hipHostFree(ctx->hscal);
+  if (ctx->fft_ready) {
+    std::string e;
+    if (const RocfftApi* F = rocfft_api(&e)) {
+      if (ctx->fft_fwd) F->plan_destroy(ctx->fft_fwd);
+      if (ctx->fft_inv) F->plan_destroy(ctx->fft_inv);
+      if (ctx->fft_info) F->info_destroy(ctx->fft_info);
+    }
+  }
+  if (ctx->fft_work) (void)hipFree(ctx->fft_work);
   delete ctx;
 }
 
@@ -1618,6 +1696,198 @@ int mg_residual(mg_ctx* ctx, int model, const mg_model_params* params, const flo
   else if (model == MG_SYMMETRON) ACHK(resid64<SYM>(ctx, C, eps_bg, &r, d_out));
   else ACHK(resid64<CQ>(ctx, C, eps_bg, &r, d_out));
   if (rel) *rel = r;
+  return MG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// CIC interpolation to particles (same cells and weights as the assignment)
+template <typename TG, typename TO>
+__global__ __launch_bounds__(kBlock) void k_interp(int n, int64_t np, int ncomp,
+                                                   const float* __restrict__ pos,
+                                                   const TG* __restrict__ grid,
+                                                   TO* __restrict__ out) {
+  int64_t p = gid();
+  if (p >= np) return;
+  const CicCell c = cic_cell(n, pos, p);
+  const int64_t m = (int64_t)n * n * n;
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int di = q & 1, dj = (q >> 1) & 1, dk = (q >> 2) & 1;
+    const double w = (di ? c.t[0] : 1.0 - c.t[0]) * (dj ? c.t[1] : 1.0 - c.t[1]) *
+                     (dk ? c.t[2] : 1.0 - c.t[2]);
+    const int ii = c.i0[0] + di == n ? 0 : c.i0[0] + di;
+    const int jj = c.i0[1] + dj == n ? 0 : c.i0[1] + dj;
+    const int kk = c.i0[2] + dk == n ? 0 : c.i0[2] + dk;
+    const int64_t cell = ((int64_t)kk * n + jj) * n + ii;
+    for (int a = 0; a < ncomp; ++a) acc[a] += w * double(grid[a * m + cell]);
+  }
+  for (int a = 0; a < ncomp; ++a) out[p * ncomp + a] = TO(acc[a]);
+}
+
+// symmetron friction term per particle: coef u(x_p) p_p
+__global__ __launch_bounds__(kBlock) void k_sym_friction(int n, int64_t np,
+                                                         const float* __restrict__ pos,
+                                                         const double* __restrict__ u,
+                                                         const float* __restrict__ mom,
+                                                         double coef, float* __restrict__ out) {
+  int64_t p = gid();
+  if (p >= np) return;
+  const CicCell c = cic_cell(n, pos, p);
+  double up = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int di = q & 1, dj = (q >> 1) & 1, dk = (q >> 2) & 1;
+    const double w = (di ? c.t[0] : 1.0 - c.t[0]) * (dj ? c.t[1] : 1.0 - c.t[1]) *
+                     (dk ? c.t[2] : 1.0 - c.t[2]);
+    const int ii = c.i0[0] + di == n ? 0 : c.i0[0] + di;
+    const int jj = c.i0[1] + dj == n ? 0 : c.i0[1] + dj;
+    const int kk = c.i0[2] + dk == n ? 0 : c.i0[2] + dk;
+    up += w * u[((int64_t)kk * n + jj) * n + ii];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) out[3 * p + a] = float(coef * up * double(mom[3 * p + a]));
+}
+
+__global__ __launch_bounds__(kBlock) void k_f2d(int64_t m, const float* __restrict__ x,
+                                                double* __restrict__ y) {
+  int64_t g = gid();
+  if (g < m) y[g] = double(x[g]);
+}
+
+// multiply the half spectrum (n x n x (n/2+1), fastest last) by the inverse of
+// the 7-point discrete Laplacian symbol -4 sum sin^2(pi m_i / n) times coef,
+// including the 1/n^3 of the unnormalised inverse transform; zero mode -> 0
+__global__ __launch_bounds__(kBlock) void k_poisson_green(int n, double2* __restrict__ c,
+                                                          double coef) {
+  const int nx = n / 2 + 1;
+  int64_t g = gid();
+  const int64_t mc = (int64_t)n * n * nx;
+  if (g >= mc) return;
+  const int kx = (int)(g % nx);
+  const int64_t r = g / nx;
+  const int ky = (int)(r % n), kz = (int)(r / n);
+  const double sx = sinpi(double(kx) / n), sy = sinpi(double(ky) / n), sz = sinpi(double(kz) / n);
+  const double k2 = 4.0 * (sx * sx + sy * sy + sz * sz);
+  const double f = (g == 0) ? 0.0 : -coef / (k2 * (double(n) * n * n));
+  c[g].x *= f;
+  c[g].y *= f;
+}
+
+int ensure_fft(mg_ctx* ctx) {
+  if (ctx->fft_ready) return MG_OK;
+  std::string e;
+  const RocfftApi* F = rocfft_api(&e);
+  if (!F) return fail(ctx, MG_EHIP, "rocFFT unavailable: " + e);
+  const size_t n = (size_t)ctx->n;
+  const size_t len[3] = {n, n, n};
+  if (F->plan_create(&ctx->fft_fwd, rocfft_placement_notinplace, rocfft_transform_type_real_forward,
+                     rocfft_precision_double, 3, len, 1, nullptr) != rocfft_status_success ||
+      F->plan_create(&ctx->fft_inv, rocfft_placement_notinplace, rocfft_transform_type_real_inverse,
+                     rocfft_precision_double, 3, len, 1, nullptr) != rocfft_status_success)
+    return fail(ctx, MG_EHIP, "rocFFT plan creation failed");
+  size_t w1 = 0, w2 = 0;
+  F->work_size(ctx->fft_fwd, &w1);
+  F->work_size(ctx->fft_inv, &w2);
+  ctx->fft_work_bytes = std::max(w1, w2);
+  if (ctx->fft_work_bytes) HIPCHK(hipMalloc(&ctx->fft_work, ctx->fft_work_bytes));
+  if (F->info_create(&ctx->fft_info) != rocfft_status_success)
+    return fail(ctx, MG_EHIP, "rocFFT execution info failed");
+  if (ctx->fft_work_bytes) F->info_set_work(ctx->fft_info, ctx->fft_work, ctx->fft_work_bytes);
+  F->info_set_stream(ctx->fft_info, ctx->stream);
+  ACHK(dalloc(ctx, &ctx->fft_c, (int64_t)n * n * (n / 2 + 1)));
+  ctx->fft_ready = true;
+  return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mg_interp_to_particles(mg_ctx* ctx, const float* grid, int ncomp, const float* pos,
+                           int64_t np, float* out) {
+  if (!ctx) return MG_EINVAL;
+  if (!grid || !pos || !out || np <= 0 || ncomp < 1 || ncomp > 3)
+    return fail(ctx, MG_EINVAL, "mg_interp_to_particles: bad arguments");
+  k_interp<float, float><<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, ncomp, pos, grid, out);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_interp_field_to_particles(mg_ctx* ctx, const double* field, const float* pos, int64_t np,
+                                 double* out) {
+  if (!ctx) return MG_EINVAL;
+  if (!field || !pos || !out || np <= 0)
+    return fail(ctx, MG_EINVAL, "mg_interp_field_to_particles: bad arguments");
+  k_interp<double, double><<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, 1, pos, field, out);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_poisson_newton(mg_ctx* ctx, const mg_model_params* params, const float* delta,
+                      double* phi_out) {
+  if (!ctx) return MG_EINVAL;
+  if (!params || !delta || !phi_out) return fail(ctx, MG_EINVAL, "mg_poisson_newton: NULL");
+  if (!(params->a > 0.0) || !(params->omega_m > 0.0))
+    return fail(ctx, MG_EINVAL, "mg_poisson_newton: need a > 0 and omega_m > 0");
+  ACHK(ensure_fft(ctx));
+  std::string e;
+  const RocfftApi* F = rocfft_api(&e);
+  const int n = ctx->n;
+  const int64_t m = (int64_t)n * n * n;
+  const int64_t mc = (int64_t)n * n * (n / 2 + 1);
+  k_f2d<<<nblk(m), kBlock, 0, ctx->stream>>>(m, delta, phi_out);
+  LAUNCHCHK();
+  void* in[1] = {phi_out};
+  void* cout[1] = {ctx->fft_c};
+  if (F->execute(ctx->fft_fwd, in, cout, ctx->fft_info) != rocfft_status_success)
+    return fail(ctx, MG_EHIP, "rocFFT forward transform failed");
+  k_poisson_green<<<nblk(mc), kBlock, 0, ctx->stream>>>(n, ctx->fft_c,
+                                                        1.5 * params->omega_m / params->a);
+  LAUNCHCHK();
+  void* cin[1] = {ctx->fft_c};
+  void* out[1] = {phi_out};
+  if (F->execute(ctx->fft_inv, cin, out, ctx->fft_info) != rocfft_status_success)
+    return fail(ctx, MG_EHIP, "rocFFT inverse transform failed");
+  return MG_OK;
+}
+
+int mg_gradient(mg_ctx* ctx, const double* phi, float* force_out) {
+  if (!ctx) return MG_EINVAL;
+  if (!phi || !force_out) return fail(ctx, MG_EINVAL, "mg_gradient: NULL array");
+  Consts C;
+  memset(&C, 0, sizeof C);
+  C.model = CQ;  // Phi5 = phi5 * f with phi5 = 1: the plain potential
+  C.phi5 = 1.0;
+  const int n = ctx->n;
+  int64_t m = (int64_t)n * n * n;
+  if (n % 4 == 0) {
+    unsigned nchunk = (unsigned)(((int64_t)n * n / 4 + kBlock - 1) / kBlock);
+    unsigned nb = nchunk * (unsigned)((n + kMarchKT - 1) / kMarchKT);
+    k_force_kv<<<nb, kBlock, 0, ctx->stream>>>(ctx->L[0], phi, C, force_out, kMarchKT);
+  } else {
+    k_force<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], phi, C, force_out);
+  }
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_symmetron_friction(mg_ctx* ctx, const mg_model_params* params, const double* u_field,
+                          const float* pos, const float* mom, int64_t np, float* out) {
+  if (!ctx) return MG_EINVAL;
+  if (!params || !u_field || !pos || !mom || !out || np <= 0)
+    return fail(ctx, MG_EINVAL, "mg_symmetron_friction: bad arguments");
+  const double a = params->a, as = params->sym_a_star;
+  if (!(a > 0.0) || !(as > 0.0) || !(as < a))
+    return fail(ctx, MG_EINVAL, "mg_symmetron_friction: need 0 < a_* < a");
+  const double coef = -9.0 * params->omega_m * params->sym_beta_star * params->sym_beta_star *
+                      params->sym_xi * params->sym_xi * sqrt(1.0 - pow(as / a, 3.0)) /
+                      pow(a, 4.0);
+  k_sym_friction<<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, pos, u_field, mom, coef, out);
+  LAUNCHCHK();
   return MG_OK;
 }
 

@@ -1,0 +1,78 @@
+"""GPU parity of the particle side after the fifth force: CIC interpolation
+of mesh fields to particles, the Newtonian FFT Poisson potential, its
+gradient, the symmetron friction term; against the oracle on the same
+seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic
+from paper_2110_00328_amd import api
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("n,npart", [(24, 20001), (64, 64 ** 3)])
+def test_interp_to_particles_matches_oracle(n, npart):
+    say("interp", n, npart)
+    rng = np.random.default_rng(n)
+    pos = rng.uniform(0, n, (npart, 3)).astype(np.float32)
+    pos[:50] = rng.integers(0, n, (50, 3)) + 0.0  # on cell corners, incl. the seam
+    pos[50:100] = np.float32(n) - np.float32(1e-4)
+    grid = rng.standard_normal((3, n, n, n)).astype(np.float32)
+    mg = api.Context(n, device=DEV)
+    got = mg.interp_to_particles(torch.from_numpy(grid).to(DEV), torch.from_numpy(pos).to(DEV))
+    ref = oracle.interp(n, pos.astype(np.float64), grid.astype(np.float64))
+    err = np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max()
+    say(f"  max rel {err:.1e}")
+    assert err < 1e-6
+    f64 = rng.standard_normal((n, n, n))
+    g1 = mg.interp_field_to_particles(torch.from_numpy(f64).to(DEV), torch.from_numpy(pos).to(DEV))
+    r1 = oracle.interp(n, pos.astype(np.float64), f64)
+    assert np.abs(g1.cpu().numpy() - r1).max() <= 1e-13 * np.abs(r1).max()
+    mg.close()
+
+
+@pytest.mark.parametrize("n", [18, 32, 48, 128])
+def test_poisson_newton_and_gradient_match_oracle(n):
+    say("poisson", n)
+    P = oracle.params(oracle.FR, n, float(n), a=0.8)
+    prm = api.model_params(float(n), a=0.8)
+    d = synthetic.lognormal_delta(n, 300 + n, sigma_delta=2.0).astype(np.float32)
+    mg = api.Context(n, device=DEV)
+    phi = mg.poisson_newton(prm, torch.from_numpy(d).to(DEV))
+    ref = oracle.poisson_newton(P, d.astype(np.float64))
+    err = np.linalg.norm(phi.cpu().numpy() - ref) / np.linalg.norm(ref)
+    g = mg.gradient(phi).cpu().numpy().astype(np.float64)
+    gref = oracle.gradient(ref)
+    gerr = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    say(f"  phi {err:.1e} grad {gerr:.1e}")
+    assert err < 1e-12 and gerr < 1e-6
+    mg.close()
+
+
+def test_symmetron_friction_matches_oracle():
+    n, npart = 32, 5000
+    kw = dict(a=1.0, a_star=0.5, xi=1.0 / oracle.C_OVER_H0, beta_star=1.2)
+    P = oracle.params(oracle.SYM, n, float(n), **kw)
+    prm = api.model_params(float(n), **kw)
+    rng = np.random.default_rng(9)
+    u = rng.uniform(0.3, 1.0, (n, n, n))
+    pos = rng.uniform(0, n, (npart, 3)).astype(np.float32)
+    mom = rng.standard_normal((npart, 3)).astype(np.float32)
+    mg = api.Context(n, device=DEV)
+    got = mg.symmetron_friction(prm, torch.from_numpy(u).to(DEV), torch.from_numpy(pos).to(DEV),
+                                torch.from_numpy(mom).to(DEV)).cpu().numpy()
+    ref = oracle.sym_friction(P, u, pos.astype(np.float64), mom.astype(np.float64))
+    assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+    with pytest.raises(api.MGError):
+        mg.symmetron_friction(api.model_params(float(n), a=0.4, a_star=0.5),
+                              torch.from_numpy(u).to(DEV), torch.from_numpy(pos).to(DEV),
+                              torch.from_numpy(mom).to(DEV))
+    mg.close()
