@@ -79,6 +79,10 @@ def cpu_baseline(n, fr0, tol):
                 seconds=dt)
 
 
+def m_cells(n):
+    return float(n) ** 3
+
+
 def _timed(fn, reps):
     import torch
     fn()
@@ -93,8 +97,9 @@ def _timed(fn, reps):
 def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
     """The other workloads the metric names, timed outside the main loop:
     |f_R0| = 1e-6 forward+adjoint, coupled quintessence forward (FP32-refined
-    and FP64), and the 64-box batched sweep in one persistent launch against
-    the same boxes solved one after another."""
+    and FP64), the particle side after the fifth force, and the 64-box
+    batched sweep in one persistent launch against the same boxes solved one
+    after another."""
     import tempfile
 
     import numpy as np
@@ -145,6 +150,29 @@ def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
         leg[prec + "_cycles"] = dict(st)
     leg["fp64_over_fp32"] = leg["fp64_ms"] / leg["fp32_ms"]
     out["cq_solve_force"] = leg
+    # the particle side after the fifth force, at the same size: Newtonian
+    # potential by FFT, total force (potentials summed, then differenced), CIC
+    # interpolation of the three components to every particle, friction term
+    prm = api.model_params(float(n), fr0=a.fr0)
+    mg.solve("fr", prm, delta, out=field, tol=tol)
+    phin = torch.empty_like(field)
+    npart = pos.shape[0]
+    ppart = torch.empty((npart, 3), dtype=torch.float32, device=dev)
+    pfric = torch.empty_like(ppart)
+    u = torch.full_like(field, 0.8)
+    prms = api.model_params(float(n), a=1.0, a_star=0.5)
+    leg = dict(particles=npart)
+    leg["poisson_fft_ms"] = _timed(lambda: mg.poisson_newton(prm, delta, out=phin), 3)
+    leg["total_force_ms"] = _timed(lambda: mg.total_force("fr", prm, phin, field, out=force), 3)
+    leg["interp_ms"] = _timed(lambda: mg.interp_to_particles(force, pos, out=ppart), 3)
+    leg["sym_friction_ms"] = _timed(
+        lambda: mg.symmetron_friction(prms, u, pos, ppart, out=pfric), 3)
+    # algorithmic bytes: positions 12 + result 12 per particle, each grid
+    # cell's three components read once (12 per cell)
+    leg["interp_GBps"] = (24.0 * npart + 12.0 * m_cells(n)) / (leg["interp_ms"] * 1e6)
+    leg["total_force_GBps"] = 28.0 * m_cells(n) / (leg["total_force_ms"] * 1e6)
+    out["particle_side"] = leg
+    del phin, ppart, pfric, u
     # 64 boxes of 64^3 / 96^3 / 128^3, f(R) with log-uniform |f_R0| and symmetron
     spec = synthetic.c4_boxes()
     boxes = []

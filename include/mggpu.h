@@ -191,6 +191,17 @@ int mg_poisson_newton(mg_ctx *ctx, const mg_model_params *params, const float *d
  * Newtonian force of eq:F_N_codeunit without H0/a-dot.  phi: n^3 device
  * doubles; force_out: [3][n^3] device floats (x, y, z). */
 int mg_gradient(mg_ctx *ctx, const double *phi, float *force_out);
+/* Total force without H0/a-dot: -grad of (s_N phi_n + Phi5(field)) by the
+ * same central differences, the two potentials summed before differencing
+ * as the paper does for coupled quintessence after
+ * eq:csf_particle_geodesic_code2.  phi_n: the potential of the standard
+ * Poisson equation (mg_poisson_newton); s_N = exp(beta phibar) for MG_CQ
+ * (the background factor of eq:csf_poisson_code applied to the force) and 1
+ * otherwise; Phi5 as in mg_force.  phi_n, field: n^3 device doubles;
+ * force_out: [3][n^3] device floats.  MG_EINVAL for NULL arrays or bad
+ * parameters. */
+int mg_total_force(mg_ctx *ctx, int model, const mg_model_params *params, const double *phi_n,
+                   const double *field, float *force_out);
 /* Symmetron friction term of eq:F_x_codeunit as printed:
  * -9 Omega_m beta_*^2 xi^2 sqrt(1 - (a_* / a)^3) a^-4 u(x_p) p_p, with u the
  * solved symmetron field (n^3 device doubles) CIC-interpolated to each

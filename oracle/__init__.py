@@ -312,6 +312,18 @@ def gradient(phi):
     return out
 
 
+def total_force(P, phi_n, v):
+    """Newtonian plus fifth force, -grad(s_N Phi_N + Phi5): the two potentials
+    are summed on the grid and then differenced (the paper's treatment of
+    coupled quintessence after eq:csf_particle_geodesic_code2).  For CQ the
+    standard Poisson potential is scaled by exp(beta phibar), the background
+    factor of eq:csf_poisson_code, which the paper applies to the Newtonian
+    force instead of the source.  gradient() and force() are both linear in
+    the potential, so their sum is the difference of the summed potential."""
+    sn = np.exp(P.beta * P.phibar) if P.model == CQ else 1.0
+    return gradient(sn * _f64(phi_n)) + force(P, v)
+
+
 def poisson_newton(P, delta):
     """Newtonian potential of eq:GR_poisson_codeunit on the grid: the
     zero-mean solution of (7-point Laplacian) Phi = (3/2) Omega_m a^-1 delta,

@@ -21,7 +21,8 @@ EXPORTS = (
     "mg_loss_force_sq", "mg_relax_halfsweep", "mg_restrict", "mg_prolong_add",
     "mg_solve_batched", "mg_prof_enable", "mg_prof_read", "mg_batched_tune",
     "mg_batched_config", "mg_batched_set_config", "mg_interp_to_particles",
-    "mg_interp_field_to_particles", "mg_poisson_newton", "mg_gradient", "mg_symmetron_friction",
+    "mg_interp_field_to_particles", "mg_poisson_newton", "mg_gradient", "mg_total_force",
+    "mg_symmetron_friction",
 )
 MG_PROF_SMOOTH32, MG_PROF_SMOOTH64, MG_PROF_LIN32, MG_PROF_LIN64 = 0, 1, 2, 3
 
@@ -118,6 +119,7 @@ def load():
         "mg_interp_field_to_particles": (ci, [vp, vp, vp, i64, vp]),
         "mg_poisson_newton": (ci, [vp, P(ModelParams), vp, vp]),
         "mg_gradient": (ci, [vp, vp, vp]),
+        "mg_total_force": (ci, [vp, ci, P(ModelParams), vp, vp, vp]),
         "mg_symmetron_friction": (ci, [vp, P(ModelParams), vp, vp, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():

@@ -230,6 +230,17 @@ class Context:
         self._check(self.lib.mg_gradient(self.ptr, _p(phi), _p(out)))
         return out
 
+    def total_force(self, model, params, phi_n, field, out=None):
+        """-grad(s_N phi_n + Phi5(field)), s_N = exp(beta phibar) for CQ, else 1."""
+        _need(phi_n, torch.float64, self._grid(), "phi_n")
+        _need(field, torch.float64, self._grid(), "field")
+        if out is None:
+            out = torch.empty((3,) + self._grid(), dtype=torch.float32, device=field.device)
+        _need(out, torch.float32, (3,) + self._grid(), "force_out")
+        self._check(self.lib.mg_total_force(self.ptr, model_id(model), ctypes.byref(params), _p(phi_n),
+                                            _p(field), _p(out)))
+        return out
+
     def symmetron_friction(self, params, u_field, pos, mom, out=None):
         _need(u_field, torch.float64, self._grid(), "u_field")
         _need(pos, torch.float32, (pos.shape[0], 3), "pos")

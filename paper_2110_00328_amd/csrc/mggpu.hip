@@ -1191,8 +1191,18 @@ __device__ __forceinline__ double dphi5_of(const Consts& C, double f) {
   return C.phi5;
 }
 
-__global__ __launch_bounds__(kBlock) void k_force(Lev L, const double* __restrict__ f, Consts C,
-                                                  float* __restrict__ out) {
+// Phi5 of the field plus, when ADD, a second potential (the Newtonian one)
+template <bool ADD>
+__device__ __forceinline__ double pot_at(const Consts& C, const double* __restrict__ f,
+                                         const double* __restrict__ pn, double sn, int64_t c) {
+  const double v = phi5_of(C, f[c]);
+  return ADD ? v + sn * pn[c] : v;
+}
+
+template <bool ADD>
+__global__ __launch_bounds__(kBlock) void k_force(Lev L, const double* __restrict__ f,
+                                                  const double* __restrict__ pn, double sn,
+                                                  Consts C, float* __restrict__ out) {
   int64_t g = gid();
   const int n = L.n;
   int64_t m = 2 * L.half;
@@ -1203,11 +1213,11 @@ __global__ __launch_bounds__(kBlock) void k_force(Lev L, const double* __restric
   int jp = j + 1 == n ? 0 : j + 1, jm = j == 0 ? n - 1 : j - 1;
   int kp = k + 1 == n ? 0 : k + 1, km = k == 0 ? n - 1 : k - 1;
   int64_t row = (int64_t)k * n + j;
-  double gx = -0.5 * (phi5_of(C, f[row * n + ip]) - phi5_of(C, f[row * n + im]));
-  double gy = -0.5 * (phi5_of(C, f[((int64_t)k * n + jp) * n + i]) -
-                      phi5_of(C, f[((int64_t)k * n + jm) * n + i]));
-  double gz = -0.5 * (phi5_of(C, f[((int64_t)kp * n + j) * n + i]) -
-                      phi5_of(C, f[((int64_t)km * n + j) * n + i]));
+  double gx = -0.5 * (pot_at<ADD>(C, f, pn, sn, row * n + ip) - pot_at<ADD>(C, f, pn, sn, row * n + im));
+  double gy = -0.5 * (pot_at<ADD>(C, f, pn, sn, ((int64_t)k * n + jp) * n + i) -
+                      pot_at<ADD>(C, f, pn, sn, ((int64_t)k * n + jm) * n + i));
+  double gz = -0.5 * (pot_at<ADD>(C, f, pn, sn, ((int64_t)kp * n + j) * n + i) -
+                      pot_at<ADD>(C, f, pn, sn, ((int64_t)km * n + j) * n + i));
   out[g] = float(gx);
   out[m + g] = float(gy);
   out[2 * m + g] = float(gz);
@@ -1217,8 +1227,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Lev L, const double* __restric
 // row and walks kMarchKT planes, keeping Phi5 of planes k-1, k, k+1 in
 // registers (the field is read from HBM once); rows j +- 1 and the row's
 // edge cells come from L1/L2.  Requires n % 4 == 0.
-__global__ __launch_bounds__(kBlock) void k_force_kv(Lev L, const double* __restrict__ f, Consts C,
-                                                     float* __restrict__ out, int kt) {
+template <bool ADD>
+__global__ __launch_bounds__(kBlock) void k_force_kv(Lev L, const double* __restrict__ f,
+                                                     const double* __restrict__ pn, double sn,
+                                                     Consts C, float* __restrict__ out, int kt) {
   constexpr int V = 4;
   const int n = L.n;
   const uint32_t ngrp = (uint32_t)n * (uint32_t)n / V;  // groups per plane
@@ -1241,6 +1253,11 @@ __global__ __launch_bounds__(kBlock) void k_force_kv(Lev L, const double* __rest
     ldn<double, V>(f + row(jr, kr) + i0, v);
 #pragma unroll
     for (int q = 0; q < V; ++q) ph[q] = phi5_of(C, v[q]);
+    if (ADD) {
+      ldn<double, V>(pn + row(jr, kr) + i0, v);
+#pragma unroll
+      for (int q = 0; q < V; ++q) ph[q] += sn * v[q];
+    }
   };
   double win[3][V];
   ld(j, k0 == 0 ? n - 1 : k0 - 1, win[0]);
@@ -1251,8 +1268,8 @@ __global__ __launch_bounds__(kBlock) void k_force_kv(Lev L, const double* __rest
     ld(jm, k, ym);
     ld(jp, k, yp);
     const int64_t r = row(j, k);
-    xv[0] = phi5_of(C, f[r + im]);
-    xv[V + 1] = phi5_of(C, f[r + ip]);
+    xv[0] = pot_at<ADD>(C, f, pn, sn, r + im);
+    xv[V + 1] = pot_at<ADD>(C, f, pn, sn, r + ip);
 #pragma unroll
     for (int q = 0; q < V; ++q) xv[q + 1] = win[1][q];
     float gx[V], gy[V], gz[V];
@@ -1777,6 +1794,23 @@ __global__ __launch_bounds__(kBlock) void k_poisson_green(int n, double2* __rest
   c[g].y *= f;
 }
 
+// -grad of Phi5(f) (+ pn): z-marching kernel when n % 4 == 0
+void launch_force(mg_ctx* ctx, const Consts& C, const double* f, const double* pn, double sn,
+                  float* out) {
+  const int n = ctx->n;
+  const int64_t m = (int64_t)n * n * n;
+  if (n % 4 == 0) {
+    unsigned nchunk = (unsigned)(((int64_t)n * n / 4 + kBlock - 1) / kBlock);
+    unsigned nb = nchunk * (unsigned)((n + kMarchKT - 1) / kMarchKT);
+    if (pn) k_force_kv<true><<<nb, kBlock, 0, ctx->stream>>>(ctx->L[0], f, pn, sn, C, out, kMarchKT);
+    else k_force_kv<false><<<nb, kBlock, 0, ctx->stream>>>(ctx->L[0], f, nullptr, 0.0, C, out,
+                                                           kMarchKT);
+  } else {
+    if (pn) k_force<true><<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], f, pn, sn, C, out);
+    else k_force<false><<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], f, nullptr, 0.0, C, out);
+  }
+}
+
 int ensure_fft(mg_ctx* ctx) {
   if (ctx->fft_ready) return MG_OK;
   std::string e;
@@ -1862,15 +1896,20 @@ int mg_gradient(mg_ctx* ctx, const double* phi, float* force_out) {
   memset(&C, 0, sizeof C);
   C.model = CQ;  // Phi5 = phi5 * f with phi5 = 1: the plain potential
   C.phi5 = 1.0;
-  const int n = ctx->n;
-  int64_t m = (int64_t)n * n * n;
-  if (n % 4 == 0) {
-    unsigned nchunk = (unsigned)(((int64_t)n * n / 4 + kBlock - 1) / kBlock);
-    unsigned nb = nchunk * (unsigned)((n + kMarchKT - 1) / kMarchKT);
-    k_force_kv<<<nb, kBlock, 0, ctx->stream>>>(ctx->L[0], phi, C, force_out, kMarchKT);
-  } else {
-    k_force<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], phi, C, force_out);
-  }
+  launch_force(ctx, C, phi, nullptr, 0.0, force_out);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
+int mg_total_force(mg_ctx* ctx, int model, const mg_model_params* params, const double* phi_n,
+                   const double* field, float* force_out) {
+  if (!ctx) return MG_EINVAL;
+  Consts C;
+  ACHK(make_consts(ctx, model, params, ctx->n, &C));
+  if (!phi_n || !field || !force_out) return fail(ctx, MG_EINVAL, "mg_total_force: NULL array");
+  // coupled quintessence: the standard potential carries exp(beta phibar)
+  const double sn = model == MG_CQ ? exp(params->cq_beta * params->cq_phibar) : 1.0;
+  launch_force(ctx, C, field, phi_n, sn, force_out);
   LAUNCHCHK();
   return MG_OK;
 }
@@ -1897,15 +1936,7 @@ int mg_force(mg_ctx* ctx, int model, const mg_model_params* params, const double
   Consts C;
   ACHK(make_consts(ctx, model, params, ctx->n, &C));
   if (!field || !force_out) return fail(ctx, MG_EINVAL, "mg_force: NULL array");
-  const int n = ctx->n;
-  int64_t m = (int64_t)n * n * n;
-  if (n % 4 == 0) {
-    unsigned nchunk = (unsigned)(((int64_t)n * n / 4 + kBlock - 1) / kBlock);
-    unsigned nb = nchunk * (unsigned)((n + kMarchKT - 1) / kMarchKT);
-    k_force_kv<<<nb, kBlock, 0, ctx->stream>>>(ctx->L[0], field, C, force_out, kMarchKT);
-  } else {
-    k_force<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], field, C, force_out);
-  }
+  launch_force(ctx, C, field, nullptr, 0.0, force_out);
   LAUNCHCHK();
   return MG_OK;
 }

@@ -76,3 +76,32 @@ def test_symmetron_friction_matches_oracle():
                               torch.from_numpy(u).to(DEV), torch.from_numpy(pos).to(DEV),
                               torch.from_numpy(mom).to(DEV))
     mg.close()
+
+
+@pytest.mark.parametrize("model,n", [("fr", 32), ("sym", 18), ("cq", 40), ("cq", 18)])
+def test_total_force_matches_oracle(model, n):
+    """Newtonian and fifth-force potentials summed, then differenced; both
+    force kernels (z-marching for n % 4 == 0, per cell otherwise)."""
+    say("total force", model, n)
+    rng = np.random.default_rng(70 + n)
+    mid = {"fr": oracle.FR, "sym": oracle.SYM, "cq": oracle.CQ}[model]
+    P = oracle.params(mid, n, 2.0 * n, a=0.9)
+    prm = api.model_params(2.0 * n, a=0.9)
+    phin = 1e-3 * rng.standard_normal((n, n, n))
+    if model == "fr":
+        w = 1e-6 * rng.uniform(0.5, 2.0, (n, n, n))
+        field, vora = -w, w  # the library's f(R) field is f_R = -w
+    elif model == "sym":
+        field = rng.uniform(0.0, 1.0, (n, n, n))
+        vora = field
+    else:
+        field = rng.standard_normal((n, n, n))
+        vora = field
+    mg = api.Context(n, device=DEV)
+    g = mg.total_force(model, prm, torch.from_numpy(phin).to(DEV),
+                       torch.from_numpy(np.ascontiguousarray(field)).to(DEV)).cpu().numpy()
+    ref = oracle.total_force(P, phin, vora)
+    err = np.abs(g - ref).max() / np.abs(ref).max()
+    say(f"  max rel {err:.1e}")
+    assert err < 1e-6
+    mg.close()

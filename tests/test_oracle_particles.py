@@ -95,3 +95,31 @@ def test_friction_is_interpolated_field_times_momentum():
     f = oracle.sym_friction(P, u, pos, mom)
     coef = -9 * OM * 1.3 ** 2 * 2e-3 ** 2 * np.sqrt(1 - 0.5 ** 3)
     assert np.allclose(f, coef * oracle.interp(n, pos, u)[:, None] * mom, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("model", ["fr", "cq"])
+def test_total_force_single_modes_closed_form(model):
+    """Phi_N varies along x, the scalar field along y: the x component is the
+    Newtonian force (scaled by exp(beta phibar) for CQ), the y component the
+    fifth force (-1/2 c~^2 f_R for f(R), beta phi~ for CQ), z vanishes."""
+    n, m1, m2 = 16, 1, 3
+    x = np.arange(n)
+    sx = np.sin(2 * np.pi * m1 * x / n)
+    sy = np.sin(2 * np.pi * m2 * x / n)
+    phin = np.broadcast_to(sx[None, None, :], (n, n, n)).copy()
+    if model == "fr":
+        P = oracle.params(oracle.FR, n, 64.0, omega_m=OM)
+        # the oracle's f(R) variable is w = -f_R > 0, and Phi5 = c~^2 w / 2
+        v = 1e-6 * (1.5 + np.broadcast_to(sy[None, :, None], (n, n, n)))
+        sn, amp = 1.0, 0.5 * oracle.ctilde(n, 64.0) ** 2 * 1e-6
+    else:
+        P = oracle.params(oracle.CQ, n, 64.0, omega_m=OM, beta=-0.2, phibar=0.5)
+        v = 3.0 * np.broadcast_to(sy[None, :, None], (n, n, n)).copy()
+        sn, amp = np.exp(-0.2 * 0.5), -0.2 * 3.0
+    g = oracle.total_force(P, phin, v)
+    gx = -sn * np.sin(2 * np.pi * m1 / n) * np.cos(2 * np.pi * m1 * x / n)
+    gy = -amp * np.sin(2 * np.pi * m2 / n) * np.cos(2 * np.pi * m2 * x / n)
+    scale = max(abs(sn), abs(amp))
+    assert np.abs(g[0] - gx[None, None, :]).max() <= 1e-13 * scale
+    assert np.abs(g[1] - gy[None, :, None]).max() <= 1e-13 * scale
+    assert np.abs(g[2]).max() <= 1e-13 * scale
