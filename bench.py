@@ -134,9 +134,11 @@ def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
         leg[prec + "_cycles"] = dict(st)
     leg["fp64_over_fp32"] = leg["fp64_ms"] / leg["fp32_ms"]
     out["fr0_1e-6_solve_adjoint"] = leg
-    # coupled quintessence (alpha=0.1, beta=-0.2; phibar=0.5 and lambda are stand-ins)
-    prmq = api.model_params(float(n))
-    leg = {}
+    # coupled quintessence (alpha=0.1, beta=-0.2) with phibar(a=1) and lambda
+    # from the background solve (H(a=1) = H0)
+    back = api.cq_background(0.1, -0.2, omega_m=0.3)
+    prmq = api.cq_model_params(float(n), 1.0, 0.1, -0.2, omega_m=0.3, background=back)
+    leg = dict(phibar=prmq.cq_phibar, lam=prmq.cq_lambda)
     for prec in ("fp32", "fp64"):
         o = api.solver_opts(precision=prec)
         st = {}

@@ -210,6 +210,49 @@ int mg_total_force(mg_ctx *ctx, int model, const mg_model_params *params, const 
 int mg_symmetron_friction(mg_ctx *ctx, const mg_model_params *params, const double *u_field,
                           const float *pos, const float *mom, int64_t n_part, float *out);
 
+/* Coupled-quintessence background (Sec. 4.3, background cosmology solver;
+ * eq:csf_background_eom, eq:csf_background_Friedmann,
+ * eq:csf_background_Raychaudhuri and their forms in N = ln a).  Host code in
+ * FP64; no context and no GPU needed.  The potential coefficient of the
+ * printed forms in N is taken as lambda^2/3, lambda being that of
+ * eq:csf_param_lambda (the lambda that mg_model_params.cq_lambda takes). */
+typedef struct mg_cq_background_params {
+  double omega_m;   /* Omega_m today, in (0, 1) */
+  double h;         /* H0 / (100 km/s/Mpc), > 0 (sets Omega_r) */
+  double t_cmb;     /* CMB temperature today in K (the paper: 2.7255) */
+  double n_eff;     /* massless neutrino species (the paper: 3.046) */
+  double alpha;     /* potential exponent, >= 0 (eq:csf_potential) */
+  double beta;      /* coupling (eq:csf_coupling_function) */
+  double z_init;    /* start of the integration (the paper: 1e5) */
+  double phi_init;  /* phi-bar at z_init, > 0 and small */
+  double dphi_init; /* d phi-bar / d ln a at z_init, small */
+  double tol;       /* target |H(a=1)/H0 - 1| of the lambda shooting, > 0 */
+} mg_cq_background_params;
+
+typedef struct mg_cq_background_info {
+  double lambda;  /* lambda of eq:csf_param_lambda giving H(a=1) = H0 */
+  double omega_r; /* Omega_r from h, t_cmb, n_eff */
+  double h_today; /* H(a=1)/H0 reached */
+  int shots;      /* integrations spent on the shooting */
+  long steps;     /* accepted integrator steps, all shots */
+} mg_cq_background_info;
+
+/* Solves for lambda by shooting from z_init to a = 1 (H(1) grows with
+ * lambda: the bracket starts at lambda = 1 and doubles, then false position
+ * until |H(1)/H0 - 1| <= tol), then integrates once more and fills
+ * table[n_table][6] (host doubles, row-major) at n_table nodes uniform in
+ * ln a from 1/(1+z_init) to 1, columns: a, H/H0, (dH/dt)/H0^2, phi-bar,
+ * d phi-bar/da, (d phi-bar/dt)/H0.  MG_EINVAL for bad parameters,
+ * n_table < 2 or NULL table; MG_ENAN if the field leaves phi-bar > 0 (or
+ * the kinetic term reaches the Friedmann bound); MG_ENOCONV if no lambda
+ * reaches H0 (matter and radiation alone exceed it).  info may be NULL. */
+int mg_cq_background(const mg_cq_background_params *p, int n_table, double *table,
+                     mg_cq_background_info *info);
+/* Linear interpolation in a of every column of a table made by
+ * mg_cq_background (the paper's lookup); row: 6 host doubles.  MG_EINVAL if a
+ * lies outside the table. */
+int mg_cq_background_at(const double *table, int n_table, double a, double *row);
+
 /* Many independent boxes of different n and model in one persistent launch
  * (the paper runs independent realisations side by side over MPI, Sec. 3.1).
  * The launch is cooperative and never has more workgroups than can be

@@ -22,7 +22,7 @@ EXPORTS = (
     "mg_solve_batched", "mg_prof_enable", "mg_prof_read", "mg_batched_tune",
     "mg_batched_config", "mg_batched_set_config", "mg_interp_to_particles",
     "mg_interp_field_to_particles", "mg_poisson_newton", "mg_gradient", "mg_total_force",
-    "mg_symmetron_friction",
+    "mg_symmetron_friction", "mg_cq_background", "mg_cq_background_at",
 )
 MG_PROF_SMOOTH32, MG_PROF_SMOOTH64, MG_PROF_LIN32, MG_PROF_LIN64 = 0, 1, 2, 3
 
@@ -42,6 +42,22 @@ class ModelParams(ctypes.Structure):
         ("cq_phibar", ctypes.c_double),
         ("cq_lambda", ctypes.c_double),
         ("cq_keep_exp", ctypes.c_int),
+    ]
+
+
+class CqBackgroundParams(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in (
+        "omega_m", "h", "t_cmb", "n_eff", "alpha", "beta", "z_init", "phi_init", "dphi_init",
+        "tol")]
+
+
+class CqBackgroundInfo(ctypes.Structure):
+    _fields_ = [
+        ("lam", ctypes.c_double),
+        ("omega_r", ctypes.c_double),
+        ("h_today", ctypes.c_double),
+        ("shots", ctypes.c_int),
+        ("steps", ctypes.c_long),
     ]
 
 
@@ -121,6 +137,8 @@ def load():
         "mg_gradient": (ci, [vp, vp, vp]),
         "mg_total_force": (ci, [vp, ci, P(ModelParams), vp, vp, vp]),
         "mg_symmetron_friction": (ci, [vp, P(ModelParams), vp, vp, vp, i64, vp]),
+        "mg_cq_background": (ci, [P(CqBackgroundParams), ci, P(dbl), P(CqBackgroundInfo)]),
+        "mg_cq_background_at": (ci, [P(dbl), ci, dbl, P(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -37,6 +37,49 @@ def model_params(box, a=1.0, omega_m=0.3, fr_n=1, fr0=1e-5, a_star=0.5, xi=1.0 /
                          lam, cq_keep_exp)
 
 
+def cq_background(alpha, beta, omega_m=0.3089, h=0.6774, n_table=4096, z_init=1e5,
+                  phi_init=1e-6, dphi_init=0.0, t_cmb=2.7255, n_eff=3.046, tol=1e-12):
+    """The coupled-quintessence background (mg_cq_background): returns
+    (info, table) with table an (n_table, 6) float64 array of rows
+    (a, H/H0, (dH/dt)/H0^2, phibar, d phibar/da, (d phibar/dt)/H0) uniform
+    in ln a.  Defaults are the paper's Planck 2015 cosmology and start."""
+    import numpy as np
+
+    p = L.CqBackgroundParams(omega_m, h, t_cmb, n_eff, alpha, beta, z_init, phi_init, dphi_init,
+                             tol)
+    tab = np.empty((n_table, 6), dtype=np.float64)
+    info = L.CqBackgroundInfo()
+    rc = L.load().mg_cq_background(ctypes.byref(p), n_table,
+                                  tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.byref(info))
+    if rc != L.MG_OK:
+        raise MGError(rc, "mg_cq_background failed")
+    return info, tab
+
+
+def cq_background_at(table, a):
+    """Row of the background table linearly interpolated at scale factor a."""
+    import numpy as np
+
+    tab = np.ascontiguousarray(table, dtype=np.float64)
+    row = np.empty(6, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    rc = L.load().mg_cq_background_at(tab.ctypes.data_as(dp), tab.shape[0], float(a),
+                                     row.ctypes.data_as(dp))
+    if rc != L.MG_OK:
+        raise MGError(rc, f"mg_cq_background_at(a={a}) outside the table")
+    return row
+
+
+def cq_model_params(box, a, alpha, beta, omega_m=0.3089, background=None, **kw):
+    """mg_model_params for coupled quintessence with phibar(a) and lambda from
+    the background solve instead of stand-ins."""
+    info, tab = background if background is not None else cq_background(alpha, beta, omega_m)
+    row = cq_background_at(tab, a)
+    return model_params(box, a=a, omega_m=omega_m, alpha=alpha, beta=beta, phibar=row[3],
+                        lam=info.lam, **kw)
+
+
 def solver_opts(cycle="V", nu_pre=1, nu_post=1, inner_cycles=0, max_cycles=64, precision="fp32",
                 coarse_sweeps=0):
     """mg_solver_opts; inner_cycles = 0 plans the cycles between FP64
