@@ -1173,6 +1173,133 @@ __global__ __launch_bounds__(kBlock) void k_prolong_v(Lev Lf, Lev Lc, T* __restr
   if (g4 < (uint32_t)(2 * Lc.half / Vec<T>::V)) op_prolong_v<T, COL0>(Lf, Lc, v, c, c2, g4);
 }
 
+// The same prolongation marching in z over coarse planes: a thread owns 4
+// coarse cells of a row (natural I0..I0+3, J) and walks kt coarse planes,
+// keeping the y-interpolated coarse difference of planes K-1, K, K+1 in
+// registers; each new plane costs three coarse rows, each read as one
+// 2-vector per colour plus its two edge cells.  Arithmetic and its order are
+// those of op_prolong_v.  Requires nc % 4 == 0.
+template <typename T>
+struct Vec2Of;
+template <>
+struct Vec2Of<float> {
+  typedef float2 type;
+};
+template <>
+struct Vec2Of<double> {
+  typedef double2 type;
+};
+// coarse row (J, K): cx[q] = (c - c2) at natural I0 - 1 + q, q = 0..5
+template <typename T>
+__device__ __forceinline__ void prolong_row(const Lev& Lc, const T* __restrict__ c,
+                                            const T* __restrict__ c2, int I0, int J, int K,
+                                            T* cx) {
+  typedef typename Vec2Of<T>::type T2;
+  const int p = (J + K) & 1;  // colour of the even cells of this row
+  const uint32_t row = prow(Lc, J, K);
+  const uint32_t he = (uint32_t)p * (uint32_t)Lc.half + row;       // even cells
+  const uint32_t ho = (uint32_t)(1 - p) * (uint32_t)Lc.half + row; // odd cells
+  const uint32_t o = (uint32_t)(I0 >> 1);
+  const uint32_t om = I0 == 0 ? (uint32_t)Lc.nh - 1 : o - 1;       // cell I0 - 1 (odd)
+  const uint32_t op = I0 + 4 == Lc.n ? 0u : o + 2;                 // cell I0 + 4 (even)
+  T2 ev = *reinterpret_cast<const T2*>(c + he + o);
+  T2 od = *reinterpret_cast<const T2*>(c + ho + o);
+  cx[0] = c[ho + om];
+  cx[1] = ev.x;
+  cx[2] = od.x;
+  cx[3] = ev.y;
+  cx[4] = od.y;
+  cx[5] = c[he + op];
+  if (c2) {
+    T2 ev2 = *reinterpret_cast<const T2*>(c2 + he + o);
+    T2 od2 = *reinterpret_cast<const T2*>(c2 + ho + o);
+    cx[0] -= c2[ho + om];
+    cx[1] -= ev2.x;
+    cx[2] -= od2.x;
+    cx[3] -= ev2.y;
+    cx[4] -= od2.y;
+    cx[5] -= c2[he + op];
+  }
+}
+// ay[y][q][x] of coarse plane K for the thread's row J (x, then y weights)
+template <typename T>
+__device__ __forceinline__ void prolong_plane(const Lev& Lc, const T* __restrict__ c,
+                                              const T* __restrict__ c2, int I0, const int* Js,
+                                              int K, T (*ay)[4][2]) {
+  T ax[3][4][2];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    T cx[6];
+    prolong_row<T>(Lc, c, c2, I0, Js[b], K, cx);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ax[b][q][0] = T(0.75) * cx[q + 1] + T(0.25) * cx[q];
+      ax[b][q][1] = T(0.75) * cx[q + 1] + T(0.25) * cx[q + 2];
+    }
+  }
+#pragma unroll
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+        ay[y][q][x] = T(0.75) * ax[1][q][x] + T(0.25) * ax[y ? 2 : 0][q][x];
+}
+__host__ __device__ inline unsigned prolong_march_blocks(int nc, int kt) {
+  const unsigned ngrp = (unsigned)nc * (unsigned)nc / 4u;
+  return ((ngrp + kBlock - 1) / kBlock) * (unsigned)((nc + kt - 1) / kt);
+}
+template <typename T, int COL0>
+__global__ __launch_bounds__(kBlock) void k_prolong_kv(Lev Lf, Lev Lc, T* __restrict__ v,
+                                                       const T* __restrict__ c,
+                                                       const T* __restrict__ c2, int kt) {
+  const int nc = Lc.n;
+  const uint32_t ngrp = (uint32_t)nc * (uint32_t)nc / 4u;
+  const uint32_t nchunk = (ngrp + kBlock - 1) / kBlock;
+  const uint32_t b = (uint32_t)xcd_block();
+  const uint32_t kb = b / nchunk, chunk = b - kb * nchunk;
+  const uint32_t grp = chunk * kBlock + threadIdx.x;
+  const int K0 = (int)kb * kt;
+  if (grp >= ngrp || K0 >= nc) return;
+  const uint32_t gpr = (uint32_t)nc / 4u;  // groups per coarse row
+  const int J = (int)(grp / gpr), I0 = (int)(grp - (uint32_t)J * gpr) * 4;
+  const int K1 = K0 + kt < nc ? K0 + kt : nc;
+  const int Js[3] = {J == 0 ? nc - 1 : J - 1, J, J + 1 == nc ? 0 : J + 1};
+  T ay[3][2][4][2];  // planes K-1, K, K+1
+  prolong_plane<T>(Lc, c, c2, I0, Js, K0 == 0 ? nc - 1 : K0 - 1, ay[0]);
+  prolong_plane<T>(Lc, c, c2, I0, Js, K0, ay[1]);
+  for (int K = K0; K < K1; ++K) {
+    prolong_plane<T>(Lc, c, c2, I0, Js, K + 1 == nc ? 0 : K + 1, ay[2]);
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int j = 2 * J + y, k = 2 * K + z;
+        const uint32_t row = prow(Lf, j, k) + (uint32_t)I0;
+#pragma unroll
+        for (int col = COL0; col < 2; ++col) {
+          const int x = (col + j + k) & 1;
+          T* dst = v + (uint32_t)col * (uint32_t)Lf.half + row;
+          T cur[4];
+          ldn_nt<T, 4>(dst, cur);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            cur[q] += T(0.75) * ay[1][y][q][x] + T(0.25) * ay[z ? 2 : 0][y][q][x];
+          stn_nt<T, 4>(dst, cur);
+        }
+      }
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          ay[0][y][q][x] = ay[1][y][q][x];
+          ay[1][y][q][x] = ay[2][y][q][x];
+        }
+  }
+}
+
 // correction form: Re -> eH and eR, R(G(e) - rho) -> rhoH, optionally R X -> XH.
 // skip1: colour 1 was the last half-sweep of an exact per-cell smoother, so
 // its residual vanishes (to rounding) and is not recomputed.

@@ -239,6 +239,20 @@ int ensure32(mg_ctx* ctx) {
   return MG_OK;
 }
 
+// v += P(c - c2) (c2 may be null): the z-marching kernel when the coarse
+// side is a multiple of 4 (the caller guarantees nc % Vec<T>::V == 0)
+constexpr int kProlongKT = 4;  // coarse planes per marching thread
+template <typename T, int COL0>
+void launch_prolong(mg_ctx* ctx, const Lev& Lf, const Lev& Lc, T* v, const T* c, const T* c2) {
+  if (Lc.n % 4 == 0 && Lc.n >= 8) {
+    k_prolong_kv<T, COL0><<<prolong_march_blocks(Lc.n, kProlongKT), kBlock, 0, ctx->stream>>>(
+        Lf, Lc, v, c, c2, kProlongKT);
+  } else {
+    k_prolong_v<T, COL0><<<nblk(cells(Lc) / Vec<T>::V), kBlock, 0, ctx->stream>>>(Lf, Lc, v, c,
+                                                                                  c2);
+  }
+}
+
 template <typename T>
 int ensure_lin(mg_ctx* ctx, WorkLin<T>& W) {
   for (int l = 0; l < ctx->nlev; ++l) {
@@ -610,8 +624,7 @@ int cycle64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   }
   if (vec) {
     // v += P(v_H - R v); colour 0 only for the Newton (CQ) smoother
-    k_prolong_v<double, M == CQ ? 0 : 1><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
-        Lf, Lc, W.v[l], W.v[l + 1], W.Rv[l + 1]);
+    launch_prolong<double, M == CQ ? 0 : 1>(ctx, Lf, Lc, W.v[l], W.v[l + 1], W.Rv[l + 1]);
   } else {
     k_coarse_diff<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(cells(Lc), W.v[l + 1],
                                                                          W.Rv[l + 1]);
@@ -795,8 +808,7 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   }
   if (vec) {
     // e += P(e_H - R e); colour 0 too only for the Newton (CQ) smoother
-    k_prolong_v<float, M == CQ ? 0 : 1><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
-        Lf, Lc, W.e[l], W.e[l + 1], W.eR[l + 1]);
+    launch_prolong<float, M == CQ ? 0 : 1>(ctx, Lf, Lc, W.e[l], W.e[l + 1], W.eR[l + 1]);
   } else {
     k_coarse_diff<float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(cells(Lc), W.e[l + 1],
                                                                         W.eR[l + 1]);
@@ -1020,8 +1032,7 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
     ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_V));
   }
   if (cvec)
-    k_prolong_v<T, 1><<<nblk(ncv), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1],
-                                                             (const T*)nullptr);
+    launch_prolong<T, 1>(ctx, Lf, Lc, W.e[l], W.e[l + 1], (const T*)nullptr);
   else
     k_prolong_block<T><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l], W.e[l + 1]);
   smooth(o->nu_post, false);
@@ -2061,8 +2072,7 @@ int mg_prolong_add(mg_ctx* ctx, const double* coarse, double* fine) {
   k_pack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, fine, ctx->w64.v[0], 1.0);
   k_pack<double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lc, coarse, ctx->w64.v[1], 1.0);
   if (Lc.n % Vec<double>::V == 0)
-    k_prolong_v<double, 0><<<nblk(cells(Lc) / Vec<double>::V), kBlock, 0, ctx->stream>>>(
-        Lf, Lc, ctx->w64.v[0], ctx->w64.v[1], (const double*)nullptr);
+    launch_prolong<double, 0>(ctx, Lf, Lc, ctx->w64.v[0], ctx->w64.v[1], (const double*)nullptr);
   else
     k_prolong_block<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, ctx->w64.v[0],
                                                                            ctx->w64.v[1]);
