@@ -307,6 +307,11 @@ __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ p, int64_t m, T
   int64_t g = gid();
   if (g < m) p[g] = v;
 }
+// 16-byte stores: p 16-byte aligned, m4 = count / 4 for floats
+__global__ __launch_bounds__(kBlock) void k_fill4(float4* __restrict__ p, int64_t m4, float v) {
+  int64_t g = gid();
+  if (g < m4) p[g] = make_float4(v, v, v, v);
+}
 
 // ---------------------------------------------------------------------------
 // Per-level operations written once, called from grid kernels (one cell per
@@ -1544,6 +1549,31 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr(Lev Lf, Lev Lc, 
   int64_t g = gid();
   if (g < 2 * Lc.half)
     op_resid_restrict_corr<M>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, g);
+}
+// the same, 4 packed cells of one colour per thread (needs nh % 4 == 0);
+// per-cell arithmetic and summation order as above
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_coarse_src_corr_v(Lev L, const float* __restrict__ eR,
+                                                              const float* __restrict__ X,
+                                                              const float* __restrict__ dens,
+                                                              float* __restrict__ rho, float h2,
+                                                              Consts C) {
+  constexpr int V = Vec<float>::V;
+  const uint32_t g4 = (uint32_t)gid();
+  if (g4 >= (uint32_t)(2 * L.half / V)) return;
+  const uint32_t g = g4 * V;
+  const int colour = g >= (uint32_t)L.half ? 1 : 0;
+  int ih0, j, k;
+  dec(g - (uint32_t)colour * (uint32_t)L.half, L, ih0, j, k);
+  float sum[V], ec[V], x[V], r[V], dc[V] = {0, 0, 0, 0};
+  nbsum_vec<float>(L, eR + (1 - colour) * L.half, ih0, j, k, (j + k + colour) & 1, sum);
+  ldv<float>(eR + g, ec);
+  ldv_nt<float>(X + g, x);
+  if (M != FR) ldv_nt<float>(dens + g, dc);
+  ldv_nt<float>(rho + g, r);
+#pragma unroll
+  for (int q = 0; q < V; ++q) r[q] = corr_G<M>(C, h2, ec[q], sum[q], x[q], dc[q]) - r[q];
+  stv_nt<float>(rho + g, r);
 }
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_coarse_src_corr(Lev L, const float* eR, const float* X,

@@ -794,8 +794,12 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
     k_resid_restrict_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
         W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C);
-  k_coarse_src_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
-      Lc, W.eR[l + 1], W.X[l + 1], W.dens[l + 1], W.rho[l + 1], float(lev_h2(l + 1)), C);
+  if (Lc.nh % Vec<float>::V == 0)
+    k_coarse_src_corr_v<M><<<nblk(cells(Lc) / Vec<float>::V), kBlock, 0, ctx->stream>>>(
+        Lc, W.eR[l + 1], W.X[l + 1], W.dens[l + 1], W.rho[l + 1], float(lev_h2(l + 1)), C);
+  else
+    k_coarse_src_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
+        Lc, W.eR[l + 1], W.X[l + 1], W.dens[l + 1], W.rho[l + 1], float(lev_h2(l + 1)), C);
   LAUNCHCHK();
   if (type == MG_CYCLE_V) {
     ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V, rx));
@@ -1342,8 +1346,8 @@ __global__ __launch_bounds__(kBlock) void k_loss_sq(int64_t m, const float* __re
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// CIC: per axis, s = x - 1/2, i0 = floor(s), t = s - i0 (exact in FP32 for
-// 0 <= x < 2^23); weights (1-t, t) to cells i0, i0+1 (periodic).  The 8
+// CIC: per axis, s = x - 1/2, i0 = floor(s), t = s - i0 (formed in FP64, so
+// exact for every float position); weights (1-t, t) to cells i0, i0+1 (periodic).  The 8
 // products are formed in FP64 and deposited as 32.32 fixed point; the last
 // weight is 2^32 minus the other seven so each particle adds exactly 1.
 __global__ __launch_bounds__(kBlock) void k_cic(int n, int64_t np, const float* __restrict__ pos,
@@ -2002,7 +2006,10 @@ int mg_loss_force_sq(mg_ctx* ctx, const float* force, const int64_t* cellsv, int
   int64_t m = (int64_t)ctx->n * ctx->n * ctx->n;
   if (nblk(n_cells) > (unsigned)ctx->part_cap)
     return fail(ctx, MG_EINVAL, "mg_loss_force_sq: too many cells");
-  k_fill<float><<<nblk(3 * m), kBlock, 0, ctx->stream>>>(grad_force_out, 3 * m, 0.0f);
+  if ((3 * m) % 4 == 0 && ((uintptr_t)grad_force_out & 15) == 0)
+    k_fill4<<<nblk(3 * m / 4), kBlock, 0, ctx->stream>>>((float4*)grad_force_out, 3 * m / 4, 0.0f);
+  else
+    k_fill<float><<<nblk(3 * m), kBlock, 0, ctx->stream>>>(grad_force_out, 3 * m, 0.0f);
   k_loss_sq<<<nblk(n_cells), kBlock, 0, ctx->stream>>>(m, force, cellsv, n_cells, grad_force_out,
                                                        ctx->part);
   ACHK(sum_on_device(ctx, nblk(n_cells), loss_out));
