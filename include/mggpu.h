@@ -94,6 +94,9 @@ typedef struct mg_ctx mg_ctx;
  * n must be even, 4 <= n <= 1600; the level pyramid is n, n/2, ... while the half
  * is even and >= 4 (4^3 coarsest for n = 2^l, 6^3 for n = 96).  Device
  * workspace is allocated on first use of each mode and kept until destroy.
+ * The environment variable MGGPU_MARCH_MIN_BLOCKS, read here, sets from how
+ * many workgroups up the residual/restriction kernels march in z (default
+ * 2048; the results are identical either way).
  * Returns MG_EINVAL for a bad n or NULL out. */
 int mg_ctx_create(mg_ctx **out, int n, void *hip_stream);
 void mg_ctx_destroy(mg_ctx *ctx);

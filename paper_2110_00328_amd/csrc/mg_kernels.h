@@ -1369,6 +1369,229 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_v(
     op_resid_restrict_corr_v<M>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, skip1, g4);
 }
 
+// Residual and restriction marching in z, for exact per-cell smoothers
+// (colour 1, swept last, has zero residual and is only restricted).  A
+// thread owns 4 coarse cells (natural I0..I0+3, row J) and walks kt coarse
+// planes; the colour-1 rows of fine planes 2K and 2K-1 around its two fine
+// rows stay in registers, so each step reads the colour-1 rows of planes
+// 2K+1 and 2K+2 once.  Per-cell arithmetic and every summation order are
+// those of op_resid_restrict_corr_v and k_lin_resid_restrict_v; coarse
+// results are written as one 2-vector per colour.  Requires nc % 4 == 0.
+template <typename T>
+struct RestrictWin {
+  T zm[2][4];  // colour-1 rows (2J+b, 2K-1)
+  T zc[2][4];  // colour-1 rows (2J+b, 2K)
+};
+// neighbour sum of the 4 colour-0 cells (I0.., j, k) from colour-1 rows:
+// centre c (x neighbours), y- ym, y+ yp, z- zm, z+ zp; same order as nbsum_vec
+template <typename T>
+__device__ __forceinline__ void rr_nbsum(const Lev& Lf, const T* __restrict__ o1, int I0, int j,
+                                         int k, const T* c, const T* ym, const T* yp,
+                                         const T* zm, const T* zp, T* sum) {
+  const uint32_t r = prow(Lf, j, k);
+  T xv[5];
+  if ((j + k) & 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xv[q] = c[q];
+    xv[4] = o1[r + (I0 + 4 == Lf.nh ? 0 : I0 + 4)];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xv[q + 1] = c[q];
+    xv[0] = o1[r + (I0 == 0 ? Lf.nh - 1 : I0 - 1)];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sum[q] = (xv[q] + xv[q + 1]) + (ym[q] + yp[q]) + (zm[q] + zp[q]);
+}
+// store 4 natural coarse values of row (J, K) from I0: even cells share one
+// colour's 2-vector, odd cells the other's
+template <typename T>
+__device__ __forceinline__ void st_coarse4(const Lev& Lc, T* __restrict__ a, int I0, int J, int K,
+                                           const T* v) {
+  typedef typename Vec2Of<T>::type T2;
+  const int p = (J + K) & 1;
+  const uint32_t row = prow(Lc, J, K) + (uint32_t)(I0 >> 1);
+  T2 ev, od;
+  ev.x = v[0];
+  ev.y = v[2];
+  od.x = v[1];
+  od.y = v[3];
+  *reinterpret_cast<T2*>(a + (uint32_t)p * (uint32_t)Lc.half + row) = ev;
+  *reinterpret_cast<T2*>(a + (uint32_t)(1 - p) * (uint32_t)Lc.half + row) = od;
+}
+struct RRPos {
+  int I0, J, Jm2, Jp2, K0, K1;  // Jm2 = fine row 2J-1, Jp2 = fine row 2J+2 (periodic)
+  bool ok;
+};
+__device__ __forceinline__ RRPos rr_pos(const Lev& Lc, int kt) {
+  RRPos P;
+  const int nc = Lc.n;
+  const uint32_t ngrp = (uint32_t)nc * (uint32_t)nc / 4u;
+  const uint32_t nchunk = (ngrp + kBlock - 1) / kBlock;
+  const uint32_t b = (uint32_t)xcd_block();
+  const uint32_t kb = b / nchunk, chunk = b - kb * nchunk;
+  const uint32_t grp = chunk * kBlock + threadIdx.x;
+  P.K0 = (int)kb * kt;
+  P.ok = grp < ngrp && P.K0 < nc;
+  const uint32_t gpr = (uint32_t)nc / 4u;
+  P.J = (int)(grp / gpr);
+  P.I0 = (int)(grp - (uint32_t)P.J * gpr) * 4;
+  const int n = 2 * nc;
+  P.Jm2 = P.J == 0 ? n - 1 : 2 * P.J - 1;
+  P.Jp2 = 2 * P.J + 2 == n ? 0 : 2 * P.J + 2;
+  P.K1 = P.K0 + kt < nc ? P.K0 + kt : nc;
+  return P;
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_kv(
+    Lev Lf, Lev Lc, const float* __restrict__ e, const float* __restrict__ X,
+    const float* __restrict__ dens, const float* __restrict__ rho, float h2,
+    float* __restrict__ eH, float* __restrict__ eR, float* __restrict__ rhoH,
+    float* __restrict__ XH, Consts C, int kt) {
+  const RRPos P = rr_pos(Lc, kt);
+  if (!P.ok) return;
+  const int n = Lf.n, I0 = P.I0, J = P.J;
+  const float* o1 = e + Lf.half;
+  auto row1 = [&](int j, int k, float* v) { ldn<float, 4>(o1 + prow(Lf, j, k) + I0, v); };
+  RestrictWin<float> W;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    row1(2 * J + b, P.K0 == 0 ? n - 1 : 2 * P.K0 - 1, W.zm[b]);
+    row1(2 * J + b, 2 * P.K0, W.zc[b]);
+  }
+  for (int K = P.K0; K < P.K1; ++K) {
+    float c1[2][4], c2[2][4];  // colour-1 rows of planes 2K+1 and 2K+2
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      row1(2 * J + b, 2 * K + 1, c1[b]);
+      row1(2 * J + b, 2 * K + 2 == n ? 0 : 2 * K + 2, c2[b]);
+    }
+    float se[4] = {0, 0, 0, 0}, sd[4] = {0, 0, 0, 0}, sx[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int k = 2 * K + d;
+      float ym[4], yp[4];
+      row1(P.Jm2, k, ym);
+      row1(P.Jp2, k, yp);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int j = 2 * J + b;
+        const float* cen = d ? c1[b] : W.zc[b];
+        const float* zmv = d ? W.zc[b] : W.zm[b];
+        const float* zpv = d ? c2[b] : c1[b];
+        const float* ymv = b ? (d ? c1[0] : W.zc[0]) : ym;
+        const float* ypv = b ? yp : (d ? c1[1] : W.zc[1]);
+        const uint32_t q0 = prow(Lf, j, k) + (uint32_t)I0;
+        float sum[4], ec[4], x[4], r[4], dc[4] = {0, 0, 0, 0};
+        rr_nbsum<float>(Lf, o1, I0, j, k, cen, ymv, ypv, zmv, zpv, sum);
+        ldn<float, 4>(e + q0, ec);
+        ldn_nt<float, 4>(X + q0, x);
+        ldn_nt<float, 4>(rho + q0, r);
+        if (M != FR) ldn_nt<float, 4>(dens + q0, dc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          se[q] += ec[q];
+          sx[q] += x[q];
+          sd[q] += corr_G<M>(C, h2, ec[q], sum[q], x[q], dc[q]) - r[q];
+        }
+        // colour 1: restricted only
+#pragma unroll
+        for (int q = 0; q < 4; ++q) se[q] += cen[q];
+        if (XH) {
+          ldn_nt<float, 4>(X + Lf.half + q0, x);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sx[q] += x[q];
+        }
+      }
+    }
+    float re[4], rd[4], rx[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      re[q] = se[q] * 0.125f;
+      rd[q] = sd[q] * 0.125f;
+      rx[q] = sx[q] * 0.125f;
+    }
+    st_coarse4<float>(Lc, eH, I0, J, K, re);
+    st_coarse4<float>(Lc, eR, I0, J, K, re);
+    st_coarse4<float>(Lc, rhoH, I0, J, K, rd);
+    if (XH) st_coarse4<float>(Lc, XH, I0, J, K, rx);
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        W.zm[b][q] = c1[b][q];
+        W.zc[b][q] = c2[b][q];
+      }
+  }
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lin_resid_restrict_kv(Lev Lf, Lev Lc,
+                                                                  const T* __restrict__ e,
+                                                                  const T* __restrict__ dg,
+                                                                  const T* __restrict__ r, T kh2,
+                                                                  T* __restrict__ rH,
+                                                                  T* __restrict__ eH, int kt) {
+  const RRPos P = rr_pos(Lc, kt);
+  if (!P.ok) return;
+  const int n = Lf.n, I0 = P.I0, J = P.J;
+  const T* o1 = e + Lf.half;
+  auto row1 = [&](int j, int k, T* v) { ldn<T, 4>(o1 + prow(Lf, j, k) + I0, v); };
+  RestrictWin<T> W;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    row1(2 * J + b, P.K0 == 0 ? n - 1 : 2 * P.K0 - 1, W.zm[b]);
+    row1(2 * J + b, 2 * P.K0, W.zc[b]);
+  }
+  const T zero[4] = {T(0), T(0), T(0), T(0)};
+  for (int K = P.K0; K < P.K1; ++K) {
+    T c1[2][4], c2[2][4];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      row1(2 * J + b, 2 * K + 1, c1[b]);
+      row1(2 * J + b, 2 * K + 2 == n ? 0 : 2 * K + 2, c2[b]);
+    }
+    T sd[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sd[q] = T(0);
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int k = 2 * K + d;
+      T ym[4], yp[4];
+      row1(P.Jm2, k, ym);
+      row1(P.Jp2, k, yp);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int j = 2 * J + b;
+        const T* cen = d ? c1[b] : W.zc[b];
+        const T* zmv = d ? W.zc[b] : W.zm[b];
+        const T* zpv = d ? c2[b] : c1[b];
+        const T* ymv = b ? (d ? c1[0] : W.zc[0]) : ym;
+        const T* ypv = b ? yp : (d ? c1[1] : W.zc[1]);
+        const uint32_t q0 = prow(Lf, j, k) + (uint32_t)I0;
+        T sum[4], ec[4], dd[4], rr[4];
+        rr_nbsum<T>(Lf, o1, I0, j, k, cen, ymv, ypv, zmv, zpv, sum);
+        ldn<T, 4>(e + q0, ec);
+        ldn_nt<T, 4>(dg + q0, dd);
+        ldn_nt<T, 4>(r + q0, rr);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          sd[q] += rr[q] - (kh2 * (T(6) * ec[q] - sum[q]) + dd[q] * ec[q]);
+      }
+    }
+    T rd[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rd[q] = sd[q] * T(0.125);
+    st_coarse4<T>(Lc, rH, I0, J, K, rd);
+    st_coarse4<T>(Lc, eH, I0, J, K, zero);
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        W.zm[b][q] = c1[b][q];
+        W.zc[b][q] = c2[b][q];
+      }
+  }
+}
+
 // direct form: R v -> Rv and vinit, R(L(v) - S) -> Sd
 template <int M, typename TD>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict_direct_v(

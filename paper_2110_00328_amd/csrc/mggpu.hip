@@ -76,6 +76,10 @@ struct WorkAdj {
 struct mg_ctx {
   int n = 0;
   hipStream_t stream = nullptr;
+  // the z-marching residual/restriction kernels are used from this many
+  // workgroups up (below it a grid is too sparse to hide the march);
+  // MGGPU_MARCH_MIN_BLOCKS overrides it at context creation
+  unsigned march_min_blocks = 2048;
   std::string err;
   int nlev = 0;
   Lev L[kMaxLev];
@@ -242,6 +246,7 @@ int ensure32(mg_ctx* ctx) {
 // v += P(c - c2) (c2 may be null): the z-marching kernel when the coarse
 // side is a multiple of 4 (the caller guarantees nc % Vec<T>::V == 0)
 constexpr int kProlongKT = 4;  // coarse planes per marching thread
+constexpr int kRestrictKT = 4;
 template <typename T, int COL0>
 void launch_prolong(mg_ctx* ctx, const Lev& Lf, const Lev& Lc, T* v, const T* c, const T* c2) {
   if (Lc.n % 4 == 0 && Lc.n >= 8) {
@@ -786,7 +791,13 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   // exact per-cell smoothers (f(R), symmetron): the colour swept last has
   // zero residual
   const int skip1 = (M != CQ && o->nu_pre > 0) ? 1 : 0;
-  if (vec)
+  if (skip1 && Lc.n % 4 == 0 && Lc.n >= 8 &&
+      prolong_march_blocks(Lc.n, kRestrictKT) >= ctx->march_min_blocks)
+    k_resid_restrict_corr_kv<M><<<prolong_march_blocks(Lc.n, kRestrictKT), kBlock, 0,
+                                  ctx->stream>>>(
+        Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
+        W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C, kRestrictKT);
+  else if (vec)
     k_resid_restrict_corr_v<M><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
         W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C, skip1);
@@ -1019,7 +1030,12 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
   smooth(o->nu_pre, fresh);
   const bool cvec = Lc.n % Vec<T>::V == 0;
   const int64_t ncv = cells(Lc) / Vec<T>::V;
-  if (cvec)  // Gauss-Seidel on a linear system is exact per cell: skip colour 1
+  if (o->nu_pre > 0 && Lc.n % 4 == 0 && Lc.n >= 8 &&  // exact per cell: colour 1 skipped
+      prolong_march_blocks(Lc.n, kRestrictKT) >= ctx->march_min_blocks)
+    k_lin_resid_restrict_kv<T><<<prolong_march_blocks(Lc.n, kRestrictKT), kBlock, 0,
+                                 ctx->stream>>>(Lf, Lc, W.e[l], W.dg[l], W.r[l], kh2, W.r[l + 1],
+                                                W.e[l + 1], kRestrictKT);
+  else if (cvec)  // Gauss-Seidel on a linear system is exact per cell: skip colour 1
     k_lin_resid_restrict_v<T><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.e[l], W.dg[l], W.r[l], kh2, W.r[l + 1], W.e[l + 1], o->nu_pre > 0 ? 1 : 0);
   else
@@ -1574,6 +1590,7 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
   if (n < 4 || (n & 1) || n > 1600) return MG_EINVAL;  // n^3 < 2^32: 32-bit indices
   mg_ctx* ctx = new mg_ctx();
   ctx->n = n;
+  if (const char* mb = getenv("MGGPU_MARCH_MIN_BLOCKS")) ctx->march_min_blocks = (unsigned)atoi(mb);
   ctx->stream = (hipStream_t)hip_stream;
   // pyramid: halve while the half is even and >= 4
   int m = n, l = 0;

@@ -380,3 +380,37 @@ def test_f_and_w_cycles_match_oracle(cycle, model):
                                   tol=1e-10, opts=api.solver_opts(cycle=cycle, precision=prec))
         assert sa.status == 0
     mg.close()
+
+
+@pytest.mark.parametrize("model", ["fr", "sym"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_marching_restriction_is_bit_identical(monkeypatch, model, prec):
+    """The z-marching residual/restriction kernels (used on large grids) give
+    bit-identical solves and adjoints; forced on here at 64^3 (coarse sides
+    32, 16, 8), and checked against the oracle too."""
+    n, box = 64, 64.0
+    say("marching restriction", model, prec)
+    P, prm = cfg(model, n, box)
+    delta = torch.from_numpy(lognormal(n, 41)).to(DEV)
+    opts = api.solver_opts(precision=prec)
+    out = []
+    for mb in (None, "0"):
+        if mb is None:
+            monkeypatch.delenv("MGGPU_MARCH_MIN_BLOCKS", raising=False)
+        else:
+            monkeypatch.setenv("MGGPU_MARCH_MIN_BLOCKS", mb)
+        mg = api.Context(n, device=DEV)
+        field, st = mg.solve(model, prm, delta, tol=1e-8, opts=opts)
+        cells = torch.from_numpy(np.random.default_rng(42).choice(n ** 3, 200, replace=False)).to(DEV)
+        force = mg.force(model, prm, field)
+        _, gforce = mg.loss_force_sq(force, cells)
+        gfield = mg.force_adjoint(model, prm, field, gforce)
+        gd, st2 = mg.solve_adjoint(model, prm, delta, field, gfield, tol=1e-8, opts=opts)
+        out.append((field.cpu().numpy(), gd.cpu().numpy(), st.cycles, st2.cycles))
+        mg.close()
+    assert out[0][2:] == out[1][2:]
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    ref, _, _, _ = oracle.solve(P, delta.cpu().numpy().astype(np.float64), tol=1e-12)
+    err = field_err(model, out[1][0], to_field(model, ref), P)
+    say(f"  field_err={err:.2e}")
+    assert err < 1e-5
