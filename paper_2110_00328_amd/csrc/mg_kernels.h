@@ -302,6 +302,51 @@ __global__ __launch_bounds__(kBlock) void k_unpack(Lev L, const TI* __restrict__
   dec_nat(g, L, i, j, k);
   nat[g] = TO(scale * double(pk[pk_of(L, i, j, k)]));
 }
+// The same transposes on 8 natural cells of a row per thread (n % 8 == 0):
+// the row's even cells are 4 consecutive packed cells of one colour, its odd
+// cells 4 of the other.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_pack8(Lev L, const TI* __restrict__ nat,
+                                                  TO* __restrict__ pk, double scale) {
+  const int64_t g8 = gid();
+  if (g8 >= 2 * L.half / 8) return;
+  const uint32_t g = (uint32_t)g8 * 8u;
+  int i0, j, k;
+  dec_nat(g, L, i0, j, k);
+  TI v[8];
+  ldn<TI, 8>(nat + g, v);
+  TO ev[4], od[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ev[q] = TO(scale * double(v[2 * q]));
+    od[q] = TO(scale * double(v[2 * q + 1]));
+  }
+  const int p = (j + k) & 1;  // colour of the row's even cells
+  const uint32_t row = prow(L, j, k) + (uint32_t)(i0 >> 1);
+  stn<TO, 4>(pk + (uint32_t)p * (uint32_t)L.half + row, ev);
+  stn<TO, 4>(pk + (uint32_t)(1 - p) * (uint32_t)L.half + row, od);
+}
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_unpack8(Lev L, const TI* __restrict__ pk,
+                                                    TO* __restrict__ nat, double scale) {
+  const int64_t g8 = gid();
+  if (g8 >= 2 * L.half / 8) return;
+  const uint32_t g = (uint32_t)g8 * 8u;
+  int i0, j, k;
+  dec_nat(g, L, i0, j, k);
+  const int p = (j + k) & 1;
+  const uint32_t row = prow(L, j, k) + (uint32_t)(i0 >> 1);
+  TI ev[4], od[4];
+  ldn<TI, 4>(pk + (uint32_t)p * (uint32_t)L.half + row, ev);
+  ldn<TI, 4>(pk + (uint32_t)(1 - p) * (uint32_t)L.half + row, od);
+  TO v[8];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[2 * q] = TO(scale * double(ev[q]));
+    v[2 * q + 1] = TO(scale * double(od[q]));
+  }
+  stn<TO, 8>(nat + g, v);
+}
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_fill(T* __restrict__ p, int64_t m, T v) {
   int64_t g = gid();

@@ -243,6 +243,27 @@ int ensure32(mg_ctx* ctx) {
   return MG_OK;
 }
 
+// caller arrays may be accessed 16 bytes at a time only when so aligned
+inline bool al16(const void* a, const void* b = nullptr) {
+  return (((uintptr_t)a | (uintptr_t)b) & 15u) == 0;
+}
+
+// natural <-> packed transposes, 8 cells per thread when n % 8 == 0
+template <typename TI, typename TO>
+void launch_pack(mg_ctx* ctx, const Lev& L, const TI* nat, TO* pk, double scale) {
+  if (L.n % 8 == 0 && al16(nat, pk))
+    k_pack8<TI, TO><<<nblk(cells(L) / 8), kBlock, 0, ctx->stream>>>(L, nat, pk, scale);
+  else
+    k_pack<TI, TO><<<nblk(cells(L)), kBlock, 0, ctx->stream>>>(L, nat, pk, scale);
+}
+template <typename TI, typename TO>
+void launch_unpack(mg_ctx* ctx, const Lev& L, const TI* pk, TO* nat, double scale) {
+  if (L.n % 8 == 0 && al16(nat, pk))
+    k_unpack8<TI, TO><<<nblk(cells(L) / 8), kBlock, 0, ctx->stream>>>(L, pk, nat, scale);
+  else
+    k_unpack<TI, TO><<<nblk(cells(L)), kBlock, 0, ctx->stream>>>(L, pk, nat, scale);
+}
+
 // v += P(c - c2) (c2 may be null): the z-marching kernel when the coarse
 // side is a multiple of 4 (the caller guarantees nc % Vec<T>::V == 0)
 constexpr int kProlongKT = 4;  // coarse planes per marching thread
@@ -665,7 +686,7 @@ int setup64(mg_ctx* ctx, const Consts& C, const float* delta, const double* fiel
   Work64& W = ctx->w64;
   const Lev& L0 = ctx->L[0];
   int64_t m = cells(L0);
-  k_pack<float, float><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, delta, W.dens0, 1.0);
+  launch_pack<float, float>(ctx, L0, delta, W.dens0, 1.0);
   for (int l = 0; l + 1 < ctx->nlev; ++l) {
     if (l == 0)
       k_restrict<float, double><<<nblk(cells(ctx->L[1])), kBlock, 0, ctx->stream>>>(
@@ -676,7 +697,7 @@ int setup64(mg_ctx* ctx, const Consts& C, const float* delta, const double* fiel
   }
   double sgn = (C.model == FR) ? -1.0 : 1.0;  // f(R): w = -f_R
   if (field_in)
-    k_pack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, field_in, W.v[0], sgn);
+    launch_pack<double, double>(ctx, L0, field_in, W.v[0], sgn);
   else
     k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(W.v[0], m, C.bg);
   LAUNCHCHK();
@@ -715,7 +736,7 @@ int solve64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   if (rc == MG_OK && rel > tol) rc = fail(ctx, MG_ENOCONV, "max_cycles reached");
   double sgn = (C.model == FR) ? -1.0 : 1.0;
   const Lev& L0 = ctx->L[0];
-  k_unpack<double, double><<<nblk(cells(L0)), kBlock, 0, ctx->stream>>>(L0, ctx->w64.v[0],
+  launch_unpack<double, double>(ctx, L0, ctx->w64.v[0],
                                                                           field_out, sgn);
   LAUNCHCHK();
   if (st) {
@@ -841,7 +862,7 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   Work32& W = ctx->w32;
   const Lev& L0 = ctx->L[0];
   int64_t m = cells(L0);
-  k_pack<float, float><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, delta, W.dens[0], 1.0);
+  launch_pack<float, float>(ctx, L0, delta, W.dens[0], 1.0);
   // the f(R) correction operator does not involve the density below level 0
   if (M != FR)
     for (int l = 0; l + 1 < ctx->nlev; ++l)
@@ -858,7 +879,7 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   const bool uni = fused && !field_in;
   double eps_bg = 1.0;
   if (field_in)
-    k_pack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, field_in, W.w, sgn);
+    launch_pack<double, double>(ctx, L0, field_in, W.w, sgn);
   else if (!uni)
     k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(W.w, m, C.bg);
   LAUNCHCHK();
@@ -926,7 +947,7 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   }
   // stopped before any correction: the master is still the background
   if (uni && outer == 0) k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(W.w, m, C.bg);
-  k_unpack<double, double><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, W.w, field_out, sgn);
+  launch_unpack<double, double>(ctx, L0, W.w, field_out, sgn);
   LAUNCHCHK();
   if (st) {
     st->cycles = outer;
@@ -968,6 +989,89 @@ __global__ __launch_bounds__(kBlock) void k_lin_setup_nat(Lev L, const double* _
   }
   double t = block_sum(bb, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+// The same set-up on 8 natural cells of a row per thread (n % 8 == 0,
+// 16-byte aligned caller arrays): the row's even cells are 4 consecutive
+// packed cells of one colour, its odd cells 4 of the other.
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_lin_setup_nat8(Lev L, const double* __restrict__ field,
+                                                           const float* __restrict__ delta,
+                                                           const double* __restrict__ grad,
+                                                           double sgn, double bsign, Consts C,
+                                                           double* v_out, double* dg, float* dg32,
+                                                           double* b, double* part) {
+  __shared__ double sh[32];
+  const int64_t g8 = gid();
+  double bb = 0.0;
+  if (g8 < 2 * L.half / 8) {
+    const uint32_t g = (uint32_t)g8 * 8u;
+    int i0, j, k;
+    dec_nat(g, L, i0, j, k);
+    const int p = (j + k) & 1;
+    const uint32_t row = prow(L, j, k) + (uint32_t)(i0 >> 1);
+    const uint32_t pe = (uint32_t)p * (uint32_t)L.half + row;
+    const uint32_t po = (uint32_t)(1 - p) * (uint32_t)L.half + row;
+    double f[8], gr[8];
+    float dl[8];
+    ldn<double, 8>(field + g, f);
+    ldn<float, 8>(delta + g, dl);
+    ldn<double, 8>(grad + g, gr);
+    double ve[4], vo[4], de[4], dodd[4], be[4], bo[4];
+    float de32[4], do32[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ve[q] = sgn * f[2 * q];
+      vo[q] = sgn * f[2 * q + 1];
+      de[q] = lin_dg<M>(C, ve[q], double(dl[2 * q]));
+      dodd[q] = lin_dg<M>(C, vo[q], double(dl[2 * q + 1]));
+      de32[q] = float(de[q]);
+      do32[q] = float(dodd[q]);
+      be[q] = bsign * gr[2 * q];
+      bo[q] = bsign * gr[2 * q + 1];
+      bb += be[q] * be[q];
+      bb += bo[q] * bo[q];
+    }
+    stn<double, 4>(dg + pe, de);
+    stn<double, 4>(dg + po, dodd);
+    if (dg32) {
+      stn<float, 4>(dg32 + pe, de32);
+      stn<float, 4>(dg32 + po, do32);
+    }
+    if (v_out) {
+      stn<double, 4>(v_out + pe, ve);
+      stn<double, 4>(v_out + po, vo);
+    }
+    stn<double, 4>(b + pe, be);
+    stn<double, 4>(b + po, bo);
+  }
+  double t = block_sum(bb, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_lin_final8(Lev L, const double* v, const double* lam,
+                                                       Consts C, double* out_nat) {
+  const int64_t g8 = gid();
+  if (g8 >= 2 * L.half / 8) return;
+  const uint32_t g = (uint32_t)g8 * 8u;
+  int i0, j, k;
+  dec_nat(g, L, i0, j, k);
+  const int p = (j + k) & 1;
+  const uint32_t row = prow(L, j, k) + (uint32_t)(i0 >> 1);
+  const uint32_t pe = (uint32_t)p * (uint32_t)L.half + row;
+  const uint32_t po = (uint32_t)(1 - p) * (uint32_t)L.half + row;
+  double le[4], lo[4], ve[4] = {0, 0, 0, 0}, vo[4] = {0, 0, 0, 0}, out[8];
+  ldn<double, 4>(lam + pe, le);
+  ldn<double, 4>(lam + po, lo);
+  if (M != FR) {  // the f(R) source derivative is constant
+    ldn<double, 4>(v + pe, ve);
+    ldn<double, 4>(v + po, vo);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    out[2 * q] = -lin_dfd<M>(C, ve[q]) * le[q];
+    out[2 * q + 1] = -lin_dfd<M>(C, vo[q]) * lo[q];
+  }
+  stn<double, 8>(out_nat + g, out);
 }
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_lin_final(Lev L, const double* v, const double* lam,
@@ -1077,13 +1181,21 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
   if (A.have64) A.w64.e[0] = A.w64.ebuf[eb];
   // v, dg, b in one pass; b = s dL/dv, s = +1 (f(R)) / -1, and
   // dL/dv = sgn_field dL/dfield.  v is kept only where dL/d(delta) needs it.
-  k_lin_setup_nat<M><<<nblk(m), kBlock, 0, ctx->stream>>>(
-      L0, field, delta, grad_field, sgn_field, lin_sign(C) * sgn_field, C,
-      M == FR ? (double*)nullptr : A.v, A.dg, f32 ? A.w32.dg[0] : (float*)nullptr, A.b,
-      ctx->part);
+  const bool nat8 = L0.n % 8 == 0 && al16(field, delta) && al16(grad_field, grad_delta);
+  const unsigned nb_setup = nat8 ? nblk(m / 8) : nblk(m);
+  if (nat8)
+    k_lin_setup_nat8<M><<<nb_setup, kBlock, 0, ctx->stream>>>(
+        L0, field, delta, grad_field, sgn_field, lin_sign(C) * sgn_field, C,
+        M == FR ? (double*)nullptr : A.v, A.dg, f32 ? A.w32.dg[0] : (float*)nullptr, A.b,
+        ctx->part);
+  else
+    k_lin_setup_nat<M><<<nb_setup, kBlock, 0, ctx->stream>>>(
+        L0, field, delta, grad_field, sgn_field, lin_sign(C) * sgn_field, C,
+        M == FR ? (double*)nullptr : A.v, A.dg, f32 ? A.w32.dg[0] : (float*)nullptr, A.b,
+        ctx->part);
   LAUNCHCHK();
   double bb;
-  ACHK(sum_to_host(ctx, nblk(m), &bb));
+  ACHK(sum_to_host(ctx, nb_setup, &bb));
   bb = sqrt(bb);
   if (!(bb > 0.0)) bb = 1.0;
   // lam starts at 0: the fused outer kernels take it as 0 until written
@@ -1193,7 +1305,10 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
     ++outer;
   }
   if (vec && outer == 0) k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(A.lam, m, 0.0);
-  k_lin_final<M><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, A.v, A.lam, C, grad_delta);
+  if (nat8)
+    k_lin_final8<M><<<nblk(m / 8), kBlock, 0, ctx->stream>>>(L0, A.v, A.lam, C, grad_delta);
+  else
+    k_lin_final<M><<<nblk(m), kBlock, 0, ctx->stream>>>(L0, A.v, A.lam, C, grad_delta);
   LAUNCHCHK();
   if (st) {
     st->cycles = outer;
@@ -1831,7 +1946,7 @@ void launch_force(mg_ctx* ctx, const Consts& C, const double* f, const double* p
                   float* out) {
   const int n = ctx->n;
   const int64_t m = (int64_t)n * n * n;
-  if (n % 4 == 0) {
+  if (n % 4 == 0 && al16(f, out) && al16(pn)) {
     unsigned nchunk = (unsigned)(((int64_t)n * n / 4 + kBlock - 1) / kBlock);
     unsigned nb = nchunk * (unsigned)((n + kMarchKT - 1) / kMarchKT);
     if (pn) k_force_kv<true><<<nb, kBlock, 0, ctx->stream>>>(ctx->L[0], f, pn, sn, C, out, kMarchKT);
@@ -2065,7 +2180,7 @@ int mg_relax_halfsweep(mg_ctx* ctx, int model, const mg_model_params* params, co
         L, ctx->w64.v[0], ctx->w64.dens0, (const double*)nullptr, colour, 1.0, C);
   }
   double sgn = (model == MG_FR) ? -1.0 : 1.0;
-  k_unpack<double, double><<<nblk(cells(L)), kBlock, 0, ctx->stream>>>(L, ctx->w64.v[0], field,
+  launch_unpack<double, double>(ctx, L, ctx->w64.v[0], field,
                                                                          sgn);
   LAUNCHCHK();
   return MG_OK;
@@ -2077,10 +2192,10 @@ int mg_restrict(mg_ctx* ctx, const double* fine, double* coarse) {
   ACHK(ensure64(ctx));
   const Lev& Lf = ctx->L[0];
   const Lev& Lc = ctx->L[1];
-  k_pack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, fine, ctx->w64.v[0], 1.0);
+  launch_pack<double, double>(ctx, Lf, fine, ctx->w64.v[0], 1.0);
   k_restrict<double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, ctx->w64.v[0],
                                                                           ctx->w64.v[1]);
-  k_unpack<double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lc, ctx->w64.v[1], coarse,
+  launch_unpack<double, double>(ctx, Lc, ctx->w64.v[1], coarse,
                                                                          1.0);
   LAUNCHCHK();
   return MG_OK;
@@ -2093,14 +2208,14 @@ int mg_prolong_add(mg_ctx* ctx, const double* coarse, double* fine) {
   ACHK(ensure64(ctx));
   const Lev& Lf = ctx->L[0];
   const Lev& Lc = ctx->L[1];
-  k_pack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, fine, ctx->w64.v[0], 1.0);
-  k_pack<double, double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lc, coarse, ctx->w64.v[1], 1.0);
+  launch_pack<double, double>(ctx, Lf, fine, ctx->w64.v[0], 1.0);
+  launch_pack<double, double>(ctx, Lc, coarse, ctx->w64.v[1], 1.0);
   if (Lc.n % Vec<double>::V == 0)
     launch_prolong<double, 0>(ctx, Lf, Lc, ctx->w64.v[0], ctx->w64.v[1], (const double*)nullptr);
   else
     k_prolong_block<double><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, ctx->w64.v[0],
                                                                            ctx->w64.v[1]);
-  k_unpack<double, double><<<nblk(cells(Lf)), kBlock, 0, ctx->stream>>>(Lf, ctx->w64.v[0], fine,
+  launch_unpack<double, double>(ctx, Lf, ctx->w64.v[0], fine,
                                                                          1.0);
   LAUNCHCHK();
   return MG_OK;
