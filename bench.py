@@ -31,7 +31,7 @@ FP32_SMOOTH_BYTES_PER_CELL = 16.0  # per updated cell: X, rho, other-colour e, w
 # FETCH_SIZE and WRITE_SIZE (scaled x2.0 and x1.0 by a 1 GiB copy):
 # profiles/k_smooth_corr_v_fr512_hbm_traffic.md.  Set to None whenever the
 # kernel changes, until the counters are taken again.
-FP32_SMOOTH_TRAFFIC_512 = 1106.1e6
+FP32_SMOOTH_TRAFFIC_512 = 1082.3e6
 
 
 def parse():
