@@ -177,7 +177,8 @@ int mg_prolong_add(mg_ctx *ctx, const double *coarse, double *fine);
  * as cic_assign (Sec. 3.1), so it is that assignment's transpose.
  * grid: ncomp (1..3) components of n^3 device floats, [ncomp][k][j][i];
  * pos: [n_part][3] device floats in [0, n); out: [n_part][ncomp] device
- * floats.  Weights and sums in FP64.  MG_EINVAL on bad sizes or NULL. */
+ * floats.  Weights and sums in FP64.  n_part = 0 does nothing (pointers
+ * unused); MG_EINVAL on a negative n_part, ncomp outside 1..3 or NULL. */
 int mg_interp_to_particles(mg_ctx *ctx, const float *grid, int ncomp, const float *pos,
                            int64_t n_part, float *out);
 /* The same for one FP64 field (n^3 doubles), out: n_part doubles. */
@@ -209,7 +210,7 @@ int mg_total_force(mg_ctx *ctx, int model, const mg_model_params *params, const 
  * -9 Omega_m beta_*^2 xi^2 sqrt(1 - (a_* / a)^3) a^-4 u(x_p) p_p, with u the
  * solved symmetron field (n^3 device doubles) CIC-interpolated to each
  * particle.  pos, mom, out: [n_part][3] device floats.  MG_EINVAL unless
- * 0 < a_* < a. */
+ * 0 < a_* < a; n_part = 0 does nothing. */
 int mg_symmetron_friction(mg_ctx *ctx, const mg_model_params *params, const double *u_field,
                           const float *pos, const float *mom, int64_t n_part, float *out);
 

@@ -1991,7 +1991,8 @@ extern "C" {
 int mg_interp_to_particles(mg_ctx* ctx, const float* grid, int ncomp, const float* pos,
                            int64_t np, float* out) {
   if (!ctx) return MG_EINVAL;
-  if (!grid || !pos || !out || np <= 0 || ncomp < 1 || ncomp > 3)
+  if (np == 0 && ncomp >= 1 && ncomp <= 3) return MG_OK;  // no particles: nothing to do
+  if (!grid || !pos || !out || np < 0 || ncomp < 1 || ncomp > 3)
     return fail(ctx, MG_EINVAL, "mg_interp_to_particles: bad arguments");
   k_interp<float, float><<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, ncomp, pos, grid, out);
   LAUNCHCHK();
@@ -2001,7 +2002,8 @@ int mg_interp_to_particles(mg_ctx* ctx, const float* grid, int ncomp, const floa
 int mg_interp_field_to_particles(mg_ctx* ctx, const double* field, const float* pos, int64_t np,
                                  double* out) {
   if (!ctx) return MG_EINVAL;
-  if (!field || !pos || !out || np <= 0)
+  if (np == 0) return MG_OK;
+  if (!field || !pos || !out || np < 0)
     return fail(ctx, MG_EINVAL, "mg_interp_field_to_particles: bad arguments");
   k_interp<double, double><<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, 1, pos, field, out);
   LAUNCHCHK();
@@ -2064,7 +2066,7 @@ int mg_total_force(mg_ctx* ctx, int model, const mg_model_params* params, const 
 int mg_symmetron_friction(mg_ctx* ctx, const mg_model_params* params, const double* u_field,
                           const float* pos, const float* mom, int64_t np, float* out) {
   if (!ctx) return MG_EINVAL;
-  if (!params || !u_field || !pos || !mom || !out || np <= 0)
+  if (!params || np < 0 || (np > 0 && (!u_field || !pos || !mom || !out)))
     return fail(ctx, MG_EINVAL, "mg_symmetron_friction: bad arguments");
   const double a = params->a, as = params->sym_a_star;
   if (!(a > 0.0) || !(as > 0.0) || !(as < a))
@@ -2072,6 +2074,7 @@ int mg_symmetron_friction(mg_ctx* ctx, const mg_model_params* params, const doub
   const double coef = -9.0 * params->omega_m * params->sym_beta_star * params->sym_beta_star *
                       params->sym_xi * params->sym_xi * sqrt(1.0 - pow(as / a, 3.0)) /
                       pow(a, 4.0);
+  if (np == 0) return MG_OK;
   k_sym_friction<<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, pos, u_field, mom, coef, out);
   LAUNCHCHK();
   return MG_OK;

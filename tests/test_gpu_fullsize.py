@@ -15,6 +15,10 @@ at their real sizes, against the FP64 CPU oracle.
   solves (h = 1e-4 on delta at 16 probe cells).
 - The autograd path (solve_force + backward) against the explicit adjoint
   chain.
+- 512^3 particle side in the bench's configuration (512^3 particles): the FFT
+  potential through the discrete Poisson equation at sampled cells (a
+  property at any size), the total force and the CIC interpolation to
+  sampled particles and the symmetron friction against the oracle.
 
 Error metrics as in the other parity tests: field_err =
 ||x - x_ora|| / ||x_ora - x_bg||, force_err = ||g - g_ora|| / ||g_ora||.
@@ -58,7 +62,7 @@ def c3():
     err = np.max(np.abs(d_gpu - d_ora)) / np.max(np.abs(d_ora))
     say(f"512^3 CIC max|diff|/max|delta| = {err:.2e}, sigma_delta = {d_ora.std():.3f}")
     del pos
-    yield dict(n=n, mg=mg, delta=delta, d_ora=d_ora, cic_err=err)
+    yield dict(n=n, mg=mg, delta=delta, d_ora=d_ora, cic_err=err, pos32=pos32)
     mg.close()
 
 
@@ -327,3 +331,56 @@ def test_c5_1024_fp32_refined_adjoint_matches_fp64():
     say(f"  fp32 vs fp64: field {ferr:.2e}, dL/d(delta) {gerr:.2e}, loss {abs(l32 - l64) / l64:.1e}")
     assert ferr < 1e-5 and gerr < 1e-5
     mg.close()
+
+
+def test_c3_particle_side_sampled(c3):
+    n, mg, delta = c3["n"], c3["mg"], c3["delta"]
+    say("c3 particle side")
+    prm = api.model_params(float(n), fr0=1e-5)
+    P = oracle.params(oracle.FR, n, float(n), fr0=1e-5)
+    field, st = mg.solve("fr", prm, delta, tol=1e-6, opts=api.solver_opts(precision="fp32"))
+    phin = mg.poisson_newton(prm, delta)
+    ph = phin.cpu().numpy()
+    d = delta.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(512)
+    cells = rng.choice(n ** 3, 4096, replace=False)
+    k, j, i = np.unravel_index(cells, (n, n, n))
+    wrap = lambda a: a % n
+    lap = (ph[wrap(k + 1), j, i] + ph[wrap(k - 1), j, i] + ph[k, wrap(j + 1), i] +
+           ph[k, wrap(j - 1), i] + ph[k, j, wrap(i + 1)] + ph[k, j, wrap(i - 1)] - 6 * ph[k, j, i])
+    src = 1.5 * 0.3 * (d[k, j, i] - d.mean())
+    perr = np.abs(lap - src).max() / np.abs(src).max()
+    # total force at the sampled cells: -(Phi(c+e) - Phi(c-e))/2, Phi = Phi_N + Phi5
+    g = mg.total_force("fr", prm, phin, field).cpu().numpy()
+    f = field.cpu().numpy()
+    pot = lambda kk, jj, ii: ph[kk, jj, ii] - 0.5 * P_ct2(P) * f[kk, jj, ii]
+    gx = -0.5 * (pot(k, j, wrap(i + 1)) - pot(k, j, wrap(i - 1)))
+    gy = -0.5 * (pot(k, wrap(j + 1), i) - pot(k, wrap(j - 1), i))
+    gz = -0.5 * (pot(wrap(k + 1), j, i) - pot(wrap(k - 1), j, i))
+    gref = np.stack([gx, gy, gz])
+    gerr = np.abs(g[:, k, j, i] - gref).max() / np.abs(gref).max()
+    # CIC interpolation of the three components to every particle, checked
+    # on 100k sampled particles against the oracle's interpolation of the
+    # same mesh values
+    pos = torch.from_numpy(c3["pos32"]).to(DEV)
+    acc = mg.interp_to_particles(torch.from_numpy(g).to(DEV), pos)
+    sel = rng.choice(pos.shape[0], 100000, replace=False)
+    ps = c3["pos32"][sel].astype(np.float64)
+    aref = oracle.interp(n, ps, g.astype(np.float64))
+    ierr = np.abs(acc.cpu().numpy()[sel] - aref).max() / np.abs(aref).max()
+    # symmetron friction on the same particles (u in [0.3, 1], unit momenta)
+    u = torch.rand((n, n, n), dtype=torch.float64, device=DEV,
+                   generator=torch.Generator(device=DEV).manual_seed(3)) * 0.7 + 0.3
+    mom = torch.ones_like(pos)
+    prms = api.model_params(float(n), a=1.0, a_star=0.5)
+    Ps = oracle.params(oracle.SYM, n, float(n), a=1.0, a_star=0.5)
+    fr = mg.symmetron_friction(prms, u, pos, mom).cpu().numpy()[sel]
+    fref = oracle.sym_friction(Ps, u.cpu().numpy(), ps, np.ones_like(ps))
+    ferr = np.abs(fr - fref).max() / np.abs(fref).max()
+    say(f"  poisson {perr:.1e} total force {gerr:.1e} interp {ierr:.1e} friction {ferr:.1e}")
+    assert perr < 1e-8 and gerr < 1e-6 and ierr < 1e-6 and ferr < 1e-6
+    del pos, acc
+
+
+def P_ct2(P):
+    return oracle.ctilde(P.n, P.box) ** 2

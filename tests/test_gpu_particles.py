@@ -105,3 +105,16 @@ def test_total_force_matches_oracle(model, n):
     say(f"  max rel {err:.1e}")
     assert err < 1e-6
     mg.close()
+
+
+def test_empty_particle_sets_are_no_ops():
+    n = 16
+    mg = api.Context(n, device=DEV)
+    pos = torch.empty((0, 3), dtype=torch.float32, device=DEV)
+    g = torch.zeros((3, n, n, n), dtype=torch.float32, device=DEV)
+    assert mg.interp_to_particles(g, pos).shape == (0, 3)
+    f = torch.zeros((n, n, n), dtype=torch.float64, device=DEV)
+    assert mg.interp_field_to_particles(f, pos).shape == (0,)
+    prm = api.model_params(float(n), a=1.0, a_star=0.5)
+    assert mg.symmetron_friction(prm, f + 0.5, pos, pos.clone()).shape == (0, 3)
+    mg.close()
