@@ -62,21 +62,40 @@ def cpu_baseline(n, fr0, tol):
     cells = np.sort(np.random.default_rng(5005).choice(n ** 3, 4096 * n ** 3 // 512 ** 3 or 64,
                                                        replace=False))
     P = oracle.params(oracle.FR, n, float(n), fr0=fr0)
-    t0 = time.perf_counter()
+    ph = {}
+    t0 = t = time.perf_counter()
+
+    def lap(name):
+        nonlocal t
+        now = time.perf_counter()
+        ph[name] = now - t
+        t = now
+
     d = oracle.cic(n, pos)
+    lap("cic")
     v, cyc, rel, _ = oracle.solve(P, d, tol=tol, max_cycles=100)
+    lap("solve")
     g = oracle.force(P, v).reshape(3, -1)
     gf = np.zeros_like(g)
     gf[:, cells] = 2.0 * g[:, cells]
+    lap("force_and_loss")
     gv = oracle.force_adjoint(P, v, gf.reshape(3, n, n, n))
     gd, it, arel = oracle.adjoint(P, d, v, gv, tol=tol)
+    lap("adjoint")
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=n ** 3 / dt, unit="cells/s", cores=threads, kind="oracle",
                 sample=f"{n}^3 box, {n} Mpc/h, same pipeline (CIC, FP64 FAS V(1,1) to {tol:g}, "
                        f"force, loss grad, force adjoint, linear-MG adjoint to {tol:g}); "
                        f"{dt:.1f} s wall, {cyc} cycles",
-                seconds=dt)
+                seconds=dt, phases_s={k: round(x, 3) for k, x in ph.items()}, cpu_model=cpu,
+                host_threads_available=os.cpu_count())
 
 
 def m_cells(n):
