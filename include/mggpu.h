@@ -70,8 +70,10 @@ typedef struct {
   int nu_pre;       /* Gauss-Seidel sweeps (each = both colours) before coarsening, >= 0 */
   int nu_post;      /* sweeps after the correction, >= 1 */
   int inner_cycles; /* cycles between FP64 residual checks (refined mode: FP32
-                       cycles per outer step); 0 = automatic, from the measured
-                       contraction per cycle (1..8) */
+                       cycles per outer step); 0 = automatic: 2 before the
+                       first check, then enough to reach tol at the measured
+                       contraction per cycle (taken no better than 0.18 from
+                       256^3 cells up) (1..8) */
   int max_cycles;   /* cap on cycles (FP64) or outer steps (refined), 1..64 */
   int precision;    /* MG_FP64 / MG_FP32_REFINED */
   int coarse_sweeps;/* cap on sweeps of the coarsest level (they stop once its

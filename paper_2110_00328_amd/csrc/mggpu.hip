@@ -477,11 +477,21 @@ int single_level_sweeps(const mg_ctx* ctx, const mg_solver_opts* o) {
 // measured).  In the refined mode one check's FP32 cycles can reduce the
 // residual by up to ~1e-6 before FP32 rounding of the correction matters.
 constexpr int kMaxPlanned = 8;
-int plan_cycles(int fixed, double rel, double rel_prev, int k_prev, double tol) {
+// Cycles to the next FP64 check, from the contraction measured over the last
+// group of cycles.  On large grids that rate is taken no better than
+// kRhoFloor: the first cycles damp the rough error fast (per-cycle rates of
+// 0.06-0.16 at 512^3) and the rate then settles near 0.2 for V(1,1), so the
+// early rate stops a cycle short of tol and costs an extra FP64 check, a
+// full pass over the master that is worth about half a cycle there.  On
+// small grids a check is cheap next to a cycle and the measured rate is used.
+constexpr double kRhoFloor = 0.18;
+constexpr int64_t kRhoFloorCells = int64_t(1) << 24;  // 256^3
+int plan_cycles(int fixed, double rel, double rel_prev, int k_prev, double tol, int64_t cells) {
   if (fixed > 0) return fixed;
   if (rel_prev <= 0.0 || k_prev <= 0 || !(rel < rel_prev)) return 2;
   double rho = pow(rel / rel_prev, 1.0 / k_prev);
-  if (rho < 0.01) rho = 0.01;
+  const double floor_rho = cells >= kRhoFloorCells ? kRhoFloor : 0.01;
+  if (rho < floor_rho) rho = floor_rho;
   if (rho > 0.9) rho = 0.9;
   double need = 1.05 * log(tol / rel) / log(rho);
   int k = (int)ceil(need);
@@ -719,7 +729,7 @@ int solve64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   if (!std::isfinite(rel)) rc = fail(ctx, MG_ENAN, "non-finite residual");
   while (rc == MG_OK && rel > tol && cyc < o->max_cycles) {
     // the residual is checked after each planned group of cycles
-    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol);
+    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol, cells(ctx->L[0]));
     if (k > o->max_cycles - cyc) k = o->max_cycles - cyc;
     for (int it = 0; it < k; ++it) ACHK(cycle64<M>(ctx, C, o, 0, o->cycle));
     cyc += k;
@@ -931,7 +941,7 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
       rc = fail(ctx, MG_ENOCONV, "max_cycles reached");
       break;
     }
-    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol);
+    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol, cells(ctx->L[0]));
     for (int it = 0; it < k; ++it)
       ACHK(cycle32<M>(ctx, C, o, 0, o->cycle, it == 0, fresh && it == 0));
     vc += k;
@@ -1278,7 +1288,7 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
       break;
     }
     // correction scheme on r = b - A lam (FP32 or FP64 inner cycles)
-    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol);
+    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol, cells(ctx->L[0]));
     if (f32) {
       for (int it = 0; it < k; ++it)
         ACHK(lin_cycle<float>(ctx, A.w32, kap, o, 0, o->cycle, fresh && it == 0));
