@@ -125,6 +125,7 @@ __device__ __forceinline__ void ldn(const T* __restrict__ p, T* out) {
   } else {
     using VT = typename Vec<T>::type;
     constexpr int P = Vec<T>::V;
+    static_assert(N % P == 0, "whole 16-byte accesses");
 #pragma unroll
     for (int c = 0; c < N / P; ++c) {
       VT v = *reinterpret_cast<const VT*>(p + c * P);
@@ -145,6 +146,7 @@ __device__ __forceinline__ void stn(T* __restrict__ p, const T* in) {
   } else {
     using VT = typename Vec<T>::type;
     constexpr int P = Vec<T>::V;
+    static_assert(N % P == 0, "whole 16-byte accesses");
 #pragma unroll
     for (int c = 0; c < N / P; ++c) {
       VT v;
@@ -194,17 +196,31 @@ __device__ __forceinline__ void stv_nt(T* __restrict__ p, const T* in) {
     __builtin_nontemporal_store(v, reinterpret_cast<nt_d2*>(p));
   }
 }
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
 template <typename T, int N>
 __device__ __forceinline__ void ldn_nt(const T* __restrict__ p, T* out) {
-  constexpr int P = Vec<T>::V;
+  if constexpr (N * sizeof(T) == 8 && sizeof(T) == 4) {
+    nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+    out[0] = v[0];
+    out[1] = v[1];
+  } else {
+    constexpr int P = Vec<T>::V;
+    static_assert(N % P == 0, "whole 16-byte accesses");
 #pragma unroll
-  for (int c = 0; c < N / P; ++c) ldv_nt<T>(p + c * P, out + c * P);
+    for (int c = 0; c < N / P; ++c) ldv_nt<T>(p + c * P, out + c * P);
+  }
 }
 template <typename T, int N>
 __device__ __forceinline__ void stn_nt(T* __restrict__ p, const T* in) {
-  constexpr int P = Vec<T>::V;
+  if constexpr (N * sizeof(T) == 8 && sizeof(T) == 4) {
+    nt_f2 v = {in[0], in[1]};
+    __builtin_nontemporal_store(v, reinterpret_cast<nt_f2*>(p));
+  } else {
+    constexpr int P = Vec<T>::V;
+    static_assert(N % P == 0, "whole 16-byte accesses");
 #pragma unroll
-  for (int c = 0; c < N / P; ++c) stv_nt<T>(p + c * P, in + c * P);
+    for (int c = 0; c < N / P; ++c) stv_nt<T>(p + c * P, in + c * P);
+  }
 }
 // Neighbour sums of the V cells (ih0 .. ih0+V-1, j, k) of colour c from the
 // other colour's array o; s = (j + k + c) & 1.  Same summation order as nbsum.

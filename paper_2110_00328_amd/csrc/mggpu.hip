@@ -899,7 +899,8 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   // the first pre-smoothing sweep of each outer step treats the correction
   // as zero, so the buffer need not be cleared (not when level 0 is relaxed
   // by the single-block kernel, which reads it, or without pre-smoothing)
-  const bool fresh = fused && o->nu_pre > 0 && ctx->fused_from > 0;
+  // (only the vectorised level-0 smoother takes the uncleared buffer as zero)
+  const bool fresh = fused && L0.nh % Vec<float>::V == 0 && o->nu_pre > 0 && ctx->fused_from > 0;
   const float* pending = nullptr;  // correction not yet added to the master
   for (;;) {
     int64_t nparts;
@@ -1239,7 +1240,9 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
   double* psum = galerkin && sum_dg > 0.0 ? ctx->part3 : nullptr;
   // the first pre-smoothing sweep of each outer step takes the correction as
   // zero, so the fused outer kernel need not clear it
-  const bool fresh = vec && o->nu_pre > 0 && ctx->fused_from > 0;
+  // (only the vectorised level-0 smoother takes the uncleared buffer as zero)
+  const bool fresh = vec && L0.nh % (f32 ? Vec<float>::V : Vec<double>::V) == 0 &&
+                     o->nu_pre > 0 && ctx->fused_from > 0;
   for (;;) {
     int64_t nparts = vec ? march_blocks(L0, kMarchKT, kVOuter) : nblk(m);
     if (vec) {
