@@ -498,15 +498,20 @@ static void mg_cycle(const ora_params *P, ora_hier *H, int l, int nu1, int nu2, 
   for (int s = 0; s < nu2; ++s) ora_relax(P, n, H->h[l], H->delta[l], H->S[l], H->v[l]);
 }
 
+/* Residual at the background field per unit density contrast: the
+ * coefficient of delta in each equation. */
+static double bg_coef(const ora_params *P) {
+  ora_consts c = consts_of(P);
+  if (P->model == ORA_FR) return c.om_a;
+  if (P->model == ORA_SYM) return c.s_amp * c.s_ratio * c.ubar;
+  return fabs(c.cq_src);
+}
+
 /* RMS of the residual at the background field: the delta term of each
  * equation (Sec. 3.2.1 global residual, evaluated at the background). */
 double ora_background_resid_rms(const ora_params *P, const double *delta) {
-  ora_consts c = consts_of(P);
   size_t m = (size_t)P->n * P->n * P->n;
-  double coef;
-  if (P->model == ORA_FR) coef = c.om_a;
-  else if (P->model == ORA_SYM) coef = c.s_amp * c.s_ratio * c.ubar;
-  else coef = c.cq_src;
+  const double coef = bg_coef(P);
   double s = 0.0;
   for (size_t q = 0; q < m; ++q) s += (coef * delta[q]) * (coef * delta[q]);
   return sqrt(s / (double)m);
@@ -543,8 +548,11 @@ int ora_solve(const ora_params *P, const double *delta, double *v, double tol,
     h *= 2.0;
   }
   size_t m0 = (size_t)P->n * P->n * P->n;
+  /* relative residual = RMS(d) / RMS(d at the background); for delta = 0 the
+   * background solves the equation and the ratio is undefined: normalise by
+   * the residual of a unit contrast instead */
   double eps_bg = ora_background_resid_rms(P, delta);
-  if (eps_bg == 0.0) eps_bg = 1.0;
+  if (eps_bg == 0.0) eps_bg = bg_coef(P);
   double r = sqrt(ora_residual(P, P->n, 1.0, delta, NULL, v, NULL) / (double)m0) / eps_bg;
   int cyc = 0;
   while (r > tol && cyc < max_cycles) {
