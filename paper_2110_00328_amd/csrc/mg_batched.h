@@ -353,8 +353,9 @@ __device__ __noinline__ bool b_finish(const BoxDev& B, Team T) {
       int ip = i + 1 == n ? 0 : i + 1, im = i == 0 ? n - 1 : i - 1;
       int jp = j + 1 == n ? 0 : j + 1, jm = j == 0 ? n - 1 : j - 1;
       int kp = k + 1 == n ? 0 : k + 1, km = k == 0 ? n - 1 : k - 1;
-      auto phi = [&](double v) {
-        return M == FR ? -B.C.phi5 * v : (M == SYM ? B.C.phi5 * v * v : B.C.phi5 * v);
+      auto phi = [&](double v) {  // rounded products: equal values give a zero difference
+        return M == FR ? -__dmul_rn(B.C.phi5, v)
+                       : (M == SYM ? __dmul_rn(__dmul_rn(B.C.phi5, v), v) : __dmul_rn(B.C.phi5, v));
       };
       int64_t row = (int64_t)k * n + j;
       B.force[g] = float(-0.5 * (phi(f[row * n + ip]) - phi(f[row * n + im])));
@@ -374,8 +375,8 @@ __device__ __noinline__ bool box_solve(const BoxDev& B, Team T, BoxOut* out, dou
   const double m = 2.0 * double(B.L[0].half);
   double tot = 0.0;
   if (!b_pack<M>(B, T, sh, &tot)) return false;
-  double eps_bg = sqrt(tot / m);
-  if (!(eps_bg > 0.0)) eps_bg = 1.0;
+  double eps_bg = sqrt(tot / m);  // delta = 0: the residual of a unit contrast
+  if (!(eps_bg > 0.0)) eps_bg = B.C.bg_coef > 0.0 ? B.C.bg_coef : 1.0;
   int outer = 0, vc = 0, k_prev = 0, status = 0;
   double rel = 0.0, rel_prev = -1.0;
   for (;;) {

@@ -949,11 +949,12 @@ __global__ __launch_bounds__(kBlock) void k_outer_fused_kv(Lev L, const double* 
                                                            Consts C, float* __restrict__ rho,
                                                            float* __restrict__ X,
                                                            float* __restrict__ e_zero,
-                                                           double* __restrict__ part, int kt) {
+                                                           double* __restrict__ part,
+                                                           double* __restrict__ part_bg, int kt) {
   constexpr int V = kVOuter;
   __shared__ double sh[32];
   const MarchPos P = march_pos(L, kt, V);
-  double acc = 0.0;
+  double acc = 0.0, accb = 0.0;  // sum d^2; sum (bg_coef delta)^2 when part_bg is given
   if (P.ok) {
     double win[2][3][V];  // [colour][plane k-1, k, k+1][cell]
     const int km0 = P.k0 == 0 ? L.n - 1 : P.k0 - 1;
@@ -980,6 +981,10 @@ __global__ __launch_bounds__(kBlock) void k_outer_fused_kv(Lev L, const double* 
           const double vc = win[c][1][q];
           double d = direct_resid<M, double>(C, 1.0, vc, sum[q], double(dn[q]), 0.0);
           acc += d * d;
+          if (part_bg) {
+            const double bd = C.bg_coef * double(dn[q]);
+            accb += bd * bd;
+          }
           ro[q] = float(-d);
           xo[q] = float(vc);
           zo[q] = 0.0f;
@@ -999,6 +1004,10 @@ __global__ __launch_bounds__(kBlock) void k_outer_fused_kv(Lev L, const double* 
   }
   double t = block_sum(acc, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (part_bg) {  // uniform over the grid: every thread reaches block_sum's barriers
+    const double tb = block_sum(accb, sh);
+    if (threadIdx.x == 0) part_bg[blockIdx.x] = tb;
+  }
 }
 
 // adjoint: lam_new = lam + e + shift, r = b - A lam_new, e_zero = 0;

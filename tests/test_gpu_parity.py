@@ -414,3 +414,68 @@ def test_marching_restriction_is_bit_identical(monkeypatch, model, prec):
     err = field_err(model, out[1][0], to_field(model, ref), P)
     say(f"  field_err={err:.2e}")
     assert err < 1e-5
+
+
+def _background(model, P):
+    if model == "fr":
+        return -oracle.background(P)  # the library's f(R) field is f_R = -w
+    return oracle.background(P)
+
+
+@pytest.mark.parametrize("model", ["fr", "sym", "cq"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zero_contrast_gives_the_background(model, prec):
+    """delta = 0: the background solves the equation exactly (its residual,
+    which normalises the relative residual, is zero): the field is the
+    background value everywhere, the force and an adjoint of a zero loss
+    gradient vanish."""
+    n = 24
+    say("zero contrast", model, prec)
+    P, prm = cfg(model, n, 2.0 * n)
+    mg = api.Context(n, device=DEV)
+    delta = torch.zeros((n, n, n), dtype=torch.float32, device=DEV)
+    opts = api.solver_opts(precision=prec)
+    field, st = mg.solve(model, prm, delta, tol=1e-10, opts=opts)
+    bg = _background(model, P)
+    assert torch.all(field == bg), (field.min().item(), field.max().item(), bg)
+    assert torch.count_nonzero(mg.force(model, prm, field)).item() == 0
+    gd, st2 = mg.solve_adjoint(model, prm, delta, field, torch.zeros_like(field), tol=1e-10,
+                               opts=opts)
+    assert torch.count_nonzero(gd).item() == 0
+    mg.close()
+
+
+@pytest.mark.parametrize("model", ["fr", "sym", "cq"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_uniform_contrast_matches_closed_form(model, prec):
+    """A uniform delta0: the Laplacian vanishes and the field is uniform, in
+    closed form for f(R) (w = wbar (K / (K + Omega_m delta0 / a))^{n+1}) and the
+    symmetron (u^2 = 1 - (1 + delta0) a*^3 / a^3); for CQ against the oracle.
+    CQ's uniform mode is nearly singular (phi~ ~ 1e7 held by a tiny mass
+    term), so rounding in the Laplacian floors its residual near 1e-8: it is
+    solved to 1e-7, and its relative field error follows the residual."""
+    n, d0 = 24, 2.0 if model == "sym" else 4.0
+    say("uniform contrast", model, prec)
+    if model == "cq":
+        d0 = 0.3
+    P, prm = cfg(model, n, 2.0 * n)
+    mg = api.Context(n, device=DEV)
+    delta = torch.full((n, n, n), d0, dtype=torch.float32, device=DEV)
+    tol = 1e-7 if model == "cq" else 1e-10
+    field, st = mg.solve(model, prm, delta, tol=tol,
+                         opts=api.solver_opts(precision=prec, max_cycles=64))
+    f = field.cpu().numpy()
+    d64 = float(np.float32(d0))  # the float32 input, in FP64 (a numpy float32 would keep
+    if model == "fr":            # the closed form in single precision)
+        a, om = P.a, P.omega_m
+        K = (om / a ** 3 + 4 * (1 - om)) * a ** 2
+        ref = -oracle.background(P) * (K / (K + om * d64 / a)) ** (P.fr_n + 1)
+    elif model == "sym":
+        ref = np.sqrt(1 - (1 + d64) * (P.a_star / P.a) ** 3)
+    else:
+        v, _, _, _ = oracle.solve(P, np.full((n, n, n), d64), tol=1e-12, max_cycles=200)
+        ref = v.mean()
+    err = np.abs(f - ref).max() / abs(ref)
+    say(f"  outer={st.cycles} rel={st.rel_resid:.1e} err={err:.1e} spread={np.ptp(f):.1e}")
+    assert err < (1e-5 if model == "cq" else (1e-9 if prec == "fp64" else 1e-6))
+    mg.close()
