@@ -1519,6 +1519,26 @@ __global__ __launch_bounds__(kBlock) void k_loss_sq(int64_t m, const float* __re
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+struct CicCell {
+  int i0[3];
+  double t[3];
+};
+// lower CIC cell and fractional offsets of one particle
+__device__ __forceinline__ CicCell cic_cell(int n, const float* __restrict__ pos, int64_t p) {
+  CicCell c;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // in double the offset and the fraction are exact for any float position
+    const double s = double(pos[3 * p + a]) - 0.5;
+    const double fl = floor(s);
+    c.t[a] = s - fl;
+    int q = (int)fl;
+    q %= n;
+    if (q < 0) q += n;
+    c.i0[a] = q;
+  }
+  return c;
+}
 // CIC: per axis, s = x - 1/2, i0 = floor(s), t = s - i0 (formed in FP64, so
 // exact for every float position); weights (1-t, t) to cells i0, i0+1 (periodic).  The 8
 // products are formed in FP64 and deposited as 32.32 fixed point; the last
@@ -1527,19 +1547,9 @@ __global__ __launch_bounds__(kBlock) void k_cic(int n, int64_t np, const float* 
                                                 unsigned long long* __restrict__ acc) {
   int64_t p = gid();
   if (p >= np) return;
-  int i0[3];
-  double t[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float x = pos[3 * p + a];
-    float s = x - 0.5f;
-    float fl = floorf(s);
-    t[a] = double(s - fl);
-    int c = (int)fl;
-    c %= n;
-    if (c < 0) c += n;
-    i0[a] = c;
-  }
+  const CicCell c = cic_cell(n, pos, p);
+  const int* i0 = c.i0;
+  const double* t = c.t;
   long long w[8];
   long long tot = 0;
 #pragma unroll
@@ -1571,26 +1581,6 @@ constexpr int kT = 16;          // tile edge (cells)
 constexpr int kTH = kT + 1;     // tile plus the +1 layer its particles reach
 constexpr int kTH3 = kTH * kTH * kTH;
 
-struct CicCell {
-  int i0[3];
-  double t[3];
-};
-// lower CIC cell and fractional offsets of one particle (same rule as k_cic)
-__device__ __forceinline__ CicCell cic_cell(int n, const float* __restrict__ pos, int64_t p) {
-  CicCell c;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    // in double the offset and the fraction are exact for any float position
-    const double s = double(pos[3 * p + a]) - 0.5;
-    const double fl = floor(s);
-    c.t[a] = s - fl;
-    int q = (int)fl;
-    q %= n;
-    if (q < 0) q += n;
-    c.i0[a] = q;
-  }
-  return c;
-}
 // 8 fixed-point weights summing to exactly 2^32 (corner q: dx = q&1, dy, dz)
 __device__ __forceinline__ void cic_weights(const CicCell& c, long long* w) {
   long long tot = 0;
