@@ -98,7 +98,9 @@ typedef struct mg_ctx mg_ctx;
  * workspace is allocated on first use of each mode and kept until destroy.
  * The environment variable MGGPU_MARCH_MIN_BLOCKS, read here, sets from how
  * many workgroups up the residual/restriction kernels march in z (default
- * 2048; the results are identical either way).
+ * 2048; the results are identical either way), and MGGPU_SMOOTH_MARCH_KT
+ * (1..64) switches the level-0 FP32 smoother to a z-marching form with that
+ * many planes per thread (default off; identical results).
  * Returns MG_EINVAL for a bad n or NULL out. */
 int mg_ctx_create(mg_ctx **out, int n, void *hip_stream);
 void mg_ctx_destroy(mg_ctx *ctx);

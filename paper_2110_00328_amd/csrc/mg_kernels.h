@@ -897,6 +897,67 @@ __host__ __device__ inline unsigned march_blocks(const Lev& L, int kt, int V) {
   unsigned nchunk = (ngrp + kBlock - 1) / kBlock;
   return nchunk * (unsigned)((L.n + kt - 1) / kt);
 }
+// The same half-sweep marching in z: a thread owns 4 packed cells of its
+// colour in row j and walks kt planes, keeping the other colour's rows
+// (j, k-1), (j, k), (j, k+1) in registers, so each plane reads one new
+// other-colour row plus the rows j +- 1.  Per-cell arithmetic and the
+// neighbour summation order are those of op_smooth_corr_v (bit-identical).
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_smooth_corr_kv(Lev L, float* e, const float* X,
+                                                           const float* dens, const float* rho,
+                                                           int colour, float h2, Consts C,
+                                                           int fresh, int kt) {
+  constexpr int V = Vec<float>::V;
+  const MarchPos P = march_pos(L, kt, V);
+  if (!P.ok) return;
+  const float* o = e + (1 - colour) * L.half;
+  float* own = e + colour * L.half;
+  const int j = P.j, ih0 = P.ih0, n = L.n;
+  const bool zero_nb = fresh && colour == 0;  // the other colour still holds no correction
+  float zm[V] = {0, 0, 0, 0}, zc[V] = {0, 0, 0, 0}, zp[V] = {0, 0, 0, 0};
+  if (!zero_nb) {
+    ldn<float, V>(o + prow(L, j, P.k0 == 0 ? n - 1 : P.k0 - 1) + ih0, zm);
+    ldn<float, V>(o + prow(L, j, P.k0) + ih0, zc);
+  }
+  for (int k = P.k0; k < P.k1; ++k) {
+    const uint32_t r = prow(L, j, k);
+    float sum[V] = {0, 0, 0, 0};
+    if (!zero_nb) {
+      ldn<float, V>(o + prow(L, j, k + 1 == n ? 0 : k + 1) + ih0, zp);
+      const int s = (j + k + colour) & 1;
+      float xv[V + 1], ym[V], yp[V];
+      if (s) {
+#pragma unroll
+        for (int q = 0; q < V; ++q) xv[q] = zc[q];
+        xv[V] = o[r + (ih0 + V == L.nh ? 0 : ih0 + V)];
+      } else {
+#pragma unroll
+        for (int q = 0; q < V; ++q) xv[q + 1] = zc[q];
+        xv[0] = o[r + (ih0 == 0 ? L.nh - 1 : ih0 - 1)];
+      }
+      ldn<float, V>(o + prow(L, P.jm, k) + ih0, ym);
+      ldn<float, V>(o + prow(L, P.jp, k) + ih0, yp);
+#pragma unroll
+      for (int q = 0; q < V; ++q)
+        sum[q] = (xv[q] + xv[q + 1]) + (ym[q] + yp[q]) + (zm[q] + zp[q]);
+    }
+    const uint32_t q0 = (uint32_t)colour * (uint32_t)L.half + r + (uint32_t)ih0;
+    float x[V], rr[V], dc[V] = {0, 0, 0, 0}, eo[V] = {0, 0, 0, 0}, out[V];
+    ldv_nt<float>(X + q0, x);
+    ldv_nt<float>(rho + q0, rr);
+    if (M != FR) ldv_nt<float>(dens + q0, dc);
+    if (M == CQ && !fresh) ldv<float>(own + r + ih0, eo);
+#pragma unroll
+    for (int q = 0; q < V; ++q) out[q] = corr_update<M>(C, h2, eo[q], sum[q], x[q], dc[q], rr[q]);
+    stv_nt<float>(own + r + ih0, out);
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      zm[q] = zc[q];
+      zc[q] = zp[q];
+    }
+  }
+}
+
 // v = w + e (e may be null; w null: the uniform value wu) of V packed cells
 // of colour c in row (j, k)
 template <typename TE, int V>

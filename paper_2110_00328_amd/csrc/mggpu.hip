@@ -80,6 +80,9 @@ struct mg_ctx {
   // workgroups up (below it a grid is too sparse to hide the march);
   // MGGPU_MARCH_MIN_BLOCKS overrides it at context creation
   unsigned march_min_blocks = 2048;
+  // planes per thread of the z-marching level-0 FP32 smoother (0: the
+  // per-row kernel); MGGPU_SMOOTH_MARCH_KT overrides it at context creation
+  int smooth_march_kt = 0;
   std::string err;
   int nlev = 0;
   Lev L[kMaxLev];
@@ -794,7 +797,12 @@ int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps, bool fresh = false
       // half-sweep reads no neighbours and is left out)
       const bool light = fresh && s == 0 && colour == 0;
       int q = (l == 0 && !light) ? prof_begin(ctx, MG_PROF_SMOOTH32) : -1;
-      if (vec)
+      const int kt = ctx->smooth_march_kt;
+      if (vec && kt > 0 && march_blocks(L, kt, Vec<float>::V) >= ctx->march_min_blocks)
+        k_smooth_corr_kv<M><<<march_blocks(L, kt, Vec<float>::V), kBlock, 0, ctx->stream>>>(
+            L, W.e[l], W.X[l], W.dens[l], W.rho[l], colour, float(lev_h2(l)), C,
+            (fresh && s == 0) ? 1 : 0, kt);
+      else if (vec)
         k_smooth_corr_v<M><<<nblk(nv), kBlock, 0, ctx->stream>>>(
             L, W.e[l], W.X[l], W.dens[l], W.rho[l], colour, float(lev_h2(l)), C,
             (fresh && s == 0) ? 1 : 0);
@@ -1738,6 +1746,10 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
   mg_ctx* ctx = new mg_ctx();
   ctx->n = n;
   if (const char* mb = getenv("MGGPU_MARCH_MIN_BLOCKS")) ctx->march_min_blocks = (unsigned)atoi(mb);
+  if (const char* sk = getenv("MGGPU_SMOOTH_MARCH_KT")) {
+    const int kt = atoi(sk);
+    ctx->smooth_march_kt = kt > 0 && kt <= 64 ? kt : 0;
+  }
   ctx->stream = (hipStream_t)hip_stream;
   // pyramid: halve while the half is even and >= 4
   int m = n, l = 0;

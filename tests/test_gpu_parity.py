@@ -385,9 +385,10 @@ def test_f_and_w_cycles_match_oracle(cycle, model):
 @pytest.mark.parametrize("model", ["fr", "sym"])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_marching_restriction_is_bit_identical(monkeypatch, model, prec):
-    """The z-marching residual/restriction kernels (used on large grids) give
-    bit-identical solves and adjoints; forced on here at 64^3 (coarse sides
-    32, 16, 8), and checked against the oracle too."""
+    """The z-marching residual/restriction kernels (used on large grids) and
+    the z-marching FP32 smoother give bit-identical solves and adjoints;
+    forced on here at 64^3 (coarse sides 32, 16, 8), and checked against the
+    oracle too."""
     n, box = 64, 64.0
     say("marching restriction", model, prec)
     P, prm = cfg(model, n, box)
@@ -397,8 +398,10 @@ def test_marching_restriction_is_bit_identical(monkeypatch, model, prec):
     for mb in (None, "0"):
         if mb is None:
             monkeypatch.delenv("MGGPU_MARCH_MIN_BLOCKS", raising=False)
+            monkeypatch.delenv("MGGPU_SMOOTH_MARCH_KT", raising=False)
         else:
             monkeypatch.setenv("MGGPU_MARCH_MIN_BLOCKS", mb)
+            monkeypatch.setenv("MGGPU_SMOOTH_MARCH_KT", "4")
         mg = api.Context(n, device=DEV)
         field, st = mg.solve(model, prm, delta, tol=1e-8, opts=opts)
         cells = torch.from_numpy(np.random.default_rng(42).choice(n ** 3, 200, replace=False)).to(DEV)
