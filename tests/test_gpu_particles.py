@@ -118,3 +118,36 @@ def test_empty_particle_sets_are_no_ops():
     prm = api.model_params(float(n), a=1.0, a_star=0.5)
     assert mg.symmetron_friction(prm, f + 0.5, pos, pos.clone()).shape == (0, 3)
     mg.close()
+
+
+def test_particle_side_error_paths():
+    """Bad arguments are rejected with MG_EINVAL and leave the context usable."""
+    n = 16
+    mg = api.Context(n, device=DEV)
+    L = mg.lib
+    prm = api.model_params(float(n))
+    g = torch.zeros((4, n, n, n), dtype=torch.float32, device=DEV)
+    pos = torch.full((10, 3), 1.5, dtype=torch.float32, device=DEV)
+    out = torch.empty((10, 4), dtype=torch.float32, device=DEV)
+    import ctypes
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    assert L.mg_interp_to_particles(mg.ptr, vp(g), 4, vp(pos), 10, vp(out)) == api.L.MG_EINVAL
+    assert L.mg_interp_to_particles(mg.ptr, vp(g), 0, vp(pos), 10, vp(out)) == api.L.MG_EINVAL
+    assert L.mg_interp_to_particles(mg.ptr, vp(g), 3, vp(pos), -1, vp(out)) == api.L.MG_EINVAL
+    assert L.mg_interp_to_particles(mg.ptr, None, 3, vp(pos), 10, vp(out)) == api.L.MG_EINVAL
+    phi = torch.zeros((n, n, n), dtype=torch.float64, device=DEV)
+    f = torch.empty((3, n, n, n), dtype=torch.float32, device=DEV)
+    assert L.mg_gradient(mg.ptr, None, vp(f)) == api.L.MG_EINVAL
+    assert L.mg_total_force(mg.ptr, api.L.MG_FR, ctypes.byref(prm), None, vp(phi), vp(f)) == \
+        api.L.MG_EINVAL
+    assert L.mg_total_force(mg.ptr, 7, ctypes.byref(prm), vp(phi), vp(phi), vp(f)) == api.L.MG_EINVAL
+    bad = api.model_params(float(n), a=-1.0)
+    assert L.mg_poisson_newton(mg.ptr, ctypes.byref(bad), vp(g), vp(phi)) == api.L.MG_EINVAL
+    with pytest.raises(api.MGError):
+        mg.symmetron_friction(api.model_params(float(n), a=0.5, a_star=0.5), phi + 0.5, pos, pos)
+    assert mg.lib.mg_last_error(mg.ptr)  # a message is kept
+    # the context still works after the rejected calls
+    d = torch.zeros((n, n, n), dtype=torch.float32, device=DEV)
+    out_phi = mg.poisson_newton(prm, d)
+    assert torch.count_nonzero(out_phi).item() == 0
+    mg.close()
