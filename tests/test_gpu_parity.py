@@ -382,14 +382,17 @@ def test_f_and_w_cycles_match_oracle(cycle, model):
     mg.close()
 
 
-@pytest.mark.parametrize("model", ["fr", "sym"])
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_marching_restriction_is_bit_identical(monkeypatch, model, prec):
+@pytest.mark.parametrize("model,prec,n", [("fr", "fp32", 64), ("fr", "fp64", 64),
+                                          ("sym", "fp32", 64), ("sym", "fp64", 64),
+                                          ("fr", "fp32", 96), ("sym", "fp32", 160),
+                                          ("fr", "fp64", 160)])
+def test_marching_restriction_is_bit_identical(monkeypatch, model, prec, n):
     """The z-marching residual/restriction kernels (used on large grids) and
     the z-marching FP32 smoother give bit-identical solves and adjoints;
-    forced on here at 64^3 (coarse sides 32, 16, 8), and checked against the
-    oracle too."""
-    n, box = 64, 64.0
+    forced on here at 64^3 (coarse sides 32, 16, 8), 96^3 (48, 24) and
+    160^3 (80, 40, 20: plane counts not divisible by the march depth), and
+    checked against the oracle too."""
+    box = float(n)
     say("marching restriction", model, prec)
     P, prm = cfg(model, n, box)
     delta = torch.from_numpy(lognormal(n, 41)).to(DEV)
