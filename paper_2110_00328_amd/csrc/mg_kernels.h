@@ -774,89 +774,11 @@ __global__ __launch_bounds__(kBlock) void k_smooth_lin_v(Lev L, T* e, const T* d
   stv_nt<T>(e + q0, out);
 }
 
-// Neighbour sums of w + e (the updated FP64 values, formed exactly as the
-// update w += double(e) stores them).
-template <typename TE, int V>
-__device__ __forceinline__ void nbsum2_vec(const Lev& L, const double* __restrict__ w,
-                                           const TE* __restrict__ e, int ih0, int j, int k,
-                                           int s, double* sum) {
-  int jm = (j == 0) ? L.n - 1 : j - 1, jp = (j == L.n - 1) ? 0 : j + 1;
-  int km = (k == 0) ? L.n - 1 : k - 1, kp = (k == L.n - 1) ? 0 : k + 1;
-  const uint32_t rows[5] = {prow(L, j, k), prow(L, jm, k), prow(L, jp, k), prow(L, j, km),
-                            prow(L, j, kp)};
-  double nv[5][V];
-#pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    TE ev[V];
-    ldn<double, V>(w + rows[q] + ih0, nv[q]);
-    ldn<TE, V>(e + rows[q] + ih0, ev);
-#pragma unroll
-    for (int t = 0; t < V; ++t) nv[q][t] += double(ev[t]);
-  }
-  uint32_t xi = s ? (ih0 + V == L.nh ? 0 : ih0 + V) : (ih0 == 0 ? L.nh - 1 : ih0 - 1);
-  double xe = w[rows[0] + xi] + double(e[rows[0] + xi]);
-  double xv[V + 1];
-#pragma unroll
-  for (int t = 0; t < V; ++t) xv[s ? t : t + 1] = nv[0][t];
-  xv[s ? V : 0] = xe;
-#pragma unroll
-  for (int q = 0; q < V; ++q)
-    sum[q] = (xv[q] + xv[q + 1]) + (nv[1][q] + nv[2][q]) + (nv[3][q] + nv[4][q]);
-}
 
 // Fused FP64 outer step of the refined mode: w_new = w + e (e may be null:
 // no update), d = F(w_new), rho = -d, X = w_new, e_zero = 0 (a different
 // buffer from e); per-block sum of d^2.
 constexpr int kVOuter = 4;  // cells per colour per thread in the outer kernels (nh % 4 == 0)
-
-template <int M>
-__global__ __launch_bounds__(kBlock) void k_outer_fused_v(Lev L, const double* w, const float* e,
-                                                          double* w_new, const float* dens,
-                                                          Consts C, float* rho, float* X,
-                                                          float* e_zero, double* part) {
-  constexpr int V = kVOuter;
-  __shared__ double sh[32];
-  uint32_t g4 = (uint32_t)gid();
-  double acc = 0.0;
-  if (g4 < (uint32_t)(L.half / V)) {
-    uint32_t g = g4 * V;
-    int ih0, j, k;
-    dec(g, L, ih0, j, k);
-#pragma unroll 1
-    for (int c = 0; c < 2; ++c) {
-      uint32_t q0 = (uint32_t)c * (uint32_t)L.half + g;
-      int s = (j + k + c) & 1;
-      double sum[V], vc[V];
-      float dn[V], ro[V], xo[V], zo[V];
-      if (e) {
-        float ev[V];
-        nbsum2_vec<float, V>(L, w + (1 - c) * L.half, e + (1 - c) * L.half, ih0, j, k, s, sum);
-        ldn<double, V>(w + q0, vc);
-        ldn<float, V>(e + q0, ev);
-#pragma unroll
-        for (int q = 0; q < V; ++q) vc[q] += double(ev[q]);
-        stn<double, V>(w_new + q0, vc);
-      } else {
-        nbsum_vec<double, V>(L, w + (1 - c) * L.half, ih0, j, k, s, sum);
-        ldn<double, V>(w + q0, vc);
-      }
-      ldn<float, V>(dens + q0, dn);
-#pragma unroll
-      for (int q = 0; q < V; ++q) {
-        double d = direct_resid<M, double>(C, 1.0, vc[q], sum[q], double(dn[q]), 0.0);
-        acc += d * d;
-        ro[q] = float(-d);
-        xo[q] = float(vc[q]);
-        zo[q] = 0.0f;
-      }
-      stn<float, V>(rho + q0, ro);
-      stn<float, V>(X + q0, xo);
-      stn<float, V>(e_zero + q0, zo);
-    }
-  }
-  double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
 
 // ---------------------------------------------------------------------------
 // k-marching versions of the FP64 outer steps.  A block owns kBlock groups of
@@ -1127,69 +1049,6 @@ __global__ __launch_bounds__(kBlock) void k_lin_outer_fused_kv(
           win[c][0][q] = win[c][1][q];
           win[c][1][q] = win[c][2][q];
         }
-    }
-  }
-  double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-  if (part_sum) {
-    t = block_sum(accs, sh);
-    if (threadIdx.x == 0) part_sum[blockIdx.x] = t;
-  }
-}
-
-// Fused FP64 outer step of the adjoint: lam_new = lam + e (e may be null),
-// r = b - A lam_new -> r (inner precision), e_zero = 0; sum of r^2
-template <typename TO>
-// lam_new = lam + e + shift (a uniform shift; the Laplacian of a constant
-// vanishes, so only the diagonal term sees it).  part_sum (optional) gets the
-// partial sums of r itself.
-__global__ __launch_bounds__(kBlock) void k_lin_outer_fused_v(Lev L, const double* lam,
-                                                              const TO* e, double* lam_new,
-                                                              const double* dg, const double* b,
-                                                              double kh2, TO* r, TO* e_zero,
-                                                              double* part, double shift,
-                                                              double* part_sum) {
-  constexpr int V = kVOuter;
-  __shared__ double sh[32];
-  uint32_t g4 = (uint32_t)gid();
-  double acc = 0.0, accs = 0.0;
-  if (g4 < (uint32_t)(L.half / V)) {
-    uint32_t g = g4 * V;
-    int ih0, j, k;
-    dec(g, L, ih0, j, k);
-#pragma unroll 1
-    for (int c = 0; c < 2; ++c) {
-      uint32_t q0 = (uint32_t)c * (uint32_t)L.half + g;
-      int s = (j + k + c) & 1;
-      double sum[V], lc[V], dd[V], bb[V];
-      TO ro[V], zo[V];
-      if (e) {
-        TO ev[V];
-        nbsum2_vec<TO, V>(L, lam + (1 - c) * L.half, e + (1 - c) * L.half, ih0, j, k, s, sum);
-        ldn<double, V>(lam + q0, lc);
-        ldn<TO, V>(e + q0, ev);
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-          lc[q] += double(ev[q]) + shift;
-          sum[q] += 6.0 * shift;
-        }
-        stn<double, V>(lam_new + q0, lc);
-      } else {
-        nbsum_vec<double, V>(L, lam + (1 - c) * L.half, ih0, j, k, s, sum);
-        ldn<double, V>(lam + q0, lc);
-      }
-      ldn<double, V>(dg + q0, dd);
-      ldn<double, V>(b + q0, bb);
-#pragma unroll
-      for (int q = 0; q < V; ++q) {
-        double d = bb[q] - (kh2 * (6.0 * lc[q] - sum[q]) + dd[q] * lc[q]);
-        acc += d * d;
-        accs += d;
-        ro[q] = TO(d);
-        zo[q] = TO(0);
-      }
-      stn<TO, V>(r + q0, ro);
-      stn<TO, V>(e_zero + q0, zo);
     }
   }
   double t = block_sum(acc, sh);
@@ -1834,12 +1693,6 @@ __global__ __launch_bounds__(kBlock) void k_coarse_src_direct(Lev L, const T* Rv
   if (g < 2 * L.half) op_coarse_src_direct<M, T, TD>(L, Rv, dens, S, h2, C, g);
 }
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong_add(Lev Lf, Lev Lc, T* v, const T* vH,
-                                                        const T* RvH) {
-  int64_t g = gid();
-  if (g < 2 * Lf.half) op_prolong_add<T>(Lf, Lc, v, vH, RvH, g);
-}
-template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong_block(Lev Lf, Lev Lc, T* v, const T* c) {
   int64_t g = gid();
   if (g < 2 * Lc.half) op_prolong_block<T>(Lf, Lc, v, c, g);
@@ -2009,24 +1862,10 @@ __global__ __launch_bounds__(kBlock) void k_add_const(int64_t m, double* y, doub
   if (g < m) y[g] += c;
 }
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sq_norm(int64_t m, const T* x, double* part) {
-  __shared__ double sh[32];
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double d = g < m ? double(x[g]) : 0.0;
-  double t = block_sum(d * d, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-template <typename T>
 __global__ __launch_bounds__(kBlock) void k_axpy_to64(int64_t m, double* y, const T* x) {
   int64_t g = gid();
   if (g < m) y[g] += double(x[g]);
 }
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cast(int64_t m, const double* x, T* y) {
-  int64_t g = gid();
-  if (g < m) y[g] = T(x[g]);
-}
-
 // ---------------------------------------------------------------------------
 // Fused coarse cycle: one workgroup runs a precomputed program of level
 // operations on the small levels (latency-bound as separate launches).
