@@ -398,12 +398,11 @@ def test_marching_restriction_is_bit_identical(monkeypatch, model, prec, n):
     delta = torch.from_numpy(lognormal(n, 41)).to(DEV)
     opts = api.solver_opts(precision=prec)
     out = []
-    for mb in (None, "0"):
-        if mb is None:
-            monkeypatch.delenv("MGGPU_MARCH_MIN_BLOCKS", raising=False)
-            monkeypatch.delenv("MGGPU_SMOOTH_MARCH_KT", raising=False)
-        else:
-            monkeypatch.setenv("MGGPU_MARCH_MIN_BLOCKS", mb)
+    for mode in ("default", "march"):
+        for var in ("MGGPU_MARCH_MIN_BLOCKS", "MGGPU_SMOOTH_MARCH_KT"):
+            monkeypatch.delenv(var, raising=False)
+        if mode != "default":
+            monkeypatch.setenv("MGGPU_MARCH_MIN_BLOCKS", "0")
             monkeypatch.setenv("MGGPU_SMOOTH_MARCH_KT", "4")
         mg = api.Context(n, device=DEV)
         field, st = mg.solve(model, prm, delta, tol=1e-8, opts=opts)
@@ -414,8 +413,9 @@ def test_marching_restriction_is_bit_identical(monkeypatch, model, prec, n):
         gd, st2 = mg.solve_adjoint(model, prm, delta, field, gfield, tol=1e-8, opts=opts)
         out.append((field.cpu().numpy(), gd.cpu().numpy(), st.cycles, st2.cycles))
         mg.close()
-    assert out[0][2:] == out[1][2:]
-    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    for o in out[1:]:
+        assert out[0][2:] == o[2:]
+        assert np.array_equal(out[0][0], o[0]) and np.array_equal(out[0][1], o[1])
     ref, _, _, _ = oracle.solve(P, delta.cpu().numpy().astype(np.float64), tol=1e-12)
     err = field_err(model, out[1][0], to_field(model, ref), P)
     say(f"  field_err={err:.2e}")
