@@ -100,7 +100,8 @@ typedef struct mg_ctx mg_ctx;
  * many workgroups up the residual/restriction kernels march in z (default
  * 2048; the results are identical either way), and MGGPU_SMOOTH_MARCH_KT
  * (1..64) switches the level-0 FP32 smoother to a z-marching form with that
- * many planes per thread (default off; identical results).
+ * many planes per thread (default off; identical results).  MGGPU_CIC_DIRECT=1
+ * makes cic_assign always take its direct atomic path (identical results).
  * Returns MG_EINVAL for a bad n or NULL out. */
 int mg_ctx_create(mg_ctx **out, int n, void *hip_stream);
 void mg_ctx_destroy(mg_ctx *ctx);
@@ -110,8 +111,11 @@ int mg_ctx_levels(const mg_ctx *ctx);
 /* Cloud-in-cell density contrast (Sec. 3.1).  pos: n_part x 3 floats (x,y,z)
  * in code units [0, n); cell c covers [c, c+1) with centre c + 1/2.  Out:
  * delta[n^3] = rho/mean - 1.  Deposits are 32.32 fixed-point integer
- * atomics, so the result does not depend on the order of the particles and
- * the total mass is exact.  MG_EINVAL if n_part <= 0. */
+ * sums, so the result does not depend on the order of the particles and
+ * the total mass is exact.  For n % 16 == 0 the particles are sorted into
+ * 16^3 tiles and each tile is summed in LDS; otherwise each corner is a global
+ * 64-bit atomic.  Workspace: 12 bytes per particle plus 96 bytes per tile.
+ * MG_EINVAL if n_part <= 0. */
 int cic_assign(mg_ctx *ctx, const float *pos_xyz, int64_t n_part, float *delta_out);
 
 /* Solve the model's scalar-field equation for delta (n^3 floats):

@@ -83,6 +83,12 @@ struct mg_ctx {
   // planes per thread of the z-marching level-0 FP32 smoother (0: the
   // per-row kernel); MGGPU_SMOOTH_MARCH_KT overrides it at context creation
   int smooth_march_kt = 0;
+  // device facts for the cooperative batched launch, queried once (property
+  // queries cost milliseconds per call): CU count, cooperative support, and
+  // resident workgroups per CU for each workgroup size (index log2(BS) - 8)
+  int bdev_cus = 0, bdev_coop = -1;
+  int bocc[3] = {0, 0, 0};
+  std::string arch;  // gcnArchName, part of the tuning-cache key
   std::string err;
   int nlev = 0;
   Lev L[kMaxLev];
@@ -100,8 +106,8 @@ struct mg_ctx {
   int64_t* cic = nullptr;      // CIC fixed-point accumulator (direct path)
   float* cic_sorted = nullptr;  // binned CIC: positions in tile order
   int64_t cic_np = 0;
-  unsigned long long* cic_blocks = nullptr;  // per-tile private 17^3 blocks
-  uint32_t* cic_cnt = nullptr;  // counts, offsets, cursors per tile
+  uint32_t* cic_cnt = nullptr;  // counts, offsets, cursors per (tile, class) bin
+  int cic_direct = 0;           // 1: always the direct atomic path (MGGPU_CIC_DIRECT)
   // batched solves
   void* bpool = nullptr;
   size_t bpool_bytes = 0;
@@ -1585,9 +1591,14 @@ __global__ __launch_bounds__(kBlock) void k_cic_finish(int64_t m, const unsigned
 }
 
 // ---- binned CIC: tiles of kT^3 cells ------------------------------------
-constexpr int kT = 16;          // tile edge (cells)
-constexpr int kTH = kT + 1;     // tile plus the +1 layer its particles reach
-constexpr int kTH3 = kTH * kTH * kTH;
+// Particles are sorted by bin = (tile, class).  Bit a of the class is set when
+// the particle's lower cell is the last layer of its tile along axis a, so
+// that the particle also reaches the next tile along a.  The workgroup of a
+// tile deposits its own particles and the reaching classes of its 7 lower
+// neighbours, so it holds every contribution to its kT^3 cells and writes δ
+// directly.  Sums are 32.32 fixed point: exact, in any order.
+constexpr int kT = 16;  // tile edge (cells)
+constexpr int kT3 = kT * kT * kT;
 
 // 8 fixed-point weights summing to exactly 2^32 (corner q: dx = q&1, dy, dz)
 __device__ __forceinline__ void cic_weights(const CicCell& c, long long* w) {
@@ -1602,127 +1613,242 @@ __device__ __forceinline__ void cic_weights(const CicCell& c, long long* w) {
   }
   w[7] = 4294967296LL - tot;
 }
-__device__ __forceinline__ uint32_t tile_of(const CicCell& c, int nt) {
-  return ((uint32_t)(c.i0[2] / kT) * nt + (uint32_t)(c.i0[1] / kT)) * nt + (uint32_t)(c.i0[0] / kT);
+__device__ __forceinline__ uint32_t bin_of(const CicCell& c, int nt) {
+  const uint32_t t =
+      ((uint32_t)(c.i0[2] / kT) * nt + (uint32_t)(c.i0[1] / kT)) * nt + (uint32_t)(c.i0[0] / kT);
+  const uint32_t cls = (c.i0[0] % kT == kT - 1 ? 1u : 0u) | (c.i0[1] % kT == kT - 1 ? 2u : 0u) |
+                       (c.i0[2] % kT == kT - 1 ? 4u : 0u);
+  return 8u * t + cls;
 }
 
-// Wave-level runs of equal tiles: one atomic per run.  Returns, for every
-// active lane, the slot base of its run plus its rank in the run.
-__device__ __forceinline__ uint32_t run_reserve(uint32_t t, bool valid, uint32_t* ctr) {
+// Wave-level runs of equal bins (consecutive lanes, same bin): the run's
+// first lane adds the run length to the bin's counter.
+struct CicRun {
+  int leader;    // lane of the run's first particle
+  uint32_t len;  // run length (on the leader)
+  bool lead;
+};
+__device__ __forceinline__ CicRun cic_run(uint32_t t, bool valid) {
   const int lane = threadIdx.x & 63;
-  uint32_t prev = __shfl_up(t, 1, 64);
-  bool leader = !valid || lane == 0 || prev != t;
-  unsigned long long lead = __ballot(leader);
-  unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-  int my_leader = 63 - __clzll(lead & upto);
-  unsigned long long above = lead & ~upto;
-  int run_end = above ? (__ffsll((long long)above) - 1) : 64;
-  uint32_t base = 0;
-  if (valid && leader) base = atomicAdd(ctr + t, (uint32_t)(run_end - lane));
-  base = __shfl(base, my_leader, 64);
-  return base + (uint32_t)(lane - my_leader);
+  const uint32_t prev = __shfl_up(t, 1, 64);
+  const bool leader = !valid || lane == 0 || prev != t;
+  const unsigned long long lead = __ballot(leader);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  CicRun r;
+  r.leader = 63 - __clzll(lead & upto);
+  const unsigned long long above = lead & ~upto;
+  const int run_end = above ? (__ffsll((long long)above) - 1) : 64;
+  r.len = (uint32_t)(run_end - lane);
+  r.lead = valid && leader;
+  return r;
+}
+
+// count and scatter take kCicPer particles per thread, strided by the block
+// size so that each wave's particles stay consecutive; all loads (and the
+// scatter's cursor atomics) are issued before their results are used
+constexpr int kCicPer = 4;
+struct CicChunk {
+  float x[kCicPer][3];
+  uint32_t bin[kCicPer];
+  bool valid[kCicPer];
+};
+__device__ __forceinline__ void cic_chunk(int n, int nt, int64_t np, const float* __restrict__ pos,
+                                          CicChunk& c) {
+  const int64_t base = (int64_t)blockIdx.x * (kBlock * kCicPer) + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kCicPer; ++q) {
+    const int64_t p = base + (int64_t)q * kBlock;
+    c.valid[q] = p < np;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) c.x[q][a] = c.valid[q] ? pos[3 * p + a] : 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < kCicPer; ++q)
+    c.bin[q] = c.valid[q] ? bin_of(cic_cell(n, c.x[q], 0), nt) : 0xffffffffu;
 }
 
 __global__ __launch_bounds__(kBlock) void k_cic_count(int n, int nt, int64_t np,
                                                       const float* __restrict__ pos,
                                                       uint32_t* cnt) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = p < np;
-  uint32_t t = valid ? tile_of(cic_cell(n, pos, p), nt) : 0xffffffffu;
-  (void)run_reserve(t, valid, cnt);
-}
-// exclusive scan of m counts in one block: contiguous chunks per thread
-__global__ __launch_bounds__(1024) void k_scan1(const uint32_t* __restrict__ cnt, int64_t m,
-                                                uint32_t* __restrict__ off,
-                                                uint32_t* __restrict__ cur) {
-  __shared__ uint32_t sh[1024];
-  int64_t chunk = (m + 1023) / 1024;
-  int64_t lo = threadIdx.x * chunk, hi = lo + chunk < m ? lo + chunk : m;
-  uint32_t s = 0;
-  for (int64_t q = lo; q < hi; ++q) s += cnt[q];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
-    uint32_t v = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0u;
-    __syncthreads();
-    sh[threadIdx.x] += v;
-    __syncthreads();
+  CicChunk c;
+  cic_chunk(n, nt, np, pos, c);
+#pragma unroll
+  for (int q = 0; q < kCicPer; ++q) {
+    const CicRun r = cic_run(c.bin[q], c.valid[q]);
+    if (r.lead) atomicAdd(cnt + c.bin[q], r.len);
   }
-  uint32_t run = threadIdx.x ? sh[threadIdx.x - 1] : 0u;
-  for (int64_t q = lo; q < hi; ++q) {
-    off[q] = run;
-    cur[q] = run;
-    run += cnt[q];
+}
+// Exclusive scan of the bin counts (8 per tile, a tile's bins contiguous) in
+// one block, 1024 tiles per round: bin offsets and scatter cursors.
+__global__ __launch_bounds__(1024) void k_cic_scan(const uint32_t* __restrict__ cnt,
+                                                   int64_t ntiles, uint32_t* __restrict__ boff,
+                                                   uint32_t* __restrict__ cur) {
+  __shared__ uint32_t wsum[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint4* c4 = reinterpret_cast<const uint4*>(cnt);
+  uint4* b4 = reinterpret_cast<uint4*>(boff);
+  uint4* u4 = reinterpret_cast<uint4*>(cur);
+  uint32_t carry = 0;
+  for (int64_t r0 = 0; r0 < ntiles; r0 += 1024) {
+    const int64_t q = r0 + threadIdx.x;
+    uint4 u = make_uint4(0u, 0u, 0u, 0u), v = u;
+    if (q < ntiles) {
+      u = c4[2 * q];
+      v = c4[2 * q + 1];
+    }
+    const uint32_t tot = u.x + u.y + u.z + u.w + v.x + v.y + v.z + v.w;
+    uint32_t inc = tot;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    uint32_t wpre = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      const uint32_t sw = wsum[w];
+      wpre += w < wv ? sw : 0u;
+      all += sw;
+    }
+    if (q < ntiles) {
+      const uint32_t e0 = carry + wpre + inc - tot;
+      const uint4 o0 = make_uint4(e0, e0 + u.x, e0 + u.x + u.y, e0 + u.x + u.y + u.z);
+      const uint32_t e1 = o0.w + u.w;
+      const uint4 o1 = make_uint4(e1, e1 + v.x, e1 + v.x + v.y, e1 + v.x + v.y + v.z);
+      b4[2 * q] = o0;
+      b4[2 * q + 1] = o1;
+      u4[2 * q] = o0;
+      u4[2 * q + 1] = o1;
+    }
+    carry += all;
+    __syncthreads();  // wsum is rewritten by the next round
   }
 }
 __global__ __launch_bounds__(kBlock) void k_cic_scatter(int n, int nt, int64_t np,
                                                         const float* __restrict__ pos,
                                                         uint32_t* cur, float* __restrict__ sorted) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool valid = p < np;
-  uint32_t t = valid ? tile_of(cic_cell(n, pos, p), nt) : 0xffffffffu;
-  uint32_t slot = run_reserve(t, valid, cur);
-  if (valid) {
-    sorted[3 * (int64_t)slot + 0] = pos[3 * p + 0];
-    sorted[3 * (int64_t)slot + 1] = pos[3 * p + 1];
-    sorted[3 * (int64_t)slot + 2] = pos[3 * p + 2];
+  CicChunk c;
+  cic_chunk(n, nt, np, pos, c);
+  const int lane = threadIdx.x & 63;
+  CicRun r[kCicPer];
+  uint32_t base[kCicPer];
+#pragma unroll
+  for (int q = 0; q < kCicPer; ++q) {
+    r[q] = cic_run(c.bin[q], c.valid[q]);
+    base[q] = r[q].lead ? atomicAdd(cur + c.bin[q], r[q].len) : 0u;
+  }
+#pragma unroll
+  for (int q = 0; q < kCicPer; ++q) {
+    const uint32_t slot = __shfl(base[q], r[q].leader, 64) + (uint32_t)(lane - r[q].leader);
+    if (c.valid[q]) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sorted[3 * (int64_t)slot + a] = c.x[q][a];
+    }
   }
 }
-// one workgroup per tile: deposit into LDS, write the private 17^3 block
+// One workgroup per tile.  Segments: the tile's own 8 bins (one contiguous
+// range, role 0) and, for each lower neighbour at offset -s (s a non-empty
+// subset of the axes, role s), its bins whose class contains s.  In role s a
+// particle's local coordinate on axis a is its in-tile layer minus kT s_a, and
+// only corners that land inside the tile are added: each corner of each
+// particle lands in exactly one (tile, role).
+constexpr int kCicSegs = 20;  // 1 + 4 + 4 + 2 + 4 + 2 + 2 + 1
+constexpr int kCicUnroll = 2;  // particles per thread in flight
 __global__ __launch_bounds__(kBlock) void k_cic_tile(int n, int nt, const float* __restrict__ sorted,
-                                                     const uint32_t* __restrict__ off,
-                                                     const uint32_t* __restrict__ cnt,
-                                                     unsigned long long* __restrict__ blocks) {
-  __shared__ unsigned long long acc[kTH3];
+                                                     const uint32_t* __restrict__ boff,
+                                                     const uint32_t* __restrict__ cnt, double scale,
+                                                     float* __restrict__ delta) {
+  __shared__ unsigned long long acc[kT3];
+  __shared__ uint32_t seg_lo[kCicSegs], seg_end[kCicSegs];
+  __shared__ int seg_role[kCicSegs];
   const uint32_t t = blockIdx.x;
-  for (int q = threadIdx.x; q < kTH3; q += blockDim.x) acc[q] = 0ull;
-  __syncthreads();
   const int ti = (int)(t % nt), tj = (int)((t / nt) % nt), tk = (int)(t / ((uint32_t)nt * nt));
-  const uint32_t lo = off[t], m = cnt[t];
-  for (uint32_t q = threadIdx.x; q < m; q += blockDim.x) {
-    CicCell c = cic_cell(n, sorted, (int64_t)lo + q);
-    long long w[8];
-    cic_weights(c, w);
-    int a = c.i0[0] - ti * kT, b = c.i0[1] - tj * kT, d = c.i0[2] - tk * kT;
+  for (int q = threadIdx.x; q < kT3; q += kBlock) acc[q] = 0ull;
+  if (threadIdx.x < 64) {
+    // lane i < kCicSegs: segment i is (role s, class c), enumerated in order
+    // of s and then c with (c & s) == s; lane 0 is the own tile's 8 bins
+    const int lane = threadIdx.x;
+    int s = 0, c = 0;
+    if (lane > 0 && lane < kCicSegs) {
+      int k = 0;
+      for (int ss = 1; ss < 8; ++ss)
+        for (int cc = 1; cc < 8; ++cc)
+          if ((cc & ss) == ss && ++k == lane) {
+            s = ss;
+            c = cc;
+          }
+    }
+    uint32_t lo = 0, m = 0;
+    if (lane < kCicSegs) {
+      const int si = (s & 1) ? (ti == 0 ? nt - 1 : ti - 1) : ti;
+      const int sj = (s & 2) ? (tj == 0 ? nt - 1 : tj - 1) : tj;
+      const int sk = (s & 4) ? (tk == 0 ? nt - 1 : tk - 1) : tk;
+      const uint32_t src = ((uint32_t)sk * nt + (uint32_t)sj) * nt + (uint32_t)si;
+      lo = boff[8 * src + c];
+      if (lane == 0) {
+        const uint4 u = reinterpret_cast<const uint4*>(cnt)[2 * src];
+        const uint4 v = reinterpret_cast<const uint4*>(cnt)[2 * src + 1];
+        m = u.x + u.y + u.z + u.w + v.x + v.y + v.z + v.w;
+      } else {
+        m = cnt[8 * src + c];
+      }
+    }
+    uint32_t end = m;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      if (w[r] == 0) continue;
-      int idx = ((d + ((r >> 2) & 1)) * kTH + (b + ((r >> 1) & 1))) * kTH + (a + (r & 1));
-      atomicAdd(&acc[idx], (unsigned long long)w[r]);
+    for (int d = 1; d < 32; d <<= 1) {
+      const uint32_t y = __shfl_up(end, d, 64);
+      if (lane >= d) end += y;
+    }
+    if (lane < kCicSegs) {
+      seg_lo[lane] = lo;
+      seg_end[lane] = end;
+      seg_role[lane] = s;
     }
   }
   __syncthreads();
-  unsigned long long* dst = blocks + (int64_t)t * kTH3;
-  for (int q = threadIdx.x; q < kTH3; q += blockDim.x) dst[q] = acc[q];
-}
-// cell (i,j,k): sum of the private blocks that cover it (its own tile, and
-// the +1 layer of the lower neighbour tile on each axis where it is first)
-__global__ __launch_bounds__(kBlock) void k_cic_gather(Lev L, int nt,
-                                                       const unsigned long long* __restrict__ blocks,
-                                                       double scale, float* __restrict__ delta) {
-  int64_t g = gid();
-  if (g >= 2 * L.half) return;
-  int i, j, k;
-  dec_nat(g, L, i, j, k);
-  const int tc[3] = {i / kT, j / kT, k / kT};
-  const int lc[3] = {i % kT, j % kT, k % kT};
-  unsigned long long sum = 0ull;
+  const uint32_t total = seg_end[kCicSegs - 1];
+  int sg = 0;
+  for (uint32_t g0 = threadIdx.x; g0 < total; g0 += kCicUnroll * kBlock) {
+    CicCell cc[kCicUnroll];
+    int role[kCicUnroll];
+    bool ok[kCicUnroll];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    int tt[3], ll[3];
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      int sft = (r >> a) & 1;  // 1: take the lower neighbour's +1 layer
-      if (sft && lc[a] != 0) ok = false;
-      tt[a] = sft ? (tc[a] == 0 ? nt - 1 : tc[a] - 1) : tc[a];
-      ll[a] = sft ? kT : lc[a];
+    for (int u = 0; u < kCicUnroll; ++u) {
+      const uint32_t g = g0 + (uint32_t)u * kBlock;
+      ok[u] = g < total;
+      role[u] = 0;
+      if (ok[u]) {
+        while (g >= seg_end[sg]) ++sg;
+        const uint32_t start = sg ? seg_end[sg - 1] : 0u;
+        role[u] = seg_role[sg];
+        cc[u] = cic_cell(n, sorted, (int64_t)seg_lo[sg] + (g - start));
+      }
     }
-    if (!ok) continue;
-    uint32_t tile = ((uint32_t)tt[2] * nt + tt[1]) * nt + tt[0];
-    sum += blocks[(int64_t)tile * kTH3 + (ll[2] * kTH + ll[1]) * kTH + ll[0]];
+#pragma unroll
+    for (int u = 0; u < kCicUnroll; ++u) {
+      if (!ok[u]) continue;
+      const int s = role[u];
+      long long w[8];
+      cic_weights(cc[u], w);
+      const int a = (cc[u].i0[0] & (kT - 1)) - ((s & 1) ? kT : 0);
+      const int b = (cc[u].i0[1] & (kT - 1)) - ((s & 2) ? kT : 0);
+      const int d = (cc[u].i0[2] & (kT - 1)) - ((s & 4) ? kT : 0);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int x = a + (r & 1), y = b + ((r >> 1) & 1), z = d + ((r >> 2) & 1);
+        if (w[r] == 0 || x < 0 || x >= kT || y < 0 || y >= kT || z < 0 || z >= kT) continue;
+        atomicAdd(&acc[(z * kT + y) * kT + x], (unsigned long long)w[r]);
+      }
+    }
   }
-  delta[g] = float(double(sum) * scale - 1.0);
+  __syncthreads();
+  for (int q = threadIdx.x; q < kT3; q += kBlock) {
+    const int x = q % kT, y = (q / kT) % kT, z = q / (kT * kT);
+    const int64_t cell = ((int64_t)(tk * kT + z) * n + (tj * kT + y)) * n + (ti * kT + x);
+    delta[cell] = float(double(acc[q]) * scale - 1.0);
+  }
 }
 
 template <int M>
@@ -1746,6 +1872,7 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
   mg_ctx* ctx = new mg_ctx();
   ctx->n = n;
   if (const char* mb = getenv("MGGPU_MARCH_MIN_BLOCKS")) ctx->march_min_blocks = (unsigned)atoi(mb);
+  if (const char* cd = getenv("MGGPU_CIC_DIRECT")) ctx->cic_direct = atoi(cd) != 0;
   if (const char* sk = getenv("MGGPU_SMOOTH_MARCH_KT")) {
     const int kt = atoi(sk);
     ctx->smooth_march_kt = kt > 0 && kt <= 64 ? kt : 0;
@@ -1830,29 +1957,25 @@ int cic_assign(mg_ctx* ctx, const float* pos, int64_t np, float* delta_out) {
   int n = ctx->n;
   int64_t m = (int64_t)n * n * n;
   double scale = double(m) / double(np) / 4294967296.0;
-  if (n % kT == 0 && np < (int64_t)0xffffffffLL) {
-    // binned path: count per tile, scan, scatter, per-tile LDS deposit, gather
+  if (n % kT == 0 && np < (int64_t)0xffffffffLL && !ctx->cic_direct) {
+    // binned path: count per bin, scan, scatter, per-tile LDS deposit
     int nt = n / kT;
     int64_t ntiles = (int64_t)nt * nt * nt;
     if (ctx->cic_np < np) {
       ACHK(dalloc(ctx, &ctx->cic_sorted, 3 * np));
       ctx->cic_np = np;
     }
-    if (!ctx->cic_blocks) {
-      ACHK(dalloc(ctx, &ctx->cic_blocks, ntiles * kTH3));
-      ACHK(dalloc(ctx, &ctx->cic_cnt, 3 * ntiles));
-    }
+    if (!ctx->cic_cnt) ACHK(dalloc(ctx, &ctx->cic_cnt, 3 * 8 * ntiles));
     uint32_t* cnt = ctx->cic_cnt;
-    uint32_t* off = cnt + ntiles;
-    uint32_t* cur = off + ntiles;
-    k_fill<uint32_t><<<nblk(ntiles), kBlock, 0, ctx->stream>>>(cnt, ntiles, 0u);
-    k_cic_count<<<nblk(np), kBlock, 0, ctx->stream>>>(n, nt, np, pos, cnt);
-    k_scan1<<<1, 1024, 0, ctx->stream>>>(cnt, ntiles, off, cur);
-    k_cic_scatter<<<nblk(np), kBlock, 0, ctx->stream>>>(n, nt, np, pos, cur, ctx->cic_sorted);
-    k_cic_tile<<<(unsigned)ntiles, kBlock, 0, ctx->stream>>>(n, nt, ctx->cic_sorted, off, cnt,
-                                                             ctx->cic_blocks);
-    k_cic_gather<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], nt, ctx->cic_blocks, scale,
-                                                      delta_out);
+    uint32_t* boff = cnt + 8 * ntiles;
+    uint32_t* cur = boff + 8 * ntiles;
+    k_fill<uint32_t><<<nblk(8 * ntiles), kBlock, 0, ctx->stream>>>(cnt, 8 * ntiles, 0u);
+    const unsigned nbp = (unsigned)((np + kBlock * kCicPer - 1) / (kBlock * kCicPer));
+    k_cic_count<<<nbp, kBlock, 0, ctx->stream>>>(n, nt, np, pos, cnt);
+    k_cic_scan<<<1, 1024, 0, ctx->stream>>>(cnt, ntiles, boff, cur);
+    k_cic_scatter<<<nbp, kBlock, 0, ctx->stream>>>(n, nt, np, pos, cur, ctx->cic_sorted);
+    k_cic_tile<<<(unsigned)ntiles, kBlock, 0, ctx->stream>>>(n, nt, ctx->cic_sorted, boff, cnt,
+                                                             scale, delta_out);
     LAUNCHCHK();
     return MG_OK;
   }
@@ -2470,15 +2593,23 @@ void plan_teams(const std::vector<BoxDev>& host, int G, int team_mode, BatchPlan
 template <int BS>
 int batch_launch_bs(mg_ctx* ctx, const std::vector<BoxDev>& host, int team_mode, int* grid_out) {
   const int nb = (int)host.size();
-  int dev = 0, per_cu = 0, coop = 0;
-  HIPCHK(hipGetDevice(&dev));
-  HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-  if (!coop) return fail(ctx, MG_EHIP, "batched solve needs cooperative launch support");
-  hipDeviceProp_t prop;
-  HIPCHK(hipGetDeviceProperties(&prop, dev));
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<BS>, BS, 0));
-  if (per_cu < 1) return fail(ctx, MG_EHIP, "batched kernel cannot be resident");
-  const int G = per_cu * prop.multiProcessorCount;
+  if (ctx->bdev_coop < 0) {
+    int dev = 0, coop = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    ctx->bdev_coop = coop;
+    ctx->bdev_cus = cus;
+  }
+  if (!ctx->bdev_coop) return fail(ctx, MG_EHIP, "batched solve needs cooperative launch support");
+  const int oi = BS == 256 ? 0 : (BS == 512 ? 1 : 2);
+  if (ctx->bocc[oi] == 0) {
+    int per_cu = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched<BS>, BS, 0));
+    if (per_cu < 1) return fail(ctx, MG_EHIP, "batched kernel cannot be resident");
+    ctx->bocc[oi] = per_cu;
+  }
+  const int G = ctx->bocc[oi] * ctx->bdev_cus;
   BatchPlan P;
   plan_teams(host, G, team_mode, P);
   const int grid = (int)P.wg.size();
@@ -2548,7 +2679,7 @@ int batch_collect(mg_ctx* ctx, int nb, std::vector<BoxOut>& outs) {
   return MG_OK;
 }
 
-std::string batch_key(int nb, const mg_box_desc* boxes, const mg_solver_opts* o) {
+std::string batch_key(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver_opts* o) {
   std::vector<std::string> parts;
   for (int b = 0; b < nb; ++b)
     parts.push_back(std::to_string(boxes[b].n) + (boxes[b].model == MG_FR ? "f" :
@@ -2562,10 +2693,13 @@ std::string batch_key(int nb, const mg_box_desc* boxes, const mg_solver_opts* o)
     k += parts[q] + "x" + std::to_string(r - q) + ",";
     q = r;
   }
-  int dev = 0;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-    k += std::string(":") + prop.gcnArchName;
+  if (ctx->arch.empty()) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      ctx->arch = prop.gcnArchName;
+  }
+  if (!ctx->arch.empty()) k += ":" + ctx->arch;
   k += ":V(" + std::to_string(o->nu_pre) + "," + std::to_string(o->nu_post) + ")c" +
        std::to_string(o->cycle);
   return k;
@@ -2672,7 +2806,7 @@ int mg_batched_tune(mg_ctx* ctx, int n_box, const mg_box_desc* boxes, const mg_s
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (rc != MG_OK) return rc;
-  std::string key = batch_key(n_box, boxes, opts);
+  std::string key = batch_key(ctx, n_box, boxes, opts);
   cache_store(key, bb, bv, bt, best);
   ctx->bkey = key;
   ctx->bpinned = false;
@@ -2695,7 +2829,7 @@ int mg_solve_batched(mg_ctx* ctx, int n_box, const mg_box_desc* boxes, const mg_
     return fail(ctx, MG_EINVAL, "mg_solve_batched: runs the FP32-refined scheme");
   // tile shape: this context's last tuning for the same batch shape, else the
   // cache file, else tune now
-  std::string key = batch_key(n_box, boxes, opts);
+  std::string key = batch_key(ctx, n_box, boxes, opts);
   int blk = 0, vec = -1, team = -1;
   if (ctx->bpinned || (ctx->bkey == key && ctx->bblock > 0)) {
     blk = ctx->bblock;

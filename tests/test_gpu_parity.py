@@ -105,6 +105,32 @@ def test_cic_matches_oracle(c1):
     mg.close()
 
 
+@pytest.mark.parametrize("n", [16, 32, 48])
+def test_cic_binned_equals_direct(n, monkeypatch):
+    """Both paths sum the same 32.32 fixed-point weights exactly, so the binned
+    path (one tile at n=16, the lower and upper neighbour tile the same at
+    n=32) must agree with the direct atomic path bit for bit."""
+    say("cic binned vs direct", n)
+    rng = np.random.default_rng(40 + n)
+    pos = np.concatenate([synthetic.zeldovich_positions(n, n // 2 + 4, seed=n, dtype=np.float32),
+                          rng.uniform(0, n, (777, 3)).astype(np.float32)])
+    pos[:20] = np.float32(n - 1e-4)
+    pos[20:40] = 0.0
+    pos[40:80, 0] = np.float32(15.5)  # lower cell on a tile's last layer
+    pos[80:120, 1] = np.float32(31.6 % n)
+    t = torch.from_numpy(pos).to(DEV)
+    mg = api.Context(n, device=DEV)
+    binned = mg.cic(t).cpu().numpy()
+    mg.close()
+    monkeypatch.setenv("MGGPU_CIC_DIRECT", "1")
+    md = api.Context(n, device=DEV)
+    direct = md.cic(t).cpu().numpy()
+    md.close()
+    assert np.array_equal(binned.view(np.uint32), direct.view(np.uint32))
+    ref = oracle.cic(n, pos.astype(np.float64))
+    assert np.max(np.abs(binned - ref)) <= 1e-6 * (1 + np.max(np.abs(ref)))
+
+
 def test_cic_direct_path_matches_oracle():
     """n not divisible by the 16-cell tile: the direct atomic kernel."""
     n = 24
