@@ -1756,7 +1756,8 @@ __global__ __launch_bounds__(kBlock) void k_cic_scatter(int n, int nt, int64_t n
 // particle lands in exactly one (tile, role).
 constexpr int kCicSegs = 20;  // 1 + 4 + 4 + 2 + 4 + 2 + 2 + 1
 constexpr int kCicUnroll = 2;  // particles per thread in flight
-__global__ __launch_bounds__(kBlock) void k_cic_tile(int n, int nt, const float* __restrict__ sorted,
+constexpr int kCicTB = 512;    // workgroup size of the tile kernel
+__global__ __launch_bounds__(kCicTB) void k_cic_tile(int n, int nt, const float* __restrict__ sorted,
                                                      const uint32_t* __restrict__ boff,
                                                      const uint32_t* __restrict__ cnt, double scale,
                                                      float* __restrict__ delta) {
@@ -1765,7 +1766,7 @@ __global__ __launch_bounds__(kBlock) void k_cic_tile(int n, int nt, const float*
   __shared__ int seg_role[kCicSegs];
   const uint32_t t = blockIdx.x;
   const int ti = (int)(t % nt), tj = (int)((t / nt) % nt), tk = (int)(t / ((uint32_t)nt * nt));
-  for (int q = threadIdx.x; q < kT3; q += kBlock) acc[q] = 0ull;
+  for (int q = threadIdx.x; q < kT3; q += kCicTB) acc[q] = 0ull;
   if (threadIdx.x < 64) {
     // lane i < kCicSegs: segment i is (role s, class c), enumerated in order
     // of s and then c with (c & s) == s; lane 0 is the own tile's 8 bins
@@ -1810,13 +1811,13 @@ __global__ __launch_bounds__(kBlock) void k_cic_tile(int n, int nt, const float*
   __syncthreads();
   const uint32_t total = seg_end[kCicSegs - 1];
   int sg = 0;
-  for (uint32_t g0 = threadIdx.x; g0 < total; g0 += kCicUnroll * kBlock) {
+  for (uint32_t g0 = threadIdx.x; g0 < total; g0 += kCicUnroll * kCicTB) {
     CicCell cc[kCicUnroll];
     int role[kCicUnroll];
     bool ok[kCicUnroll];
 #pragma unroll
     for (int u = 0; u < kCicUnroll; ++u) {
-      const uint32_t g = g0 + (uint32_t)u * kBlock;
+      const uint32_t g = g0 + (uint32_t)u * kCicTB;
       ok[u] = g < total;
       role[u] = 0;
       if (ok[u]) {
@@ -1844,7 +1845,7 @@ __global__ __launch_bounds__(kBlock) void k_cic_tile(int n, int nt, const float*
     }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < kT3; q += kBlock) {
+  for (int q = threadIdx.x; q < kT3; q += kCicTB) {
     const int x = q % kT, y = (q / kT) % kT, z = q / (kT * kT);
     const int64_t cell = ((int64_t)(tk * kT + z) * n + (tj * kT + y)) * n + (ti * kT + x);
     delta[cell] = float(double(acc[q]) * scale - 1.0);
@@ -1974,7 +1975,7 @@ int cic_assign(mg_ctx* ctx, const float* pos, int64_t np, float* delta_out) {
     k_cic_count<<<nbp, kBlock, 0, ctx->stream>>>(n, nt, np, pos, cnt);
     k_cic_scan<<<1, 1024, 0, ctx->stream>>>(cnt, ntiles, boff, cur);
     k_cic_scatter<<<nbp, kBlock, 0, ctx->stream>>>(n, nt, np, pos, cur, ctx->cic_sorted);
-    k_cic_tile<<<(unsigned)ntiles, kBlock, 0, ctx->stream>>>(n, nt, ctx->cic_sorted, boff, cnt,
+    k_cic_tile<<<(unsigned)ntiles, kCicTB, 0, ctx->stream>>>(n, nt, ctx->cic_sorted, boff, cnt,
                                                              scale, delta_out);
     LAUNCHCHK();
     return MG_OK;
