@@ -2036,8 +2036,8 @@ int mg_residual(mg_ctx* ctx, int model, const mg_model_params* params, const flo
 namespace {
 
 // CIC interpolation to particles (same cells and weights as the assignment)
-template <typename TG, typename TO>
-__global__ __launch_bounds__(kBlock) void k_interp(int n, int64_t np, int ncomp,
+template <typename TG, typename TO, int NC>
+__global__ __launch_bounds__(kBlock) void k_interp(int n, int64_t np,
                                                    const float* __restrict__ pos,
                                                    const TG* __restrict__ grid,
                                                    TO* __restrict__ out) {
@@ -2045,19 +2045,31 @@ __global__ __launch_bounds__(kBlock) void k_interp(int n, int64_t np, int ncomp,
   if (p >= np) return;
   const CicCell c = cic_cell(n, pos, p);
   const int64_t m = (int64_t)n * n * n;
-  double acc[3] = {0.0, 0.0, 0.0};
+  double w[8];
+  int64_t cell[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int di = q & 1, dj = (q >> 1) & 1, dk = (q >> 2) & 1;
-    const double w = (di ? c.t[0] : 1.0 - c.t[0]) * (dj ? c.t[1] : 1.0 - c.t[1]) *
-                     (dk ? c.t[2] : 1.0 - c.t[2]);
+    w[q] = (di ? c.t[0] : 1.0 - c.t[0]) * (dj ? c.t[1] : 1.0 - c.t[1]) *
+           (dk ? c.t[2] : 1.0 - c.t[2]);
     const int ii = c.i0[0] + di == n ? 0 : c.i0[0] + di;
     const int jj = c.i0[1] + dj == n ? 0 : c.i0[1] + dj;
     const int kk = c.i0[2] + dk == n ? 0 : c.i0[2] + dk;
-    const int64_t cell = ((int64_t)kk * n + jj) * n + ii;
-    for (int a = 0; a < ncomp; ++a) acc[a] += w * double(grid[a * m + cell]);
+    cell[q] = ((int64_t)kk * n + jj) * n + ii;
   }
-  for (int a = 0; a < ncomp; ++a) out[p * ncomp + a] = TO(acc[a]);
+  // all 8 NC loads are independent: issue them together
+  TG v[NC][8];
+#pragma unroll
+  for (int a = 0; a < NC; ++a)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[a][q] = grid[a * m + cell[q]];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += w[q] * double(v[a][q]);
+    out[p * NC + a] = TO(acc);
+  }
 }
 
 // symmetron friction term per particle: coef u(x_p) p_p
@@ -2162,7 +2174,12 @@ int mg_interp_to_particles(mg_ctx* ctx, const float* grid, int ncomp, const floa
   if (np == 0 && ncomp >= 1 && ncomp <= 3) return MG_OK;  // no particles: nothing to do
   if (!grid || !pos || !out || np < 0 || ncomp < 1 || ncomp > 3)
     return fail(ctx, MG_EINVAL, "mg_interp_to_particles: bad arguments");
-  k_interp<float, float><<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, ncomp, pos, grid, out);
+  if (ncomp == 3)
+    k_interp<float, float, 3><<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, pos, grid, out);
+  else if (ncomp == 2)
+    k_interp<float, float, 2><<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, pos, grid, out);
+  else
+    k_interp<float, float, 1><<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, pos, grid, out);
   LAUNCHCHK();
   return MG_OK;
 }
@@ -2173,7 +2190,7 @@ int mg_interp_field_to_particles(mg_ctx* ctx, const double* field, const float* 
   if (np == 0) return MG_OK;
   if (!field || !pos || !out || np < 0)
     return fail(ctx, MG_EINVAL, "mg_interp_field_to_particles: bad arguments");
-  k_interp<double, double><<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, 1, pos, field, out);
+  k_interp<double, double, 1><<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, pos, field, out);
   LAUNCHCHK();
   return MG_OK;
 }

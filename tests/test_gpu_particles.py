@@ -32,6 +32,14 @@ def test_interp_to_particles_matches_oracle(n, npart):
     err = np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max()
     say(f"  max rel {err:.1e}")
     assert err < 1e-6
+    tpos = torch.from_numpy(pos).to(DEV)
+    for nc in (1, 2):  # fewer components, and a plain (n, n, n) grid
+        sub = mg.interp_to_particles(torch.from_numpy(np.ascontiguousarray(grid[:nc])).to(DEV), tpos)
+        assert sub.shape == (npart, nc)
+        assert np.abs(sub.cpu().numpy() - ref[:, :nc]).max() <= 1e-6 * np.abs(ref).max()
+    one = mg.interp_to_particles(torch.from_numpy(np.ascontiguousarray(grid[2])).to(DEV), tpos)
+    assert one.shape == (npart,)
+    assert np.abs(one.cpu().numpy() - ref[:, 2]).max() <= 1e-6 * np.abs(ref).max()
     f64 = rng.standard_normal((n, n, n))
     g1 = mg.interp_field_to_particles(torch.from_numpy(f64).to(DEV), torch.from_numpy(pos).to(DEV))
     r1 = oracle.interp(n, pos.astype(np.float64), f64)
