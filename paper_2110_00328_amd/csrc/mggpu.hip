@@ -104,7 +104,7 @@ struct mg_ctx {
   double* scal = nullptr;      // device scalars
   double* hscal = nullptr;     // pinned host mirror
   int64_t* cic = nullptr;      // CIC fixed-point accumulator (direct path)
-  float* cic_sorted = nullptr;  // binned CIC: positions in tile order
+  float* cic_sorted = nullptr;  // binned CIC: positions in (tile, class) bin order
   int64_t cic_np = 0;
   uint32_t* cic_cnt = nullptr;  // counts, offsets, cursors per (tile, class) bin
   int cic_direct = 0;           // 1: always the direct atomic path (MGGPU_CIC_DIRECT)
@@ -1491,6 +1491,87 @@ __global__ __launch_bounds__(kBlock) void k_force_kv(Lev L, const double* __rest
     }
   }
 }
+// The same force on tiles of 64 x 16 cells of a plane (16 threads x 4 cells
+// per row, 16 rows), marching kt planes in z.  Plane k's values go through
+// LDS, so the y neighbours (and the x neighbours inside the tile) come from
+// other threads; only the tile's two edge rows and its x-edge cells are read
+// again from memory.  Same arithmetic as k_force_kv, so the same bits.
+constexpr int kFTX = 16, kFTY = 16;  // threads per row, rows per tile
+template <bool ADD>
+__global__ __launch_bounds__(kBlock) void k_force_tile(Lev L, const double* __restrict__ f,
+                                                       const double* __restrict__ pn, double sn,
+                                                       Consts C, float* __restrict__ out, int kt) {
+  constexpr int V = 4, W = kFTX * V;
+  __shared__ double sp[2][kFTY + 2][W];
+  const int n = L.n;
+  const uint32_t ntx = (uint32_t)(n / W), tiles = ntx * (uint32_t)(n / kFTY);
+  const uint32_t b = (uint32_t)xcd_block();
+  const uint32_t kb = b / tiles, tile = b - kb * tiles;
+  const uint32_t ty0 = tile / ntx, tx0 = tile - ty0 * ntx;
+  const int tx = (int)threadIdx.x % kFTX, ty = (int)threadIdx.x / kFTX;
+  const int i0 = (int)tx0 * W + tx * V, j = (int)ty0 * kFTY + ty;
+  const int k0 = (int)kb * kt;
+  if (k0 >= n) return;  // the whole workgroup
+  const int k1 = k0 + kt < n ? k0 + kt : n;
+  const int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
+  const int im = i0 == 0 ? n - 1 : i0 - 1, ip = i0 + V == n ? 0 : i0 + V;
+  const int64_t m = 2 * L.half;
+  auto row = [&](int jr, int kr) { return ((int64_t)kr * n + jr) * n; };
+  auto ld = [&](int jr, int kr, double* ph) {
+    double v[V];
+    ldn<double, V>(f + row(jr, kr) + i0, v);
+#pragma unroll
+    for (int q = 0; q < V; ++q) ph[q] = phi5_of(C, v[q]);
+    if (ADD) {
+      ldn<double, V>(pn + row(jr, kr) + i0, v);
+#pragma unroll
+      for (int q = 0; q < V; ++q) ph[q] = __dadd_rn(ph[q], __dmul_rn(sn, v[q]));
+    }
+  };
+  double win[3][V];
+  ld(j, k0 == 0 ? n - 1 : k0 - 1, win[0]);
+  ld(j, k0, win[1]);
+  int buf = 0;
+  for (int k = k0; k < k1; ++k, buf ^= 1) {
+    ld(j, k + 1 == n ? 0 : k + 1, win[2]);
+    double(*s)[W] = sp[buf];
+#pragma unroll
+    for (int q = 0; q < V; ++q) s[ty + 1][tx * V + q] = win[1][q];
+    if (ty == 0 || ty == kFTY - 1) {
+      double h[V];
+      ld(ty == 0 ? jm : jp, k, h);
+#pragma unroll
+      for (int q = 0; q < V; ++q) s[ty == 0 ? 0 : kFTY + 1][tx * V + q] = h[q];
+    }
+    // double-buffered: a buffer is rewritten only after the next barrier
+    __syncthreads();
+    const int64_t r = row(j, k);
+    double ym[V], yp[V], xv[V + 2];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      ym[q] = s[ty][tx * V + q];
+      yp[q] = s[ty + 2][tx * V + q];
+      xv[q + 1] = win[1][q];
+    }
+    xv[0] = tx > 0 ? s[ty + 1][tx * V - 1] : pot_at<ADD>(C, f, pn, sn, r + im);
+    xv[V + 1] = tx < kFTX - 1 ? s[ty + 1][tx * V + V] : pot_at<ADD>(C, f, pn, sn, r + ip);
+    float gx[V], gy[V], gz[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      gx[q] = float(-0.5 * (xv[q + 2] - xv[q]));
+      gy[q] = float(-0.5 * (yp[q] - ym[q]));
+      gz[q] = float(-0.5 * (win[2][q] - win[0][q]));
+    }
+    stn_nt<float, V>(out + r + i0, gx);
+    stn_nt<float, V>(out + m + r + i0, gy);
+    stn_nt<float, V>(out + 2 * m + r + i0, gz);
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      win[0][q] = win[1][q];
+      win[1][q] = win[2][q];
+    }
+  }
+}
 __global__ __launch_bounds__(kBlock) void k_force_adjoint(Lev L, const double* __restrict__ f,
                                                           const float* __restrict__ gf, Consts C,
                                                           double* __restrict__ out) {
@@ -1510,6 +1591,78 @@ __global__ __launch_bounds__(kBlock) void k_force_adjoint(Lev L, const double* _
              (double(gf[2 * m + ((int64_t)kp * n + j) * n + i]) -
               double(gf[2 * m + ((int64_t)km * n + j) * n + i]));
   out[g] = 0.5 * s * dphi5_of(C, f[g]);
+}
+
+// Transpose of the fifth-force gradient on the force kernel's 64 x 16 tiles,
+// marching kt planes in z: the x component's x neighbours and the y
+// component's rows j +- 1 come from LDS, the z component's planes k +- 1 from
+// a register window.  Same arithmetic, in the same order, as k_force_adjoint.
+__global__ __launch_bounds__(kBlock) void k_force_adjoint_tile(
+    Lev L, const double* __restrict__ f, const float* __restrict__ gf, Consts C,
+    double* __restrict__ out, int kt) {
+  constexpr int V = 4, W = kFTX * V;
+  __shared__ float sx[2][kFTY][W];
+  __shared__ float sy[2][kFTY + 2][W];
+  const int n = L.n;
+  const uint32_t ntx = (uint32_t)(n / W), tiles = ntx * (uint32_t)(n / kFTY);
+  const uint32_t b = (uint32_t)xcd_block();
+  const uint32_t kb = b / tiles, tile = b - kb * tiles;
+  const uint32_t ty0 = tile / ntx, tx0 = tile - ty0 * ntx;
+  const int tx = (int)threadIdx.x % kFTX, ty = (int)threadIdx.x / kFTX;
+  const int i0 = (int)tx0 * W + tx * V, j = (int)ty0 * kFTY + ty;
+  const int k0 = (int)kb * kt;
+  if (k0 >= n) return;  // the whole workgroup
+  const int k1 = k0 + kt < n ? k0 + kt : n;
+  const int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
+  const int im = i0 == 0 ? n - 1 : i0 - 1, ip = i0 + V == n ? 0 : i0 + V;
+  const int64_t m = 2 * L.half;
+  const float* gx = gf;
+  const float* gy = gf + m;
+  const float* gz = gf + 2 * m;
+  auto row = [&](int jr, int kr) { return ((int64_t)kr * n + jr) * n; };
+  float zw[3][V];
+  ldn<float, V>(gz + row(j, k0 == 0 ? n - 1 : k0 - 1) + i0, zw[0]);
+  ldn<float, V>(gz + row(j, k0) + i0, zw[1]);
+  int buf = 0;
+  for (int k = k0; k < k1; ++k, buf ^= 1) {
+    const int64_t r = row(j, k);
+    ldn<float, V>(gz + row(j, k + 1 == n ? 0 : k + 1) + i0, zw[2]);
+    float xc[V], yc[V];
+    ldn<float, V>(gx + r + i0, xc);
+    ldn<float, V>(gy + r + i0, yc);
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      sx[buf][ty][tx * V + q] = xc[q];
+      sy[buf][ty + 1][tx * V + q] = yc[q];
+    }
+    if (ty == 0 || ty == kFTY - 1) {
+      float h[V];
+      ldn<float, V>(gy + row(ty == 0 ? jm : jp, k) + i0, h);
+#pragma unroll
+      for (int q = 0; q < V; ++q) sy[buf][ty == 0 ? 0 : kFTY + 1][tx * V + q] = h[q];
+    }
+    double fv[V] = {0.0, 0.0, 0.0, 0.0};
+    if (C.model != FR) ldn<double, V>(f + r + i0, fv);
+    // double-buffered: a buffer is rewritten only after the next barrier
+    __syncthreads();
+    const float xl = tx > 0 ? sx[buf][ty][tx * V - 1] : gx[r + im];
+    const float xr = tx < kFTX - 1 ? sx[buf][ty][tx * V + V] : gx[r + ip];
+    double o[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const float xm = q == 0 ? xl : xc[q - 1], xp = q == V - 1 ? xr : xc[q + 1];
+      const double s = (double(xp) - double(xm)) +
+                       (double(sy[buf][ty + 2][tx * V + q]) - double(sy[buf][ty][tx * V + q])) +
+                       (double(zw[2][q]) - double(zw[0][q]));
+      o[q] = 0.5 * s * dphi5_of(C, fv[q]);
+    }
+    stn_nt<double, V>(out + r + i0, o);
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      zw[0][q] = zw[1][q];
+      zw[1][q] = zw[2][q];
+    }
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_loss_sq(int64_t m, const float* __restrict__ force,
@@ -2126,7 +2279,16 @@ void launch_force(mg_ctx* ctx, const Consts& C, const double* f, const double* p
                   float* out) {
   const int n = ctx->n;
   const int64_t m = (int64_t)n * n * n;
-  if (n % 4 == 0 && al16(f, out) && al16(pn)) {
+  if (n % (4 * kFTX) == 0 && al16(f, out) && al16(pn)) {
+    static_assert(kFTX * kFTY == kBlock, "one thread per 4-cell group of the tile");
+    const unsigned tiles = (unsigned)((n / (4 * kFTX)) * (n / kFTY));
+    const unsigned nb = tiles * (unsigned)((n + kMarchKT - 1) / kMarchKT);
+    if (pn)
+      k_force_tile<true><<<nb, kBlock, 0, ctx->stream>>>(ctx->L[0], f, pn, sn, C, out, kMarchKT);
+    else
+      k_force_tile<false><<<nb, kBlock, 0, ctx->stream>>>(ctx->L[0], f, nullptr, 0.0, C, out,
+                                                          kMarchKT);
+  } else if (n % 4 == 0 && al16(f, out) && al16(pn)) {
     unsigned nchunk = (unsigned)(((int64_t)n * n / 4 + kBlock - 1) / kBlock);
     unsigned nb = nchunk * (unsigned)((n + kMarchKT - 1) / kMarchKT);
     if (pn) k_force_kv<true><<<nb, kBlock, 0, ctx->stream>>>(ctx->L[0], f, pn, sn, C, out, kMarchKT);
@@ -2283,9 +2445,17 @@ int mg_force_adjoint(mg_ctx* ctx, int model, const mg_model_params* params, cons
   ACHK(make_consts(ctx, model, params, ctx->n, &C));
   if (!field || !grad_force || !grad_field_out)
     return fail(ctx, MG_EINVAL, "mg_force_adjoint: NULL array");
-  int64_t m = (int64_t)ctx->n * ctx->n * ctx->n;
-  k_force_adjoint<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], field, grad_force, C,
-                                                       grad_field_out);
+  const int n = ctx->n;
+  int64_t m = (int64_t)n * n * n;
+  if (n % (4 * kFTX) == 0 && al16(field, grad_force) && al16(grad_field_out)) {
+    const unsigned tiles = (unsigned)((n / (4 * kFTX)) * (n / kFTY));
+    const unsigned nb = tiles * (unsigned)((n + kMarchKT - 1) / kMarchKT);
+    k_force_adjoint_tile<<<nb, kBlock, 0, ctx->stream>>>(ctx->L[0], field, grad_force, C,
+                                                         grad_field_out, kMarchKT);
+  } else {
+    k_force_adjoint<<<nblk(m), kBlock, 0, ctx->stream>>>(ctx->L[0], field, grad_force, C,
+                                                         grad_field_out);
+  }
   LAUNCHCHK();
   return MG_OK;
 }
