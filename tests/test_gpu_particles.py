@@ -73,6 +73,8 @@ def test_symmetron_friction_matches_oracle():
     rng = np.random.default_rng(9)
     u = rng.uniform(0.3, 1.0, (n, n, n))
     pos = rng.uniform(0, n, (npart, 3)).astype(np.float32)
+    pos[:20, 0] = np.float32(n - 0.25)  # lower cell n - 1: the x pair wraps the seam
+    pos[20:40, 0] = np.float32(0.25)    # lower cell -1 -> n - 1
     mom = rng.standard_normal((npart, 3)).astype(np.float32)
     mg = api.Context(n, device=DEV)
     got = mg.symmetron_friction(prm, torch.from_numpy(u).to(DEV), torch.from_numpy(pos).to(DEV),
