@@ -2249,33 +2249,16 @@ __global__ __launch_bounds__(kBlock) void k_sym_friction(int n, int64_t np,
   int64_t p = gid();
   if (p >= np) return;
   const CicCell c = cic_cell(n, pos, p);
-  // corners q and q+1 are x-neighbours: one 2-element load unless the pair
-  // wraps the periodic seam
-  typedef double two_t __attribute__((ext_vector_type(2), aligned(sizeof(double))));
-  const bool pair = c.i0[0] + 1 < n;
-  double v[8];
-#pragma unroll
-  for (int q = 0; q < 8; q += 2) {
-    const int dj = (q >> 1) & 1, dk = (q >> 2) & 1;
-    const int jj = c.i0[1] + dj == n ? 0 : c.i0[1] + dj;
-    const int kk = c.i0[2] + dk == n ? 0 : c.i0[2] + dk;
-    const int64_t r = ((int64_t)kk * n + jj) * n;
-    if (pair) {
-      const two_t two = *reinterpret_cast<const two_t*>(u + r + c.i0[0]);
-      v[q] = two.x;
-      v[q + 1] = two.y;
-    } else {
-      v[q] = u[r + c.i0[0]];
-      v[q + 1] = u[r];
-    }
-  }
   double up = 0.0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int di = q & 1, dj = (q >> 1) & 1, dk = (q >> 2) & 1;
     const double w = (di ? c.t[0] : 1.0 - c.t[0]) * (dj ? c.t[1] : 1.0 - c.t[1]) *
                      (dk ? c.t[2] : 1.0 - c.t[2]);
-    up += w * v[q];
+    const int ii = c.i0[0] + di == n ? 0 : c.i0[0] + di;
+    const int jj = c.i0[1] + dj == n ? 0 : c.i0[1] + dj;
+    const int kk = c.i0[2] + dk == n ? 0 : c.i0[2] + dk;
+    up += w * u[((int64_t)kk * n + jj) * n + ii];
   }
 #pragma unroll
   for (int a = 0; a < 3; ++a) out[3 * p + a] = float(coef * up * double(mom[3 * p + a]));
