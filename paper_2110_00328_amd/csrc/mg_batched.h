@@ -22,6 +22,17 @@
 
 namespace mgg {
 
+// Pointers read from a descriptor in device memory are generic to the
+// compiler, so accesses through them would be flat memory operations (which
+// also count against the LDS/scalar counter and force full waits).  These
+// pointers always address global memory; passing them through an integer
+// into the global address space lets the compiler use global operations.
+template <typename T>
+__device__ __forceinline__ T* glb(T* p) {
+  typedef __attribute__((address_space(1))) T gT;
+  return (T*)(gT*)(uintptr_t)p;
+}
+
 constexpr int kMaxLevB = 8;
 constexpr int kMaxOpsB = 160;
 constexpr int kLeadN = 16;                 // levels of n <= 16 run on one workgroup
@@ -93,15 +104,15 @@ __device__ bool team_sync(const Team& T) {
   if (threadIdx.x == 0) {
     const unsigned gen = *T.s_gen + 1u;
     *T.s_gen = gen;
-    atomicAdd(T.ctr, 1u);
+    atomicAdd(glb(T.ctr), 1u);
     const unsigned target = gen * (unsigned)T.size;
     unsigned spins = 0;
     int ok = 1;
-    while (__hip_atomic_load(T.ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(T.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+    while (__hip_atomic_load(glb(T.ctr), __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(glb(T.abort), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
           ++spins > kSpinLimit) {
         ok = 0;
-        atomicExch(T.abort, 1);
+        atomicExch(glb(T.abort), 1);
         break;
       }
       __builtin_amdgcn_s_sleep(2);
@@ -126,7 +137,7 @@ __device__ bool team_sum(const Team& T, double v, double* sh, double* out) {
     return true;
   }
   const unsigned r = *T.s_red;  // read by every thread before the barrier below
-  double* slot = T.part + (r & 1u) * (unsigned)T.size;
+  double* slot = glb(T.part) + (r & 1u) * (unsigned)T.size;
   if (threadIdx.x == 0)
     __hip_atomic_store(slot + T.rank, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (!team_sync(T)) return false;
@@ -152,14 +163,18 @@ template <int M>
 __device__ __noinline__ bool b_smooth(const BoxDev& B, Team T, int l, int sweeps) {
   const Lev L = B.L[l];
   const bool vec = B.vec && (L.nh % 4) == 0;
+  float* e = glb(B.e[l]);
+  const float* X = glb(B.X[l]);
+  const float* dn = glb(B.dens[l]);
+  const float* rho = glb(B.rho[l]);
   for (int it = 0; it < sweeps; ++it)
     for (int colour = 0; colour < 2; ++colour) {
       if (vec) {
         for (uint32_t g4 = T.gtid; g4 < (uint32_t)(L.half / 4); g4 += T.gnt)
-          op_smooth_corr_v<M>(L, B.e[l], B.X[l], B.dens[l], B.rho[l], colour, B.h2[l], B.C, g4);
+          op_smooth_corr_v<M>(L, e, X, dn, rho, colour, B.h2[l], B.C, g4);
       } else {
         for (int64_t g = T.gtid; g < L.half; g += T.gnt)
-          op_smooth_corr<M>(L, B.e[l], B.X[l], B.dens[l], B.rho[l], colour, B.h2[l], B.C, g);
+          op_smooth_corr<M>(L, e, X, dn, rho, colour, B.h2[l], B.C, g);
       }
       if (!team_sync(T)) return false;
     }
@@ -169,37 +184,46 @@ __device__ __noinline__ bool b_smooth(const BoxDev& B, Team T, int l, int sweeps
 template <int M>
 __device__ __noinline__ bool b_down(const BoxDev& B, Team T, int l, bool rx) {
   const Lev Lf = B.L[l], Lc = B.L[l + 1];
-  float* XH = rx ? B.X[l + 1] : nullptr;
+  const float* e = glb(B.e[l]);
+  const float* X = glb(B.X[l]);
+  const float* dn = glb(B.dens[l]);
+  const float* rho = glb(B.rho[l]);
+  float* eH = glb(B.e[l + 1]);
+  float* eRH = glb(B.eR[l + 1]);
+  float* XH1 = glb(B.X[l + 1]);
+  const float* dnH = glb(B.dens[l + 1]);
+  float* rhoH = glb(B.rho[l + 1]);
+  float* XH = rx ? XH1 : nullptr;
   if (B.vec && (Lc.n % 4) == 0) {
     for (uint32_t g4 = T.gtid; g4 < (uint32_t)(2 * Lc.half / 4); g4 += T.gnt)
-      op_resid_restrict_corr_v<M>(Lf, Lc, B.e[l], B.X[l], B.dens[l], B.rho[l], B.h2[l],
-                                  B.e[l + 1], B.eR[l + 1], B.rho[l + 1], XH, B.C,
+      op_resid_restrict_corr_v<M>(Lf, Lc, e, X, dn, rho, B.h2[l], eH, eRH, rhoH, XH, B.C,
                                   (M != CQ && B.nu1 > 0) ? 1 : 0, g4);
   } else {
     for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
-      op_resid_restrict_corr<M>(Lf, Lc, B.e[l], B.X[l], B.dens[l], B.rho[l], B.h2[l], B.e[l + 1],
-                                B.eR[l + 1], B.rho[l + 1], XH, B.C, g);
+      op_resid_restrict_corr<M>(Lf, Lc, e, X, dn, rho, B.h2[l], eH, eRH, rhoH, XH, B.C, g);
   }
   if (!team_sync(T)) return false;
   for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
-    op_coarse_src_corr<M>(Lc, B.eR[l + 1], B.X[l + 1], B.dens[l + 1], B.rho[l + 1], B.h2[l + 1],
-                          B.C, g);
+    op_coarse_src_corr<M>(Lc, eRH, XH1, dnH, rhoH, B.h2[l + 1], B.C, g);
   return team_sync(T);
 }
 
 template <int M>
 __device__ __noinline__ bool b_up(const BoxDev& B, Team T, int l) {
   const Lev Lf = B.L[l], Lc = B.L[l + 1];
+  float* e = glb(B.e[l]);
+  float* eH = glb(B.e[l + 1]);
+  float* eRH = glb(B.eR[l + 1]);
   if (B.vec && (Lc.n % 4) == 0) {
     // e += P(e_H - R e) in one pass; colour 0 too only for CQ's Newton smoother
     for (uint32_t g4 = T.gtid; g4 < (uint32_t)(2 * Lc.half / 4); g4 += T.gnt)
-      op_prolong_v<float, M == CQ ? 0 : 1>(Lf, Lc, B.e[l], B.e[l + 1], B.eR[l + 1], g4);
+      op_prolong_v<float, M == CQ ? 0 : 1>(Lf, Lc, e, eH, eRH, g4);
   } else {
     for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
-      B.eR[l + 1][g] = B.e[l + 1][g] - B.eR[l + 1][g];
+      eRH[g] = eH[g] - eRH[g];
     if (!team_sync(T)) return false;
     for (int64_t g = T.gtid; g < 2 * Lc.half; g += T.gnt)
-      op_prolong_block<float>(Lf, Lc, B.e[l], B.eR[l + 1], g);
+      op_prolong_block<float>(Lf, Lc, e, eRH, g);
   }
   return team_sync(T);
 }
@@ -211,21 +235,25 @@ template <int M>
 __device__ __noinline__ void b_coarsest(const BoxDev& B, int l, double* sh) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const Lev L = B.L[l];
+  float* e = glb(B.e[l]);
+  const float* X = glb(B.X[l]);
+  const float* dn = glb(B.dens[l]);
+  const float* rho = glb(B.rho[l]);
   double r0 = -1.0;
   for (int it = 0; it < B.coarse_sweeps; ++it) {
     for (int colour = 0; colour < 2; ++colour) {
       for (int64_t g = tid; g < L.half; g += nt)
-        op_smooth_corr<M>(L, B.e[l], B.X[l], B.dens[l], B.rho[l], colour, B.h2[l], B.C, g);
+        op_smooth_corr<M>(L, e, X, dn, rho, colour, B.h2[l], B.C, g);
       __syncthreads();
     }
     if ((it & 3) != 3 && it + 1 < B.coarse_sweeps) continue;
     double s2 = 0.0, sd = 0.0, sj = 0.0;
     for (int64_t g = tid; g < 2 * L.half; g += nt) {
-      double d = double(cell_resid_corr<M>(L, B.e[l], B.X[l], B.dens[l], B.rho[l], B.h2[l], B.C, g));
+      double d = double(cell_resid_corr<M>(L, e, X, dn, rho, B.h2[l], B.C, g));
       s2 += d * d;
       if (M == CQ) {
         sd += d;
-        sj += double(corr_diag<M>(B.C, B.h2[l], B.e[l][g], B.X[l][g], B.dens[l][g])) +
+        sj += double(corr_diag<M>(B.C, B.h2[l], e[g], X[g], dn[g])) +
               6.0 / double(B.h2[l]);
       }
     }
@@ -235,7 +263,7 @@ __device__ __noinline__ void b_coarsest(const BoxDev& B, int l, double* sh) {
       double Jd = block_sum_all(sj, sh);
       if (Jd != 0.0) {
         float mu = float(-D / Jd);
-        for (int64_t g = tid; g < 2 * L.half; g += nt) B.e[l][g] += mu;
+        for (int64_t g = tid; g < 2 * L.half; g += nt) e[g] += mu;
       }
       __syncthreads();
     }
@@ -292,9 +320,9 @@ __device__ __noinline__ bool b_pack(const BoxDev& B, Team T, double* sh, double*
     int i, j, k;
     dec_nat(g, L0, i, j, k);
     uint32_t pk = pk_of(L0, i, j, k);
-    float d = B.delta[g];
-    B.dens[0][pk] = d;
-    B.w[pk] = (B.use_field_in && !B.trial) ? sgn * B.field[g] : B.C.bg;
+    float d = glb(B.delta)[g];
+    glb(B.dens[0])[pk] = d;
+    glb(B.w)[pk] = (B.use_field_in && !B.trial) ? sgn * glb(B.field)[g] : B.C.bg;
     double t = B.C.bg_coef * double(d);
     bsq += t * t;
   }
@@ -302,7 +330,7 @@ __device__ __noinline__ bool b_pack(const BoxDev& B, Team T, double* sh, double*
   if (M != FR) {
     for (int l = 0; l + 1 < B.nlev; ++l) {
       for (int64_t g = T.gtid; g < 2 * B.L[l + 1].half; g += T.gnt)
-        op_restrict<float, float>(B.L[l], B.L[l + 1], B.dens[l], B.dens[l + 1], g);
+        op_restrict<float, float>(B.L[l], B.L[l + 1], glb(B.dens[l]), glb(B.dens[l + 1]), g);
       if (!team_sync(T)) return false;
     }
   }
@@ -317,17 +345,17 @@ __device__ __noinline__ bool b_outer(const BoxDev& B, Team T, bool add, double* 
   const Lev L0 = B.L[0];
   const int64_t m = 2 * L0.half;
   if (add) {
-    for (int64_t g = T.gtid; g < m; g += T.gnt) B.w[g] += double(B.e[0][g]);
+    for (int64_t g = T.gtid; g < m; g += T.gnt) glb(B.w)[g] += double(glb(B.e[0])[g]);
     if (!team_sync(T)) return false;
   }
   double acc = 0.0;
   for (int64_t g = T.gtid; g < m; g += T.gnt) {
-    double d = cell_resid_direct<M, double, float>(L0, B.w, B.dens[0], (const double*)nullptr,
-                                                   1.0, B.C, g);
+    double d = cell_resid_direct<M, double, float>(L0, glb(B.w), glb(B.dens[0]),
+                                                   (const double*)nullptr, 1.0, B.C, g);
     acc += d * d;
-    B.rho[0][g] = float(-d);
-    B.X[0][g] = float(B.w[g]);
-    B.e[0][g] = 0.0f;
+    glb(B.rho[0])[g] = float(-d);
+    glb(B.X[0])[g] = float(glb(B.w)[g]);
+    glb(B.e[0])[g] = 0.0f;
   }
   return team_sum(T, acc, sh, sq_out);
 }
@@ -341,12 +369,12 @@ __device__ __noinline__ bool b_finish(const BoxDev& B, Team T) {
   for (int64_t g = T.gtid; g < m; g += T.gnt) {
     int i, j, k;
     dec_nat(g, L0, i, j, k);
-    B.field[g] = sgn * B.w[pk_of(L0, i, j, k)];
+    glb(B.field)[g] = sgn * glb(B.w)[pk_of(L0, i, j, k)];
   }
   if (!team_sync(T)) return false;
   if (B.force) {
     const int n = L0.n;
-    const double* f = B.field;
+    const double* f = glb(B.field);
     for (int64_t g = T.gtid; g < m; g += T.gnt) {
       int i, j, k;
       dec_nat(g, L0, i, j, k);
@@ -358,10 +386,10 @@ __device__ __noinline__ bool b_finish(const BoxDev& B, Team T) {
                        : (M == SYM ? __dmul_rn(__dmul_rn(B.C.phi5, v), v) : __dmul_rn(B.C.phi5, v));
       };
       int64_t row = (int64_t)k * n + j;
-      B.force[g] = float(-0.5 * (phi(f[row * n + ip]) - phi(f[row * n + im])));
-      B.force[m + g] = float(-0.5 * (phi(f[((int64_t)k * n + jp) * n + i]) -
+      glb(B.force)[g] = float(-0.5 * (phi(f[row * n + ip]) - phi(f[row * n + im])));
+      glb(B.force)[m + g] = float(-0.5 * (phi(f[((int64_t)k * n + jp) * n + i]) -
                                      phi(f[((int64_t)k * n + jm) * n + i])));
-      B.force[2 * m + g] = float(-0.5 * (phi(f[((int64_t)kp * n + j) * n + i]) -
+      glb(B.force)[2 * m + g] = float(-0.5 * (phi(f[((int64_t)kp * n + j) * n + i]) -
                                          phi(f[((int64_t)km * n + j) * n + i])));
     }
   }
