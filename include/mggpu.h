@@ -77,8 +77,9 @@ typedef struct {
   int max_cycles;   /* cap on cycles (FP64) or outer steps (refined), 1..64 */
   int precision;    /* MG_FP64 / MG_FP32_REFINED */
   int coarse_sweeps;/* cap on sweeps of the coarsest level (they stop once its
-                       residual has dropped by 1e-8); 0 = default: 24 for a
-                       coarsest level of n <= 8, else 2 n^2 */
+                       residual has dropped by 1e-8); 0 = default: for a
+                       coarsest level of n <= 8, 24 in hierarchies of at most
+                       4 levels and 8 from 5 levels up; else 2 n^2 */
 } mg_solver_opts;
 
 typedef struct {

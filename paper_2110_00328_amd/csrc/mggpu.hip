@@ -468,15 +468,21 @@ int check_opts(mg_ctx* ctx, const mg_solver_opts* o) {
 double lev_h2(int l) { return double(1u << l) * double(1u << l); }
 
 // Cap on Gauss-Seidel sweeps of the coarsest level (they stop early once the
-// RMS residual has dropped by 1e-8): 24 for the usual 4^3 / 6^3 / 8^3; a
-// larger coarsest level (n = odd * 2^l with a big odd factor) needs about
-// 2 n^2 sweeps, the slowest mode contracting by 1 - O(1/n^2) per sweep.
-int default_coarse_sweeps(int nc) { return nc <= 8 ? 24 : 2 * nc * nc; }
+// RMS residual has dropped by 1e-8).  For the usual 4^3 / 6^3 / 8^3: 24 when
+// the hierarchy has at most 4 levels, where the coarsest solve sets the
+// cycle's contraction; 8 from 5 levels up, where the cycle contraction was
+// measured to be the same with 4 to 24 sweeps.  A larger coarsest level
+// (n = odd * 2^l with a big odd factor) needs about 2 n^2 sweeps, the slowest
+// mode contracting by 1 - O(1/n^2) per sweep.
+int default_coarse_sweeps(int nc, int nlev) {
+  if (nc <= 8) return nlev >= 5 ? 8 : 24;
+  return 2 * nc * nc;
+}
 
 // Sweeps per cycle of a grid that cannot be coarsened (n/2 odd or < 4):
 // it is its own coarsest level, relaxed without the early stop.
 int single_level_sweeps(const mg_ctx* ctx, const mg_solver_opts* o) {
-  int cap = o->coarse_sweeps > 0 ? o->coarse_sweeps : default_coarse_sweeps(ctx->L[0].n);
+  int cap = o->coarse_sweeps > 0 ? o->coarse_sweeps : default_coarse_sweeps(ctx->L[0].n, 1);
   int nu = o->nu_pre + o->nu_post;
   return cap > nu ? cap : nu;
 }
@@ -593,7 +599,7 @@ int make_prog(mg_ctx* ctx, int l, const mg_solver_opts* o, int type, FusedProg* 
   if ((int)ops.size() > kMaxOps) return fail(ctx, MG_EINVAL, "fused cycle program too long");
   P->nops = (int)ops.size();
   P->coarse_sweeps =
-      o->coarse_sweeps > 0 ? o->coarse_sweeps : default_coarse_sweeps(ctx->L[ctx->nlev - 1].n);
+      o->coarse_sweeps > 0 ? o->coarse_sweeps : default_coarse_sweeps(ctx->L[ctx->nlev - 1].n, ctx->nlev);
   P->rx = rx;
   for (size_t q = 0; q < ops.size(); ++q) P->op[q] = ops[q];
   return MG_OK;
@@ -2706,7 +2712,7 @@ int batch_setup(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver_o
     B.fixed_inner = trial ? 2 : o->inner_cycles;
     B.max_outer = trial ? 1 : o->max_cycles;
     B.coarse_sweeps =
-        o->coarse_sweeps > 0 ? o->coarse_sweeps : default_coarse_sweeps(B.L[B.nlev - 1].n);
+        o->coarse_sweeps > 0 ? o->coarse_sweeps : default_coarse_sweeps(B.L[B.nlev - 1].n, B.nlev);
     B.use_field_in = D.field_in ? 1 : 0;
     B.trial = trial ? 1 : 0;
     B.tol = trial ? 1e-300 : tol;
