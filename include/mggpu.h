@@ -215,10 +215,13 @@ int mg_gradient(mg_ctx *ctx, const double *phi, float *force_out);
  * parameters. */
 int mg_total_force(mg_ctx *ctx, int model, const mg_model_params *params, const double *phi_n,
                    const double *field, float *force_out);
-/* Symmetron friction term of eq:F_x_codeunit as printed:
- * -9 Omega_m beta_*^2 xi^2 sqrt(1 - (a_* / a)^3) a^-4 u(x_p) p_p, with u the
- * solved symmetron field (n^3 device doubles) CIC-interpolated to each
- * particle.  pos, mom, out: [n_part][3] device floats.  MG_EINVAL unless
+/* Symmetron friction term dp~/da of eq:csf_particle_geodesic_qsa in code
+ * units, -(dA/dphi)(d phi-bar/da) p~ with A of eq:sym_coupling_function,
+ * phi_* of eq:varphi_ast and phi-bar(a) of eq:varphi_min_symm:
+ * -9 Omega_m beta_*^2 xi^2 a^-4 (u(x_p) / u-bar) p_p, u-bar =
+ * sqrt(1 - (a_* / a)^3) (eq:F_x_codeunit prints u-bar in place of 1/u-bar),
+ * with u the solved symmetron field (n^3 device doubles) CIC-interpolated to
+ * each particle.  pos, mom, out: [n_part][3] device floats.  MG_EINVAL unless
  * 0 < a_* < a; n_part = 0 does nothing. */
 int mg_symmetron_friction(mg_ctx *ctx, const mg_model_params *params, const double *u_field,
                           const float *pos, const float *mom, int64_t n_part, float *out);

@@ -658,14 +658,21 @@ void ora_interp(int n, int64_t np, const double *pos, const double *grid, int nc
   }
 }
 
-/* Symmetron friction term of eq:F_x_codeunit, as printed:
- * F_x = -9 Omega_m beta_star^2 xi^2 sqrt(1 - (a_star / a)^3) a^-4 u(x_p) p_p, u
- * CIC-interpolated from the solved field; mom and out are [np][3]. */
+/* Symmetron friction term, dp~/da = -(d ln A/d phi) (d phi-bar/da) p~ (the
+ * last term of eq:csf_particle_geodesic_qsa in code units, with the field's
+ * time derivative taken from the background under the quasi-static
+ * approximation).  With A of eq:sym_coupling_function (A ~ 1),
+ * phi_* of eq:varphi_ast and phi-bar of eq:varphi_min_symm this is
+ *   F_x = -9 Omega_m beta_star^2 xi^2 a^-4 (u(x_p) / u-bar) p_p,
+ * u-bar = sqrt(1 - (a_star / a)^3).  eq:F_x_codeunit prints u-bar in the
+ * numerator; the two differ by the factor u-bar^2 (the derivation above is
+ * taken).  u is CIC-interpolated from the solved field; mom and out are
+ * [np][3]. */
 void ora_sym_friction(const ora_params *P, const double *u, const double *pos,
                       const double *mom, int64_t np, double *out) {
   double ratio = pow(P->a_star / P->a, 3.0);
-  double coef = -9.0 * P->omega_m * P->beta_star * P->beta_star * P->xi * P->xi *
-                sqrt(1.0 - ratio) / pow(P->a, 4.0);
+  double coef = -9.0 * P->omega_m * P->beta_star * P->beta_star * P->xi * P->xi /
+                (sqrt(1.0 - ratio) * pow(P->a, 4.0));
   for (int64_t p = 0; p < np; ++p) {
     double up;
     ora_interp(P->n, 1, pos + 3 * p, u, 1, &up);

@@ -226,6 +226,8 @@ class Context:
             grad_out = torch.empty_like(force)
         if loss_out is None:
             loss_out = torch.empty(1, dtype=torch.float64, device=force.device)
+        _need(grad_out, torch.float32, (3,) + self._grid(), "grad_out")
+        _need(loss_out, torch.float64, (1,), "loss_out")
         self._check(self.lib.mg_loss_force_sq(self.ptr, _p(force), _p(cells), cells.numel(),
                                               _p(grad_out), _p(loss_out)))
         return loss_out, grad_out
@@ -251,6 +253,7 @@ class Context:
         _need(pos, torch.float32, (pos.shape[0], 3), "pos")
         if out is None:
             out = torch.empty(pos.shape[0], dtype=torch.float64, device=pos.device)
+        _need(out, torch.float64, (pos.shape[0],), "out")
         self._check(self.lib.mg_interp_field_to_particles(self.ptr, _p(field), _p(pos),
                                                           pos.shape[0], _p(out)))
         return out
@@ -290,6 +293,7 @@ class Context:
         _need(mom, torch.float32, pos.shape, "mom")
         if out is None:
             out = torch.empty_like(mom)
+        _need(out, torch.float32, (pos.shape[0], 3), "out")
         self._check(self.lib.mg_symmetron_friction(self.ptr, ctypes.byref(params), _p(u_field),
                                                    _p(pos), _p(mom), pos.shape[0], _p(out)))
         return out
@@ -382,7 +386,8 @@ class MGSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(fctx, delta, mg, model, params, tol, opts, adj_tol):
-        field, _ = mg.solve(model, params, delta.contiguous(), tol=tol, opts=opts)
+        delta = delta.contiguous()
+        field, _ = mg.solve(model, params, delta, tol=tol, opts=opts)
         fctx.save_for_backward(delta, field)
         fctx.mg, fctx.model, fctx.params, fctx.opts, fctx.adj_tol = mg, model, params, opts, adj_tol
         return field

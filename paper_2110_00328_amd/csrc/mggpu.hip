@@ -2466,9 +2466,13 @@ int mg_symmetron_friction(mg_ctx* ctx, const mg_model_params* params, const doub
   const double a = params->a, as = params->sym_a_star;
   if (!(a > 0.0) || !(as > 0.0) || !(as < a))
     return fail(ctx, MG_EINVAL, "mg_symmetron_friction: need 0 < a_* < a");
+  // -(dA/dphi)(d phi-bar/da) of eq:csf_particle_geodesic_qsa with A of
+  // eq:sym_coupling_function, phi_* of eq:varphi_ast and phi-bar(a) of
+  // eq:varphi_min_symm: 9 Om beta*^2 xi^2 a^-4 u / u-bar (eq:F_x_codeunit
+  // prints u-bar in place of 1/u-bar)
   const double coef = -9.0 * params->omega_m * params->sym_beta_star * params->sym_beta_star *
-                      params->sym_xi * params->sym_xi * sqrt(1.0 - pow(as / a, 3.0)) /
-                      pow(a, 4.0);
+                      params->sym_xi * params->sym_xi /
+                      (sqrt(1.0 - pow(as / a, 3.0)) * pow(a, 4.0));
   if (np == 0) return MG_OK;
   k_sym_friction<<<nblk(np), kBlock, 0, ctx->stream>>>(ctx->n, np, pos, u_field, mom, coef, out);
   LAUNCHCHK();

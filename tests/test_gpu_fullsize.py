@@ -372,8 +372,8 @@ def test_c3_particle_side_sampled(c3):
     u = torch.rand((n, n, n), dtype=torch.float64, device=DEV,
                    generator=torch.Generator(device=DEV).manual_seed(3)) * 0.7 + 0.3
     mom = torch.ones_like(pos)
-    prms = api.model_params(float(n), a=1.0, a_star=0.5)
-    Ps = oracle.params(oracle.SYM, n, float(n), a=1.0, a_star=0.5)
+    prms = api.model_params(float(n), a=0.8, a_star=0.5)
+    Ps = oracle.params(oracle.SYM, n, float(n), a=0.8, a_star=0.5)
     fr = mg.symmetron_friction(prms, u, pos, mom).cpu().numpy()[sel]
     fref = oracle.sym_friction(Ps, u.cpu().numpy(), ps, np.ones_like(ps))
     ferr = np.abs(fr - fref).max() / np.abs(fref).max()

@@ -65,9 +65,11 @@ def test_poisson_newton_and_gradient_match_oracle(n):
     mg.close()
 
 
-def test_symmetron_friction_matches_oracle():
+@pytest.mark.parametrize("a", [1.0, 0.8])
+def test_symmetron_friction_matches_oracle(a):
     n, npart = 32, 5000
-    kw = dict(a=1.0, a_star=0.5, xi=1.0 / oracle.C_OVER_H0, beta_star=1.2)
+    say("symmetron friction, a =", a)
+    kw = dict(a=a, a_star=0.5, xi=1.0 / oracle.C_OVER_H0, beta_star=1.2)
     P = oracle.params(oracle.SYM, n, float(n), **kw)
     prm = api.model_params(float(n), **kw)
     rng = np.random.default_rng(9)

@@ -20,15 +20,22 @@ def _delta(n, seed, sig=0.8):
     return d - d.mean()
 
 
+# the symmetron also at a = 0.8 (a_* = 0.5), where the a^2/(2 xi^2) and
+# (a_*/a)^3 factors of eq:sym_eom_code_unit differ from their a = 1 values
+SYM08 = "sym08"
+MODELS = [oracle.FR, oracle.SYM, SYM08, oracle.CQ]
+
+
 def _model(model, n, box):
     if model == oracle.FR:
         return oracle.params(model, n, box, fr0=1e-5)
-    if model == oracle.SYM:
-        return oracle.params(model, n, box, a_star=0.5, xi=2.0 / CH, beta_star=1.0)
+    if model in (oracle.SYM, SYM08):
+        return oracle.params(oracle.SYM, n, box, a=0.8 if model == SYM08 else 1.0, a_star=0.5,
+                             xi=2.0 / CH, beta_star=1.0)
     return oracle.params(model, n, box)
 
 
-@pytest.mark.parametrize("model", [oracle.FR, oracle.SYM, oracle.CQ])
+@pytest.mark.parametrize("model", MODELS)
 def test_jacobian_is_symmetric(model):
     n = 8
     P = _model(model, n, 8.0)
@@ -44,7 +51,7 @@ def test_jacobian_is_symmetric(model):
 def test_jacobian_matches_finite_difference_of_operator():
     """J x = d/de F(v + e x) at e = 0 (central difference of the residual)."""
     n = 8
-    for model in (oracle.FR, oracle.SYM, oracle.CQ):
+    for model in MODELS:
         P = _model(model, n, 8.0)
         delta = _delta(n, 3)
         v, _, _, _ = oracle.solve(P, delta, tol=1e-13)
@@ -77,7 +84,7 @@ def test_adjoint_at_background_matches_fft():
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-12
 
 
-@pytest.mark.parametrize("model", [oracle.FR, oracle.SYM, oracle.CQ])
+@pytest.mark.parametrize("model", MODELS)
 def test_multigrid_adjoint_equals_cg(model):
     n = 16
     P = _model(model, n, 16.0)
@@ -103,12 +110,12 @@ def test_force_adjoint_is_transpose():
     whose force is quadratic in u, G^T g is the derivative of <g5(u), g>."""
     n = 8
     rng = np.random.default_rng(8)
-    for model in (oracle.FR, oracle.CQ, oracle.SYM):
+    for model in (oracle.FR, oracle.CQ, oracle.SYM, SYM08):
         P = _model(model, n, 8.0)
         v = 0.5 + 0.1 * rng.standard_normal((n, n, n))
         gf = rng.standard_normal((3, n, n, n))
         gv = oracle.force_adjoint(P, v, gf)
-        if model != oracle.SYM:
+        if model not in (oracle.SYM, SYM08):
             assert abs(np.vdot(oracle.force(P, v), gf) - np.vdot(v, gv)) < 1e-10 * abs(np.vdot(v, gv))
         else:
             x = rng.standard_normal((n, n, n))
@@ -126,7 +133,7 @@ def _loss_and_grad_force(P, v, cells):
     return L, gf.reshape(g.shape)
 
 
-@pytest.mark.parametrize("model", [oracle.FR, oracle.SYM, oracle.CQ])
+@pytest.mark.parametrize("model", MODELS)
 def test_adjoint_matches_central_finite_differences(model):
     """Loss = sum of |g5|^2 over a seeded cell set; dL/d(delta) at probe cells
     against central differences with h = 1e-4 and forward solves to 1e-13."""

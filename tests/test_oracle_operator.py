@@ -47,13 +47,14 @@ def test_homogeneous_fr_random_guess():
     assert np.max(np.abs(v / wbar - 1.0)) < 1e-12
 
 
-def test_homogeneous_sym_random_guess():
-    """delta = 0 -> u = sqrt(1-(a*/a)^3) from random u in (0,1]; a*=0.5,
-    xi=1e-3, beta*=0.1 (Sec. 4.2.1)."""
+@pytest.mark.parametrize("a", [1.0, 0.8])
+def test_homogeneous_sym_random_guess(a):
+    """delta = 0 -> u = sqrt(1-(a*/a)^3) (eq:varphi_min_symm) from random u in
+    (0,1]; a*=0.5, xi=1e-3, beta*=0.1 (Sec. 4.2.1), at a = 1 and a = 0.8."""
     n = 16
-    P = oracle.params(oracle.SYM, n, 256.0, a_star=0.5, xi=1e-3, beta_star=0.1)
+    P = oracle.params(oracle.SYM, n, 256.0, a=a, a_star=0.5, xi=1e-3, beta_star=0.1)
     ubar = oracle.background(P)
-    assert abs(ubar - np.sqrt(1 - 0.125)) < 1e-15
+    assert abs(ubar - np.sqrt(1 - (0.5 / a) ** 3)) < 1e-15
     rng = np.random.default_rng(1)
     v0 = rng.uniform(0.05, 1.0, (n, n, n))
     v, cyc, rel, _ = oracle.solve(P, np.zeros((n, n, n)), v0, tol=1e-13, max_cycles=60)
@@ -87,9 +88,10 @@ def test_uniform_contrast_fr_closed_form(fr_n):
     assert np.max(np.abs(v / w_exact - 1)) < 1e-12
 
 
-def test_uniform_contrast_sym_closed_form():
+@pytest.mark.parametrize("a", [1.0, 0.8])
+def test_uniform_contrast_sym_closed_form(a):
     """Uniform delta0 in eq:sym_eom_code_unit: u^2 = 1 - (1+delta0) a*^3/a^3."""
-    n, a, ast, d0 = 8, 1.0, 0.5, 2.0
+    n, ast, d0 = 8, 0.5, 2.0 if a == 1.0 else 1.5
     P = oracle.params(oracle.SYM, n, 8.0, a=a, a_star=ast, xi=2e-3)
     u_exact = np.sqrt(1 - (1 + d0) * (ast / a) ** 3)
     v, _, _, _ = oracle.solve(P, np.full((n, n, n), d0), tol=1e-14, max_cycles=100)
@@ -148,12 +150,14 @@ def test_sine_mode_fr(fr_n, axis):
     assert np.max(np.abs(v - exact)) / np.max(np.abs(exact + fbar)) < 1e-10
 
 
+@pytest.mark.parametrize("a", [1.0, 0.8])
 @pytest.mark.parametrize("axis", [0, 1, 2])
-def test_sine_mode_sym(axis):
+def test_sine_mode_sym(axis, a):
     """u = 1/2 + A sin(2 pi x/N) (eq:sine_field_sym) with A = 0.25 (A = 0.5 would
     drive u through zero); a*=0.5, xi=1e-3, beta*=0.1, density from the printed
-    formula with the discrete symbol."""
-    n, box, a, ast, xi, A = 32, 256.0, 1.0, 0.5, 1e-3, 0.25
+    formula with the discrete symbol, at a = 1 and a = 0.8 (where the printed
+    density's a^3/a*^3 and 2/a^2 factors differ from 8 and 2)."""
+    n, box, ast, xi, A = 32, 256.0, 0.5, 1e-3, 0.25
     P = oracle.params(oracle.SYM, n, box, a=a, a_star=ast, xi=xi, beta_star=0.1)
     ct2 = (n * CH / box) ** 2
     s = np.sin(sine_phase(n, axis))
@@ -222,8 +226,12 @@ def test_linear_limit_fr_matches_paper_meff(a):
     assert err < 1e-5, err
 
 
-def test_linear_limit_sym():
-    n, box, a, ast, xi = 32, 32.0, 1.0, 0.5, 1.0 / CH
+@pytest.mark.parametrize("a", [1.0, 0.8])
+def test_linear_limit_sym(a):
+    """delta ~ 1e-6: u - ubar solves (Lap - m^2) x = s delta with
+    m^2 = a^2 (1 - a*^3/a^3) / (xi c~)^2 and s = a*^3 ubar / (2 xi^2 c~^2 a),
+    the linearisation of eq:sym_eom_code_unit about eq:varphi_min_symm."""
+    n, box, ast, xi = 32, 32.0, 0.5, 1.0 / CH
     P = oracle.params(oracle.SYM, n, box, a=a, a_star=ast, xi=xi)
     ct2 = (n * CH / box) ** 2
     ubar = np.sqrt(1 - (ast / a) ** 3)

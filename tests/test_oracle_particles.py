@@ -7,9 +7,11 @@ assignment; it reproduces cell values at cell centres, constants, and linear
 fields exactly.  The Poisson potential satisfies the 7-point discrete
 equation (checked by finite differences, not by the FFT), has zero mean, and
 matches the closed form for a single Fourier mode.  The friction term's
-coefficient is the printed expression of eq:F_x_codeunit (parity unpinned
-beyond that: the paper gives no worked value); its interpolation part is
-pinned through interp.
+coefficient is derived here a second way, numerically: the last term of
+eq:csf_particle_geodesic_qsa in code units is -(dA/dphi)(d phi-bar/da) p~,
+with A of eq:sym_coupling_function, phi_* of eq:varphi_ast and phi-bar(a) of
+eq:varphi_min_symm, differentiated by mpmath at a != 1 (which exposes the
+a^-4 factor); its interpolation part is pinned through interp.
 """
 import numpy as np
 import pytest
@@ -85,16 +87,62 @@ def test_gradient_of_sine_is_exact_central_difference():
     assert np.abs(g[0]).max() == 0.0 and np.abs(g[1]).max() == 0.0
 
 
+def _friction_coef_from_geodesic(a, a_star, xi, beta_star, om, u):
+    """-(dA/dphi)(d phi-bar/da) at phi = phi_* u, in units M_Pl = 1, by
+    numerical differentiation (50 digits).  The paper's parameters: phi_* =
+    6 Omega_m beta_* xi^2 a_*^-3 (eq:varphi_ast); beta_* = M_Pl phi_* / M^2
+    fixes M^2; A = 1 + phi^2 / (2 M^2) (eq:sym_coupling_function); phi-bar
+    = phi_* sqrt(1 - (a_*/a)^3) (eq:varphi_min_symm).  The field's time
+    derivative is the background's (quasi-static approximation), and
+    dp~/da = (dp~/dt)/a-dot turns phi-dot into d phi-bar / da."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    a, a_star, xi, beta_star, om, u = (mp.mpf(x) for x in (a, a_star, xi, beta_star, om, u))
+    phi_star = 6 * om * beta_star * xi ** 2 / a_star ** 3
+    M2 = phi_star / beta_star
+
+    def A(phi):
+        return 1 + phi ** 2 / (2 * M2)
+
+    def phibar(aa):
+        return phi_star * mp.sqrt(1 - (a_star / aa) ** 3)
+
+    return float(-mp.diff(A, phi_star * u) * mp.diff(phibar, a))
+
+
+@pytest.mark.parametrize("a", [1.0, 0.8, 0.6])
+def test_friction_coefficient_from_the_geodesic_equation(a):
+    """The oracle's friction per unit momentum equals the coefficient
+    derived numerically from the geodesic equation, at a = 1, 0.8, 0.6
+    (a_* = 0.5), for fields u of either side of the background."""
+    n, ast, xi, bst = 8, 0.5, 2e-3, 1.3
+    P = oracle.params(oracle.SYM, n, float(n), a=a, a_star=ast, xi=xi, beta_star=bst, omega_m=OM)
+    rng = np.random.default_rng(4)
+    pos = (np.arange(n)[rng.integers(0, n, (6, 3))] + 0.5).astype(np.float64)  # cell centres
+    for uval in (0.3, 0.9, 1.4):
+        u = np.full((n, n, n), uval)
+        mom = rng.standard_normal((6, 3))
+        f = oracle.sym_friction(P, u, pos, mom)
+        coef = _friction_coef_from_geodesic(a, ast, xi, bst, OM, uval)
+        assert np.allclose(f, coef * mom, rtol=1e-12, atol=0), (a, uval)
+    # eq:F_x_codeunit as printed carries u-bar = sqrt(1 - (a_*/a)^3) where the
+    # derivation gives 1 / u-bar: the printed value is u-bar^2 times this one
+    ubar2 = 1 - (ast / a) ** 3
+    printed = -9 * OM * bst ** 2 * xi ** 2 * np.sqrt(ubar2) / a ** 4 * 0.9
+    derived = _friction_coef_from_geodesic(a, ast, xi, bst, OM, 0.9)
+    assert abs(printed / derived - ubar2) < 1e-12
+
+
 def test_friction_is_interpolated_field_times_momentum():
-    n = 8
-    P = oracle.params(oracle.SYM, n, float(n), a=1.0, a_star=0.5, xi=2e-3, beta_star=1.3)
+    n, a, ast, xi, bst = 8, 0.8, 0.5, 2e-3, 1.3
+    P = oracle.params(oracle.SYM, n, float(n), a=a, a_star=ast, xi=xi, beta_star=bst)
     rng = np.random.default_rng(4)
     u = rng.uniform(0.5, 1.0, (n, n, n))
     pos = rng.uniform(0, n, (40, 3))
     mom = rng.standard_normal((40, 3))
     f = oracle.sym_friction(P, u, pos, mom)
-    coef = -9 * OM * 1.3 ** 2 * 2e-3 ** 2 * np.sqrt(1 - 0.5 ** 3)
-    assert np.allclose(f, coef * oracle.interp(n, pos, u)[:, None] * mom, rtol=1e-14, atol=0)
+    coef = _friction_coef_from_geodesic(a, ast, xi, bst, OM, 1.0)  # linear in u
+    assert np.allclose(f, coef * oracle.interp(n, pos, u)[:, None] * mom, rtol=1e-12, atol=0)
 
 
 @pytest.mark.parametrize("model", ["fr", "cq"])
