@@ -12,9 +12,10 @@ the background field.  value = grid cells per second through the step.
 
 Also reported: the plain FP64 GPU step at the same tolerances, the
 roofline of the dominant kernel (FP32 finest-level smoother half-sweep,
-timed with HIP events on the solve's stream over the timed steps), and the
-FP64 CPU oracle timed on a bounded sample (a 128^3 box with the same cell
-size and the same pipeline) on this machine's host cores.
+timed with HIP events on the solve's stream over the timed steps; its
+algorithmic bytes are 12 per updated cell, beside the 16 this layout moves),
+and the FP64 CPU oracle on the same 512^3 pipeline on all of this machine's
+host threads, plus a 192^3 box on one thread.
 """
 import argparse
 import json
@@ -26,7 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-FP32_SMOOTH_BYTES_PER_CELL = 16.0  # per updated cell: X, rho, other-colour e, write e
+# Algorithmic bytes of the FP32 smoother: 12 B per cell per full sweep, i.e.
+# per updated cell of a half-sweep: read the other colour's field and the
+# cell's coefficient, write the cell (4 + 4 + 4).
+FP32_SMOOTH_BYTES_PER_CELL = 12.0
+# What this library's correction-form smoother must move per updated cell:
+# linearisation point X, right-hand side rho, the other colour's correction,
+# the written correction (4 + 4 + 4 + 4).
+FP32_SMOOTH_LAYOUT_BYTES_PER_CELL = 16.0
 # HBM bytes per finest-level launch of that kernel at 512^3, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE (scaled x2.0 and x1.0 by a 1 GiB copy):
 # profiles/k_smooth_corr_v_fr512_hbm_traffic.md.  Set to None whenever the
@@ -43,7 +51,12 @@ def parse():
     ap.add_argument("--fr0", type=float, default=1e-5)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=384)
+    ap.add_argument("--cpu-n", type=int, default=512,
+                    help="oracle sample box at all host threads (the metric's own 512^3)")
+    ap.add_argument("--cpu-n1", type=int, default=192,
+                    help="oracle sample box on one host thread")
+    ap.add_argument("--cpu-leg", type=int, nargs=2, metavar=("N", "THREADS"),
+                    help=argparse.SUPPRESS)  # internal: one oracle run, JSON to stdout
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the |f_R0|=1e-6, coupled-quintessence and batched legs")
     ap.add_argument("--calib-copy", action="store_true",
@@ -84,18 +97,53 @@ def cpu_baseline(n, fr0, tol):
     lap("adjoint")
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    cpu = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-    except OSError:
-        pass
     return dict(value=n ** 3 / dt, unit="cells/s", cores=threads, kind="oracle",
                 sample=f"{n}^3 box, {n} Mpc/h, same pipeline (CIC, FP64 FAS V(1,1) to {tol:g}, "
                        f"force, loss grad, force adjoint, linear-MG adjoint to {tol:g}); "
                        f"{dt:.1f} s wall, {cyc} cycles",
-                seconds=dt, phases_s={k: round(x, 3) for k, x in ph.items()}, cpu_model=cpu,
-                host_threads_available=os.cpu_count())
+                seconds=dt, phases_s={k: round(x, 3) for k, x in ph.items()})
+
+
+def cpu_model():
+    """The host CPU as /proc/cpuinfo names it (model name, family/model/stepping)."""
+    info = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if not ln.strip():
+                    break
+                k, _, v = ln.partition(":")
+                info[k.strip()] = v.strip()
+    except OSError:
+        return "unknown"
+    return (f"{info.get('model name', '?')} (vendor {info.get('vendor_id', '?')}, family "
+            f"{info.get('cpu family', '?')}, model {info.get('model', '?')}, stepping "
+            f"{info.get('stepping', '?')}, {info.get('cpu MHz', '?')} MHz)")
+
+
+def cpu_leg(n, threads, fr0, tol):
+    """One oracle run in a child process with OMP_NUM_THREADS = threads (the
+    OpenMP runtime reads it when the oracle library loads)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", str(n),
+                        str(threads), "--fr0", repr(fr0)], env=env, capture_output=True,
+                       text=True, check=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baselines(a, tol):
+    """The oracle on the metric's pipeline: the full 512^3 box on all host
+    threads (the reported value), and a smaller box on one thread."""
+    nproc = len(os.sched_getaffinity(0))
+    full = cpu_leg(a.cpu_n, nproc, a.fr0, tol)
+    one = cpu_leg(a.cpu_n1, 1, a.fr0, tol)
+    full.update(cpu_model=cpu_model(), host_threads_available=os.cpu_count(),
+                single_thread=dict(value=one["value"], unit="cells/s", cores=1,
+                                   sample=one["sample"], seconds=one["seconds"],
+                                   phases_s=one["phases_s"]),
+                threads_speedup_per_cell=full["value"] / one["value"])
+    return full
 
 
 def m_cells(n):
@@ -216,7 +264,22 @@ def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
                   3)
     blk, vec, teams = bctx.batched_config()
     bctx.close()
+    # each box's batched field and force against its own plain FP64 single-box
+    # solve to the same tolerance (max over boxes of the L2 and max-norm ratios)
     singles = {nb: api.Context(nb, device=dev) for nb in (64, 96, 128)}
+    worst_field = worst_force = 0.0
+    o64 = api.solver_opts(precision="fp64")
+    for b in boxes:
+        c = singles[b["n"]]
+        f64, _ = c.solve(b["model"], b["params"], b["delta"], tol=tol, opts=o64)
+        g64 = c.force(b["model"], b["params"], f64).double()
+        bg = f64.mean()
+        x, g = b["field"], b["force"].double()
+        worst_field = max(worst_field, float((x - f64).norm() / (f64 - bg).norm()),
+                          float((x - f64).abs().max() / (f64 - bg).abs().max()))
+        worst_force = max(worst_force, float((g - g64).norm() / g64.norm()),
+                          float((g - g64).abs().max() / g64.abs().max()))
+        del f64, g64
 
     def one_by_one():
         for b in boxes:
@@ -232,6 +295,7 @@ def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
         cells_per_s=cells_total / (b_ms * 1e-3), block=blk, cells_per_thread=4 if vec else 1,
         teams="one sized team per box" if teams else "single-workgroup teams",
         tune_ms=tune_ms, max_rel_resid=max(s.rel_resid for s in stats),
+        max_err_vs_fp64_single_box=dict(field=worst_field, force=worst_force),
         outer_steps=[int(min(s.cycles for s in stats)), int(max(s.cycles for s in stats))],
         one_by_one_ms=s_ms, batched_speedup=s_ms / b_ms)
     return out
@@ -239,6 +303,9 @@ def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
 
 def main():
     a = parse()
+    if a.cpu_leg:
+        print(json.dumps(cpu_baseline(a.cpu_leg[0], a.fr0, 1e-6)), flush=True)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the library has no "
               "multi-GPU path", file=sys.stderr)
@@ -312,9 +379,12 @@ def main():
 
     extra = {} if a.no_extra else extra_legs(a, mg, pos, delta, field, force, cells, n, tol)
 
+    mg.close()
     avg = sm_ms / max(sm_n, 1)
     bytes_per_launch = FP32_SMOOTH_BYTES_PER_CELL * (m / 2)
     achieved = bytes_per_launch / (avg * 1e-3) / 1e9 if sm_n else None
+    layout_bytes = FP32_SMOOTH_LAYOUT_BYTES_PER_CELL * (m / 2)
+    layout_gbs = layout_bytes / (avg * 1e-3) / 1e9 if sm_n else None
     out = {
         "metric": "512^3 f(R) MG solve to 1e-6 resid: FP32+adjoint vs FP64 time; % HBM peak",
         "value": m / (ms * 1e-3),
@@ -343,10 +413,14 @@ def main():
                      "traffic_unit": "bytes per launch (HBM, counted)",
                      "kernel": "k_smooth_corr<FR> (finest-level FP32 half-sweep)",
                      "avg_launch_ms": avg, "launches": sm_n,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "algorithmic_bytes_per_cell": FP32_SMOOTH_BYTES_PER_CELL,
+                     "layout_bytes_per_launch": layout_bytes,
+                     "layout_GBps": layout_gbs,
+                     "layout_frac": (layout_gbs / HBM_PEAK_GBS) if layout_gbs else None},
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.cpu_n, a.fr0, tol)
+        out["cpu_baseline"] = cpu_baselines(a, tol)
     print(json.dumps(out), flush=True)
 
 

@@ -1,6 +1,8 @@
-"""Batched persistent solve: every box of a mixed batch (grid sizes, models)
-against its own single-box solve through mg_solve and, for two boxes,
-against the FP64 oracle; plus the autotuner's cache round trip."""
+"""Batched solve: every box of a mixed batch (grid sizes, models) against its
+own single-box solve through mg_solve and against the FP64 oracle; the
+batched sweep itself (64 boxes of 64^3/96^3/128^3, |f_R0| log-uniform in
+[1e-7, 1e-4] and symmetron beta_* in [0.5, 2]) box by box against FP64
+single-box GPU solves and the oracle; the autotuner's cache round trip."""
 import json
 import os
 
@@ -69,14 +71,17 @@ def test_batched_matches_single_box_solves(tmp_path, monkeypatch):
               f"rel={st.rel_resid:.1e} field_diff={err:.1e} force_diff={gerr:.1e}", flush=True)
         assert err < 1e-6 and gerr < 1e-6
         single.close()
-    # two boxes against the oracle
-    for q in (0, 1, 7, 8):
+    # boxes of each model against the oracle
+    for q in (0, 1, 5, 7, 8):
         b = boxes[q]
         ref, _, _, _ = oracle.solve(b["P"], b["delta_np"].astype(np.float64), tol=1e-12)
         ref = -ref if b["model"] == "fr" else ref
         bgv = oracle.background(b["P"])
         bgv = -bgv if b["model"] == "fr" else bgv
-        err = np.linalg.norm(b["field"].cpu().numpy() - ref) / np.linalg.norm(ref - bgv)
+        x = b["field"].cpu().numpy()
+        if b["model"] == "cq":
+            x, ref, bgv = x - x.mean(), ref - ref.mean(), 0.0
+        err = np.linalg.norm(x - ref) / np.linalg.norm(ref - bgv)
         assert err < 1e-5, (q, err)
     # second call reuses the tuned shape, warm-started from the solution
     for b in boxes:
@@ -143,4 +148,80 @@ def test_batched_set_config_rejects_bad_shapes():
     with pytest.raises(api.MGError):
         mg.batched_set_config(256, 2, 1)
     mg.batched_set_config(0)
+    mg.close()
+
+
+def _c4_boxes():
+    out = []
+    for b in synthetic.c4_boxes():
+        n = b["n"]
+        d = b["delta"].astype(np.float32)
+        if b["model"] == "fr":
+            prm = api.model_params(b["box"], **b["params"])
+            P = oracle.params(oracle.FR, n, b["box"], **b["params"])
+        else:
+            prm = api.model_params(b["box"], **b["params"])
+            P = oracle.params(oracle.SYM, n, b["box"], **b["params"])
+        out.append(dict(n=n, model=b["model"], params=prm, P=P, delta_np=d,
+                        delta=torch.from_numpy(d).to(DEV),
+                        field=torch.zeros((n, n, n), dtype=torch.float64, device=DEV),
+                        force=torch.zeros((3, n, n, n), dtype=torch.float32, device=DEV)))
+    return out
+
+
+def _errs(x, ref, bg):
+    return (np.linalg.norm(x - ref) / np.linalg.norm(ref - bg),
+            np.max(np.abs(x - ref)) / np.max(np.abs(ref - bg)))
+
+
+def test_c4_batch_matches_fp64_single_box_solves_and_oracle(tmp_path, monkeypatch):
+    """The batched sweep at its own configuration: 64 boxes (22 x 64^3,
+    21 x 96^3, 21 x 128^3), even boxes f(R) with |f_R0| = 10^U(-7,-4), odd
+    boxes symmetron with beta_* ~ U(0.5, 2), FP32-refined to 1e-6 in one
+    batched call with the force.  Every box against its own plain FP64
+    single-box GPU solve to the same tolerance and against the oracle's solve
+    to 1e-10, field and force in the L2 and the max norm (<= 1e-5)."""
+    monkeypatch.setenv("MGGPU_TUNE_CACHE", str(tmp_path / "tune.json"))
+    boxes = _c4_boxes()
+    mg = api.Context(16, device=DEV)
+    tol = 1e-6
+    stats = mg.solve_batched(boxes, tol=tol, opts=api.solver_opts(precision="fp32"))
+    print(f"c4 batch: tile shape {mg.batched_config()}", flush=True)
+    singles = {}
+    o64 = api.solver_opts(precision="fp64")
+    worst = dict(single=0.0, oracle=0.0)
+    for q, (b, st) in enumerate(zip(boxes, stats)):
+        assert st.status == 0 and st.rel_resid <= tol, (q, st.status, st.rel_resid)
+        n = b["n"]
+        if n not in singles:
+            singles[n] = api.Context(n, device=DEV)
+        sc = singles[n]
+        f1, s1 = sc.solve(b["model"], b["params"], b["delta"], tol=tol, opts=o64)
+        g1 = sc.force(b["model"], b["params"], f1).cpu().numpy().astype(np.float64)
+        x = b["field"].cpu().numpy()
+        g = b["force"].cpu().numpy().astype(np.float64)
+        x1 = f1.cpu().numpy()
+        bg = oracle.background(b["P"])
+        bg = -bg if b["model"] == "fr" else bg
+        ref, _, _, _ = oracle.solve(b["P"], b["delta_np"].astype(np.float64), tol=1e-10,
+                                    max_cycles=200)
+        ref = -ref if b["model"] == "fr" else ref
+        g_ref = oracle.force(b["P"], -ref if b["model"] == "fr" else ref)
+        e1, m1 = _errs(x, x1, bg)
+        ge1, gm1 = _errs(g, g1, 0.0)
+        eo, mo = _errs(x, ref, bg)
+        geo, gmo = _errs(g, g_ref, 0.0)
+        tag = (f"fr0={b['P'].fr0:.1e}" if b["model"] == "fr" else f"beta*={b['P'].beta_star:.2f}")
+        print(f"box {q:2d} n={n} {b['model']} {tag}: outer={st.cycles} vc={st.vcycles} "
+              f"rel={st.rel_resid:.1e} | vs fp64 field {e1:.1e} (max {m1:.1e}) force {ge1:.1e} "
+              f"(max {gm1:.1e}) | vs oracle field {eo:.1e} (max {mo:.1e}) force {geo:.1e} "
+              f"(max {gmo:.1e})", flush=True)
+        worst["single"] = max(worst["single"], e1, m1, ge1, gm1)
+        worst["oracle"] = max(worst["oracle"], eo, mo, geo, gmo)
+        assert max(e1, m1, ge1, gm1) < 1e-5, q
+        assert max(eo, mo, geo, gmo) < 1e-5, q
+    print(f"c4 worst: vs fp64 single-box {worst['single']:.2e}, vs oracle {worst['oracle']:.2e}",
+          flush=True)
+    for sc in singles.values():
+        sc.close()
     mg.close()

@@ -6,8 +6,9 @@ at their real sizes, against the FP64 CPU oracle.
   V(1,1) to relative residual 1e-6): CIC against the oracle's CIC; field and
   force against the oracle's solve of the oracle's own density to 1e-10; the
   oracle's residual of the GPU field; the plain FP64 GPU solve beside it.
-- 512^3 coupled quintessence: the oracle's residual of the GPU field (a
-  property at any size) and FP32-refined against FP64 on the GPU.
+- 512^3 coupled quintessence, with and without exp(beta phi~/c~^2) before
+  (1+delta): field and force against the oracle's solve of the same density,
+  the oracle's residual of the GPU field, FP32-refined against FP64.
 - 256^3 f(R) and symmetron on a lognormal field with 20 NFW-like clumps
   (peak delta up to 1e4): field and force against the oracle.
 - 256^3 f(R) adjoint of Loss = sum over 4096 cells of |F5|^2: against the
@@ -21,7 +22,8 @@ at their real sizes, against the FP64 CPU oracle.
   sampled particles and the symmetron friction against the oracle.
 
 Error metrics as in the other parity tests: field_err =
-||x - x_ora|| / ||x_ora - x_bg||, force_err = ||g - g_ora|| / ||g_ora||.
+||x - x_ora|| / ||x_ora - x_bg||, force_err = ||g - g_ora|| / ||g_ora||, and
+the same ratios in the max norm.
 """
 import time
 
@@ -44,6 +46,12 @@ def say(*a):
 
 def rel_err(x, ref, bg=0.0):
     return float(np.linalg.norm(x - ref) / np.linalg.norm(ref - bg))
+
+
+def max_err(x, ref, bg=0.0):
+    """max |x - ref| / max |ref - bg|: an error confined to a few cells (a
+    clump) shows here long before it moves the L2 ratio."""
+    return float(np.max(np.abs(x - ref)) / np.max(np.abs(ref - bg)))
 
 
 @pytest.fixture(scope="module")
@@ -87,23 +95,37 @@ def test_c3_fr_solve_and_force_match_oracle(c3, fr0):
         g = mg.force("fr", prm, field).cpu().numpy().astype(np.float64)
         x = field.cpu().numpy()
         ferr, gerr = rel_err(x, ref, bg), rel_err(g, g_ref)
+        fmax, gmax = max_err(x, ref, bg), max_err(g, g_ref)
         # the oracle's own relative residual of the GPU field (on the GPU's density)
         r, _ = oracle.residual(P, delta.cpu().numpy().astype(np.float64), -x)
         rel_by_oracle = np.sqrt(np.mean(r * r)) / oracle.background_resid_rms(
             P, delta.cpu().numpy().astype(np.float64))
         say(f"  {prec}: V-cycles={st.vcycles} rel={st.rel_resid:.2e} oracle-rel={rel_by_oracle:.2e} "
-            f"field_err={ferr:.2e} force_err={gerr:.2e}")
-        out[prec] = (ferr, gerr, rel_by_oracle, st.rel_resid)
-    for prec, (ferr, gerr, rel_o2, rel_g) in out.items():
+            f"field_err={ferr:.2e} (max {fmax:.2e}) force_err={gerr:.2e} (max {gmax:.2e})")
+        out[prec] = (ferr, gerr, fmax, gmax, rel_by_oracle, st.rel_resid)
+    for prec, (ferr, gerr, fmax, gmax, rel_o2, rel_g) in out.items():
         assert rel_o2 <= 1e-6 and abs(rel_o2 - rel_g) <= 1e-3 * rel_g + 1e-12
-        assert ferr < 1e-5 and gerr < 1e-5
+        assert ferr < 1e-5 and gerr < 1e-5 and fmax < 1e-5 and gmax < 1e-5
 
 
-def test_c3_cq_residual_by_oracle_and_fp32_vs_fp64(c3):
+@pytest.mark.parametrize("keep_exp", [1, 0])
+def test_c3_cq_solve_and_force_match_oracle(c3, keep_exp):
+    """512^3 coupled quintessence, eq:csf_eom_code as printed (keep_exp = 1)
+    and with exp(beta phi~/c~^2) dropped as the paper's runs do (keep_exp =
+    0): field (uniform mode removed: it is fixed only to ~tol/m^2 and the
+    force does not see it) and force against the oracle's solve of the same
+    density to 1e-9; the oracle's residual of the GPU field; FP32-refined
+    against FP64 on the GPU."""
     n, mg, delta = c3["n"], c3["mg"], c3["delta"]
-    P = oracle.params(oracle.CQ, n, float(n))
-    prm = api.model_params(float(n))
+    P = oracle.params(oracle.CQ, n, float(n), cq_keep_exp=keep_exp)
+    prm = api.model_params(float(n), cq_keep_exp=keep_exp)
     d64 = delta.cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    ref, cyc, rel_ref, _ = oracle.solve(P, d64, tol=1e-9, max_cycles=200)
+    say(f"cq keep_exp={keep_exp}: oracle solve {time.perf_counter() - t0:.1f} s, {cyc} cycles, "
+        f"rel {rel_ref:.1e}")
+    g_ref = oracle.force(P, ref)
+    ref0 = ref - ref.mean()
     eps_bg = oracle.background_resid_rms(P, d64)
     fields = {}
     for prec in ("fp32", "fp64"):
@@ -111,8 +133,14 @@ def test_c3_cq_residual_by_oracle_and_fp32_vs_fp64(c3):
         x = field.cpu().numpy()
         r, _ = oracle.residual(P, d64, x)
         rel_o = np.sqrt(np.mean(r * r)) / eps_bg
-        say(f"  cq {prec}: V-cycles={st.vcycles} rel={st.rel_resid:.2e} oracle-rel={rel_o:.2e}")
+        g = mg.force("cq", prm, field).cpu().numpy().astype(np.float64)
+        x0 = x - x.mean()
+        ferr, fmax = rel_err(x0, ref0), max_err(x0, ref0)
+        gerr, gmax = rel_err(g, g_ref), max_err(g, g_ref)
+        say(f"  cq {prec}: V-cycles={st.vcycles} rel={st.rel_resid:.2e} oracle-rel={rel_o:.2e} "
+            f"field_err={ferr:.2e} (max {fmax:.2e}) force_err={gerr:.2e} (max {gmax:.2e})")
         assert rel_o <= 1e-6 and abs(rel_o - st.rel_resid) <= 1e-3 * st.rel_resid + 1e-12
+        assert ferr < 1e-5 and gerr < 1e-5 and fmax < 1e-5 and gmax < 1e-5
         fields[prec] = x
     a, b = fields["fp32"], fields["fp64"]
     err = rel_err(a - a.mean(), b - b.mean())
@@ -150,12 +178,15 @@ def test_c2_fp32_solve_and_force_match_oracle(c2, model):
     for tol in (1e-6, 1e-8):
         field, st = mg.solve(model, prm, c2["delta"], tol=tol, opts=api.solver_opts(precision="fp32"))
         g = mg.force(model, prm, field).cpu().numpy().astype(np.float64)
-        ferr = rel_err(field.cpu().numpy(), sgn * ref, bg)
-        gerr = rel_err(g, g_ref)
+        x = field.cpu().numpy()
+        ferr, fmax = rel_err(x, sgn * ref, bg), max_err(x, sgn * ref, bg)
+        gerr, gmax = rel_err(g, g_ref), max_err(g, g_ref)
         say(f"  tol {tol:g}: V-cycles={st.vcycles} rel={st.rel_resid:.2e} field_err={ferr:.2e} "
-            f"force_err={gerr:.2e}")
+            f"(max {fmax:.2e}) force_err={gerr:.2e} (max {gmax:.2e})")
         # the stated 1e-5 at the configured tolerance; 1e-6 when driven to 1e-8
-        assert ferr < (1e-5 if tol == 1e-6 else 1e-6) and gerr < (1e-5 if tol == 1e-6 else 1e-6)
+        lim = 1e-5 if tol == 1e-6 else 1e-6
+        assert ferr < lim and gerr < lim
+        assert fmax < 1e-5 and gmax < 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -207,8 +238,10 @@ def test_c5_adjoint_matches_oracle_and_finite_differences(c5):
     gd_ora, _, _ = oracle.adjoint(P, d64, ref, gv, tol=1e-12)
     say(f"oracle solve + adjoint {time.perf_counter() - t0:.1f} s")
     e32, e64 = rel_err(gd32, gd_ora), rel_err(gd64, gd_ora)
-    say(f"adjoint vs oracle: fp32 {e32:.2e} ({st32.vcycles} cycles), fp64 {e64:.2e}")
-    assert e32 < 1e-5 and e64 < 1e-6
+    m32, m64 = max_err(gd32, gd_ora), max_err(gd64, gd_ora)
+    say(f"adjoint vs oracle: fp32 {e32:.2e} (max {m32:.2e}, {st32.vcycles} cycles), "
+        f"fp64 {e64:.2e} (max {m64:.2e})")
+    assert e32 < 1e-5 and e64 < 1e-6 and m32 < 1e-5 and m64 < 1e-6
     # central differences of FP64 GPU solves on delta at 16 probe cells
     rng = np.random.default_rng(5006)
     near = []

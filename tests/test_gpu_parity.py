@@ -547,3 +547,34 @@ def test_uniform_contrast_matches_closed_form(model, prec):
     say(f"  outer={st.cycles} rel={st.rel_resid:.1e} err={err:.1e} spread={np.ptp(f):.1e}")
     assert err < (1e-5 if model == "cq" else (1e-9 if prec == "fp64" else 1e-6))
     mg.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_deep_screening_fr0_1e7_matches_oracle(prec):
+    """|f_R0| = 1e-7, the smallest the batched sweep draws (the strongest
+    screening), on a 64^3 lognormal box (sigma_delta = 2, 1 Mpc/h cells, as
+    in that sweep).  At the sweep's tolerance 1e-6 and driven to 1e-9."""
+    n = 64
+    say("deep screening |f_R0| = 1e-7", prec)
+    P = oracle.params(oracle.FR, n, float(n), fr0=1e-7)
+    prm = api.model_params(float(n), fr0=1e-7)
+    delta = synthetic.lognormal_delta(n, 4000).astype(np.float32)
+    d64 = delta.astype(np.float64)
+    ref, cyc, rel_o, _ = oracle.solve(P, d64, tol=1e-11, max_cycles=200)
+    g_ref = oracle.force(P, ref)
+    wr = ref / oracle.background(P)
+    say(f"  oracle: {cyc} cycles, rel {rel_o:.1e}, f_R / f_R-bar in [{wr.min():.2e}, {wr.max():.2f}]")
+    mg = api.Context(n, device=DEV)
+    for tol in (1e-6, 1e-9):
+        field, st = mg.solve("fr", prm, torch.from_numpy(delta).to(DEV), tol=tol,
+                             opts=api.solver_opts(precision=prec))
+        x = field.cpu().numpy()
+        err, merr = field_err("fr", x, -ref, P), field_maxerr("fr", x, -ref, P)
+        g = mg.force("fr", prm, field).cpu().numpy().astype(np.float64)
+        gerr, gmerr = force_errs(g, g_ref)
+        say(f"  tol {tol:g}: checks={st.cycles} cycles={st.vcycles} rel={st.rel_resid:.1e} "
+            f"field_err={err:.1e} (max {merr:.1e}) force_err={gerr:.1e} (max {gmerr:.1e})")
+        assert st.rel_resid <= tol
+        lim = 1e-5 if tol == 1e-6 else 1e-7
+        assert err < lim and gerr < lim and merr < 10 * lim and gmerr < 10 * lim
+    mg.close()
