@@ -80,6 +80,14 @@ typedef struct {
                        residual has dropped by 1e-8); 0 = default: for a
                        coarsest level of n <= 8, 24 in hierarchies of at most
                        4 levels and 8 from 5 levels up; else 2 n^2 */
+  int fixed_cycles; /* 0: iterate to tol.  k > 0: run exactly k cycles from
+                       field_in (or the background) with no convergence test,
+                       as the paper's production runs do with two V-cycles per
+                       time step warm-started from the previous step's field
+                       (Sec. 4.3); returns MG_OK unless the residual is
+                       non-finite.  Refined mode: one outer step of k FP32
+                       cycles.  stats->rel_resid is the residual after them
+                       (computed only when stats is given in FP64 mode). */
 } mg_solver_opts;
 
 typedef struct {
@@ -89,6 +97,9 @@ typedef struct {
   double resid_hist[64]; /* rel_resid at each check */
   double ms_total;       /* wall time of the call (stream-synchronised) */
   int vcycles;           /* multigrid cycles run on the finest level */
+  int fallback;          /* 1: the FP32-refined solve diverged and the result
+                            is that of the plain FP64 solve rerun from the
+                            same start */
 } mg_stats;
 
 typedef struct mg_ctx mg_ctx;
@@ -130,7 +141,14 @@ int cic_assign(mg_ctx *ctx, const float *pos_xyz, int64_t n_part, float *delta_o
  * field_in: initial guess (NULL = background value); field_out: solution
  * (n^3 doubles; may equal field_in).  Returns MG_ENOCONV with the last
  * iterate in field_out if max_cycles is reached, MG_ENAN on a non-finite
- * residual.  stats may be NULL. */
+ * residual.  Divergence: when the FP64 residual has grown at two
+ * consecutive checks and exceeds twice the best one, the FP64 mode stops
+ * with MG_ENOCONV and the FP32-refined mode (also on a non-finite residual
+ * after a finite start) reruns the plain FP64 solve once from the same
+ * start and returns its result (stats->fallback = 1).  stats may be NULL.
+ * Environment, read at context creation: MGGPU_TEST_CORRECTION_SCALE = s
+ * scales each FP32 correction by s before it is added to the FP64 field
+ * (a test hook that forces the divergence path from the host; default 1). */
 int mg_solve(mg_ctx *ctx, int model, const mg_model_params *params,
              const mg_solver_opts *opts, const float *delta, const double *field_in,
              double *field_out, double tol, mg_stats *stats);
@@ -156,8 +174,9 @@ int mg_force_adjoint(mg_ctx *ctx, int model, const mg_model_params *params,
  * dLoss/ddelta = -(dF/ddelta) J^{-1} dLoss/dfield, with J = dF/dfield the
  * symmetric "Laplacian plus diagonal" Jacobian of the same equation, solved
  * by linear multigrid (FP64, or FP32 inner cycles with FP64 residuals as
- * selected by opts->precision) to ||r||/||b|| <= tol.  All arrays n^3;
- * delta float, the rest double. */
+ * selected by opts->precision) to ||r||/||b|| <= tol (opts->fixed_cycles is
+ * ignored: the adjoint always iterates to tol).  All arrays n^3; delta
+ * float, the rest double. */
 int mg_solve_adjoint(mg_ctx *ctx, int model, const mg_model_params *params,
                      const mg_solver_opts *opts, const float *delta, const double *field,
                      const double *grad_field, double *grad_delta_out, double tol,
@@ -284,7 +303,8 @@ int mg_cq_background_at(const double *table, int n_table, double a, double *row)
  * team split) comes from mg_batched_set_config if pinned, else from the last
  * tuning of this context for the same multiset of (n, model), else from the
  * cache file $MGGPU_TUNE_CACHE (default $HOME/.mggpu_tune.json), else
- * mg_batched_tune runs first.  opts->precision must be MG_FP32_REFINED.
+ * mg_batched_tune runs first.  opts->precision must be MG_FP32_REFINED and
+ * opts->fixed_cycles 0.
  * Returns MG_OK when every box converged, else MG_ENAN / MG_ENOCONV
  * (per-box status in per_box, which may be NULL). */
 typedef struct {

@@ -70,6 +70,7 @@ class SolverOpts(ctypes.Structure):
         ("max_cycles", ctypes.c_int),
         ("precision", ctypes.c_int),
         ("coarse_sweeps", ctypes.c_int),
+        ("fixed_cycles", ctypes.c_int),
     ]
 
 
@@ -81,6 +82,7 @@ class Stats(ctypes.Structure):
         ("resid_hist", ctypes.c_double * 64),
         ("ms_total", ctypes.c_double),
         ("vcycles", ctypes.c_int),
+        ("fallback", ctypes.c_int),
     ]
 
 

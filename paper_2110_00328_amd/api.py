@@ -81,12 +81,14 @@ def cq_model_params(box, a, alpha, beta, omega_m=0.3089, background=None, **kw):
 
 
 def solver_opts(cycle="V", nu_pre=1, nu_post=1, inner_cycles=0, max_cycles=64, precision="fp32",
-                coarse_sweeps=0):
+                coarse_sweeps=0, fixed_cycles=0):
     """mg_solver_opts; inner_cycles = 0 plans the cycles between FP64
-    residual checks from the measured contraction."""
+    residual checks from the measured contraction; fixed_cycles = k runs
+    exactly k cycles with no convergence test (the paper's V2 per step)."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     cyc = CYCLES[cycle] if isinstance(cycle, str) else int(cycle)
-    return L.SolverOpts(cyc, nu_pre, nu_post, inner_cycles, max_cycles, prec, coarse_sweeps)
+    return L.SolverOpts(cyc, nu_pre, nu_post, inner_cycles, max_cycles, prec, coarse_sweeps,
+                        fixed_cycles)
 
 
 def _p(t):

@@ -83,6 +83,10 @@ struct mg_ctx {
   // planes per thread of the z-marching level-0 FP32 smoother (0: the
   // per-row kernel); MGGPU_SMOOTH_MARCH_KT overrides it at context creation
   int smooth_march_kt = 0;
+  // scale applied to each FP32 correction before the FP64 update (1: the
+  // method; another value forces the divergence path from the host in tests;
+  // MGGPU_TEST_CORRECTION_SCALE overrides it at context creation)
+  float test_escale = 1.0f;
   // device facts for the cooperative batched launch, queried once (property
   // queries cost milliseconds per call): CU count, cooperative support, and
   // resident workgroups per CU for each workgroup size (index log2(BS) - 8)
@@ -462,8 +466,25 @@ int check_opts(mg_ctx* ctx, const mg_solver_opts* o) {
     return fail(ctx, MG_EINVAL, "inner_cycles in 0 (automatic) .. 16");
   if (o->coarse_sweeps < 0 || o->coarse_sweeps > 5000)
     return fail(ctx, MG_EINVAL, "coarse_sweeps in 0..5000");
+  if (o->fixed_cycles < 0 || o->fixed_cycles > 64)
+    return fail(ctx, MG_EINVAL, "fixed_cycles in 0 (iterate to tol) .. 64");
   return MG_OK;
 }
+
+// Divergence test of the outer loops: the FP64 residual grew at two
+// consecutive checks and is above twice the best seen.  A monotone problem
+// contracts at every check, so this does not fire on a converging solve (at
+// a rounding floor the residual wanders by far less than a factor of two).
+struct GrowthWatch {
+  int grew = 0;
+  double best = HUGE_VAL, last = -1.0;
+  bool diverging(double rel) {
+    grew = (last >= 0.0 && rel > last) ? grew + 1 : 0;
+    last = rel;
+    if (rel < best) best = rel;
+    return grew >= 2 && rel > 2.0 * best;
+  }
+};
 
 double lev_h2(int l) { return double(1u << l) * double(1u << l); }
 
@@ -572,13 +593,27 @@ int bg_rms(mg_ctx* ctx, const Consts& C, const float* delta, double* out) {
 // ---------------------------------------------------------------------------
 // fused-program generation (same recursion as the grid levels)
 // ---------------------------------------------------------------------------
-void gen_prog(std::vector<Op>& ops, int l, int lmax, int type, int nu1, int nu2) {
+// A cycle program in a fixed host buffer (no heap allocation per cycle);
+// 'over' records a program longer than the buffer.
+struct OpList {
+  static constexpr int kCap = kMaxOpsB > kMaxOps ? kMaxOpsB : kMaxOps;
+  Op op[kCap];
+  int n = 0;
+  bool over = false;
+  void push(Op o) {
+    if (n < kCap) op[n++] = o;
+    else over = true;
+  }
+};
+
+void gen_prog(OpList& ops, int l, int lmax, int type, int nu1, int nu2) {
+  if (ops.over) return;
   if (l == lmax) {
-    ops.push_back(Op{OP_COARSEST, (uint8_t)l, 0, 0});
+    ops.push(Op{OP_COARSEST, (uint8_t)l, 0, 0});
     return;
   }
-  if (nu1 > 0) ops.push_back(Op{OP_SMOOTH, (uint8_t)l, (uint8_t)nu1, 0});
-  ops.push_back(Op{OP_DOWN, (uint8_t)l, 0, 0});
+  if (nu1 > 0) ops.push(Op{OP_SMOOTH, (uint8_t)l, (uint8_t)nu1, 0});
+  ops.push(Op{OP_DOWN, (uint8_t)l, 0, 0});
   if (type == MG_CYCLE_V) {
     gen_prog(ops, l + 1, lmax, MG_CYCLE_V, nu1, nu2);
   } else if (type == MG_CYCLE_W) {
@@ -588,20 +623,20 @@ void gen_prog(std::vector<Op>& ops, int l, int lmax, int type, int nu1, int nu2)
     gen_prog(ops, l + 1, lmax, MG_CYCLE_F, nu1, nu2);
     gen_prog(ops, l + 1, lmax, MG_CYCLE_V, nu1, nu2);
   }
-  ops.push_back(Op{OP_UP, (uint8_t)l, 0, 0});
-  ops.push_back(Op{OP_SMOOTH, (uint8_t)l, (uint8_t)nu2, 0});
+  ops.push(Op{OP_UP, (uint8_t)l, 0, 0});
+  ops.push(Op{OP_SMOOTH, (uint8_t)l, (uint8_t)nu2, 0});
 }
 
 int make_prog(mg_ctx* ctx, int l, const mg_solver_opts* o, int type, FusedProg* P, int rx = 0) {
-  std::vector<Op> ops;
+  OpList ops;
   int f = ctx->fused_from;
   gen_prog(ops, l - f, ctx->nlev - 1 - f, type, o->nu_pre, o->nu_post);
-  if ((int)ops.size() > kMaxOps) return fail(ctx, MG_EINVAL, "fused cycle program too long");
-  P->nops = (int)ops.size();
+  if (ops.over || ops.n > kMaxOps) return fail(ctx, MG_EINVAL, "fused cycle program too long");
+  P->nops = ops.n;
   P->coarse_sweeps =
       o->coarse_sweeps > 0 ? o->coarse_sweeps : default_coarse_sweeps(ctx->L[ctx->nlev - 1].n, ctx->nlev);
   P->rx = rx;
-  for (size_t q = 0; q < ops.size(); ++q) P->op[q] = ops[q];
+  for (int q = 0; q < ops.n; ++q) P->op[q] = ops.op[q];
   return MG_OK;
 }
 
@@ -756,6 +791,26 @@ int solve64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
             const double* field_in, double* field_out, double tol, mg_stats* st) {
   ACHK(ensure64(ctx));
   ACHK(setup64(ctx, C, delta, field_in));
+  double sgn = (C.model == FR) ? -1.0 : 1.0;
+  const Lev& L0 = ctx->L[0];
+  if (o->fixed_cycles > 0) {
+    // the paper's fixed cycles per time step: no residual unless asked for
+    for (int it = 0; it < o->fixed_cycles; ++it) ACHK(cycle64<M>(ctx, C, o, 0, o->cycle));
+    int rc = MG_OK;
+    if (st) {
+      double eps_bg, rel;
+      ACHK(bg_rms(ctx, C, delta, &eps_bg));
+      ACHK(resid64<M>(ctx, C, eps_bg, &rel, nullptr));
+      st->cycles = 1;
+      st->vcycles = o->fixed_cycles;
+      st->rel_resid = rel;
+      st->resid_hist[0] = rel;
+      if (!std::isfinite(rel)) rc = fail(ctx, MG_ENAN, "non-finite residual");
+    }
+    launch_unpack<double, double>(ctx, L0, ctx->w64.v[0], field_out, sgn);
+    LAUNCHCHK();
+    return rc;
+  }
   double eps_bg;
   ACHK(bg_rms(ctx, C, delta, &eps_bg));
   double rel;
@@ -763,6 +818,8 @@ int solve64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   int cyc = 0, checks = 0, k_prev = 0;
   double rel_prev = -1.0;
   int rc = MG_OK;
+  GrowthWatch watch;
+  watch.diverging(rel);
   if (!std::isfinite(rel)) rc = fail(ctx, MG_ENAN, "non-finite residual");
   while (rc == MG_OK && rel > tol && cyc < o->max_cycles) {
     // the residual is checked after each planned group of cycles
@@ -779,12 +836,13 @@ int solve64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
       rc = fail(ctx, MG_ENAN, "non-finite residual");
       break;
     }
+    if (rel > tol && watch.diverging(rel)) {
+      rc = fail(ctx, MG_ENOCONV, "residual grew at two consecutive checks (diverging)");
+      break;
+    }
   }
   if (rc == MG_OK && rel > tol) rc = fail(ctx, MG_ENOCONV, "max_cycles reached");
-  double sgn = (C.model == FR) ? -1.0 : 1.0;
-  const Lev& L0 = ctx->L[0];
-  launch_unpack<double, double>(ctx, L0, ctx->w64.v[0],
-                                                                          field_out, sgn);
+  launch_unpack<double, double>(ctx, L0, ctx->w64.v[0], field_out, sgn);
   LAUNCHCHK();
   if (st) {
     st->cycles = checks;
@@ -797,6 +855,12 @@ int solve64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
 // ---------------------------------------------------------------------------
 // FP32 correction multigrid inside an FP64 outer loop
 // ---------------------------------------------------------------------------
+// e *= s over m cells (the divergence test hook, MGGPU_TEST_CORRECTION_SCALE)
+__global__ __launch_bounds__(kBlock) void k_scale(float* __restrict__ e, int64_t m, float s) {
+  const int64_t g = gid();
+  if (g < m) e[g] *= s;
+}
+
 template <int M>
 // fresh: the correction buffer was not cleared; the first sweep takes it as 0
 int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps, bool fresh = false) {
@@ -938,6 +1002,9 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   if (!uni) ACHK(bg_rms(ctx, C, delta, &eps_bg));
   int outer = 0, rc = MG_OK, vc = 0, k_prev = 0;
   double rel = 0.0, rel_prev = -1.0;
+  const bool fixed = o->fixed_cycles > 0;
+  bool diverged = false;
+  GrowthWatch watch;
   // the first pre-smoothing sweep of each outer step treats the correction
   // as zero, so the buffer need not be cleared (not when level 0 is relaxed
   // by the single-block kernel, which reads it, or without pre-smoothing)
@@ -982,17 +1049,28 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
     rel = sqrt(s / double(m)) / eps_bg;
     if (outer > 0 && st && outer - 1 < 64) st->resid_hist[outer - 1] = rel;
     if (!std::isfinite(rel)) {
-      rc = fail(ctx, MG_ENAN, "non-finite residual");
+      // a finite start that the FP32 cycles turned non-finite: diverged
+      if (outer > 0 && !fixed) diverged = true;
+      else rc = fail(ctx, MG_ENAN, "non-finite residual");
       break;
     }
-    if (rel <= tol) break;
+    if (fixed ? outer > 0 : rel <= tol) break;
+    if (watch.diverging(rel)) {
+      diverged = true;
+      break;
+    }
     if (outer >= o->max_cycles) {
       rc = fail(ctx, MG_ENOCONV, "max_cycles reached");
       break;
     }
-    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol, cells(ctx->L[0]));
+    int k = fixed ? o->fixed_cycles
+                  : plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol, cells(ctx->L[0]));
     for (int it = 0; it < k; ++it)
       ACHK(cycle32<M>(ctx, C, o, 0, o->cycle, it == 0, fresh && it == 0));
+    if (ctx->test_escale != 1.0f) {
+      k_scale<<<nblk(m), kBlock, 0, ctx->stream>>>(W.e[0], m, ctx->test_escale);
+      LAUNCHCHK();
+    }
     vc += k;
     rel_prev = rel;
     k_prev = k;
@@ -1003,6 +1081,15 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
       LAUNCHCHK();
     }
     ++outer;
+  }
+  if (diverged) {
+    // one rerun in plain FP64 from the same start (field_in is unchanged:
+    // nothing has been written to field_out yet, which may alias it)
+    mg_solver_opts o64 = *o;
+    o64.precision = MG_FP64;
+    const int rc64 = solve64<M>(ctx, C, &o64, delta, field_in, field_out, tol, st);
+    if (st) st->fallback = 1;
+    return rc64;
   }
   // stopped before any correction: the master is still the background
   if (uni && outer == 0) k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(W.w, m, C.bg);
@@ -2034,6 +2121,7 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
   ctx->n = n;
   if (const char* mb = getenv("MGGPU_MARCH_MIN_BLOCKS")) ctx->march_min_blocks = (unsigned)atoi(mb);
   if (const char* cd = getenv("MGGPU_CIC_DIRECT")) ctx->cic_direct = atoi(cd) != 0;
+  if (const char* ts = getenv("MGGPU_TEST_CORRECTION_SCALE")) ctx->test_escale = (float)atof(ts);
   if (const char* sk = getenv("MGGPU_SMOOTH_MARCH_KT")) {
     const int kt = atoi(sk);
     ctx->smooth_march_kt = kt > 0 && kt <= 64 ? kt : 0;
@@ -2705,11 +2793,11 @@ int batch_setup(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver_o
     B.model = D.model;
     B.nlev = box_levels(D.n, B.L);
     for (int l = 0; l < B.nlev; ++l) B.h2[l] = float(lev_h2(l));
-    std::vector<Op> ops;
+    OpList ops;
     gen_prog(ops, 0, B.nlev - 1, o->cycle, o->nu_pre, o->nu_post);
-    if ((int)ops.size() > kMaxOpsB) return fail(ctx, MG_EINVAL, "cycle program too long");
-    B.nops = (int)ops.size();
-    for (size_t q = 0; q < ops.size(); ++q) B.op[q] = ops[q];
+    if (ops.over || ops.n > kMaxOpsB) return fail(ctx, MG_EINVAL, "cycle program too long");
+    B.nops = ops.n;
+    for (int q = 0; q < ops.n; ++q) B.op[q] = ops.op[q];
     B.vec = vec;
     B.nu1 = o->nu_pre;
     B.nu2 = o->nu_post;
@@ -3067,6 +3155,8 @@ int mg_solve_batched(mg_ctx* ctx, int n_box, const mg_box_desc* boxes, const mg_
   if (!(tol > 0.0)) return fail(ctx, MG_EINVAL, "mg_solve_batched: tol must be > 0");
   if (opts->precision != MG_FP32_REFINED)
     return fail(ctx, MG_EINVAL, "mg_solve_batched: runs the FP32-refined scheme");
+  if (opts->fixed_cycles > 0)
+    return fail(ctx, MG_EINVAL, "mg_solve_batched: iterates to tol (fixed_cycles must be 0)");
   // tile shape: this context's last tuning for the same batch shape, else the
   // cache file, else tune now
   std::string key = batch_key(ctx, n_box, boxes, opts);

@@ -578,3 +578,74 @@ def test_deep_screening_fr0_1e7_matches_oracle(prec):
         lim = 1e-5 if tol == 1e-6 else 1e-7
         assert err < lim and gerr < lim and merr < 10 * lim and gmerr < 10 * lim
     mg.close()
+
+
+@pytest.mark.parametrize("model", ["fr", "sym"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fixed_cycles_mode(model, prec):
+    """The paper's production setting (Sec. 4.3): exactly k cycles per call,
+    warm-started from the previous step's field, no convergence test.
+    - k fixed cycles give the same field, bit for bit, as the iterating loop
+      stopped after the same k cycles (inner_cycles = k, one check);
+    - a time-step analogue: the solution for delta1, then two V-cycles
+      (V2) for a density that has grown by 1% cut the error against the
+      oracle's solution for the new density by at least 20x."""
+    n, box = 48, 48.0
+    say("fixed cycles", model, prec)
+    P, prm = cfg(model, n, box)
+    d1 = lognormal(n, 81)
+    mg = api.Context(n, device=DEV)
+    for k in (1, 2, 3):
+        loop = api.solver_opts(precision=prec, inner_cycles=k,
+                               max_cycles=k if prec == "fp64" else 1)
+        f_loop, s_loop = mg.solve(model, prm, torch.from_numpy(d1).to(DEV), tol=1e-14, opts=loop,
+                                  allow_noconv=True)
+        f_fix, s_fix = mg.solve(model, prm, torch.from_numpy(d1).to(DEV), tol=1e-14,
+                                opts=api.solver_opts(precision=prec, fixed_cycles=k))
+        say(f"  k={k}: loop rel={s_loop.rel_resid:.2e} status={s_loop.status}, fixed "
+            f"rel={s_fix.rel_resid:.2e} status={s_fix.status} cycles={s_fix.vcycles}")
+        assert s_fix.status == 0 and s_fix.vcycles == k
+        assert torch.equal(f_loop, f_fix)
+        assert s_fix.rel_resid == pytest.approx(s_loop.rel_resid, rel=1e-12)
+    f1, _ = mg.solve(model, prm, torch.from_numpy(d1).to(DEV), tol=1e-10,
+                     opts=api.solver_opts(precision=prec))
+    d2 = (d1.astype(np.float64) * 1.01).astype(np.float32)  # delta grows by 1% (mean zero)
+    ref2, _, _, _ = oracle.solve(P, d2.astype(np.float64), tol=1e-12)
+    ref2 = to_field(model, ref2)
+    e_prev = field_err(model, f1.cpu().numpy(), ref2, P)
+    f2, s2 = mg.solve(model, prm, torch.from_numpy(d2).to(DEV), field_in=f1, tol=1e-14,
+                      opts=api.solver_opts(precision=prec, fixed_cycles=2))
+    e_v2 = field_err(model, f2.cpu().numpy(), ref2, P)
+    say(f"  time step: previous field err {e_prev:.2e}, after V2 {e_v2:.2e} "
+        f"(rel resid {s2.rel_resid:.2e})")
+    assert s2.status == 0 and e_v2 < e_prev / 20
+    mg.close()
+
+
+@pytest.mark.parametrize("model", ["fr", "sym"])
+def test_refined_divergence_falls_back_to_fp64(model, monkeypatch):
+    """Failure handling: a host-set test hook (MGGPU_TEST_CORRECTION_SCALE =
+    -1) subtracts each FP32 correction instead of adding it, so the refined
+    outer loop's FP64 residual grows; the solve detects it and reruns the
+    plain FP64 solve once, whose result it returns (bit for bit the FP64
+    solve's, stats.fallback = 1).  Without the hook nothing falls back."""
+    n, box = 32, 32.0
+    say("divergence fallback", model)
+    P, prm = cfg(model, n, box)
+    delta = torch.from_numpy(lognormal(n, 91)).to(DEV)
+    monkeypatch.setenv("MGGPU_TEST_CORRECTION_SCALE", "-1")
+    mg = api.Context(n, device=DEV)
+    field, st = mg.solve(model, prm, delta, tol=1e-8, opts=api.solver_opts(precision="fp32"))
+    mg.close()
+    monkeypatch.delenv("MGGPU_TEST_CORRECTION_SCALE")
+    say(f"  forced: status={st.status} fallback={st.fallback} rel={st.rel_resid:.1e} "
+        f"cycles={st.vcycles}")
+    assert st.status == 0 and st.fallback == 1 and st.rel_resid <= 1e-8
+    mg = api.Context(n, device=DEV)
+    f64, s64 = mg.solve(model, prm, delta, tol=1e-8, opts=api.solver_opts(precision="fp64"))
+    assert s64.fallback == 0 and torch.equal(field, f64)
+    f32, s32 = mg.solve(model, prm, delta, tol=1e-8, opts=api.solver_opts(precision="fp32"))
+    assert s32.status == 0 and s32.fallback == 0
+    ref, _, _, _ = oracle.solve(P, delta.cpu().numpy().astype(np.float64), tol=1e-12)
+    assert field_err(model, field.cpu().numpy(), to_field(model, ref), P) < 1e-6
+    mg.close()
