@@ -153,6 +153,23 @@ int mg_solve(mg_ctx *ctx, int model, const mg_model_params *params,
              const mg_solver_opts *opts, const float *delta, const double *field_in,
              double *field_out, double tol, mg_stats *stats);
 
+/* mg_solve without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, arithmetic and results as mg_solve (bit for
+ * bit), but the call's whole workspace (the FP32-refined and the FP64 level
+ * pyramids and the reduction partials) lives in one static 16 MiB device
+ * array per GPU instead of the context's allocations: it calls no hipMalloc,
+ * hipFree or other allocating routine, and the context must only have been
+ * created (mg_ctx_create, which allocates its few scalars, at set-up).
+ * Limit: the workspace of an n^3 solve must fit the array, which holds
+ * n <= 64 (about 15 MB at n = 64); larger n returns MG_EINVAL.  Every call
+ * on one GPU shares that GPU's array, whatever the context or stream, and
+ * leaves its contents behind (the solve reads nothing it has not written):
+ * calls that overlap on one GPU race. */
+int mg_solve_noalloc(mg_ctx *ctx, int model, const mg_model_params *params,
+                     const mg_solver_opts *opts, const float *delta, const double *field_in,
+                     double *field_out, double tol, mg_stats *stats);
+
 /* Residual of a field: d = F(field) in FP64 (n^3 doubles out, may be NULL)
  * and its RMS relative to the background residual in *rel. */
 int mg_residual(mg_ctx *ctx, int model, const mg_model_params *params,

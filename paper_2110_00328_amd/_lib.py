@@ -22,7 +22,7 @@ EXPORTS = (
     "mg_solve_batched", "mg_prof_enable", "mg_prof_read", "mg_batched_tune",
     "mg_batched_config", "mg_batched_set_config", "mg_interp_to_particles",
     "mg_interp_field_to_particles", "mg_poisson_newton", "mg_gradient", "mg_total_force",
-    "mg_symmetron_friction", "mg_cq_background", "mg_cq_background_at",
+    "mg_symmetron_friction", "mg_cq_background", "mg_cq_background_at", "mg_solve_noalloc",
 )
 MG_PROF_SMOOTH32, MG_PROF_SMOOTH64, MG_PROF_LIN32, MG_PROF_LIN64 = 0, 1, 2, 3
 
@@ -118,6 +118,8 @@ def load():
         "mg_ctx_levels": (ci, [vp]),
         "cic_assign": (ci, [vp, vp, i64, vp]),
         "mg_solve": (ci, [vp, ci, P(ModelParams), P(SolverOpts), vp, vp, vp, dbl, P(Stats)]),
+        "mg_solve_noalloc": (ci, [vp, ci, P(ModelParams), P(SolverOpts), vp, vp, vp, dbl,
+                                  P(Stats)]),
         "mg_residual": (ci, [vp, ci, P(ModelParams), vp, vp, vp, P(dbl)]),
         "mg_force": (ci, [vp, ci, P(ModelParams), vp, vp]),
         "mg_force_adjoint": (ci, [vp, ci, P(ModelParams), vp, vp, vp]),

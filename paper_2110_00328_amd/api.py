@@ -173,6 +173,23 @@ class Context:
         self._check(rc, allow=(L.MG_ENOCONV,) if allow_noconv else ())
         return out, st
 
+    def solve_noalloc(self, model, params, delta, out, field_in=None, tol=1e-6, opts=None,
+                      allow_noconv=False):
+        """mg_solve_noalloc: the same solve with its workspace in the library's
+        static device array (n <= 64); out (float64, n^3) is caller-provided."""
+        _need(delta, torch.float32, self._grid(), "delta")
+        if field_in is not None:
+            _need(field_in, torch.float64, self._grid(), "field_in")
+        _need(out, torch.float64, self._grid(), "field_out")
+        opts = opts if opts is not None else solver_opts()
+        st = L.Stats()
+        rc = self.lib.mg_solve_noalloc(self.ptr, model_id(model), ctypes.byref(params),
+                                       ctypes.byref(opts), _p(delta),
+                                       _p(field_in) if field_in is not None else None, _p(out),
+                                       tol, ctypes.byref(st))
+        self._check(rc, allow=(L.MG_ENOCONV,) if allow_noconv else ())
+        return out, st
+
     def residual(self, model, params, delta, field, d_out=None):
         _need(delta, torch.float32, self._grid(), "delta")
         _need(field, torch.float64, self._grid(), "field")

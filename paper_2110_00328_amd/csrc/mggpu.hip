@@ -87,6 +87,9 @@ struct mg_ctx {
   // method; another value forces the divergence path from the host in tests;
   // MGGPU_TEST_CORRECTION_SCALE overrides it at context creation)
   float test_escale = 1.0f;
+  // set while mg_solve_noalloc runs on the static scratch array: any device
+  // allocation is then an error instead
+  bool noalloc = false;
   // device facts for the cooperative batched launch, queried once (property
   // queries cost milliseconds per call): CU count, cooperative support, and
   // resident workgroups per CU for each workgroup size (index log2(BS) - 8)
@@ -201,6 +204,10 @@ int fail(mg_ctx* c, int code, const std::string& msg) {
 
 template <typename T>
 int dalloc(mg_ctx* ctx, T** p, int64_t count) {
+  if (ctx->noalloc) {
+    *p = nullptr;
+    return fail(ctx, MG_EHIP, "device allocation requested inside mg_solve_noalloc");
+  }
   void* q = nullptr;
   hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
   if (e != hipSuccess) {
@@ -2106,6 +2113,109 @@ int dispatch_solve(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const 
   return solve64<M>(ctx, C, o, delta, fin, fout, tol, st);
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free solve: the workspace of one n^3 solve (both precisions, so
+// the refined mode's FP64 fallback needs nothing more, and the reduction
+// partials) lives in one static device array per GPU.  In host code
+// 'scratch' names a host-side stand-in: its device address on the current
+// GPU comes from hipGetSymbolAddress, looked up once per device.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_at[kMaxDevices] = {};
+
+int scratch_base(mg_ctx* ctx, char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(ctx, MG_EHIP, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_at[dev] = (char*)p;
+  }
+  *out = g_scratch_at[dev];
+  return MG_OK;
+}
+
+// Carves the workspace of ctx's level pyramid from base (the same roles as
+// ensure32 and ensure64 allocate) and returns the bytes it takes; with base
+// null it only counts.
+struct NoallocWork {
+  Work32 w32;
+  Work64 w64;
+  double *part = nullptr, *part2 = nullptr, *part3 = nullptr, *scal = nullptr;
+};
+size_t noalloc_layout(const mg_ctx* ctx, char* base, NoallocWork* W) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? (void*)(base + off) : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  W->part = (double*)take(sizeof(double) * (size_t)ctx->part_cap);
+  W->part2 = (double*)take(sizeof(double) * 256);
+  W->part3 = (double*)take(sizeof(double) * (size_t)ctx->part_cap);
+  W->scal = (double*)take(sizeof(double) * 16);
+  const size_t m0 = (size_t)cells(ctx->L[0]);
+  W->w32.wbuf[0] = (double*)take(8 * m0);
+  W->w32.wbuf[1] = (double*)take(8 * m0);
+  W->w32.ebuf[1] = (float*)take(4 * m0);
+  W->w32.w = W->w32.wbuf[0];
+  W->w64.dens0 = (float*)take(4 * m0);
+  for (int l = 0; l < ctx->nlev; ++l) {
+    const size_t m = (size_t)cells(ctx->L[l]);
+    W->w32.e[l] = (float*)take(4 * m);
+    W->w32.X[l] = (float*)take(4 * m);
+    W->w32.rho[l] = (float*)take(4 * m);
+    W->w32.dens[l] = (float*)take(4 * m);
+    if (l > 0) W->w32.eR[l] = (float*)take(4 * m);
+    W->w64.v[l] = (double*)take(8 * m);
+    if (l > 0) {
+      W->w64.dens[l] = (double*)take(8 * m);
+      W->w64.S[l] = (double*)take(8 * m);
+      W->w64.Rv[l] = (double*)take(8 * m);
+    }
+  }
+  W->w32.ebuf[0] = W->w32.e[0];
+  return off;
+}
+
+// Points ctx's workspace at the scratch array for one call and restores the
+// context's own (allocated or not) afterwards.
+struct NoallocScope {
+  mg_ctx* c;
+  Work32 w32;
+  Work64 w64;
+  bool h32, h64;
+  double *part, *part2, *part3, *scal;
+  NoallocScope(mg_ctx* x, const NoallocWork& W)
+      : c(x), w32(x->w32), w64(x->w64), h32(x->have32), h64(x->have64), part(x->part),
+        part2(x->part2), part3(x->part3), scal(x->scal) {
+    c->w32 = W.w32;
+    c->w64 = W.w64;
+    c->have32 = c->have64 = true;
+    c->part = W.part;
+    c->part2 = W.part2;
+    c->part3 = W.part3;
+    c->scal = W.scal;
+    c->noalloc = true;
+  }
+  ~NoallocScope() {
+    c->w32 = w32;
+    c->w64 = w64;
+    c->have32 = h32;
+    c->have64 = h64;
+    c->part = part;
+    c->part2 = part2;
+    c->part3 = part3;
+    c->scal = scal;
+    c->noalloc = false;
+  }
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2260,6 +2370,24 @@ int mg_solve(mg_ctx* ctx, int model, const mg_model_params* params, const mg_sol
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return rc;
+}
+
+int mg_solve_noalloc(mg_ctx* ctx, int model, const mg_model_params* params,
+                     const mg_solver_opts* opts, const float* delta, const double* field_in,
+                     double* field_out, double tol, mg_stats* stats) {
+  if (!ctx) return MG_EINVAL;
+  ACHK(check_opts(ctx, opts));
+  NoallocWork W;
+  const size_t need = noalloc_layout(ctx, nullptr, &W);
+  if (need > kScratchBytes)
+    return fail(ctx, MG_EINVAL, "mg_solve_noalloc: an n^3 solve needs " + std::to_string(need) +
+                                    " bytes of workspace; the scratch array holds " +
+                                    std::to_string(kScratchBytes) + " (n <= 64)");
+  char* base = nullptr;
+  ACHK(scratch_base(ctx, &base));
+  noalloc_layout(ctx, base, &W);
+  NoallocScope scope(ctx, W);
+  return mg_solve(ctx, model, params, opts, delta, field_in, field_out, tol, stats);
 }
 
 int mg_residual(mg_ctx* ctx, int model, const mg_model_params* params, const float* delta,
