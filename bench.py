@@ -13,7 +13,7 @@ the background field.  value = grid cells per second through the step.
 Also reported: the plain FP64 GPU step at the same tolerances, the
 roofline of the dominant kernel (FP32 finest-level smoother half-sweep,
 timed with HIP events on the solve's stream over the timed steps; its
-algorithmic bytes are 12 per updated cell, beside the 16 this layout moves),
+algorithmic bytes are 12 per updated cell),
 and the FP64 CPU oracle on the same 512^3 pipeline on all of this machine's
 host threads, plus a 192^3 box on one thread.
 """
@@ -31,15 +31,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # per updated cell of a half-sweep: read the other colour's field and the
 # cell's coefficient, write the cell (4 + 4 + 4).
 FP32_SMOOTH_BYTES_PER_CELL = 12.0
-# What this library's correction-form smoother must move per updated cell:
-# linearisation point X, right-hand side rho, the other colour's correction,
-# the written correction (4 + 4 + 4 + 4).
-FP32_SMOOTH_LAYOUT_BYTES_PER_CELL = 16.0
+# This library's correction-form smoother moves exactly that: the
+# linearisation point X and the right-hand side rho in 16-bit floats, the
+# other colour's FP32 correction, the written correction (2 + 2 + 4 + 4).
 # HBM bytes per finest-level launch of that kernel at 512^3, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE (scaled x2.0 and x1.0 by a 1 GiB copy):
-# profiles/k_smooth_corr_v_fr512_hbm_traffic.md.  Set to None whenever the
-# kernel changes, until the counters are taken again.
-FP32_SMOOTH_TRAFFIC_512 = 1082.3e6
+# FETCH_SIZE and WRITE_SIZE (scaled by a plain copy of known size).  Set to
+# None whenever the kernel changes, until the counters are taken again.
+FP32_SMOOTH_TRAFFIC_512 = None
 
 
 def parse():
@@ -383,8 +381,6 @@ def main():
     avg = sm_ms / max(sm_n, 1)
     bytes_per_launch = FP32_SMOOTH_BYTES_PER_CELL * (m / 2)
     achieved = bytes_per_launch / (avg * 1e-3) / 1e9 if sm_n else None
-    layout_bytes = FP32_SMOOTH_LAYOUT_BYTES_PER_CELL * (m / 2)
-    layout_gbs = layout_bytes / (avg * 1e-3) / 1e9 if sm_n else None
     out = {
         "metric": "512^3 f(R) MG solve to 1e-6 resid: FP32+adjoint vs FP64 time; % HBM peak",
         "value": m / (ms * 1e-3),
@@ -411,13 +407,10 @@ def main():
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": FP32_SMOOTH_TRAFFIC_512 if n == 512 else None,
                      "traffic_unit": "bytes per launch (HBM, counted)",
-                     "kernel": "k_smooth_corr<FR> (finest-level FP32 half-sweep)",
+                     "kernel": "k_smooth_corr_kv<FR, h16, h16> (finest-level FP32 half-sweep)",
                      "avg_launch_ms": avg, "launches": sm_n,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "algorithmic_bytes_per_cell": FP32_SMOOTH_BYTES_PER_CELL,
-                     "layout_bytes_per_launch": layout_bytes,
-                     "layout_GBps": layout_gbs,
-                     "layout_frac": (layout_gbs / HBM_PEAK_GBS) if layout_gbs else None},
+                     "algorithmic_bytes_per_cell": FP32_SMOOTH_BYTES_PER_CELL},
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baselines(a, tol)

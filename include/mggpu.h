@@ -110,9 +110,13 @@ typedef struct mg_ctx mg_ctx;
  * workspace is allocated on first use of each mode and kept until destroy.
  * The environment variable MGGPU_MARCH_MIN_BLOCKS, read here, sets from how
  * many workgroups up the residual/restriction kernels march in z (default
- * 2048; the results are identical either way), and MGGPU_SMOOTH_MARCH_KT
- * (1..64) switches the level-0 FP32 smoother to a z-marching form with that
- * many planes per thread (default off; identical results).  MGGPU_CIC_DIRECT=1
+ * 2048; the results are identical either way), MGGPU_SMOOTH_MARCH_KT sets
+ * the planes per thread of the z-marching FP32 smoother used on large levels
+ * (default 4; 0 selects the per-row form; identical results), and
+ * MGGPU_FP16_STORAGE=0 keeps the finest level's X and rho of the
+ * FP32-refined solve in FP32 instead of 16-bit floats (default 1; n % 8 == 0
+ * grids; changes rounding inside the FP32 correction cycles only, the FP64
+ * residual and the solution's tolerance are unaffected).  MGGPU_CIC_DIRECT=1
  * makes cic_assign always take its direct atomic path (identical results).
  * Returns MG_EINVAL for a bad n or NULL out. */
 int mg_ctx_create(mg_ctx **out, int n, void *hip_stream);

@@ -43,6 +43,10 @@ struct Consts {
   double bg_coef;  // |d| at the background per unit delta
   // FP32 copies used by the correction-form kernels
   float f_ct2, f_kw, f_s_ratio, f_s_amp, f_beta, f_alpha, f_phibar, f_cq_src, f_cq_pot;
+  float f_i6ct2;     // 1 / (6 c~^2)
+  float f_ict2;      // 1 / c~^2
+  float f_isamp;     // 1 / s_amp
+  float f_ct2_samp;  // c~^2 / s_amp
 };
 
 // ---------------------------------------------------------------------------
@@ -74,6 +78,16 @@ __device__ __forceinline__ double d_pow(double x, double y) { return pow(x, y); 
 __device__ __forceinline__ float d_pow(float x, float y) { return powf(x, y); }
 __device__ __forceinline__ double d_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float d_rsqrt(float x) { return rsqrtf(x); }
+
+// Hardware FP32 reciprocal, square root and reciprocal square root (single
+// instructions, about 1 ulp) for the correction-form arithmetic, whose
+// per-cell results are polished by Newton steps and whose FP32 inner
+// problem only has to shrink the FP64-computed residual: the library's
+// correctly rounded forms cost ten or more instructions each.
+__device__ __forceinline__ float f_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float f_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float f_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float f_div(float a, float b) { return a * f_rcp(b); }
 
 // Root of t^3 + p t + q = 0 on the branch the paper's closed forms select:
 // the single real root, else the largest of three (for q < 0: the unique
@@ -117,24 +131,24 @@ __device__ __forceinline__ float cubic_root_approx(float p, float q) {
     float c = a > 0.0f ? __expf(__logf(a) * (1.0f / 3.0f)) : 0.0f;
     return q > 0.0f ? -c : c;
   }
-  float s = sqrtf(fabsf(p) * (1.0f / 3.0f));
-  float x = __fdividef(1.5f * q, p * s);
+  float s = f_sqrt(fabsf(p) * (1.0f / 3.0f));
+  float x = f_div(1.5f * q, p * s);
   float ax = fabsf(x);
   if (p > 0.0f) {
     float y;
     if (ax < 1e-3f) {
       y = ax * (1.0f / 3.0f);
     } else {
-      float L = ax > 1e18f ? __logf(2.0f * ax) : __logf(ax + sqrtf(ax * ax + 1.0f));
+      float L = ax > 1e18f ? __logf(2.0f * ax) : __logf(ax + f_sqrt(ax * ax + 1.0f));
       float t = __expf(L * (1.0f / 3.0f));
-      y = 0.5f * (t - __frcp_rn(t));
+      y = 0.5f * (t - f_rcp(t));
     }
     return -2.0f * s * copysignf(y, x);
   }
   if (ax >= 1.0f) {
-    float L = ax > 1e18f ? __logf(2.0f * ax) : __logf(ax + sqrtf(ax * ax - 1.0f));
+    float L = ax > 1e18f ? __logf(2.0f * ax) : __logf(ax + f_sqrt(ax * ax - 1.0f));
     float t = __expf(L * (1.0f / 3.0f));
-    float y = 0.5f * (t + __frcp_rn(t));
+    float y = 0.5f * (t + f_rcp(t));
     return copysignf(2.0f * s * y, x);
   }
   return 2.0f * s * __cosf(acosf(x) * (1.0f / 3.0f));
@@ -287,11 +301,12 @@ __device__ __forceinline__ float log1p_small(float z) {
 // factor only); the differences use expm1_small / log1p_small.
 __device__ __forceinline__ void cq_corr_terms(const Consts& C, float x, float e, float dc,
                                               float* dn, float* dnp) {
-  const float ict2 = 1.0f / C.f_ct2;
+  const float ict2 = C.f_ict2;
   const float a1 = 1.0f + C.f_alpha;
   const float Y = C.f_phibar + x * ict2;
+  const float iY = f_rcp(Y);
   const float PX = __expf(-a1 * __logf(Y));  // Y^{-(1+alpha)}
-  const float u = e * ict2 / Y;
+  const float u = e * ict2 * iY;
   const float E2 = expm1_small(-a1 * log1p_small(u));
   float src = 0.0f, dsrc = 0.0f;
   if (C.cq_keep_exp) {
@@ -301,7 +316,7 @@ __device__ __forceinline__ void cq_corr_terms(const Consts& C, float x, float e,
     dsrc = C.f_beta * ict2 * ex * (1.0f + E1);
   }
   *dn = -C.f_cq_src * src + C.f_cq_pot * PX * E2;
-  *dnp = -C.f_cq_src * dsrc - C.f_cq_pot * a1 * ict2 * (PX / Y) * (1.0f + E2) / (1.0f + u);
+  *dnp = -C.f_cq_src * dsrc - C.f_cq_pot * a1 * ict2 * (PX * iY) * (1.0f + E2) * f_rcp(1.0f + u);
 }
 
 // Nonlinear part N(x+e) - N(x) of each model, accurate relative to e.
@@ -312,14 +327,15 @@ __device__ __forceinline__ float corr_nl(const Consts& C, float e, float x, floa
     // t = e/x, A = K wbar^m x^{-m}; written without cancellation:
     //   n = 0: A t/(1+t);  n = 1: A t/(s(1+s)), s = sqrt(1+t);
     //   n = 2: A t/(c(c^2+c+1)), c = cbrt(1+t)
-    float t = e / x;
+    float ix = f_rcp(x);
+    float t = e * ix;
     if (C.fr_n == 1) {
-      float s = sqrtf(1.0f + t);
-      return C.f_kw * rsqrtf(x) * t / (s * (1.0f + s));
+      float s = f_sqrt(1.0f + t);
+      return C.f_kw * f_rsq(x) * t * f_rcp(s * (1.0f + s));
     }
-    if (C.fr_n == 0) return C.f_kw / x * t / (1.0f + t);
+    if (C.fr_n == 0) return C.f_kw * ix * t * f_rcp(1.0f + t);
     float c = cbrtf(1.0f + t);
-    return C.f_kw / cbrtf(x) * t / (c * ((c + 1.0f) * c + 1.0f));
+    return C.f_kw * f_rcp(cbrtf(x)) * t * f_rcp(c * ((c + 1.0f) * c + 1.0f));
   } else if constexpr (M == SYM) {
     // -s_amp [ (rho a*^3/a^3 - 1 + 3x^2) e + 3x e^2 + e^3 ]
     float m = (1.0f + dc) * C.f_s_ratio - 1.0f + 3.0f * x * x;
@@ -336,7 +352,7 @@ __device__ __forceinline__ float corr_nl(const Consts& C, float e, float x, floa
 template <int M>
 __device__ __forceinline__ float corr_G(const Consts& C, float h2, float ec, float sum, float x,
                                         float dc) {
-  float lap = (sum - 6.0f * ec) / h2;
+  float lap = (sum - 6.0f * ec) * (1.0f / h2);  // h2 = 4^l: exact
   if constexpr (M == FR) return -C.f_ct2 * lap + corr_nl<M>(C, ec, x, dc);
   else if constexpr (M == SYM) return C.f_ct2 * lap + corr_nl<M>(C, ec, x, dc);
   else return lap + corr_nl<M>(C, ec, x, dc);
@@ -353,15 +369,15 @@ __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec
     //   (1+sigma)^{n+2} - 1 + (beta - 1 - gamma) sigma - gamma = 0,
     //   whose linear coefficient is c1 = n + 1 + beta - gamma.
     const int n = C.fr_n;
-    float iD = h2 * (1.0f / 6.0f) / C.f_ct2;  // h^2 / (6 c^2), a level constant
-    float ix = __frcp_rn(x);
-    float xm = n == 1 ? ix * sqrtf(ix) : (n == 0 ? ix * ix : ix * cbrtf(ix));  // x^{-(m+1)}
+    float iD = h2 * C.f_i6ct2;  // h^2 / (6 c^2), a level constant
+    float ix = f_rcp(x);
+    float xm = n == 1 ? ix * f_rsq(x) : (n == 0 ? ix * ix : ix * cbrtf(ix));  // x^{-(m+1)}
     float beta = C.f_kw * iD * xm;
     float gamma = (rho * iD + sum * (1.0f / 6.0f)) * ix;
     float c1 = float(n + 1) + beta - gamma;
     float sg;
     if (fabsf(gamma) < 1e-2f * c1) {
-      sg = __fdividef(gamma, c1);  // small correction: linear guess, Newton below
+      sg = f_div(gamma, c1);  // small correction: linear guess, Newton below
     } else if (n == 1) {
       sg = cubic_root_approx(beta - 1.0f - gamma, -beta) - 1.0f;
     } else if (n == 0) {
@@ -374,7 +390,7 @@ __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec
       for (int it = 0; it < 2; ++it) {
         float f = ((sg + 3.0f) * sg + c1) * sg - gamma;
         float fp = (3.0f * sg + 6.0f) * sg + c1;
-        sg -= __fdividef(f, fp);
+        sg -= f_div(f, fp);
       }
       return x * sg * (sg + 2.0f);
     }
@@ -383,7 +399,7 @@ __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec
       for (int it = 0; it < 2; ++it) {
         float f = (sg + c1) * sg - gamma;
         float fp = 2.0f * sg + c1;
-        sg -= __fdividef(f, fp);
+        sg -= f_div(f, fp);
       }
       return x * sg;
     }
@@ -391,18 +407,18 @@ __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec
     for (int it = 0; it < 2; ++it) {
       float f = (((sg + 4.0f) * sg + 6.0f) * sg + c1) * sg - gamma;
       float fp = ((4.0f * sg + 12.0f) * sg + 12.0f) * sg + c1;
-      sg -= __fdividef(f, fp);
+      sg -= f_div(f, fp);
     }
     return x * sg * ((sg + 3.0f) * sg + 3.0f);
   } else if constexpr (M == SYM) {
     // e^3 + 3x e^2 + P e + Q = 0, P = m + 6 kap, Q = rho/s_amp - kap sum,
     // m = (1+delta) a*^3/a^3 - 1 + 3x^2, kap = c^2/(s_amp h^2)
-    float kap = C.f_ct2 / (C.f_s_amp * h2);
+    float kap = C.f_ct2_samp * (1.0f / h2);
     float P = (1.0f + dc) * C.f_s_ratio - 1.0f + 3.0f * x * x + 6.0f * kap;
-    float Q = rho / C.f_s_amp - kap * sum;
+    float Q = rho * C.f_isamp - kap * sum;
     float e;
     if (P > 0.0f && fabsf(Q) < 1e-2f * P * fabsf(x)) {
-      e = __fdividef(-Q, P);
+      e = f_div(-Q, P);
     } else {
       // total field y = x + e solves y^3 + p y + q = 0 (paper's branch)
       float p = P - 3.0f * x * x;
@@ -413,17 +429,64 @@ __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec
     for (int it = 0; it < 2; ++it) {
       float g = ((e + 3.0f * x) * e + P) * e + Q;
       float gp = (3.0f * e + 6.0f * x) * e + P;
-      if (gp != 0.0f) e -= g / gp;
+      if (gp != 0.0f) e -= f_div(g, gp);
     }
     return e;
   } else {
     // Newton-Gauss-Seidel (eq:relaxation_iteration) on the correction
     float dn, dnp;
     cq_corr_terms(C, x, ec_old, dc, &dn, &dnp);
-    float G = (sum - 6.0f * ec_old) / h2 + dn - rho;
-    float dG = -6.0f / h2 + dnp;
-    return ec_old - G / dG;
+    const float ih2 = 1.0f / h2;  // h2 = 4^l: exact
+    float G = (sum - 6.0f * ec_old) * ih2 + dn - rho;
+    float dG = -6.0f * ih2 + dnp;
+    return ec_old - f_div(G, dG);
   }
+}
+
+// Four consecutive cells of corr_update.  f(R) n = 1, the hot case, takes
+// all four through the same steps so that the common small-correction path
+// has no per-cell branch: every cell gets the linear guess, the closed-form
+// start replaces it only where the correction is large, then all four take
+// the two Newton steps together.  Same arithmetic as corr_update.
+template <int M>
+__device__ __forceinline__ void corr_update4(const Consts& C, float h2, const float* eo,
+                                             const float* sum, const float* x, const float* dc,
+                                             const float* rho, float* out) {
+  if constexpr (M == FR) {
+    if (C.fr_n == 1) {
+      const float iD = h2 * C.f_i6ct2;
+      float gamma[4], c1[4], sg[4], beta[4];
+      bool big = false;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float ix = f_rcp(x[q]);
+        beta[q] = C.f_kw * iD * (ix * f_rsq(x[q]));
+        gamma[q] = (rho[q] * iD + sum[q] * (1.0f / 6.0f)) * ix;
+        c1[q] = 2.0f + beta[q] - gamma[q];
+        sg[q] = f_div(gamma[q], c1[q]);
+        big |= !(fabsf(gamma[q]) < 1e-2f * c1[q]);
+      }
+      if (big) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (!(fabsf(gamma[q]) < 1e-2f * c1[q]))
+            sg[q] = cubic_root_approx(beta[q] - 1.0f - gamma[q], -beta[q]) - 1.0f;
+      }
+#pragma unroll
+      for (int it = 0; it < 2; ++it)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float f = ((sg[q] + 3.0f) * sg[q] + c1[q]) * sg[q] - gamma[q];
+          const float fp = (3.0f * sg[q] + 6.0f) * sg[q] + c1[q];
+          sg[q] -= f_div(f, fp);
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[q] = x[q] * sg[q] * (sg[q] + 2.0f);
+      return;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = corr_update<M>(C, h2, eo[q], sum[q], x[q], dc[q], rho[q]);
 }
 
 // d G_c / d e_c (diagonal of the correction operator; used by the uniform-

@@ -222,6 +222,42 @@ __device__ __forceinline__ void stn_nt(T* __restrict__ p, const T* in) {
     for (int c = 0; c < N / P; ++c) stv_nt<T>(p + c * P, in + c * P);
   }
 }
+// ---------------------------------------------------------------------------
+// Storage of the finest level's per-cell data of the correction problem (the
+// linearisation point X and the right-hand side rho): FP32, or 16-bit floats
+// with a power-of-two scale (enc on the way in, dec = 1/enc on the way out).
+// The kernels that read them decode identically, so the FP32 inner problem
+// is exactly the correction equation at the decoded X; the FP64 outer
+// residual is computed from the FP64 field and does not see the rounding.
+// ---------------------------------------------------------------------------
+typedef _Float16 h16;
+typedef _Float16 nt_h4 __attribute__((ext_vector_type(4)));
+struct Store {
+  float x_enc, x_dec;  // X: f(R) 1024/wbar, symmetron 1024 (unused for FP32)
+  float r_enc, r_dec;  // rho: 2^s chosen per outer step (unused for FP32)
+};
+// 4 consecutive stored cells -> float (streaming load)
+template <typename TS>
+__device__ __forceinline__ void ld4s(const TS* __restrict__ p, float dec, float* out) {
+  if constexpr (sizeof(TS) == 4) {
+    ldv_nt<float>(reinterpret_cast<const float*>(p), out);
+  } else {
+    const nt_h4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_h4*>(p));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = float(v[q]) * dec;
+  }
+}
+// float -> 4 consecutive stored cells (streaming store)
+template <typename TS>
+__device__ __forceinline__ void st4s(TS* __restrict__ p, const float* in, float enc) {
+  if constexpr (sizeof(TS) == 4) {
+    stv_nt<float>(reinterpret_cast<float*>(p), in);
+  } else {
+    const nt_h4 v = {h16(in[0] * enc), h16(in[1] * enc), h16(in[2] * enc), h16(in[3] * enc)};
+    __builtin_nontemporal_store(v, reinterpret_cast<nt_h4*>(p));
+  }
+}
+
 // Neighbour sums of the V cells (ih0 .. ih0+V-1, j, k) of colour c from the
 // other colour's array o; s = (j + k + c) & 1.  Same summation order as nbsum.
 template <typename T, int V = Vec<T>::V>
@@ -275,6 +311,28 @@ __device__ __forceinline__ double block_sum_all(double v, double* sh) {
   if (threadIdx.x == 0) sh[16] = t;
   __syncthreads();
   return sh[16];
+}
+// Maximum over the block (v >= 0); result valid in thread 0.
+__device__ __forceinline__ double block_max(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int q = 1; q < nw; ++q) v = fmax(v, sh[q]);
+  }
+  return v;
+}
+// Maximum of m partial maxima (one block)
+__global__ void k_max_partials(const double* __restrict__ part, int64_t m, double* out) {
+  __shared__ double sh[32];
+  double v = 0.0;
+  for (int64_t q = threadIdx.x; q < m; q += blockDim.x) v = fmax(v, part[q]);
+  v = block_max(v, sh);
+  if (threadIdx.x == 0) *out = v;
 }
 
 // stage 1: block b sums the contiguous chunk [b*chunk, (b+1)*chunk)
@@ -714,13 +772,13 @@ __global__ __launch_bounds__(kBlock) void k_smooth_direct_v(Lev L, double* v, co
 // fresh: first half-sweeps after an outer step, whose correction starts at
 // zero: the buffer is not cleared, the old values are taken as 0 instead
 // (colour 0: neighbours and own value; colour 1: own value).
-template <int M>
+template <int M, typename TX = float, typename TR = float>
 __device__ __forceinline__ void op_smooth_corr_v(const Lev& L, float* __restrict__ e,
-                                                 const float* __restrict__ X,
+                                                 const TX* __restrict__ X,
                                                  const float* __restrict__ dens,
-                                                 const float* __restrict__ rho, int colour,
+                                                 const TR* __restrict__ rho, int colour,
                                                  float h2, const Consts& C, uint32_t g4,
-                                                 int fresh = 0) {
+                                                 int fresh = 0, Store S = Store{1, 1, 1, 1}) {
   constexpr int V = Vec<float>::V;
   uint32_t g = g4 * V;
   int ih0, j, k;
@@ -730,22 +788,21 @@ __device__ __forceinline__ void op_smooth_corr_v(const Lev& L, float* __restrict
   uint32_t q0 = (uint32_t)colour * (uint32_t)L.half + g;
   float sum[V] = {0, 0, 0, 0}, x[V], r[V], dc[V] = {0, 0, 0, 0}, eo[V] = {0, 0, 0, 0}, out[V];
   if (!(fresh && colour == 0)) nbsum_vec<float>(L, e + (1 - colour) * L.half, ih0, j, k, s, sum);
-  ldv_nt<float>(X + q0, x);
-  ldv_nt<float>(rho + q0, r);
+  ld4s<TX>(X + q0, S.x_dec, x);
+  ld4s<TR>(rho + q0, S.r_dec, r);
   if (M != FR) ldv_nt<float>(dens + q0, dc);
   if (M == CQ && !fresh) ldv<float>(own + g, eo);
-#pragma unroll
-  for (int q = 0; q < V; ++q) out[q] = corr_update<M>(C, h2, eo[q], sum[q], x[q], dc[q], r[q]);
+  corr_update4<M>(C, h2, eo, sum, x, dc, r, out);
   stv_nt<float>(own + g, out);
 }
-template <int M>
-__global__ __launch_bounds__(kBlock) void k_smooth_corr_v(Lev L, float* e, const float* X,
-                                                          const float* dens, const float* rho,
+template <int M, typename TX = float, typename TR = float>
+__global__ __launch_bounds__(kBlock) void k_smooth_corr_v(Lev L, float* e, const TX* X,
+                                                          const float* dens, const TR* rho,
                                                           int colour, float h2, Consts C,
-                                                          int fresh) {
+                                                          int fresh, Store S = Store{1, 1, 1, 1}) {
   uint32_t g4 = (uint32_t)gid();
   if (g4 < (uint32_t)(L.half / Vec<float>::V))
-    op_smooth_corr_v<M>(L, e, X, dens, rho, colour, h2, C, g4, fresh);
+    op_smooth_corr_v<M, TX, TR>(L, e, X, dens, rho, colour, h2, C, g4, fresh, S);
 }
 
 template <typename T>
@@ -770,7 +827,10 @@ __global__ __launch_bounds__(kBlock) void k_smooth_lin_v(Lev L, T* e, const T* d
   ldv_nt<T>(dg + q0, d);
   ldv_nt<T>(r + q0, rr);
 #pragma unroll
-  for (int q = 0; q < V; ++q) out[q] = (rr[q] + kh2 * sum[q]) / (T(6) * kh2 + d[q]);
+  for (int q = 0; q < V; ++q) {
+    if constexpr (sizeof(T) == 4) out[q] = (rr[q] + kh2 * sum[q]) * f_rcp(T(6) * kh2 + d[q]);
+    else out[q] = (rr[q] + kh2 * sum[q]) / (T(6) * kh2 + d[q]);
+  }
   stv_nt<T>(e + q0, out);
 }
 
@@ -824,11 +884,12 @@ __host__ __device__ inline unsigned march_blocks(const Lev& L, int kt, int V) {
 // (j, k-1), (j, k), (j, k+1) in registers, so each plane reads one new
 // other-colour row plus the rows j +- 1.  Per-cell arithmetic and the
 // neighbour summation order are those of op_smooth_corr_v (bit-identical).
-template <int M>
-__global__ __launch_bounds__(kBlock) void k_smooth_corr_kv(Lev L, float* e, const float* X,
-                                                           const float* dens, const float* rho,
+template <int M, typename TX = float, typename TR = float>
+__global__ __launch_bounds__(kBlock) void k_smooth_corr_kv(Lev L, float* e, const TX* X,
+                                                           const float* dens, const TR* rho,
                                                            int colour, float h2, Consts C,
-                                                           int fresh, int kt) {
+                                                           int fresh, int kt,
+                                                           Store S = Store{1, 1, 1, 1}) {
   constexpr int V = Vec<float>::V;
   const MarchPos P = march_pos(L, kt, V);
   if (!P.ok) return;
@@ -865,12 +926,11 @@ __global__ __launch_bounds__(kBlock) void k_smooth_corr_kv(Lev L, float* e, cons
     }
     const uint32_t q0 = (uint32_t)colour * (uint32_t)L.half + r + (uint32_t)ih0;
     float x[V], rr[V], dc[V] = {0, 0, 0, 0}, eo[V] = {0, 0, 0, 0}, out[V];
-    ldv_nt<float>(X + q0, x);
-    ldv_nt<float>(rho + q0, rr);
+    ld4s<TX>(X + q0, S.x_dec, x);
+    ld4s<TR>(rho + q0, S.r_dec, rr);
     if (M != FR) ldv_nt<float>(dens + q0, dc);
     if (M == CQ && !fresh) ldv<float>(own + r + ih0, eo);
-#pragma unroll
-    for (int q = 0; q < V; ++q) out[q] = corr_update<M>(C, h2, eo[q], sum[q], x[q], dc[q], rr[q]);
+    corr_update4<M>(C, h2, eo, sum, x, dc, rr, out);
     stv_nt<float>(own + r + ih0, out);
 #pragma unroll
     for (int q = 0; q < V; ++q) {
@@ -924,20 +984,24 @@ __device__ __forceinline__ void march_nbsum(const Lev& L, const double* __restri
     sum[q] = (xv[q] + xv[q + 1]) + (ym[q] + yp[q]) + (wo[0][q] + wo[2][q]);
 }
 
-template <int M>
+template <int M, typename TX = float, typename TR = float>
 __global__ __launch_bounds__(kBlock) void k_outer_fused_kv(Lev L, const double* __restrict__ w,
                                                            const float* __restrict__ e,
                                                            double* __restrict__ w_new,
                                                            const float* __restrict__ dens,
-                                                           Consts C, float* __restrict__ rho,
-                                                           float* __restrict__ X,
+                                                           Consts C, TR* __restrict__ rho,
+                                                           TX* __restrict__ X,
                                                            float* __restrict__ e_zero,
                                                            double* __restrict__ part,
-                                                           double* __restrict__ part_bg, int kt) {
+                                                           double* __restrict__ part_bg, int kt,
+                                                           Store S = Store{1, 1, 1, 1},
+                                                           double* __restrict__ part_max = nullptr) {
   constexpr int V = kVOuter;
+  static_assert(V == 4, "the stored 4-cell groups");
   __shared__ double sh[32];
   const MarchPos P = march_pos(L, kt, V);
   double acc = 0.0, accb = 0.0;  // sum d^2; sum (bg_coef delta)^2 when part_bg is given
+  double amax = 0.0;             // max |d| when part_max is given
   if (P.ok) {
     double win[2][3][V];  // [colour][plane k-1, k, k+1][cell]
     const int km0 = P.k0 == 0 ? L.n - 1 : P.k0 - 1;
@@ -968,12 +1032,13 @@ __global__ __launch_bounds__(kBlock) void k_outer_fused_kv(Lev L, const double* 
             const double bd = C.bg_coef * double(dn[q]);
             accb += bd * bd;
           }
+          amax = fmax(amax, fabs(d));
           ro[q] = float(-d);
           xo[q] = float(vc);
           zo[q] = 0.0f;
         }
-        stn_nt<float, V>(rho + q0, ro);
-        stn_nt<float, V>(X + q0, xo);
+        st4s<TR>(rho + q0, ro, S.r_enc);
+        st4s<TX>(X + q0, xo, S.x_enc);
         if (e_zero) stn_nt<float, V>(e_zero + q0, zo);
       }
 #pragma unroll
@@ -990,6 +1055,10 @@ __global__ __launch_bounds__(kBlock) void k_outer_fused_kv(Lev L, const double* 
   if (part_bg) {  // uniform over the grid: every thread reaches block_sum's barriers
     const double tb = block_sum(accb, sh);
     if (threadIdx.x == 0) part_bg[blockIdx.x] = tb;
+  }
+  if (part_max) {  // uniform over the grid as well
+    const double tm = block_max(amax, sh);
+    if (threadIdx.x == 0) part_max[blockIdx.x] = tm;
   }
 }
 
@@ -1298,11 +1367,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong_kv(Lev Lf, Lev Lc, T* __rest
 // correction form: Re -> eH and eR, R(G(e) - rho) -> rhoH, optionally R X -> XH.
 // skip1: colour 1 was the last half-sweep of an exact per-cell smoother, so
 // its residual vanishes (to rounding) and is not recomputed.
-template <int M>
+template <int M, typename TX = float, typename TR = float>
 __device__ __forceinline__ void op_resid_restrict_corr_v(
-    const Lev& Lf, const Lev& Lc, const float* __restrict__ e, const float* __restrict__ X,
-    const float* __restrict__ dens, const float* __restrict__ rho, float h2, float* eH, float* eR,
-    float* rhoH, float* XH, const Consts& C, int skip1, uint32_t g4) {
+    const Lev& Lf, const Lev& Lc, const float* __restrict__ e, const TX* __restrict__ X,
+    const float* __restrict__ dens, const TR* __restrict__ rho, float h2, float* eH, float* eR,
+    float* rhoH, float* XH, const Consts& C, int skip1, uint32_t g4,
+    Store S = Store{1, 1, 1, 1}) {
   constexpr int V = Vec<float>::V;
   int I0, J, K;
   dec_nat(g4 * V, Lc, I0, J, K);
@@ -1321,15 +1391,15 @@ __device__ __forceinline__ void op_resid_restrict_corr_v(
 #pragma unroll
           for (int q = 0; q < V; ++q) se[q] += ec[q];
           if (XH) {
-            ldv_nt<float>(X + q0, x);
+            ld4s<TX>(X + q0, S.x_dec, x);
 #pragma unroll
             for (int q = 0; q < V; ++q) sx[q] += x[q];
           }
           continue;
         }
         nbsum_vec<float>(Lf, e + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
-        ldv_nt<float>(X + q0, x);
-        ldv_nt<float>(rho + q0, r);
+        ld4s<TX>(X + q0, S.x_dec, x);
+        ld4s<TR>(rho + q0, S.r_dec, r);
         if (M != FR) ldv_nt<float>(dens + q0, dc);
 #pragma unroll
         for (int q = 0; q < V; ++q) {
@@ -1349,14 +1419,15 @@ __device__ __forceinline__ void op_resid_restrict_corr_v(
     if (XH) XH[pc] = sx[q] * 0.125f;
   }
 }
-template <int M>
+template <int M, typename TX = float, typename TR = float>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_v(
-    Lev Lf, Lev Lc, const float* __restrict__ e, const float* __restrict__ X,
-    const float* __restrict__ dens, const float* __restrict__ rho, float h2, float* eH, float* eR,
-    float* rhoH, float* XH, Consts C, int skip1) {
+    Lev Lf, Lev Lc, const float* __restrict__ e, const TX* __restrict__ X,
+    const float* __restrict__ dens, const TR* __restrict__ rho, float h2, float* eH, float* eR,
+    float* rhoH, float* XH, Consts C, int skip1, Store S = Store{1, 1, 1, 1}) {
   uint32_t g4 = (uint32_t)gid();
   if (g4 < (uint32_t)(2 * Lc.half / Vec<float>::V))
-    op_resid_restrict_corr_v<M>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, skip1, g4);
+    op_resid_restrict_corr_v<M, TX, TR>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, skip1,
+                                        g4, S);
 }
 
 // Residual and restriction marching in z, for exact per-cell smoothers
@@ -1431,12 +1502,12 @@ __device__ __forceinline__ RRPos rr_pos(const Lev& Lc, int kt) {
   P.K1 = P.K0 + kt < nc ? P.K0 + kt : nc;
   return P;
 }
-template <int M>
+template <int M, typename TX = float, typename TR = float>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_kv(
-    Lev Lf, Lev Lc, const float* __restrict__ e, const float* __restrict__ X,
-    const float* __restrict__ dens, const float* __restrict__ rho, float h2,
+    Lev Lf, Lev Lc, const float* __restrict__ e, const TX* __restrict__ X,
+    const float* __restrict__ dens, const TR* __restrict__ rho, float h2,
     float* __restrict__ eH, float* __restrict__ eR, float* __restrict__ rhoH,
-    float* __restrict__ XH, Consts C, int kt) {
+    float* __restrict__ XH, Consts C, int kt, Store S = Store{1, 1, 1, 1}) {
   const RRPos P = rr_pos(Lc, kt);
   if (!P.ok) return;
   const int n = Lf.n, I0 = P.I0, J = P.J;
@@ -1474,8 +1545,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_kv(
         float sum[4], ec[4], x[4], r[4], dc[4] = {0, 0, 0, 0};
         rr_nbsum<float>(Lf, o1, I0, j, k, cen, ymv, ypv, zmv, zpv, sum);
         ldn<float, 4>(e + q0, ec);
-        ldn_nt<float, 4>(X + q0, x);
-        ldn_nt<float, 4>(rho + q0, r);
+        ld4s<TX>(X + q0, S.x_dec, x);
+        ld4s<TR>(rho + q0, S.r_dec, r);
         if (M != FR) ldn_nt<float, 4>(dens + q0, dc);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -1487,7 +1558,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_kv(
 #pragma unroll
         for (int q = 0; q < 4; ++q) se[q] += cen[q];
         if (XH) {
-          ldn_nt<float, 4>(X + Lf.half + q0, x);
+          ld4s<TX>(X + Lf.half + q0, S.x_dec, x);
 #pragma unroll
           for (int q = 0; q < 4; ++q) sx[q] += x[q];
         }

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -52,6 +53,8 @@ struct Work32 {  // FP32 correction mode
   float* rho[kMaxLev] = {};
   float* dens[kMaxLev] = {};
   float* eR[kMaxLev] = {};
+  h16* X16 = nullptr;          // level-0 X in 16 bits (when the context stores 16-bit data)
+  h16* R16 = nullptr;          // level-0 rho in 16 bits
 };
 template <typename T>
 struct WorkLin {  // adjoint linear multigrid in precision T
@@ -80,9 +83,11 @@ struct mg_ctx {
   // workgroups up (below it a grid is too sparse to hide the march);
   // MGGPU_MARCH_MIN_BLOCKS overrides it at context creation
   unsigned march_min_blocks = 2048;
-  // planes per thread of the z-marching level-0 FP32 smoother (0: the
-  // per-row kernel); MGGPU_SMOOTH_MARCH_KT overrides it at context creation
-  int smooth_march_kt = 0;
+  // planes per thread of the z-marching FP32 smoother on large levels (0:
+  // the per-row kernel); 4 was fastest with 16-bit X and rho at 512^3
+  // (164 us per half-sweep against 175 per row; 2, 8, 16: 171, 169, 171);
+  // MGGPU_SMOOTH_MARCH_KT overrides it at context creation
+  int smooth_march_kt = 4;
   // scale applied to each FP32 correction before the FP64 update (1: the
   // method; another value forces the divergence path from the host in tests;
   // MGGPU_TEST_CORRECTION_SCALE overrides it at context creation)
@@ -90,6 +95,15 @@ struct mg_ctx {
   // set while mg_solve_noalloc runs on the static scratch array: any device
   // allocation is then an error instead
   bool noalloc = false;
+  // finest-level X and rho of the FP32-refined solve in 16-bit floats
+  // (MGGPU_FP16_STORAGE=0 at context creation keeps them in FP32)
+  bool fp16 = true;
+  // storage of level 0 in the current outer step of the refined solve
+  struct {
+    bool x16 = false, r16 = false;
+    Store S{1.0f, 1.0f, 1.0f, 1.0f};
+  } s0;
+  double* part4 = nullptr;     // block maxima (same capacity as part)
   // device facts for the cooperative batched launch, queried once (property
   // queries cost milliseconds per call): CU count, cooperative support, and
   // resident workgroups per CU for each workgroup size (index log2(BS) - 8)
@@ -260,6 +274,8 @@ int ensure32(mg_ctx* ctx) {
     ACHK(dalloc(ctx, &W.dens[l], m));
     if (l > 0) ACHK(dalloc(ctx, &W.eR[l], m));
   }
+  ACHK(dalloc(ctx, &W.X16, cells(ctx->L[0])));
+  ACHK(dalloc(ctx, &W.R16, cells(ctx->L[0])));
   ctx->have32 = true;
   return MG_OK;
 }
@@ -457,6 +473,10 @@ int make_consts(mg_ctx* ctx, int model, const mg_model_params* P, int n, Consts*
   C.f_phibar = float(C.phibar);
   C.f_cq_src = float(C.cq_src);
   C.f_cq_pot = float(C.cq_pot);
+  C.f_i6ct2 = float(1.0 / (6.0 * C.ct2));
+  C.f_ict2 = float(1.0 / C.ct2);
+  C.f_isamp = C.s_amp > 0.0 ? float(1.0 / C.s_amp) : 0.0f;
+  C.f_ct2_samp = C.s_amp > 0.0 ? float(C.ct2 / C.s_amp) : 0.0f;
   *out = C;
   return MG_OK;
 }
@@ -529,15 +549,24 @@ constexpr int kMaxPlanned = 8;
 // full pass over the master that is worth about half a cycle there.  On
 // small grids a check is cheap next to a cycle and the measured rate is used.
 constexpr double kRhoFloor = 0.18;
+// Reduction one outer step is asked for when level 0's X and rho are stored
+// in 16 bits (their rounding, ~1e-4 relative, perturbs the inner operator
+// and right-hand side, which bounds what one step can deliver).
+constexpr double kStore16Step = 1e-3;
 constexpr int64_t kRhoFloorCells = int64_t(1) << 24;  // 256^3
-int plan_cycles(int fixed, double rel, double rel_prev, int k_prev, double tol, int64_t cells) {
+// step_floor > 0: one check's cycles aim no lower than rel * step_floor (the
+// reduction one outer step can deliver when the finest level's data are
+// stored in 16 bits); first: cycles before anything is measured.
+int plan_cycles(int fixed, double rel, double rel_prev, int k_prev, double tol, int64_t cells,
+                double step_floor = 0.0, int first = 2) {
   if (fixed > 0) return fixed;
-  if (rel_prev <= 0.0 || k_prev <= 0 || !(rel < rel_prev)) return 2;
+  if (rel_prev <= 0.0 || k_prev <= 0 || !(rel < rel_prev)) return first;
   double rho = pow(rel / rel_prev, 1.0 / k_prev);
   const double floor_rho = cells >= kRhoFloorCells ? kRhoFloor : 0.01;
   if (rho < floor_rho) rho = floor_rho;
   if (rho > 0.9) rho = 0.9;
-  double need = 1.05 * log(tol / rel) / log(rho);
+  const double target = tol > rel * step_floor ? tol : rel * step_floor;
+  double need = 1.05 * log(target / rel) / log(rho);
   int k = (int)ceil(need);
   return k < 1 ? 1 : (k > kMaxPlanned ? kMaxPlanned : k);
 }
@@ -574,6 +603,24 @@ int sum2_to_host(mg_ctx* ctx, int64_t nparts, double* a, double* b, const double
   HIPCHK(hipStreamSynchronize(ctx->stream));
   *a = ctx->hscal[0];
   *b = ctx->hscal[1];
+  return MG_OK;
+}
+
+// Reductions of one refined outer pass with one synchronisation: sum d^2
+// (ctx->part) -> *s; with bg, sum (bg_coef delta)^2 (ctx->part3) -> *sb; with
+// mx_on, max |d| (ctx->part4) -> *mx.
+int outer_sums(mg_ctx* ctx, int64_t nparts, bool bg, bool mx_on, double* s, double* sb,
+               double* mx) {
+  ACHK(sum_on_device(ctx, nparts, ctx->scal));
+  if (bg) ACHK(sum_on_device(ctx, nparts, ctx->scal + 1, ctx->part3));
+  if (mx_on) k_max_partials<<<1, 256, 0, ctx->stream>>>(ctx->part4, nparts, ctx->scal + 2);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(ctx->hscal, ctx->scal, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *s = ctx->hscal[0];
+  if (bg) *sb = ctx->hscal[1];
+  if (mx_on) *mx = ctx->hscal[2];
   return MG_OK;
 }
 
@@ -862,6 +909,21 @@ int solve64(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
 // ---------------------------------------------------------------------------
 // FP32 correction multigrid inside an FP64 outer loop
 // ---------------------------------------------------------------------------
+// Calls fn(X, rho) with level 0's X and rho in the current outer step's
+// storage (FP32 or 16-bit); other levels are FP32.
+template <typename Fn>
+void with_level_store(mg_ctx* ctx, int l, Fn&& fn) {
+  Work32& W = ctx->w32;
+  const bool x16 = l == 0 && ctx->s0.x16, r16 = l == 0 && ctx->s0.r16;
+  if (x16 && r16) fn(W.X16, W.R16);
+  else if (x16) fn(W.X16, W.rho[l]);
+  else if (r16) fn(W.X[l], W.R16);
+  else fn(W.X[l], W.rho[l]);
+}
+inline Store level_store(const mg_ctx* ctx, int l) {
+  return l == 0 ? ctx->s0.S : Store{1.0f, 1.0f, 1.0f, 1.0f};
+}
+
 // e *= s over m cells (the divergence test hook, MGGPU_TEST_CORRECTION_SCALE)
 __global__ __launch_bounds__(kBlock) void k_scale(float* __restrict__ e, int64_t m, float s) {
   const int64_t g = gid();
@@ -882,14 +944,23 @@ int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps, bool fresh = false
       const bool light = fresh && s == 0 && colour == 0;
       int q = (l == 0 && !light) ? prof_begin(ctx, MG_PROF_SMOOTH32) : -1;
       const int kt = ctx->smooth_march_kt;
+      const Store S = level_store(ctx, l);
+      const int fr = (fresh && s == 0) ? 1 : 0;
       if (vec && kt > 0 && march_blocks(L, kt, Vec<float>::V) >= ctx->march_min_blocks)
-        k_smooth_corr_kv<M><<<march_blocks(L, kt, Vec<float>::V), kBlock, 0, ctx->stream>>>(
-            L, W.e[l], W.X[l], W.dens[l], W.rho[l], colour, float(lev_h2(l)), C,
-            (fresh && s == 0) ? 1 : 0, kt);
+        with_level_store(ctx, l, [&](auto* X, auto* R) {
+          using TX = std::remove_pointer_t<decltype(X)>;
+          using TR = std::remove_pointer_t<decltype(R)>;
+          k_smooth_corr_kv<M, TX, TR>
+              <<<march_blocks(L, kt, Vec<float>::V), kBlock, 0, ctx->stream>>>(
+                  L, W.e[l], X, W.dens[l], R, colour, float(lev_h2(l)), C, fr, kt, S);
+        });
       else if (vec)
-        k_smooth_corr_v<M><<<nblk(nv), kBlock, 0, ctx->stream>>>(
-            L, W.e[l], W.X[l], W.dens[l], W.rho[l], colour, float(lev_h2(l)), C,
-            (fresh && s == 0) ? 1 : 0);
+        with_level_store(ctx, l, [&](auto* X, auto* R) {
+          using TX = std::remove_pointer_t<decltype(X)>;
+          using TR = std::remove_pointer_t<decltype(R)>;
+          k_smooth_corr_v<M, TX, TR><<<nblk(nv), kBlock, 0, ctx->stream>>>(
+              L, W.e[l], X, W.dens[l], R, colour, float(lev_h2(l)), C, fr, S);
+        });
       else
         k_smooth_corr<M><<<nblk(L.half), kBlock, 0, ctx->stream>>>(L, W.e[l], W.X[l], W.dens[l],
                                                                    W.rho[l], colour,
@@ -935,16 +1006,25 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   // exact per-cell smoothers (f(R), symmetron): the colour swept last has
   // zero residual
   const int skip1 = (M != CQ && o->nu_pre > 0) ? 1 : 0;
+  const Store S = level_store(ctx, l);
   if (skip1 && Lc.n % 4 == 0 && Lc.n >= 8 &&
       prolong_march_blocks(Lc.n, kRestrictKT) >= ctx->march_min_blocks)
-    k_resid_restrict_corr_kv<M><<<prolong_march_blocks(Lc.n, kRestrictKT), kBlock, 0,
-                                  ctx->stream>>>(
-        Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
-        W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C, kRestrictKT);
+    with_level_store(ctx, l, [&](auto* X, auto* R) {
+      using TX = std::remove_pointer_t<decltype(X)>;
+      using TR = std::remove_pointer_t<decltype(R)>;
+      k_resid_restrict_corr_kv<M, TX, TR>
+          <<<prolong_march_blocks(Lc.n, kRestrictKT), kBlock, 0, ctx->stream>>>(
+              Lf, Lc, W.e[l], X, W.dens[l], R, float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
+              W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C, kRestrictKT, S);
+    });
   else if (vec)
-    k_resid_restrict_corr_v<M><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
-        Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
-        W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C, skip1);
+    with_level_store(ctx, l, [&](auto* X, auto* R) {
+      using TX = std::remove_pointer_t<decltype(X)>;
+      using TR = std::remove_pointer_t<decltype(R)>;
+      k_resid_restrict_corr_v<M, TX, TR><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
+          Lf, Lc, W.e[l], X, W.dens[l], R, float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
+          W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C, skip1, S);
+    });
   else
     k_resid_restrict_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
@@ -1000,6 +1080,28 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   // the master as that constant instead of reading it; the first residual is
   // then exactly the background residual whose RMS normalises rel.
   const bool uni = fused && !field_in;
+  // 16-bit storage of level 0's X (f(R), symmetron: X/scale near 1 in
+  // [2^-24, 32]) and rho (scaled per outer step by a power of two); the
+  // first step from a given field keeps rho in FP32 (its scale is unknown).
+  // Not for CQ: its Newton smoother is bound by its exp/log arithmetic, so
+  // the bytes saved do not pay for the extra cycle the 16-bit floor costs
+  // (29.0 against 26.5 ms for the 512^3 solve and force).
+  const bool f16 = ctx->fp16 && fused && L0.n % 8 == 0 && M != CQ;
+  struct Store0Reset {  // level 0 is FP32 again outside this solve
+    mg_ctx* c;
+    ~Store0Reset() {
+      c->s0.x16 = c->s0.r16 = false;
+      c->s0.S = Store{1.0f, 1.0f, 1.0f, 1.0f};
+    }
+  } store0_reset{ctx};
+  ctx->s0.x16 = f16;
+  ctx->s0.r16 = false;
+  ctx->s0.S = Store{1.0f, 1.0f, 1.0f, 1.0f};
+  if (ctx->s0.x16) {
+    const double xs = (M == FR ? 1024.0 / C.wbar : 1024.0);
+    ctx->s0.S.x_enc = float(xs);
+    ctx->s0.S.x_dec = float(1.0 / xs);
+  }
   double eps_bg = 1.0;
   if (field_in)
     launch_pack<double, double>(ctx, L0, field_in, W.w, sgn);
@@ -1020,18 +1122,42 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
   const float* pending = nullptr;  // correction not yet added to the master
   for (;;) {
     int64_t nparts;
+    double s, sb = 0.0;
     if (fused) {
       // w_new = w + pending, residual at w_new, next correction buffer zeroed
       nparts = march_blocks(L0, kMarchKT, kVOuter);
       double* wn = pending ? W.wbuf[1 - cur] : W.w;
       float* ez = fresh ? nullptr : W.ebuf[pending ? 1 - eb : eb];
       const double* wsrc = (uni && outer <= 1) ? nullptr : W.w;
-      // the uniform start also sums (bg_coef delta)^2: the background residual
-      // in exact arithmetic, which normalises rel (zero for delta = 0, where
-      // the computed first residual is rounding noise)
-      k_outer_fused_kv<M><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-          L0, wsrc, pending, wn, W.dens[0], C, W.rho[0], W.X[0], ez, ctx->part,
-          (uni && outer == 0) ? ctx->part3 : nullptr, kMarchKT);
+      // rho's scale: the residual's RMS expected at this check mapped to 2^4
+      // (at a uniform start bg_coef delta, whose delta = 1 then maps to 1;
+      // after cycles 1/100 of the last check's); a pass whose largest |rho|
+      // would overflow is redone with the scale its maximum allows
+      const bool r16 = f16 && (uni || outer > 0);
+      double rms_pred = outer == 0 ? 16.0 * C.bg_coef : rel * eps_bg * 1e-2;
+      int rexp = r16 ? (int)lround(log2(16.0 / (rms_pred > 0.0 ? rms_pred : 1.0))) : 0;
+      for (int pass = 0;; ++pass) {
+        rexp = rexp > 120 ? 120 : (rexp < -120 ? -120 : rexp);
+        ctx->s0.r16 = r16;
+        ctx->s0.S.r_enc = float(ldexp(1.0, rexp));
+        ctx->s0.S.r_dec = float(ldexp(1.0, -rexp));
+        const bool bgsum = uni && outer == 0;
+        // the uniform start also sums (bg_coef delta)^2: the background residual
+        // in exact arithmetic, which normalises rel (zero for delta = 0, where
+        // the computed first residual is rounding noise)
+        with_level_store(ctx, 0, [&](auto* X, auto* R) {
+          using TX = std::remove_pointer_t<decltype(X)>;
+          using TR = std::remove_pointer_t<decltype(R)>;
+          k_outer_fused_kv<M, TX, TR><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+              L0, wsrc, pending, wn, W.dens[0], C, R, X, ez, ctx->part,
+              bgsum ? ctx->part3 : nullptr, kMarchKT, ctx->s0.S, r16 ? ctx->part4 : nullptr);
+        });
+        LAUNCHCHK();
+        double mx = 0.0;
+        ACHK(outer_sums(ctx, nparts, bgsum, r16, &s, &sb, &mx));
+        if (!r16 || !(mx * ldexp(1.0, rexp) > 6.0e4) || pass > 0 || !std::isfinite(mx)) break;
+        rexp = (int)floor(log2(3.0e4 / mx));
+      }
       if (pending) {
         cur = 1 - cur;
         eb = 1 - eb;
@@ -1045,14 +1171,8 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
           L0, W.w, W.dens[0], C, W.rho[0], W.X[0], W.e[0], ctx->part);
     }
     LAUNCHCHK();
-    double s;
-    if (uni && outer == 0) {
-      double sb;
-      ACHK(sum2_to_host(ctx, nparts, &s, &sb, ctx->part3));
-      eps_bg = bg_norm_of(C, sqrt(sb / double(m)));
-    } else {
-      ACHK(sum_to_host(ctx, nparts, &s));
-    }
+    if (!fused) ACHK(sum_to_host(ctx, nparts, &s));
+    if (uni && outer == 0) eps_bg = bg_norm_of(C, sqrt(sb / double(m)));
     rel = sqrt(s / double(m)) / eps_bg;
     if (outer > 0 && st && outer - 1 < 64) st->resid_hist[outer - 1] = rel;
     if (!std::isfinite(rel)) {
@@ -1071,7 +1191,8 @@ int solve32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const float* 
       break;
     }
     int k = fixed ? o->fixed_cycles
-                  : plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol, cells(ctx->L[0]));
+                  : plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol, cells(ctx->L[0]),
+                                f16 ? kStore16Step : 0.0, f16 ? 4 : 2);
     for (int it = 0; it < k; ++it)
       ACHK(cycle32<M>(ctx, C, o, 0, o->cycle, it == 0, fresh && it == 0));
     if (ctx->test_escale != 1.0f) {
@@ -2146,7 +2267,7 @@ int scratch_base(mg_ctx* ctx, char** out) {
 struct NoallocWork {
   Work32 w32;
   Work64 w64;
-  double *part = nullptr, *part2 = nullptr, *part3 = nullptr, *scal = nullptr;
+  double *part = nullptr, *part2 = nullptr, *part3 = nullptr, *part4 = nullptr, *scal = nullptr;
 };
 size_t noalloc_layout(const mg_ctx* ctx, char* base, NoallocWork* W) {
   size_t off = 0;
@@ -2158,12 +2279,15 @@ size_t noalloc_layout(const mg_ctx* ctx, char* base, NoallocWork* W) {
   W->part = (double*)take(sizeof(double) * (size_t)ctx->part_cap);
   W->part2 = (double*)take(sizeof(double) * 256);
   W->part3 = (double*)take(sizeof(double) * (size_t)ctx->part_cap);
+  W->part4 = (double*)take(sizeof(double) * (size_t)ctx->part_cap);
   W->scal = (double*)take(sizeof(double) * 16);
   const size_t m0 = (size_t)cells(ctx->L[0]);
   W->w32.wbuf[0] = (double*)take(8 * m0);
   W->w32.wbuf[1] = (double*)take(8 * m0);
   W->w32.ebuf[1] = (float*)take(4 * m0);
   W->w32.w = W->w32.wbuf[0];
+  W->w32.X16 = (h16*)take(2 * m0);
+  W->w32.R16 = (h16*)take(2 * m0);
   W->w64.dens0 = (float*)take(4 * m0);
   for (int l = 0; l < ctx->nlev; ++l) {
     const size_t m = (size_t)cells(ctx->L[l]);
@@ -2190,16 +2314,17 @@ struct NoallocScope {
   Work32 w32;
   Work64 w64;
   bool h32, h64;
-  double *part, *part2, *part3, *scal;
+  double *part, *part2, *part3, *part4, *scal;
   NoallocScope(mg_ctx* x, const NoallocWork& W)
       : c(x), w32(x->w32), w64(x->w64), h32(x->have32), h64(x->have64), part(x->part),
-        part2(x->part2), part3(x->part3), scal(x->scal) {
+        part2(x->part2), part3(x->part3), part4(x->part4), scal(x->scal) {
     c->w32 = W.w32;
     c->w64 = W.w64;
     c->have32 = c->have64 = true;
     c->part = W.part;
     c->part2 = W.part2;
     c->part3 = W.part3;
+    c->part4 = W.part4;
     c->scal = W.scal;
     c->noalloc = true;
   }
@@ -2211,6 +2336,7 @@ struct NoallocScope {
     c->part = part;
     c->part2 = part2;
     c->part3 = part3;
+    c->part4 = part4;
     c->scal = scal;
     c->noalloc = false;
   }
@@ -2232,6 +2358,7 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
   if (const char* mb = getenv("MGGPU_MARCH_MIN_BLOCKS")) ctx->march_min_blocks = (unsigned)atoi(mb);
   if (const char* cd = getenv("MGGPU_CIC_DIRECT")) ctx->cic_direct = atoi(cd) != 0;
   if (const char* ts = getenv("MGGPU_TEST_CORRECTION_SCALE")) ctx->test_escale = (float)atof(ts);
+  if (const char* fs = getenv("MGGPU_FP16_STORAGE")) ctx->fp16 = atoi(fs) != 0;
   if (const char* sk = getenv("MGGPU_SMOOTH_MARCH_KT")) {
     const int kt = atoi(sk);
     ctx->smooth_march_kt = kt > 0 && kt <= 64 ? kt : 0;
@@ -2267,6 +2394,7 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
   int rc = dalloc(ctx, &ctx->part, ctx->part_cap);
   if (rc == MG_OK) rc = dalloc(ctx, &ctx->part2, 256);
   if (rc == MG_OK) rc = dalloc(ctx, &ctx->part3, ctx->part_cap);
+  if (rc == MG_OK) rc = dalloc(ctx, &ctx->part4, ctx->part_cap);
   if (rc == MG_OK) rc = dalloc(ctx, &ctx->scal, 16);
   if (rc == MG_OK) {
     void* h = nullptr;

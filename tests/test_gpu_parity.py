@@ -460,10 +460,10 @@ def test_marching_restriction_is_bit_identical(monkeypatch, model, prec, n):
     delta = torch.from_numpy(lognormal(n, 41)).to(DEV)
     opts = api.solver_opts(precision=prec)
     out = []
-    for mode in ("default", "march"):
-        for var in ("MGGPU_MARCH_MIN_BLOCKS", "MGGPU_SMOOTH_MARCH_KT"):
-            monkeypatch.delenv(var, raising=False)
-        if mode != "default":
+    for mode in ("per-row", "march"):
+        monkeypatch.delenv("MGGPU_MARCH_MIN_BLOCKS", raising=False)
+        monkeypatch.setenv("MGGPU_SMOOTH_MARCH_KT", "0")
+        if mode != "per-row":
             monkeypatch.setenv("MGGPU_MARCH_MIN_BLOCKS", "0")
             monkeypatch.setenv("MGGPU_SMOOTH_MARCH_KT", "4")
         mg = api.Context(n, device=DEV)
@@ -649,3 +649,35 @@ def test_refined_divergence_falls_back_to_fp64(model, monkeypatch):
     ref, _, _, _ = oracle.solve(P, delta.cpu().numpy().astype(np.float64), tol=1e-12)
     assert field_err(model, field.cpu().numpy(), to_field(model, ref), P) < 1e-6
     mg.close()
+
+
+@pytest.mark.parametrize("model", ["fr", "sym", "cq"])
+def test_16bit_storage_matches_fp32_storage_and_the_oracle(model, monkeypatch):
+    """The refined solve with the finest level's X and rho in 16-bit floats
+    (default) and in FP32 (MGGPU_FP16_STORAGE=0) converge to the same
+    discrete solution; a density with a clump of delta = 3e5 makes the first
+    pass's scaled rho overflow 16 bits, which the solve detects and redoes
+    with a smaller scale."""
+    n, box = 64, 64.0
+    say("16-bit storage", model)
+    P, prm = cfg(model, n, box)
+    d = lognormal(n, 97)
+    d[10, 20, 30] = 3e5
+    d[40, 41, 42] = 1e5
+    d = (d - d.mean()).astype(np.float32)
+    dd = torch.from_numpy(d).to(DEV)
+    out = {}
+    for f16 in ("1", "0"):
+        monkeypatch.setenv("MGGPU_FP16_STORAGE", f16)
+        mg = api.Context(n, device=DEV)
+        field, st = mg.solve(kind(model), prm, dd, tol=1e-9, opts=api.solver_opts(precision="fp32"))
+        mg.close()
+        say(f"  fp16={f16}: checks={st.cycles} cycles={st.vcycles} rel={st.rel_resid:.1e}")
+        assert st.status == 0 and st.rel_resid <= 1e-9
+        out[f16] = field.cpu().numpy()
+    ref, _, _, _ = oracle.solve(P, d.astype(np.float64), tol=1e-12, max_cycles=200)
+    for f16, x in out.items():
+        err = field_err(model, x, to_field(model, ref), P)
+        say(f"  fp16={f16}: field_err={err:.1e}")
+        assert err < 1e-6
+    assert field_err(model, out["1"], out["0"], P) < 1e-6
