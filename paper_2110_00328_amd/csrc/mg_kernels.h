@@ -257,6 +257,17 @@ __device__ __forceinline__ void st4s(TS* __restrict__ p, const float* in, float 
     __builtin_nontemporal_store(v, reinterpret_cast<nt_h4*>(p));
   }
 }
+// N (= 4, or Vec<T>::V) consecutive stored cells -> T: float arithmetic reads
+// FP32 or 16-bit storage, FP64 arithmetic FP64 storage
+template <typename T, typename TS, int N>
+__device__ __forceinline__ void ldNs(const TS* __restrict__ p, float dec, T* out) {
+  if constexpr (sizeof(T) == 4) {
+    static_assert(N == 4, "float cells come in fours");
+    ld4s<TS>(p, dec, out);
+  } else {
+    ldn_nt<T, N>(p, out);
+  }
+}
 
 // Neighbour sums of the V cells (ih0 .. ih0+V-1, j, k) of colour c from the
 // other colour's array o; s = (j + k + c) & 1.  Same summation order as nbsum.
@@ -325,6 +336,35 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
     for (int q = 1; q < nw; ++q) v = fmax(v, sh[q]);
   }
   return v;
+}
+// dst = 16-bit (src * enc), four cells per thread (m % 4 == 0)
+__global__ __launch_bounds__(kBlock) void k_to_h16(int64_t m4, const float* __restrict__ src,
+                                                   h16* __restrict__ dst, float enc) {
+  const int64_t g = gid();
+  if (g >= m4) return;
+  float v[4];
+  ld4s<float>(src + 4 * g, 1.0f, v);
+  st4s<h16>(dst + 4 * g, v, enc);
+}
+// block maxima of |x| over m floats
+__global__ __launch_bounds__(kBlock) void k_absmax_f32(int64_t m, const float* __restrict__ x,
+                                                       double* __restrict__ part) {
+  __shared__ double sh[32];
+  const int64_t g = gid();
+  const double v = g < m ? fabs(double(x[g])) : 0.0;
+  const double t = block_max(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+// Maxima of fixed chunks of m partial maxima, one block per chunk
+__global__ void k_max_chunks(const double* __restrict__ part, int64_t m, int64_t chunk,
+                             double* __restrict__ out) {
+  __shared__ double sh[32];
+  const int64_t lo = (int64_t)blockIdx.x * chunk;
+  const int64_t hi = lo + chunk < m ? lo + chunk : m;
+  double v = 0.0;
+  for (int64_t q = lo + threadIdx.x; q < hi; q += blockDim.x) v = fmax(v, part[q]);
+  v = block_max(v, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 // Maximum of m partial maxima (one block)
 __global__ void k_max_partials(const double* __restrict__ part, int64_t m, double* out) {
@@ -805,10 +845,13 @@ __global__ __launch_bounds__(kBlock) void k_smooth_corr_v(Lev L, float* e, const
     op_smooth_corr_v<M, TX, TR>(L, e, X, dens, rho, colour, h2, C, g4, fresh, S);
 }
 
-template <typename T>
-// fresh (colour 0 only): the correction starts at zero, neighbours are 0
-__global__ __launch_bounds__(kBlock) void k_smooth_lin_v(Lev L, T* e, const T* dg, const T* r,
-                                                         int colour, T kh2, int fresh) {
+// fresh (colour 0 only): the correction starts at zero, neighbours are 0.
+// TD, TR: storage of dg and r (16-bit on the finest level of an FP32 solve;
+// S.x_dec decodes dg, S.r_dec decodes r)
+template <typename T, typename TD = T, typename TR = T>
+__global__ __launch_bounds__(kBlock) void k_smooth_lin_v(Lev L, T* e, const TD* dg, const TR* r,
+                                                         int colour, T kh2, int fresh,
+                                                         Store S = Store{1, 1, 1, 1}) {
   constexpr int V = Vec<T>::V;
   uint32_t g4 = (uint32_t)gid();
   if (g4 >= (uint32_t)(L.half / V)) return;
@@ -824,8 +867,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_lin_v(Lev L, T* e, const T* d
   } else {
     nbsum_vec<T>(L, e + (1 - colour) * L.half, ih0, j, k, s, sum);
   }
-  ldv_nt<T>(dg + q0, d);
-  ldv_nt<T>(r + q0, rr);
+  ldNs<T, TD, V>(dg + q0, S.x_dec, d);
+  ldNs<T, TR, V>(r + q0, S.r_dec, rr);
 #pragma unroll
   for (int q = 0; q < V; ++q) {
     if constexpr (sizeof(T) == 4) out[q] = (rr[q] + kh2 * sum[q]) * f_rcp(T(6) * kh2 + d[q]);
@@ -939,6 +982,63 @@ __global__ __launch_bounds__(kBlock) void k_smooth_corr_kv(Lev L, float* e, cons
     }
   }
 }
+// The linear half-sweep marching in z (FP32): a thread owns 4 packed cells
+// of its colour in row j and walks kt planes, keeping the other colour's
+// rows (j, k-1), (j, k), (j, k+1) in registers.  Same per-cell arithmetic
+// and neighbour summation order as k_smooth_lin_v (bit-identical).
+template <typename TD, typename TR>
+__global__ __launch_bounds__(kBlock) void k_smooth_lin_kv(Lev L, float* e, const TD* dg,
+                                                          const TR* r, int colour, float kh2,
+                                                          int fresh, int kt, Store S) {
+  constexpr int V = 4;
+  const MarchPos P = march_pos(L, kt, V);
+  if (!P.ok) return;
+  const float* o = e + (1 - colour) * L.half;
+  float* own = e + colour * L.half;
+  const int j = P.j, ih0 = P.ih0, n = L.n;
+  const bool zero_nb = fresh && colour == 0;
+  float zm[V] = {0, 0, 0, 0}, zc[V] = {0, 0, 0, 0}, zp[V] = {0, 0, 0, 0};
+  if (!zero_nb) {
+    ldn<float, V>(o + prow(L, j, P.k0 == 0 ? n - 1 : P.k0 - 1) + ih0, zm);
+    ldn<float, V>(o + prow(L, j, P.k0) + ih0, zc);
+  }
+  for (int k = P.k0; k < P.k1; ++k) {
+    const uint32_t rw = prow(L, j, k);
+    float sum[V] = {0, 0, 0, 0};
+    if (!zero_nb) {
+      ldn<float, V>(o + prow(L, j, k + 1 == n ? 0 : k + 1) + ih0, zp);
+      const int s = (j + k + colour) & 1;
+      float xv[V + 1], ym[V], yp[V];
+      if (s) {
+#pragma unroll
+        for (int q = 0; q < V; ++q) xv[q] = zc[q];
+        xv[V] = o[rw + (ih0 + V == L.nh ? 0 : ih0 + V)];
+      } else {
+#pragma unroll
+        for (int q = 0; q < V; ++q) xv[q + 1] = zc[q];
+        xv[0] = o[rw + (ih0 == 0 ? L.nh - 1 : ih0 - 1)];
+      }
+      ldn<float, V>(o + prow(L, P.jm, k) + ih0, ym);
+      ldn<float, V>(o + prow(L, P.jp, k) + ih0, yp);
+#pragma unroll
+      for (int q = 0; q < V; ++q)
+        sum[q] = (xv[q] + xv[q + 1]) + (ym[q] + yp[q]) + (zm[q] + zp[q]);
+    }
+    const uint32_t q0 = (uint32_t)colour * (uint32_t)L.half + rw + (uint32_t)ih0;
+    float d[V], rr[V], out[V];
+    ld4s<TD>(dg + q0, S.x_dec, d);
+    ld4s<TR>(r + q0, S.r_dec, rr);
+#pragma unroll
+    for (int q = 0; q < V; ++q) out[q] = (rr[q] + kh2 * sum[q]) * f_rcp(6.0f * kh2 + d[q]);
+    stv_nt<float>(own + rw + ih0, out);
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      zm[q] = zc[q];
+      zc[q] = zp[q];
+    }
+  }
+}
+
 
 // v = w + e (e may be null; w null: the uniform value wu) of V packed cells
 // of colour c in row (j, k)
@@ -1064,16 +1164,18 @@ __global__ __launch_bounds__(kBlock) void k_outer_fused_kv(Lev L, const double* 
 
 // adjoint: lam_new = lam + e + shift, r = b - A lam_new, e_zero = 0;
 // partial sums of r^2 (and of r when part_sum is given)
-template <typename TO>
+// TR: storage of r (16-bit, scaled by S.r_enc, for an FP32 solve's finest
+// level); part_max: block maxima of |r| when given
+template <typename TO, typename TR = TO>
 __global__ __launch_bounds__(kBlock) void k_lin_outer_fused_kv(
     Lev L, const double* __restrict__ lam, const TO* __restrict__ e, double* __restrict__ lam_new,
-    const double* __restrict__ dg, const double* __restrict__ b, double kh2, TO* __restrict__ r,
+    const double* __restrict__ dg, const double* __restrict__ b, double kh2, TR* __restrict__ r,
     TO* __restrict__ e_zero, double* __restrict__ part, double shift, double* __restrict__ part_sum,
-    int kt) {
+    int kt, Store S = Store{1, 1, 1, 1}, double* __restrict__ part_max = nullptr) {
   constexpr int V = kVOuter;
   __shared__ double sh[32];
   const MarchPos P = march_pos(L, kt, V);
-  double acc = 0.0, accs = 0.0;
+  double acc = 0.0, accs = 0.0, amax = 0.0;
   if (P.ok) {
     double win[2][3][V];
     const int km0 = P.k0 == 0 ? L.n - 1 : P.k0 - 1;
@@ -1105,10 +1207,12 @@ __global__ __launch_bounds__(kBlock) void k_lin_outer_fused_kv(
           double d = bb[q] - (kh2 * (6.0 * lc[q] - sum[q]) + dd[q] * lc[q]);
           acc += d * d;
           accs += d;
+          amax = fmax(amax, fabs(d));
           ro[q] = TO(d);
           zo[q] = TO(0);
         }
-        stn<TO, V>(r + q0, ro);
+        if constexpr (sizeof(TO) == 4) st4s<TR>(r + q0, ro, S.r_enc);
+        else stn<TO, V>(r + q0, ro);
         if (e_zero) stn<TO, V>(e_zero + q0, zo);
       }
 #pragma unroll
@@ -1125,6 +1229,10 @@ __global__ __launch_bounds__(kBlock) void k_lin_outer_fused_kv(
   if (part_sum) {
     t = block_sum(accs, sh);
     if (threadIdx.x == 0) part_sum[blockIdx.x] = t;
+  }
+  if (part_max) {  // uniform over the grid
+    t = block_max(amax, sh);
+    if (threadIdx.x == 0) part_max[blockIdx.x] = t;
   }
 }
 
@@ -1584,13 +1692,14 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_kv(
       }
   }
 }
-template <typename T>
+template <typename T, typename TD = T, typename TR = T>
 __global__ __launch_bounds__(kBlock) void k_lin_resid_restrict_kv(Lev Lf, Lev Lc,
                                                                   const T* __restrict__ e,
-                                                                  const T* __restrict__ dg,
-                                                                  const T* __restrict__ r, T kh2,
+                                                                  const TD* __restrict__ dg,
+                                                                  const TR* __restrict__ r, T kh2,
                                                                   T* __restrict__ rH,
-                                                                  T* __restrict__ eH, int kt) {
+                                                                  T* __restrict__ eH, int kt,
+                                                                  Store S = Store{1, 1, 1, 1}) {
   const RRPos P = rr_pos(Lc, kt);
   if (!P.ok) return;
   const int n = Lf.n, I0 = P.I0, J = P.J;
@@ -1631,8 +1740,8 @@ __global__ __launch_bounds__(kBlock) void k_lin_resid_restrict_kv(Lev Lf, Lev Lc
         T sum[4], ec[4], dd[4], rr[4];
         rr_nbsum<T>(Lf, o1, I0, j, k, cen, ymv, ypv, zmv, zpv, sum);
         ldn<T, 4>(e + q0, ec);
-        ldn_nt<T, 4>(dg + q0, dd);
-        ldn_nt<T, 4>(r + q0, rr);
+        ldNs<T, TD, 4>(dg + q0, S.x_dec, dd);
+        ldNs<T, TR, 4>(r + q0, S.r_dec, rr);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           sd[q] += rr[q] - (kh2 * (T(6) * ec[q] - sum[q]) + dd[q] * ec[q]);
@@ -1700,12 +1809,13 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_direct_v(
 }
 
 // linear: rH = R(r - A e), eH = 0
-template <typename T>
+template <typename T, typename TD = T, typename TR = T>
 __global__ __launch_bounds__(kBlock) void k_lin_resid_restrict_v(Lev Lf, Lev Lc,
                                                                  const T* __restrict__ e,
-                                                                 const T* __restrict__ dg,
-                                                                 const T* __restrict__ r, T kh2,
-                                                                 T* rH, T* eH, int skip1) {
+                                                                 const TD* __restrict__ dg,
+                                                                 const TR* __restrict__ r, T kh2,
+                                                                 T* rH, T* eH, int skip1,
+                                                                 Store S = Store{1, 1, 1, 1}) {
   constexpr int V = Vec<T>::V;
   uint32_t g4 = (uint32_t)gid();
   if (g4 >= (uint32_t)(2 * Lc.half / V)) return;
@@ -1725,8 +1835,8 @@ __global__ __launch_bounds__(kBlock) void k_lin_resid_restrict_v(Lev Lf, Lev Lc,
         T sum[V], ec[V], dd[V], rr[V];
         nbsum_vec<T>(Lf, e + (1 - col) * Lf.half, I0, j, k, (j + k + col) & 1, sum);
         ldv<T>(e + q0, ec);
-        ldv_nt<T>(dg + q0, dd);
-        ldv_nt<T>(r + q0, rr);
+        ldNs<T, TD, V>(dg + q0, S.x_dec, dd);
+        ldNs<T, TR, V>(r + q0, S.r_dec, rr);
 #pragma unroll
         for (int q = 0; q < V; ++q) sd[q] += rr[q] - (kh2 * (T(6) * ec[q] - sum[q]) + dd[q] * ec[q]);
       }

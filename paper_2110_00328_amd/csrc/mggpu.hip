@@ -62,6 +62,8 @@ struct WorkLin {  // adjoint linear multigrid in precision T
   T* e[kMaxLev] = {};
   T* r[kMaxLev] = {};
   T* dg[kMaxLev] = {};
+  h16* dg16 = nullptr;  // level-0 dg and r in 16 bits (FP32 solve only)
+  h16* r16 = nullptr;
 };
 struct WorkAdj {
   double* v = nullptr;    // forward field (solved variable), packed
@@ -104,6 +106,12 @@ struct mg_ctx {
     Store S{1.0f, 1.0f, 1.0f, 1.0f};
   } s0;
   double* part4 = nullptr;     // block maxima (same capacity as part)
+  // storage of level 0's dg and r in the current adjoint solve (16-bit when
+  // on; x_* scales dg, r_* scales r)
+  struct {
+    bool on = false;
+    Store S{1.0f, 1.0f, 1.0f, 1.0f};
+  } a0;
   // device facts for the cooperative batched launch, queried once (property
   // queries cost milliseconds per call): CU count, cooperative support, and
   // resident workgroups per CU for each workgroup size (index log2(BS) - 8)
@@ -326,7 +334,24 @@ int ensure_lin(mg_ctx* ctx, WorkLin<T>& W) {
   }
   W.ebuf[0] = W.e[0];
   ACHK(dalloc(ctx, &W.ebuf[1], cells(ctx->L[0])));
+  if (sizeof(T) == 4) {
+    ACHK(dalloc(ctx, &W.dg16, cells(ctx->L[0])));
+    ACHK(dalloc(ctx, &W.r16, cells(ctx->L[0])));
+  }
   return MG_OK;
+}
+
+// Calls fn(dg, r) with the level's dg and r in the adjoint's current storage
+// (16-bit on level 0 of an FP32 solve when ctx->a0.on).
+template <typename T, typename Fn>
+void with_lin_store(mg_ctx* ctx, WorkLin<T>& W, int l, Fn&& fn) {
+  if constexpr (sizeof(T) == 4) {
+    if (l == 0 && ctx->a0.on) {
+      fn(W.dg16, W.r16);
+      return;
+    }
+  }
+  fn(W.dg[l], W.r[l]);
 }
 
 int ensure_adj(mg_ctx* ctx, int precision) {
@@ -586,6 +611,17 @@ int sum_on_device(mg_ctx* ctx, int64_t nparts, double* dst, const double* src = 
   return MG_OK;
 }
 
+// the same for maxima of non-negative partials: src -> *dst on the device
+int max_on_device(mg_ctx* ctx, int64_t nparts, const double* src, double* dst) {
+  int64_t nb = (nparts + 2047) / 2048;
+  if (nb > 256) nb = 256;
+  const int64_t chunk = (nparts + nb - 1) / nb;
+  k_max_chunks<<<(unsigned)nb, 256, 0, ctx->stream>>>(src, nparts, chunk, ctx->part2);
+  k_max_partials<<<1, 256, 0, ctx->stream>>>(ctx->part2, nb, dst);
+  LAUNCHCHK();
+  return MG_OK;
+}
+
 int sum_to_host(mg_ctx* ctx, int64_t nparts, double* out, const double* src = nullptr) {
   ACHK(sum_on_device(ctx, nparts, ctx->scal, src));
   HIPCHK(hipMemcpyAsync(ctx->hscal, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -613,7 +649,7 @@ int outer_sums(mg_ctx* ctx, int64_t nparts, bool bg, bool mx_on, double* s, doub
                double* mx) {
   ACHK(sum_on_device(ctx, nparts, ctx->scal));
   if (bg) ACHK(sum_on_device(ctx, nparts, ctx->scal + 1, ctx->part3));
-  if (mx_on) k_max_partials<<<1, 256, 0, ctx->stream>>>(ctx->part4, nparts, ctx->scal + 2);
+  if (mx_on) ACHK(max_on_device(ctx, nparts, ctx->part4, ctx->scal + 2));
   LAUNCHCHK();
   HIPCHK(hipMemcpyAsync(ctx->hscal, ctx->scal, 3 * sizeof(double), hipMemcpyDeviceToHost,
                         ctx->stream));
@@ -1386,13 +1422,28 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
   T kh2 = T(kap / lev_h2(l));
   const bool vec = (Lf.nh % Vec<T>::V) == 0;
   const int64_t nv = Lf.half / Vec<T>::V;
+  const Store S0 = l == 0 ? ctx->a0.S : Store{1.0f, 1.0f, 1.0f, 1.0f};
   auto smooth = [&](int sweeps, bool first_fresh) {
     for (int s = 0; s < sweeps; ++s)
       for (int colour = 0; colour < 2; ++colour) {
         int q = l == 0 ? prof_begin(ctx, sizeof(T) == 4 ? MG_PROF_LIN32 : MG_PROF_LIN64) : -1;
-        if (vec)
-          k_smooth_lin_v<T><<<nblk(nv), kBlock, 0, ctx->stream>>>(
-              Lf, W.e[l], W.dg[l], W.r[l], colour, kh2, (first_fresh && s == 0) ? 1 : 0);
+        const int kt = ctx->smooth_march_kt;
+        const int fr = (first_fresh && s == 0) ? 1 : 0;
+        if (sizeof(T) == 4 && vec && kt > 0 && march_blocks(Lf, kt, 4) >= ctx->march_min_blocks)
+          with_lin_store<T>(ctx, W, l, [&](auto* D, auto* R) {
+            using TD = std::remove_pointer_t<decltype(D)>;
+            using TR = std::remove_pointer_t<decltype(R)>;
+            if constexpr (sizeof(T) == 4)
+              k_smooth_lin_kv<TD, TR><<<march_blocks(Lf, kt, 4), kBlock, 0, ctx->stream>>>(
+                  Lf, (float*)W.e[l], D, R, colour, float(kh2), fr, kt, S0);
+          });
+        else if (vec)
+          with_lin_store<T>(ctx, W, l, [&](auto* D, auto* R) {
+            using TD = std::remove_pointer_t<decltype(D)>;
+            using TR = std::remove_pointer_t<decltype(R)>;
+            k_smooth_lin_v<T, TD, TR><<<nblk(nv), kBlock, 0, ctx->stream>>>(
+                Lf, W.e[l], D, R, colour, kh2, fr, S0);
+          });
         else
           k_smooth_lin<T><<<nblk(Lf.half), kBlock, 0, ctx->stream>>>(Lf, W.e[l], W.dg[l], W.r[l],
                                                                       colour, kh2);
@@ -1410,12 +1461,20 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
   const int64_t ncv = cells(Lc) / Vec<T>::V;
   if (o->nu_pre > 0 && Lc.n % 4 == 0 && Lc.n >= 8 &&  // exact per cell: colour 1 skipped
       prolong_march_blocks(Lc.n, kRestrictKT) >= ctx->march_min_blocks)
-    k_lin_resid_restrict_kv<T><<<prolong_march_blocks(Lc.n, kRestrictKT), kBlock, 0,
-                                 ctx->stream>>>(Lf, Lc, W.e[l], W.dg[l], W.r[l], kh2, W.r[l + 1],
-                                                W.e[l + 1], kRestrictKT);
+    with_lin_store<T>(ctx, W, l, [&](auto* D, auto* R) {
+      using TD = std::remove_pointer_t<decltype(D)>;
+      using TR = std::remove_pointer_t<decltype(R)>;
+      k_lin_resid_restrict_kv<T, TD, TR>
+          <<<prolong_march_blocks(Lc.n, kRestrictKT), kBlock, 0, ctx->stream>>>(
+              Lf, Lc, W.e[l], D, R, kh2, W.r[l + 1], W.e[l + 1], kRestrictKT, S0);
+    });
   else if (cvec)  // Gauss-Seidel on a linear system is exact per cell: skip colour 1
-    k_lin_resid_restrict_v<T><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
-        Lf, Lc, W.e[l], W.dg[l], W.r[l], kh2, W.r[l + 1], W.e[l + 1], o->nu_pre > 0 ? 1 : 0);
+    with_lin_store<T>(ctx, W, l, [&](auto* D, auto* R) {
+      using TD = std::remove_pointer_t<decltype(D)>;
+      using TR = std::remove_pointer_t<decltype(R)>;
+      k_lin_resid_restrict_v<T, TD, TR><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
+          Lf, Lc, W.e[l], D, R, kh2, W.r[l + 1], W.e[l + 1], o->nu_pre > 0 ? 1 : 0, S0);
+    });
   else
     k_lin_resid_restrict<T><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
         Lf, Lc, W.e[l], W.dg[l], W.r[l], kh2, W.r[l + 1], W.e[l + 1]);
@@ -1474,10 +1533,37 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
   if (!(bb > 0.0)) bb = 1.0;
   // lam starts at 0: the fused outer kernels take it as 0 until written
   if (!vec) k_fill<double><<<nblk(m), kBlock, 0, ctx->stream>>>(A.lam, m, 0.0);
+  // 16-bit dg and r on level 0 of an FP32 solve (as the forward solve's X and
+  // rho; not for CQ): dg scaled so that its largest value maps to ~2^15
+  struct A0Reset {  // level 0 is FP32 again outside this solve
+    mg_ctx* c;
+    ~A0Reset() {
+      c->a0.on = false;
+      c->a0.S = Store{1.0f, 1.0f, 1.0f, 1.0f};
+    }
+  } a0_reset{ctx};
+  const bool f16 = f32 && ctx->fp16 && vec && L0.n % 8 == 0 && M != CQ;
   if (f32) {
     for (int l = 0; l + 1 < ctx->nlev; ++l)
       k_restrict<float, float><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
           ctx->L[l], ctx->L[l + 1], A.w32.dg[l], A.w32.dg[l + 1]);
+    if (f16) {
+      k_absmax_f32<<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.w32.dg[0], ctx->part4);
+      ACHK(max_on_device(ctx, nblk(m), ctx->part4, ctx->scal + 2));
+      HIPCHK(hipMemcpyAsync(ctx->hscal + 2, ctx->scal + 2, sizeof(double), hipMemcpyDeviceToHost,
+                            ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      const double dmax = ctx->hscal[2];
+      const int dexp = dmax > 0.0 && std::isfinite(dmax) ? (int)floor(log2(3.2e4 / dmax)) : 0;
+      ctx->a0.on = std::isfinite(dmax) && dexp > -120 && dexp < 120;
+      ctx->a0.S.x_enc = float(ldexp(1.0, dexp));
+      ctx->a0.S.x_dec = float(ldexp(1.0, -dexp));
+      if (ctx->a0.on) {
+        k_to_h16<<<nblk(m / 4), kBlock, 0, ctx->stream>>>(m / 4, A.w32.dg[0], A.w32.dg16,
+                                                           ctx->a0.S.x_enc);
+        LAUNCHCHK();
+      }
+    }
   } else {
     for (int l = 0; l + 1 < ctx->nlev; ++l)
       k_restrict<double, double><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
@@ -1508,11 +1594,33 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
                      o->nu_pre > 0 && ctx->fused_from > 0;
   for (;;) {
     int64_t nparts = vec ? march_blocks(L0, kMarchKT, kVOuter) : nblk(m);
+    double s_pass = -1.0;  // sum r^2 when the 16-bit pass has reduced it already
     if (vec) {
       double* ln = pending ? A.lambuf[1 - cur] : A.lam;
       int ez = pending ? 1 - eb : eb;
       const double* lsrc = outer <= 1 ? nullptr : A.lam;  // null: lam = 0
-      if (f32)
+      if (f32 && ctx->a0.on) {
+        // r's scale: its RMS expected at this check mapped to 2^4 (b at the
+        // start, 1/100 of the last check's after cycles); a pass whose
+        // largest |r| would overflow is redone with the scale that allows
+        const double rms_pred = (outer == 0 ? 1.0 : rel * 1e-2) * bb / sqrt(double(m));
+        int rexp = (int)lround(log2(16.0 / (rms_pred > 0.0 ? rms_pred : 1.0)));
+        for (int pass = 0;; ++pass) {
+          rexp = rexp > 120 ? 120 : (rexp < -120 ? -120 : rexp);
+          ctx->a0.S.r_enc = float(ldexp(1.0, rexp));
+          ctx->a0.S.r_dec = float(ldexp(1.0, -rexp));
+          k_lin_outer_fused_kv<float, h16><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+              L0, lsrc, (const float*)pending, ln, A.dg, A.b, kap, A.w32.r16,
+              fresh ? (float*)nullptr : A.w32.ebuf[ez], ctx->part, shift, psum, kMarchKT,
+              ctx->a0.S, ctx->part4);
+          LAUNCHCHK();
+          double mx = 0.0, s0 = 0.0, sb0 = 0.0;
+          ACHK(outer_sums(ctx, nparts, false, true, &s0, &sb0, &mx));
+          s_pass = s0;
+          if (!(mx * ldexp(1.0, rexp) > 6.0e4) || pass > 0 || !std::isfinite(mx)) break;
+          rexp = (int)floor(log2(3.0e4 / mx));
+        }
+      } else if (f32)
         k_lin_outer_fused_kv<float><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
             L0, lsrc, (const float*)pending, ln, A.dg, A.b, kap, A.w32.r[0],
             fresh ? (float*)nullptr : A.w32.ebuf[ez], ctx->part, shift, psum, kMarchKT);
@@ -1539,9 +1647,9 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
     }
     shift = 0.0;
     LAUNCHCHK();
-    double s;
+    double s = s_pass;
     if (psum) ACHK(sum_to_host(ctx, nparts, &sum_r, psum));
-    ACHK(sum_to_host(ctx, nparts, &s));
+    if (s < 0.0) ACHK(sum_to_host(ctx, nparts, &s));
     rel = sqrt(s) / bb;
     if (outer > 0 && st && outer - 1 < 64) st->resid_hist[outer - 1] = rel;
     if (!std::isfinite(rel)) {
@@ -1554,7 +1662,8 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
       break;
     }
     // correction scheme on r = b - A lam (FP32 or FP64 inner cycles)
-    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol, cells(ctx->L[0]));
+    int k = plan_cycles(o->inner_cycles, rel, rel_prev, k_prev, tol, cells(ctx->L[0]),
+                        ctx->a0.on ? kStore16Step : 0.0, ctx->a0.on ? 4 : 2);
     if (f32) {
       for (int it = 0; it < k; ++it)
         ACHK(lin_cycle<float>(ctx, A.w32, kap, o, 0, o->cycle, fresh && it == 0));
