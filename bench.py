@@ -291,7 +291,9 @@ def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
     out["batched_c4"] = dict(
         boxes=len(boxes), cells=cells_total, ms=b_ms, boxes_per_s=len(boxes) / (b_ms * 1e-3),
         cells_per_s=cells_total / (b_ms * 1e-3), block=blk, cells_per_thread=4 if vec else 1,
-        teams="one sized team per box" if teams else "single-workgroup teams",
+        teams={0: "persistent launch, single-workgroup teams",
+               1: "persistent launch, one sized team per box",
+               2: "grouped level launches per (n, model) class"}[teams],
         tune_ms=tune_ms, max_rel_resid=max(s.rel_resid for s in stats),
         max_err_vs_fp64_single_box=dict(field=worst_field, force=worst_force),
         outer_steps=[int(min(s.cycles for s in stats)), int(max(s.cycles for s in stats))],

@@ -309,22 +309,29 @@ int mg_cq_background(const mg_cq_background_params *p, int n_table, double *tabl
  * lies outside the table. */
 int mg_cq_background_at(const double *table, int n_table, double a, double *row);
 
-/* Many independent boxes of different n and model in one persistent launch
- * (the paper runs independent realisations side by side over MPI, Sec. 3.1).
- * The launch is cooperative and never has more workgroups than can be
- * resident.  Each box is run by a team of workgroups: either one team per
- * box, sized by its cell count (a big box gets several workgroups, a small
- * one a single workgroup; levels of n <= 16 run on one workgroup of the
- * team), or single-workgroup teams each running a longest-first list of
- * boxes.  A team runs its box's whole FP32-refined solve (the scheme of
- * mg_solve with MG_FP32_REFINED), then its force if requested.  Team
- * barriers wait for a bounded time; if one times out every workgroup leaves
- * and the call returns MG_EHIP.  Workspace for all boxes lives in ctx (its n
- * is not used).  The tile shape (workgroup size; 1 or 4 cells per thread;
- * team split) comes from mg_batched_set_config if pinned, else from the last
- * tuning of this context for the same multiset of (n, model), else from the
- * cache file $MGGPU_TUNE_CACHE (default $HOME/.mggpu_tune.json), else
- * mg_batched_tune runs first.  opts->precision must be MG_FP32_REFINED and
+/* Many independent boxes of different n and model in one call (the paper
+ * runs independent realisations side by side over MPI, Sec. 3.1), each solved
+ * with the scheme of mg_solve with MG_FP32_REFINED, then its force if
+ * requested.  Two designs, chosen by the autotuner:
+ *  - grouped level launches (teams = 2): boxes of the same (n, model) form a
+ *    class; each level operation of the cycle is one launch per class with
+ *    the box index in the grid, per-box constants and pointers from a table,
+ *    and a per-box control word that switches a box off once it has
+ *    converged or run its planned cycles; one synchronisation per outer
+ *    step serves all boxes;
+ *  - one persistent cooperative launch (teams = 0/1) that never has more
+ *    workgroups than can be resident: each box is run by a team of
+ *    workgroups, either one team per box sized by its cell count (levels of
+ *    n <= 16 on one workgroup of the team) or single-workgroup teams each
+ *    running a longest-first list of boxes.  Team barriers wait for a
+ *    bounded time; if one times out every workgroup leaves and the call
+ *    returns MG_EHIP.
+ * Workspace for all boxes lives in ctx (its n is not used).  The shape
+ * (design; for the persistent launch the workgroup size, 1 or 4 cells per
+ * thread and the team split) comes from mg_batched_set_config if pinned,
+ * else from the last tuning of this context for the same multiset of
+ * (n, model), else from the cache file $MGGPU_TUNE_CACHE (default
+ * $HOME/.mggpu_tune.json), else mg_batched_tune runs first.  opts->precision must be MG_FP32_REFINED and
  * opts->fixed_cycles 0.
  * Returns MG_OK when every box converged, else MG_ENAN / MG_ENOCONV
  * (per-box status in per_box, which may be NULL). */
@@ -351,18 +358,20 @@ int mg_prof_read(mg_ctx *ctx, int kernel_class, double *total_ms, int64_t *launc
 int mg_solve_batched(mg_ctx *ctx, int n_box, const mg_box_desc *boxes,
                      const mg_solver_opts *opts, double tol, mg_stats *per_box);
 
-/* Autotuner of the batched launch: times one outer step (2 FP32 cycles) of
- * the given batch for each workgroup size in {256, 512, 1024}, 1 or 4 cells
- * per thread, and both team splits; keeps the fastest for this context and
+/* Autotuner of the batched solve: times one outer step (2 FP32 cycles) of
+ * the given batch with the grouped level launches and with the persistent
+ * launch for each workgroup size in {256, 512, 1024}, 1 or 4 cells per
+ * thread, and both team splits; keeps the fastest for this context and
  * writes it to the cache file.  Overwrites nothing the caller owns. */
 int mg_batched_tune(mg_ctx *ctx, int n_box, const mg_box_desc *boxes,
                     const mg_solver_opts *opts, int *block_out, int *vec_out);
-/* Tile shape the last batched call used: workgroup size, vec (1: 4 cells per
- * thread), teams (1: one sized team per box; 0: single-workgroup teams).
- * (0, -1, -1) before any. */
+/* Shape the last batched call used: workgroup size, vec (1: 4 cells per
+ * thread), teams (2: grouped level launches, block and vec then unused; 1:
+ * persistent launch, one sized team per box; 0: persistent launch,
+ * single-workgroup teams).  (0, -1, -1) before any. */
 int mg_batched_config(const mg_ctx *ctx, int *block, int *vec, int *teams);
-/* Pins the tile shape for later batched calls (block 256/512/1024, vec 0/1,
- * teams 0/1); block = 0 unpins.  MG_EINVAL on other values. */
+/* Pins the shape for later batched calls (block 256/512/1024, vec 0/1,
+ * teams 0/1/2); block = 0 unpins.  MG_EINVAL on other values. */
 int mg_batched_set_config(mg_ctx *ctx, int block, int vec, int teams);
 
 #ifdef __cplusplus

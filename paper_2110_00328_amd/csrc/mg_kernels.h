@@ -1941,14 +1941,12 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr(Lev Lf, Lev Lc, 
 // the same, 4 packed cells of one colour per thread (needs nh % 4 == 0);
 // per-cell arithmetic and summation order as above
 template <int M>
-__global__ __launch_bounds__(kBlock) void k_coarse_src_corr_v(Lev L, const float* __restrict__ eR,
-                                                              const float* __restrict__ X,
-                                                              const float* __restrict__ dens,
-                                                              float* __restrict__ rho, float h2,
-                                                              Consts C) {
+__device__ __forceinline__ void op_coarse_src_corr_v(const Lev& L, const float* __restrict__ eR,
+                                                     const float* __restrict__ X,
+                                                     const float* __restrict__ dens,
+                                                     float* __restrict__ rho, float h2,
+                                                     const Consts& C, uint32_t g4) {
   constexpr int V = Vec<float>::V;
-  const uint32_t g4 = (uint32_t)gid();
-  if (g4 >= (uint32_t)(2 * L.half / V)) return;
   const uint32_t g = g4 * V;
   const int colour = g >= (uint32_t)L.half ? 1 : 0;
   int ih0, j, k;
@@ -1962,6 +1960,16 @@ __global__ __launch_bounds__(kBlock) void k_coarse_src_corr_v(Lev L, const float
 #pragma unroll
   for (int q = 0; q < V; ++q) r[q] = corr_G<M>(C, h2, ec[q], sum[q], x[q], dc[q]) - r[q];
   stv_nt<float>(rho + g, r);
+}
+template <int M>
+__global__ __launch_bounds__(kBlock) void k_coarse_src_corr_v(Lev L, const float* __restrict__ eR,
+                                                              const float* __restrict__ X,
+                                                              const float* __restrict__ dens,
+                                                              float* __restrict__ rho, float h2,
+                                                              Consts C) {
+  const uint32_t g4 = (uint32_t)gid();
+  if (g4 < (uint32_t)(2 * L.half / Vec<float>::V))
+    op_coarse_src_corr_v<M>(L, eR, X, dens, rho, h2, C, g4);
 }
 template <int M>
 __global__ __launch_bounds__(kBlock) void k_coarse_src_corr(Lev L, const float* eR, const float* X,
@@ -2163,8 +2171,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_direct(FusedDirect<T, T
 }
 
 template <int M>
-__global__ __launch_bounds__(kFusedThreads) void k_fused_corr(FusedCorr F, FusedProg P, Consts C) {
-  __shared__ double sh[32];
+__device__ __forceinline__ void fused_corr_body(const FusedCorr& F, const FusedProg& P,
+                                                const Consts& C, double* sh) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int o = 0; o < P.nops; ++o) {
     const Op op = P.op[o];
@@ -2228,6 +2236,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_fused_corr(FusedCorr F, Fused
     }
   }
 }
+template <int M>
+__global__ __launch_bounds__(kFusedThreads) void k_fused_corr(FusedCorr F, FusedProg P, Consts C) {
+  __shared__ double sh[32];
+  fused_corr_body<M>(F, P, C, sh);
+}
+
 
 template <typename T>
 __global__ __launch_bounds__(kFusedThreads) void k_fused_lin(FusedLin<T> F, FusedProg P) {

@@ -108,10 +108,12 @@ def _big_boxes():
     return out
 
 
-@pytest.mark.parametrize("shape", [(1024, 1, 1), (256, 1, 1), (512, 0, 1), (1024, 1, 0)])
+@pytest.mark.parametrize("shape", [(1024, 1, 1), (256, 1, 1), (512, 0, 1), (1024, 1, 0),
+                                   (256, 1, 2)])
 def test_batched_team_splits_match_single_box_solves(shape):
     """Boxes big enough to be split over many workgroups (teams of up to 64
-    workgroups for 128^3), for pinned tile shapes of both team splits."""
+    workgroups for 128^3), for pinned tile shapes of both team splits of the
+    persistent launch and for the grouped level launches (teams = 2)."""
     boxes = _big_boxes()
     mg = api.Context(16, device=DEV)
     mg.batched_set_config(*shape)
@@ -141,12 +143,61 @@ def test_batched_team_splits_match_single_box_solves(shape):
     mg.close()
 
 
+def test_grouped_launches_match_single_box_solves_and_oracle():
+    """The grouped level launches (pinned) on the mixed batch: f(R) n = 0, 1,
+    2, symmetron and CQ, n = 16 ... 40 (40^3 and 24^3 take the per-cell level
+    kernels: 20 and 12 are not multiples of 4), several boxes per class;
+    each against its single-box solve and the oracle; a warm restart from
+    the solutions takes no step."""
+    boxes = _boxes() + _boxes()[:4]
+    for b in boxes[len(_boxes()):]:
+        b["field"] = torch.zeros_like(b["field"])
+        b["force"] = torch.zeros_like(b["force"])
+    mg = api.Context(16, device=DEV)
+    mg.batched_set_config(256, 1, 2)
+    tol = 1e-8
+    opts = api.solver_opts(precision="fp32")
+    stats = mg.solve_batched(boxes, tol=tol, opts=opts)
+    assert mg.batched_config()[2] == 2
+    for q, (b, st) in enumerate(zip(boxes, stats)):
+        assert st.status == 0 and st.rel_resid <= tol, (q, st.status, st.rel_resid)
+        single = api.Context(b["n"], device=DEV)
+        f1, _ = single.solve(b["model"], b["params"], b["delta"], tol=tol, opts=opts)
+        g1 = single.force(b["model"], b["params"], f1)
+        x, ref = b["field"].cpu().numpy(), f1.cpu().numpy()
+        if b["model"] == "cq":
+            x, ref, bg = x - x.mean(), ref - ref.mean(), 0.0
+        else:
+            bg = ref.mean()
+        err = np.linalg.norm(x - ref) / np.linalg.norm(ref - bg)
+        gerr = np.linalg.norm((b["force"] - g1).cpu().numpy()) / np.linalg.norm(g1.cpu().numpy())
+        o, _, _, _ = oracle.solve(b["P"], b["delta_np"].astype(np.float64), tol=1e-12)
+        o = -o if b["model"] == "fr" else o
+        bgo = oracle.background(b["P"])
+        bgo = -bgo if b["model"] == "fr" else bgo
+        xo = b["field"].cpu().numpy()
+        if b["model"] == "cq":
+            xo, o, bgo = xo - xo.mean(), o - o.mean(), 0.0
+        oerr = np.linalg.norm(xo - o) / np.linalg.norm(o - bgo)
+        print(f"grouped box {q} n={b['n']} {b['model']}: outer={st.cycles} vc={st.vcycles} "
+              f"rel={st.rel_resid:.1e} vs single {err:.1e} force {gerr:.1e} vs oracle {oerr:.1e}",
+              flush=True)
+        assert err < 1e-6 and gerr < 1e-6 and oerr < 1e-5
+        single.close()
+    for b in boxes:
+        b["field_in"] = 1
+    assert all(s.cycles == 0 for s in mg.solve_batched(boxes, tol=tol, opts=opts))
+    mg.close()
+
+
 def test_batched_set_config_rejects_bad_shapes():
     mg = api.Context(16, device=DEV)
     with pytest.raises(api.MGError):
         mg.batched_set_config(300, 1, 1)
     with pytest.raises(api.MGError):
         mg.batched_set_config(256, 2, 1)
+    with pytest.raises(api.MGError):
+        mg.batched_set_config(256, 1, 3)
     mg.batched_set_config(0)
     mg.close()
 
