@@ -164,6 +164,11 @@ struct mg_ctx {
   double* ghsum = nullptr;
   int gcap = 0;
   int64_t gpart_cap = 0;
+  // classes are independent: each runs on one of these streams (default
+  // priority), forked from and joined back into the context's stream
+  static constexpr int kGStreams = 4;
+  hipStream_t gst[kGStreams] = {};
+  hipEvent_t gfork = nullptr, gjoin[kGStreams] = {};
   double* nat64 = nullptr;     // natural-layout scratch (debug entry points)
   // Newtonian potential by FFT (rocFFT, FP64), created at first use
   bool fft_ready = false;
@@ -2541,6 +2546,11 @@ void mg_ctx_destroy(mg_ctx* ctx) {
                   (void*)ctx->gpart, (void*)ctx->gsum})
     if (p) (void)hipFree(p);
   if (ctx->ghsum) (void)hipHostFree(ctx->ghsum);
+  for (int i = 0; i < mg_ctx::kGStreams; ++i) {
+    if (ctx->gst[i]) (void)hipStreamDestroy(ctx->gst[i]);
+    if (ctx->gjoin[i]) (void)hipEventDestroy(ctx->gjoin[i]);
+  }
+  if (ctx->gfork) (void)hipEventDestroy(ctx->gfork);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->hscal) (void)hipHostFree(ctx->hscal);
   if (ctx->fft_ready) {
@@ -3415,25 +3425,47 @@ int g_grow(mg_ctx* ctx, int nb, int pstride) {
     ctx->gcap = nb;
     ctx->gpart_cap = (int64_t)nb * pstride;
   }
+  if (!ctx->gfork) {
+    for (int i = 0; i < mg_ctx::kGStreams; ++i) {
+      HIPCHK(hipStreamCreateWithFlags(&ctx->gst[i], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&ctx->gjoin[i], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&ctx->gfork, hipEventDisableTiming));
+  }
+  return MG_OK;
+}
+
+// the class streams wait for the context's stream, and it for them
+int g_fork(mg_ctx* ctx, int ns) {
+  HIPCHK(hipEventRecord(ctx->gfork, ctx->stream));
+  for (int i = 0; i < ns; ++i) HIPCHK(hipStreamWaitEvent(ctx->gst[i], ctx->gfork, 0));
+  return MG_OK;
+}
+int g_join(mg_ctx* ctx, int ns) {
+  for (int i = 0; i < ns; ++i) {
+    HIPCHK(hipEventRecord(ctx->gjoin[i], ctx->gst[i]));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->gjoin[i], 0));
+  }
   return MG_OK;
 }
 
 template <int M>
-void g_smooth(mg_ctx* ctx, const GClass& K, const Lev& L, int it, int l, int sweeps) {
+void g_smooth(mg_ctx* ctx, hipStream_t st, const GClass& K, const Lev& L, int it, int l,
+              int sweeps) {
   const GBox* tab = ctx->gtab + K.first;
   const GCtl* ctl = ctx->gctl + K.first;
   const bool vec = g_vec_rows(L);
   const unsigned bx = vec ? nblk(L.half / 4) : nblk(L.half);
   for (int s = 0; s < sweeps; ++s)
     for (int colour = 0; colour < 2; ++colour)
-      kg_smooth<M><<<dim3(bx, K.count), kBlock, 0, ctx->stream>>>(tab, ctl, it, l, colour,
+      kg_smooth<M><<<dim3(bx, K.count), kBlock, 0, st>>>(tab, ctl, it, l, colour,
                                                                   vec ? 1 : 0);
 }
 
 // one cycle of a class from level l down (the recursion of cycle32)
 template <int M>
-int g_cycle(mg_ctx* ctx, const GClass& K, const Lev* L, const mg_solver_opts* o, int it, int l,
-            int type, bool rx) {
+int g_cycle(mg_ctx* ctx, hipStream_t st, const GClass& K, const Lev* L,
+            const mg_solver_opts* o, int it, int l, int type, bool rx) {
   const GBox* tab = ctx->gtab + K.first;
   const GCtl* ctl = ctx->gctl + K.first;
   if (l >= K.f) {
@@ -3446,51 +3478,52 @@ int g_cycle(mg_ctx* ctx, const GClass& K, const Lev* L, const mg_solver_opts* o,
                                            : default_coarse_sweeps(L[K.nlev - 1].n, K.nlev);
     P.rx = rx ? 1 : 0;
     for (int q = 0; q < ops.n; ++q) P.op[q] = ops.op[q];
-    kg_fused<M><<<K.count, kFusedThreads, 0, ctx->stream>>>(tab, ctl, it, P);
+    kg_fused<M><<<K.count, kFusedThreads, 0, st>>>(tab, ctl, it, P);
     LAUNCHCHK();
     return MG_OK;
   }
   if (l == K.nlev - 1) {  // a grid that cannot be coarsened
     const int cap = o->coarse_sweeps > 0 ? o->coarse_sweeps : default_coarse_sweeps(L[0].n, 1);
     const int nu = o->nu_pre + o->nu_post;
-    g_smooth<M>(ctx, K, L[l], it, l, cap > nu ? cap : nu);
+    g_smooth<M>(ctx, st, K, L[l], it, l, cap > nu ? cap : nu);
     LAUNCHCHK();
     return MG_OK;
   }
   const Lev& Lc = L[l + 1];
-  g_smooth<M>(ctx, K, L[l], it, l, o->nu_pre);
+  g_smooth<M>(ctx, st, K, L[l], it, l, o->nu_pre);
   const int skip1 = (M != CQ && o->nu_pre > 0) ? 1 : 0;
   const bool rvec = g_vec_coarse(Lc) && g_vec_rows(L[l]);
   const bool cvec = g_vec_rows(Lc);
   kg_down<M><<<dim3(rvec ? nblk(2 * Lc.half / 4) : nblk(2 * Lc.half), K.count), kBlock, 0,
-               ctx->stream>>>(tab, ctl, it, l, rx ? 1 : 0, skip1, rvec ? 1 : 0);
+               st>>>(tab, ctl, it, l, rx ? 1 : 0, skip1, rvec ? 1 : 0);
   kg_csrc<M><<<dim3(cvec ? nblk(2 * Lc.half / 4) : nblk(2 * Lc.half), K.count), kBlock, 0,
-               ctx->stream>>>(tab, ctl, it, l + 1, cvec ? 1 : 0);
+               st>>>(tab, ctl, it, l + 1, cvec ? 1 : 0);
   LAUNCHCHK();
   if (type == MG_CYCLE_V) {
-    ACHK(g_cycle<M>(ctx, K, L, o, it, l + 1, MG_CYCLE_V, rx));
+    ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_V, rx));
   } else if (type == MG_CYCLE_W) {
-    ACHK(g_cycle<M>(ctx, K, L, o, it, l + 1, MG_CYCLE_W, rx));
-    ACHK(g_cycle<M>(ctx, K, L, o, it, l + 1, MG_CYCLE_W, false));
+    ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_W, rx));
+    ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_W, false));
   } else {
-    ACHK(g_cycle<M>(ctx, K, L, o, it, l + 1, MG_CYCLE_F, rx));
-    ACHK(g_cycle<M>(ctx, K, L, o, it, l + 1, MG_CYCLE_V, false));
+    ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_F, rx));
+    ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_V, false));
   }
   if (g_vec_coarse(Lc)) {
-    kg_up<M == CQ ? 0 : 1><<<dim3(nblk(2 * Lc.half / 4), K.count), kBlock, 0, ctx->stream>>>(
+    kg_up<M == CQ ? 0 : 1><<<dim3(nblk(2 * Lc.half / 4), K.count), kBlock, 0, st>>>(
         tab, ctl, it, l);
   } else {
-    kg_coarse_diff<<<dim3(nblk(2 * Lc.half), K.count), kBlock, 0, ctx->stream>>>(tab, ctl, it, l);
-    kg_up_block<<<dim3(nblk(2 * Lc.half), K.count), kBlock, 0, ctx->stream>>>(tab, ctl, it, l);
+    kg_coarse_diff<<<dim3(nblk(2 * Lc.half), K.count), kBlock, 0, st>>>(tab, ctl, it, l);
+    kg_up_block<<<dim3(nblk(2 * Lc.half), K.count), kBlock, 0, st>>>(tab, ctl, it, l);
   }
-  g_smooth<M>(ctx, K, L[l], it, l, o->nu_post);
+  g_smooth<M>(ctx, st, K, L[l], it, l, o->nu_post);
   LAUNCHCHK();
   return MG_OK;
 }
 
 template <int M>
-int g_class_cycle(mg_ctx* ctx, const GClass& K, const Lev* L, const mg_solver_opts* o, int it) {
-  return g_cycle<M>(ctx, K, L, o, it, 0, o->cycle, it == 0);
+int g_class_cycle(mg_ctx* ctx, hipStream_t st, const GClass& K, const Lev* L,
+                  const mg_solver_opts* o, int it) {
+  return g_cycle<M>(ctx, st, K, L, o, it, 0, o->cycle, it == 0);
 }
 
 // The whole batch: trial = one outer step of two cycles, no outputs (tuning).
@@ -3537,6 +3570,8 @@ int grouped_solve(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver
     ctx->bpool_bytes = total;
   }
   ACHK(g_grow(ctx, nb, pstride));
+  const int ns = std::min((int)cls.size(), (int)mg_ctx::kGStreams);
+  auto cst = [&](size_t c) { return ctx->gst[c % ns]; };
   char* base = (char*)ctx->bpool;
   auto take = [&](size_t bytes) {
     char* p = base;
@@ -3589,30 +3624,32 @@ int grouped_solve(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver
   HIPCHK(hipMemcpyAsync(ctx->gtab, host.data(), sizeof(GBox) * nb, hipMemcpyHostToDevice,
                         ctx->stream));
   // inputs packed, density pyramids, background norms
+  ACHK(g_fork(ctx, ns));
   for (size_t c = 0; c < cls.size(); ++c) {
     const GClass& K = cls[c];
     const Lev* L = &levs[c * kMaxLevB];
     const GBox* tab = ctx->gtab + K.first;
     double* part = ctx->gpart + (int64_t)K.first * pstride;
     const dim3 g0(nblk(2 * L[0].half), K.count);
-    if (K.model == MG_FR) kg_pack<FR><<<g0, kBlock, 0, ctx->stream>>>(tab, part, pstride);
-    else if (K.model == MG_SYMMETRON) kg_pack<SYM><<<g0, kBlock, 0, ctx->stream>>>(tab, part, pstride);
-    else kg_pack<CQ><<<g0, kBlock, 0, ctx->stream>>>(tab, part, pstride);
+    hipStream_t st = cst(c);
+    if (K.model == MG_FR) kg_pack<FR><<<g0, kBlock, 0, st>>>(tab, part, pstride);
+    else if (K.model == MG_SYMMETRON) kg_pack<SYM><<<g0, kBlock, 0, st>>>(tab, part, pstride);
+    else kg_pack<CQ><<<g0, kBlock, 0, st>>>(tab, part, pstride);
     if (K.model != MG_FR)
       for (int l = 0; l + 1 < K.nlev; ++l)
-        kg_restrict_dens<<<dim3(nblk(2 * L[l + 1].half), K.count), kBlock, 0, ctx->stream>>>(tab,
-                                                                                            l);
+        kg_restrict_dens<<<dim3(nblk(2 * L[l + 1].half), K.count), kBlock, 0, st>>>(tab, l);
     LAUNCHCHK();
   }
+  // per-box sums of the partials (class streams), then joined and copied out
   auto box_sums = [&](std::vector<double>& s) -> int {
     for (size_t c = 0; c < cls.size(); ++c) {
       const GClass& K = cls[c];
       const Lev* L = &levs[c * kMaxLevB];
-      kg_sum_box<<<K.count, 256, 0, ctx->stream>>>(ctx->gpart + (int64_t)K.first * pstride,
-                                                    pstride, (int)nblk(2 * L[0].half),
-                                                    ctx->gsum + K.first);
+      kg_sum_box<<<K.count, 256, 0, cst(c)>>>(ctx->gpart + (int64_t)K.first * pstride, pstride,
+                                               (int)nblk(2 * L[0].half), ctx->gsum + K.first);
     }
     LAUNCHCHK();
+    ACHK(g_join(ctx, ns));
     HIPCHK(hipMemcpyAsync(ctx->ghsum, ctx->gsum, sizeof(double) * nb, hipMemcpyDeviceToHost,
                           ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -3634,6 +3671,7 @@ int grouped_solve(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver
   for (;;) {
     HIPCHK(hipMemcpyAsync(ctx->gctl, ctl.data(), sizeof(GCtl) * nb, hipMemcpyHostToDevice,
                           ctx->stream));
+    ACHK(g_fork(ctx, ns));
     for (size_t c = 0; c < cls.size(); ++c) {
       const GClass& K = cls[c];
       const Lev* L = &levs[c * kMaxLevB];
@@ -3641,11 +3679,11 @@ int grouped_solve(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver
       const GCtl* gc = ctx->gctl + K.first;
       double* part = ctx->gpart + (int64_t)K.first * pstride;
       const dim3 g0(nblk(2 * L[0].half), K.count);
-      kg_update<<<g0, kBlock, 0, ctx->stream>>>(tab, gc);
-      if (K.model == MG_FR) kg_outer<FR><<<g0, kBlock, 0, ctx->stream>>>(tab, gc, part, pstride);
-      else if (K.model == MG_SYMMETRON)
-        kg_outer<SYM><<<g0, kBlock, 0, ctx->stream>>>(tab, gc, part, pstride);
-      else kg_outer<CQ><<<g0, kBlock, 0, ctx->stream>>>(tab, gc, part, pstride);
+      hipStream_t st = cst(c);
+      kg_update<<<g0, kBlock, 0, st>>>(tab, gc);
+      if (K.model == MG_FR) kg_outer<FR><<<g0, kBlock, 0, st>>>(tab, gc, part, pstride);
+      else if (K.model == MG_SYMMETRON) kg_outer<SYM><<<g0, kBlock, 0, st>>>(tab, gc, part, pstride);
+      else kg_outer<CQ><<<g0, kBlock, 0, st>>>(tab, gc, part, pstride);
     }
     LAUNCHCHK();
     ACHK(box_sums(sums));
@@ -3682,33 +3720,39 @@ int grouped_solve(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver
     if (kmax == 0) break;
     HIPCHK(hipMemcpyAsync(ctx->gctl, ctl.data(), sizeof(GCtl) * nb, hipMemcpyHostToDevice,
                           ctx->stream));
+    ACHK(g_fork(ctx, ns));
     for (int it = 0; it < kmax; ++it)
       for (size_t c = 0; c < cls.size(); ++c) {
         const GClass& K = cls[c];
         const Lev* L = &levs[c * kMaxLevB];
-        if (K.model == MG_FR) ACHK(g_class_cycle<FR>(ctx, K, L, o, it));
-        else if (K.model == MG_SYMMETRON) ACHK(g_class_cycle<SYM>(ctx, K, L, o, it));
-        else ACHK(g_class_cycle<CQ>(ctx, K, L, o, it));
+        hipStream_t st = cst(c);
+        if (K.model == MG_FR) ACHK(g_class_cycle<FR>(ctx, st, K, L, o, it));
+        else if (K.model == MG_SYMMETRON) ACHK(g_class_cycle<SYM>(ctx, st, K, L, o, it));
+        else ACHK(g_class_cycle<CQ>(ctx, st, K, L, o, it));
       }
+    ACHK(g_join(ctx, ns));  // before the control words are rewritten
   }
   if (!trial) {
+    ACHK(g_fork(ctx, ns));
     for (size_t c = 0; c < cls.size(); ++c) {
       const GClass& K = cls[c];
       const Lev* L = &levs[c * kMaxLevB];
       const GBox* tab = ctx->gtab + K.first;
       const dim3 g0(nblk(2 * L[0].half), K.count);
+      hipStream_t st = cst(c);
       if (K.model == MG_FR) {
-        kg_unpack<FR><<<g0, kBlock, 0, ctx->stream>>>(tab);
-        kg_force<FR><<<g0, kBlock, 0, ctx->stream>>>(tab);
+        kg_unpack<FR><<<g0, kBlock, 0, st>>>(tab);
+        kg_force<FR><<<g0, kBlock, 0, st>>>(tab);
       } else if (K.model == MG_SYMMETRON) {
-        kg_unpack<SYM><<<g0, kBlock, 0, ctx->stream>>>(tab);
-        kg_force<SYM><<<g0, kBlock, 0, ctx->stream>>>(tab);
+        kg_unpack<SYM><<<g0, kBlock, 0, st>>>(tab);
+        kg_force<SYM><<<g0, kBlock, 0, st>>>(tab);
       } else {
-        kg_unpack<CQ><<<g0, kBlock, 0, ctx->stream>>>(tab);
-        kg_force<CQ><<<g0, kBlock, 0, ctx->stream>>>(tab);
+        kg_unpack<CQ><<<g0, kBlock, 0, st>>>(tab);
+        kg_force<CQ><<<g0, kBlock, 0, st>>>(tab);
       }
     }
     LAUNCHCHK();
+    ACHK(g_join(ctx, ns));
   }
   // the host table must outlive its asynchronous upload
   HIPCHK(hipStreamSynchronize(ctx->stream));
