@@ -134,7 +134,9 @@ struct mg_ctx {
   double* scal = nullptr;      // device scalars
   double* hscal = nullptr;     // pinned host mirror
   int64_t* cic = nullptr;      // CIC fixed-point accumulator (direct path)
-  float* cic_sorted = nullptr;  // binned CIC: positions in (tile, class) bin order
+  uint2* cic_rec = nullptr;     // binned CIC: run records, one region per count block
+  uint32_t* cic_nrec = nullptr;  // records per region
+  unsigned long long* cic_runs = nullptr;  // runs in (tile, class) bin order
   int64_t cic_np = 0;
   uint32_t* cic_cnt = nullptr;  // counts, offsets, cursors per (tile, class) bin
   int cic_direct = 0;           // 1: always the direct atomic path (MGGPU_CIC_DIRECT)
@@ -2046,33 +2048,53 @@ __device__ __forceinline__ CicCell cic_cell(int n, const float* __restrict__ pos
     const double fl = floor(s);
     c.t[a] = s - fl;
     int q = (int)fl;
-    q %= n;
-    if (q < 0) q += n;
+    if (q < 0 || q >= n) {  // periodic wrap; only q = -1 for positions in [0, n)
+      q %= n;
+      if (q < 0) q += n;
+    }
     c.i0[a] = q;
   }
   return c;
 }
+// 8 fixed-point weights (units of 2^-32) summing to exactly 2^32, corner q:
+// dx = q&1, dy = (q>>1)&1, dz = q>>2, axis weights (1 - t, t).  The corner
+// whose axis weights are all the larger ones ("big", >= 1/8) takes 2^32
+// minus the other seven; each of those is ((wx wy) wz) 2^32 formed in FP64
+// and rounded to nearest even, at most 2^31 (one factor is <= 1/2), so it
+// converts to 32 bits directly.  No weight is negative.
+__device__ __forceinline__ void cic_weights(const CicCell& c, long long* w) {
+  const double wx[2] = {1.0 - c.t[0], c.t[0]};
+  const double wy[2] = {1.0 - c.t[1], c.t[1]};
+  const double wz[2] = {(1.0 - c.t[2]) * 4294967296.0, c.t[2] * 4294967296.0};
+  const int big = (c.t[0] > 0.5 ? 1 : 0) | (c.t[1] > 0.5 ? 2 : 0) | (c.t[2] > 0.5 ? 4 : 0);
+  long long tot = 0;
+#pragma unroll
+  for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 2; ++dx) {
+      const double xy = wx[dx] * wy[dy];
+#pragma unroll
+      for (int dz = 0; dz < 2; ++dz) {
+        const int q = dx | (dy << 1) | (dz << 2);
+        w[q] = q == big ? 0ll : (long long)(uint32_t)rint(xy * wz[dz]);
+        tot += w[q];
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (q == big) w[q] = (1ll << 32) - tot;
+}
 // CIC: per axis, s = x - 1/2, i0 = floor(s), t = s - i0 (formed in FP64, so
-// exact for every float position); weights (1-t, t) to cells i0, i0+1 (periodic).  The 8
-// products are formed in FP64 and deposited as 32.32 fixed point; the last
-// weight is 2^32 minus the other seven so each particle adds exactly 1.
+// exact for every float position); weights (1-t, t) to cells i0, i0+1
+// (periodic), deposited as 32.32 fixed point (cic_weights).
 __global__ __launch_bounds__(kBlock) void k_cic(int n, int64_t np, const float* __restrict__ pos,
                                                 unsigned long long* __restrict__ acc) {
   int64_t p = gid();
   if (p >= np) return;
   const CicCell c = cic_cell(n, pos, p);
   const int* i0 = c.i0;
-  const double* t = c.t;
   long long w[8];
-  long long tot = 0;
-#pragma unroll
-  for (int q = 0; q < 7; ++q) {
-    int di = q & 1, dj = (q >> 1) & 1, dk = (q >> 2) & 1;
-    double ww = (di ? t[0] : 1.0 - t[0]) * (dj ? t[1] : 1.0 - t[1]) * (dk ? t[2] : 1.0 - t[2]);
-    w[q] = llrint(ww * 4294967296.0);
-    tot += w[q];
-  }
-  w[7] = 4294967296LL - tot;
+  cic_weights(c, w);
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     if (w[q] == 0) continue;
@@ -2099,19 +2121,6 @@ __global__ __launch_bounds__(kBlock) void k_cic_finish(int64_t m, const unsigned
 constexpr int kT = 16;  // tile edge (cells)
 constexpr int kT3 = kT * kT * kT;
 
-// 8 fixed-point weights summing to exactly 2^32 (corner q: dx = q&1, dy, dz)
-__device__ __forceinline__ void cic_weights(const CicCell& c, long long* w) {
-  long long tot = 0;
-#pragma unroll
-  for (int q = 0; q < 7; ++q) {
-    int di = q & 1, dj = (q >> 1) & 1, dk = (q >> 2) & 1;
-    double ww = (di ? c.t[0] : 1.0 - c.t[0]) * (dj ? c.t[1] : 1.0 - c.t[1]) *
-                (dk ? c.t[2] : 1.0 - c.t[2]);
-    w[q] = llrint(ww * 4294967296.0);
-    tot += w[q];
-  }
-  w[7] = 4294967296LL - tot;
-}
 __device__ __forceinline__ uint32_t bin_of(const CicCell& c, int nt) {
   const uint32_t t =
       ((uint32_t)(c.i0[2] / kT) * nt + (uint32_t)(c.i0[1] / kT)) * nt + (uint32_t)(c.i0[0] / kT);
@@ -2120,8 +2129,8 @@ __device__ __forceinline__ uint32_t bin_of(const CicCell& c, int nt) {
   return 8u * t + cls;
 }
 
-// Wave-level runs of equal bins (consecutive lanes, same bin): the run's
-// first lane adds the run length to the bin's counter.
+// Wave-level runs of equal bins: consecutive lanes (consecutive particles)
+// whose particles fall in the same bin.
 struct CicRun {
   int leader;    // lane of the run's first particle
   uint32_t len;  // run length (on the leader)
@@ -2142,21 +2151,58 @@ __device__ __forceinline__ CicRun cic_run(uint32_t t, bool valid) {
   return r;
 }
 
-// count and scatter take kCicPer particles per thread, strided by the block
-// size so that each wave's particles stay consecutive; all loads (and the
-// scatter's cursor atomics) are issued before their results are used
+// The count and placement passes take a region of kCicRegion consecutive
+// particles per workgroup, kCicRounds rounds of kCicPer groups of kCicCB
+// consecutive particles (a wave's 64 lanes hold 64 consecutive particles);
+// all loads of a round are issued before their results are used.
+constexpr int kCicCB = 512;    // workgroup size of the count and placement passes
 constexpr int kCicPer = 4;
+constexpr int kCicRounds = 4;
+constexpr int kCicRegion = kCicCB * kCicPer * kCicRounds;  // particles (and at most runs)
+constexpr int kCicBinBits = 26;  // run record: bin | (length - 1) << 26
+// Per-workgroup LDS table bin -> count (open addressing, linear probing):
+// the global counters and cursors take one atomic per distinct bin of a
+// region instead of one per run.  A bin whose probe window is full is
+// counted or placed with its own global atomics (consistent: no entry is
+// ever removed, so a bin is either in its window or never inserted).
+constexpr int kCicH = 4096;
+constexpr int kCicProbe = 32;
+constexpr uint32_t kCicEmpty = 0xffffffffu;
+__device__ __forceinline__ uint32_t cic_hash(uint32_t bin) {
+  return (bin * 2654435761u) >> (32 - 12);
+}
+// slot of bin in the table, inserting it if absent; -1 if its window is full
+__device__ __forceinline__ int cic_insert(uint32_t* key, uint32_t bin) {
+  uint32_t h = cic_hash(bin);
+  for (int k = 0; k < kCicProbe; ++k) {
+    const uint32_t old = atomicCAS(&key[h], kCicEmpty, bin);
+    if (old == kCicEmpty || old == bin) return (int)h;
+    h = (h + 1) & (kCicH - 1);
+  }
+  return -1;
+}
+// slot of bin in the finished table; -1 if it was never inserted
+__device__ __forceinline__ int cic_find(const uint32_t* key, uint32_t bin) {
+  uint32_t h = cic_hash(bin);
+  for (int k = 0; k < kCicProbe; ++k) {
+    const uint32_t v = key[h];
+    if (v == bin) return (int)h;
+    if (v == kCicEmpty) return -1;
+    h = (h + 1) & (kCicH - 1);
+  }
+  return -1;
+}
 struct CicChunk {
   float x[kCicPer][3];
   uint32_t bin[kCicPer];
   bool valid[kCicPer];
 };
+// particle first + q kCicCB + threadIdx.x for q < kCicPer
 __device__ __forceinline__ void cic_chunk(int n, int nt, int64_t np, const float* __restrict__ pos,
-                                          CicChunk& c) {
-  const int64_t base = (int64_t)blockIdx.x * (kBlock * kCicPer) + threadIdx.x;
+                                          int64_t first, CicChunk& c) {
 #pragma unroll
   for (int q = 0; q < kCicPer; ++q) {
-    const int64_t p = base + (int64_t)q * kBlock;
+    const int64_t p = first + (int64_t)q * kCicCB + threadIdx.x;
     c.valid[q] = p < np;
 #pragma unroll
     for (int a = 0; a < 3; ++a) c.x[q][a] = c.valid[q] ? pos[3 * p + a] : 0.f;
@@ -2166,19 +2212,75 @@ __device__ __forceinline__ void cic_chunk(int n, int nt, int64_t np, const float
     c.bin[q] = c.valid[q] ? bin_of(cic_cell(n, c.x[q], 0), nt) : 0xffffffffu;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cic_count(int n, int nt, int64_t np,
-                                                      const float* __restrict__ pos,
-                                                      uint32_t* cnt) {
-  CicChunk c;
-  cic_chunk(n, nt, np, pos, c);
-#pragma unroll
-  for (int q = 0; q < kCicPer; ++q) {
-    const CicRun r = cic_run(c.bin[q], c.valid[q]);
-    if (r.lead) atomicAdd(cnt + c.bin[q], r.len);
+// Count pass: each run of equal bins becomes one record {first particle,
+// bin | (length - 1) << 26}, written compacted into the workgroup's own
+// region (no global counter), with the region's record count in nrec;
+// cnt[bin] counts runs.  Particles in a spatially coherent order (a
+// Lagrangian grid order) give runs of several particles, so the records are
+// a small fraction of the positions' bytes; a random order degrades to one
+// record per particle and stays correct.
+__global__ __launch_bounds__(kCicCB) void k_cic_runs(int n, int nt, int64_t np,
+                                                     const float* __restrict__ pos, uint32_t* cnt,
+                                                     uint2* __restrict__ rec,
+                                                     uint32_t* __restrict__ nrec) {
+  constexpr int kW = kCicCB / 64;
+  __shared__ uint32_t key[kCicH], val[kCicH];
+  __shared__ uint32_t wcount[kCicPer * kW], woff[kCicPer * kW];
+  static_assert(kCicPer * kW <= 64, "one wave scans the per-(group, wave) run counts");
+  for (int h = threadIdx.x; h < kCicH; h += kCicCB) {
+    key[h] = kCicEmpty;
+    val[h] = 0u;
   }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint2* R = rec + (int64_t)blockIdx.x * kCicRegion;
+  uint32_t rbase = 0;  // records written by the earlier rounds (same on every thread)
+  for (int round = 0; round < kCicRounds; ++round) {
+    const int64_t first = (int64_t)blockIdx.x * kCicRegion + (int64_t)round * kCicCB * kCicPer;
+    CicChunk c;
+    cic_chunk(n, nt, np, pos, first, c);
+    CicRun r[kCicPer];
+    uint32_t rank[kCicPer];
+#pragma unroll
+    for (int q = 0; q < kCicPer; ++q) {
+      r[q] = cic_run(c.bin[q], c.valid[q]);
+      const unsigned long long m = __ballot(r[q].lead);
+      rank[q] = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      if (lane == 0) wcount[q * kW + wv] = (uint32_t)__popcll(m);
+      if (r[q].lead) {
+        const int h = cic_insert(key, c.bin[q]);
+        if (h >= 0) atomicAdd(&val[h], 1u);
+        else atomicAdd(cnt + c.bin[q], 1u);
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {  // exclusive scan of the counts in (group, wave) order
+      const uint32_t v = lane < kCicPer * kW ? wcount[lane] : 0u;
+      uint32_t inc = v;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
+      }
+      if (lane < kCicPer * kW) woff[lane] = inc - v;
+    }
+    __syncthreads();
+    const uint32_t total = woff[kCicPer * kW - 1] + wcount[kCicPer * kW - 1];
+#pragma unroll
+    for (int q = 0; q < kCicPer; ++q)
+      if (r[q].lead)
+        R[rbase + woff[q * kW + wv] + rank[q]] =
+            make_uint2((uint32_t)(first + (int64_t)q * kCicCB + threadIdx.x),
+                       c.bin[q] | ((r[q].len - 1u) << kCicBinBits));
+    rbase += total;
+    __syncthreads();  // wcount and woff are rewritten by the next round; the table is complete after the last
+  }
+  for (int h = threadIdx.x; h < kCicH; h += kCicCB)
+    if (key[h] != kCicEmpty) atomicAdd(cnt + key[h], val[h]);
+  if (threadIdx.x == 0) nrec[blockIdx.x] = rbase;
 }
 // Exclusive scan of the bin counts (8 per tile, a tile's bins contiguous) in
-// one block, 1024 tiles per round: bin offsets and scatter cursors.
+// one block, 1024 tiles per round: bin offsets and placement cursors.
 __global__ __launch_bounds__(1024) void k_cic_scan(const uint32_t* __restrict__ cnt,
                                                    int64_t ntiles, uint32_t* __restrict__ boff,
                                                    uint32_t* __restrict__ cur) {
@@ -2225,51 +2327,79 @@ __global__ __launch_bounds__(1024) void k_cic_scan(const uint32_t* __restrict__ 
     __syncthreads();  // wsum is rewritten by the next round
   }
 }
-__global__ __launch_bounds__(kBlock) void k_cic_scatter(int n, int nt, int64_t np,
-                                                        const float* __restrict__ pos,
-                                                        uint32_t* cur, float* __restrict__ sorted) {
-  CicChunk c;
-  cic_chunk(n, nt, np, pos, c);
-  const int lane = threadIdx.x & 63;
-  CicRun r[kCicPer];
-  uint32_t base[kCicPer];
-#pragma unroll
-  for (int q = 0; q < kCicPer; ++q) {
-    r[q] = cic_run(c.bin[q], c.valid[q]);
-    base[q] = r[q].lead ? atomicAdd(cur + c.bin[q], r[q].len) : 0u;
+// Placement: each record goes to the next slot of its bin, as the word
+// first particle << 6 | (length - 1).  One workgroup per count region: the
+// region's runs of one bin take consecutive slots, reserved with one global
+// atomic per distinct bin (the table of the count pass, rebuilt).
+__global__ __launch_bounds__(kCicCB) void k_cic_place(const uint2* __restrict__ rec,
+                                                      const uint32_t* __restrict__ nrec,
+                                                      uint32_t* cur,
+                                                      unsigned long long* __restrict__ runs) {
+  __shared__ uint32_t key[kCicH], val[kCicH], base[kCicH];
+  for (int h = threadIdx.x; h < kCicH; h += kCicCB) {
+    key[h] = kCicEmpty;
+    val[h] = 0u;
   }
-#pragma unroll
-  for (int q = 0; q < kCicPer; ++q) {
-    const uint32_t slot = __shfl(base[q], r[q].leader, 64) + (uint32_t)(lane - r[q].leader);
-    if (c.valid[q]) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) sorted[3 * (int64_t)slot + a] = c.x[q][a];
+  __syncthreads();
+  const uint32_t nr = nrec[blockIdx.x];
+  const uint2* R = rec + (int64_t)blockIdx.x * kCicRegion;
+  for (uint32_t i = threadIdx.x; i < nr; i += kCicCB) {
+    const int h = cic_insert(key, R[i].y & ((1u << kCicBinBits) - 1u));
+    if (h >= 0) atomicAdd(&val[h], 1u);
+  }
+  __syncthreads();
+  for (int h = threadIdx.x; h < kCicH; h += kCicCB)
+    if (key[h] != kCicEmpty) {
+      base[h] = atomicAdd(cur + key[h], val[h]);
+      val[h] = 0u;
     }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < nr; i += kCicCB) {
+    const uint2 v = R[i];
+    const uint32_t bin = v.y & ((1u << kCicBinBits) - 1u);
+    const int h = cic_find(key, bin);
+    const uint32_t slot = h >= 0 ? base[h] + atomicAdd(&val[h], 1u) : atomicAdd(cur + bin, 1u);
+    runs[slot] = ((unsigned long long)v.x << 6) | (unsigned long long)(v.y >> kCicBinBits);
   }
 }
 // One workgroup per tile.  Segments: the tile's own 8 bins (one contiguous
-// range, role 0) and, for each lower neighbour at offset -s (s a non-empty
-// subset of the axes, role s), its bins whose class contains s.  In role s a
-// particle's local coordinate on axis a is its in-tile layer minus kT s_a, and
-// only corners that land inside the tile are added: each corner of each
-// particle lands in exactly one (tile, role).
+// range of runs, role 0) and, for each lower neighbour at offset -s (s a
+// non-empty subset of the axes, role s), its bins whose class contains s.
+// In role s a particle's local coordinate on axis a is its in-tile layer
+// minus kT s_a, and only corners that land inside the tile are added: each
+// corner of each particle lands in exactly one (tile, role).  Runs are taken
+// kCicTB at a time: their lengths are prefix-summed, the batch's particles
+// are numbered consecutively, and a bitmap of run starts (with per-word
+// prefix counts) maps a particle number to its run in one LDS read, so that
+// consecutive threads read consecutive particles of a run.  Workgroups of
+// one XCD (every 8th workgroup id) take a contiguous range of tiles, so
+// tiles that share position cache lines run on the same L2.
 constexpr int kCicSegs = 20;  // 1 + 4 + 4 + 2 + 4 + 2 + 2 + 1
-constexpr int kCicUnroll = 2;  // particles per thread in flight
+constexpr int kCicUnroll = 4;  // particles per thread in flight
 constexpr int kCicTB = 512;    // workgroup size of the tile kernel
-__global__ __launch_bounds__(kCicTB) void k_cic_tile(int n, int nt, const float* __restrict__ sorted,
+constexpr int kCicWords = kCicTB * 64 / 32;  // bitmap words: a batch holds <= 64 kCicTB particles
+__global__ __launch_bounds__(kCicTB) void k_cic_tile(int n, int nt, const float* __restrict__ pos,
+                                                     const unsigned long long* __restrict__ runs,
                                                      const uint32_t* __restrict__ boff,
                                                      const uint32_t* __restrict__ cnt, double scale,
                                                      float* __restrict__ delta) {
-  __shared__ unsigned long long acc[kT3];
+  // kT^3 cells, then one slot per lane for the corners outside the tile
+  // (every corner is deposited, those outside into the lane's own slot)
+  __shared__ unsigned long long acc[kT3 + 64];
   __shared__ uint32_t seg_lo[kCicSegs], seg_end[kCicSegs];
   __shared__ int seg_role[kCicSegs];
-  const uint32_t t = blockIdx.x;
+  __shared__ uint2 rinfo[kCicTB];    // run: first particle minus its batch number, role
+  __shared__ uint2 bm[kCicWords];    // run-start bits, runs starting in earlier words
+  __shared__ uint32_t wsum[kCicTB / 64];
+  const uint32_t ntiles = (uint32_t)nt * nt * nt;
+  uint32_t t = blockIdx.x;
+  if (ntiles % 8 == 0) t = (t & 7u) * (ntiles / 8) + (t >> 3);
   const int ti = (int)(t % nt), tj = (int)((t / nt) % nt), tk = (int)(t / ((uint32_t)nt * nt));
   for (int q = threadIdx.x; q < kT3; q += kCicTB) acc[q] = 0ull;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x < 64) {
     // lane i < kCicSegs: segment i is (role s, class c), enumerated in order
     // of s and then c with (c & s) == s; lane 0 is the own tile's 8 bins
-    const int lane = threadIdx.x;
     int s = 0, c = 0;
     if (lane > 0 && lane < kCicSegs) {
       int k = 0;
@@ -2310,40 +2440,100 @@ __global__ __launch_bounds__(kCicTB) void k_cic_tile(int n, int nt, const float*
   __syncthreads();
   const uint32_t total = seg_end[kCicSegs - 1];
   int sg = 0;
-  for (uint32_t g0 = threadIdx.x; g0 < total; g0 += kCicUnroll * kCicTB) {
-    CicCell cc[kCicUnroll];
-    int role[kCicUnroll];
-    bool ok[kCicUnroll];
+  for (uint32_t r0 = 0; r0 < total; r0 += kCicTB) {
+    // this batch's runs: first particle, role, and the exclusive prefix of
+    // the lengths (the batch number of the run's first particle)
+    for (int w = threadIdx.x; w < kCicWords; w += kCicTB) bm[w].x = 0u;
+    const uint32_t r = r0 + threadIdx.x;
+    uint32_t len = 0, p0 = 0;
+    int role = 0;
+    if (r < total) {
+      while (r >= seg_end[sg]) ++sg;
+      const uint32_t start = sg ? seg_end[sg - 1] : 0u;
+      const unsigned long long v = runs[seg_lo[sg] + (r - start)];
+      p0 = (uint32_t)(v >> 6);
+      len = (uint32_t)(v & 63ull) + 1u;
+      role = seg_role[sg];
+    }
+    uint32_t inc = len;
 #pragma unroll
-    for (int u = 0; u < kCicUnroll; ++u) {
-      const uint32_t g = g0 + (uint32_t)u * kCicTB;
-      ok[u] = g < total;
-      role[u] = 0;
-      if (ok[u]) {
-        while (g >= seg_end[sg]) ++sg;
-        const uint32_t start = sg ? seg_end[sg - 1] : 0u;
-        role[u] = seg_role[sg];
-        cc[u] = cic_cell(n, sorted, (int64_t)seg_lo[sg] + (g - start));
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();  // wsum complete, bitmap cleared
+    uint32_t wpre = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kCicTB / 64; ++w) {
+      const uint32_t sw = wsum[w];
+      wpre += w < wv ? sw : 0u;
+      all += sw;
+    }
+    const uint32_t first = wpre + inc - len;
+    rinfo[threadIdx.x] = make_uint2(p0 - first, (uint32_t)role);
+    if (len) atomicOr(&bm[first >> 5].x, 1u << (first & 31));
+    __syncthreads();  // bits set; wsum is reused by the word scan
+    {
+      // exclusive prefix of the run starts over the words (2 per thread)
+      const uint32_t c0 = __popc(bm[2 * threadIdx.x].x), c1 = __popc(bm[2 * threadIdx.x + 1].x);
+      uint32_t ic = c0 + c1;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(ic, d, 64);
+        if (lane >= d) ic += y;
+      }
+      if (lane == 63) wsum[wv] = ic;
+      __syncthreads();
+      uint32_t wp = 0;
+#pragma unroll
+      for (int w = 0; w < kCicTB / 64; ++w) wp += w < wv ? wsum[w] : 0u;
+      const uint32_t e0 = wp + ic - c0 - c1;
+      bm[2 * threadIdx.x].y = e0;
+      bm[2 * threadIdx.x + 1].y = e0 + c0;
+    }
+    __syncthreads();
+    for (uint32_t g0 = threadIdx.x; g0 < all; g0 += kCicUnroll * kCicTB) {
+      CicCell cc[kCicUnroll];
+      int rl[kCicUnroll];
+      bool ok[kCicUnroll];
+#pragma unroll
+      for (int u = 0; u < kCicUnroll; ++u) {
+        const uint32_t g = g0 + (uint32_t)u * kCicTB;
+        ok[u] = g < all;
+        rl[u] = 0;
+        if (ok[u]) {
+          const uint2 e = bm[g >> 5];
+          const uint32_t k = e.y + __popc(e.x & ((2u << (g & 31)) - 1u)) - 1u;
+          const uint2 info = rinfo[k];
+          rl[u] = (int)info.y;
+          cc[u] = cic_cell(n, pos, (int64_t)(uint32_t)(info.x + g));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kCicUnroll; ++u) {
+        if (!ok[u]) continue;
+        const int s = rl[u];
+        long long w[8];
+        cic_weights(cc[u], w);
+        // local lower corner in [-1, kT - 1] per axis (-1: the lower
+        // neighbour's last layer, role bit set)
+        const int a = (cc[u].i0[0] & (kT - 1)) - ((s & 1) ? kT : 0);
+        const int b = (cc[u].i0[1] & (kT - 1)) - ((s & 2) ? kT : 0);
+        const int d = (cc[u].i0[2] & (kT - 1)) - ((s & 4) ? kT : 0);
+        const bool ox[2] = {a >= 0, a < kT - 1}, oy[2] = {b >= 0, b < kT - 1},
+                   oz[2] = {d >= 0, d < kT - 1};
+        const int c0 = (d * kT + b) * kT + a;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+          const int at = ox[dx] && oy[dy] && oz[dz] ? c0 + (dz * kT + dy) * kT + dx : kT3 + lane;
+          atomicAdd(&acc[at], (unsigned long long)w[q]);
+        }
       }
     }
-#pragma unroll
-    for (int u = 0; u < kCicUnroll; ++u) {
-      if (!ok[u]) continue;
-      const int s = role[u];
-      long long w[8];
-      cic_weights(cc[u], w);
-      const int a = (cc[u].i0[0] & (kT - 1)) - ((s & 1) ? kT : 0);
-      const int b = (cc[u].i0[1] & (kT - 1)) - ((s & 2) ? kT : 0);
-      const int d = (cc[u].i0[2] & (kT - 1)) - ((s & 4) ? kT : 0);
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int x = a + (r & 1), y = b + ((r >> 1) & 1), z = d + ((r >> 2) & 1);
-        if (w[r] == 0 || x < 0 || x >= kT || y < 0 || y >= kT || z < 0 || z >= kT) continue;
-        atomicAdd(&acc[(z * kT + y) * kT + x], (unsigned long long)w[r]);
-      }
-    }
+    __syncthreads();  // rinfo, bm and wsum are rewritten by the next batch
   }
-  __syncthreads();
   for (int q = threadIdx.x; q < kT3; q += kCicTB) {
     const int x = q % kT, y = (q / kT) % kT, z = q / (kT * kT);
     const int64_t cell = ((int64_t)(tk * kT + z) * n + (tj * kT + y)) * n + (ti * kT + x);
@@ -2575,12 +2765,17 @@ int cic_assign(mg_ctx* ctx, const float* pos, int64_t np, float* delta_out) {
   int n = ctx->n;
   int64_t m = (int64_t)n * n * n;
   double scale = double(m) / double(np) / 4294967296.0;
-  if (n % kT == 0 && np < (int64_t)0xffffffffLL && !ctx->cic_direct) {
-    // binned path: count per bin, scan, scatter, per-tile LDS deposit
-    int nt = n / kT;
-    int64_t ntiles = (int64_t)nt * nt * nt;
+  const int nt = n / kT;
+  const int64_t ntiles = (int64_t)nt * nt * nt;
+  if (n % kT == 0 && np < (int64_t)0xffffffffLL - kCicRegion &&
+      8 * ntiles < ((int64_t)1 << kCicBinBits) && !ctx->cic_direct) {
+    // binned path: runs of equal bins counted and recorded, scan, runs
+    // placed in bin order, per-tile LDS deposit
+    const unsigned nbp = (unsigned)((np + kCicRegion - 1) / kCicRegion);
     if (ctx->cic_np < np) {
-      ACHK(dalloc(ctx, &ctx->cic_sorted, 3 * np));
+      ACHK(dalloc(ctx, &ctx->cic_rec, (int64_t)nbp * kCicRegion));
+      ACHK(dalloc(ctx, &ctx->cic_nrec, (int64_t)nbp));
+      ACHK(dalloc(ctx, &ctx->cic_runs, np));
       ctx->cic_np = np;
     }
     if (!ctx->cic_cnt) ACHK(dalloc(ctx, &ctx->cic_cnt, 3 * 8 * ntiles));
@@ -2588,11 +2783,10 @@ int cic_assign(mg_ctx* ctx, const float* pos, int64_t np, float* delta_out) {
     uint32_t* boff = cnt + 8 * ntiles;
     uint32_t* cur = boff + 8 * ntiles;
     k_fill<uint32_t><<<nblk(8 * ntiles), kBlock, 0, ctx->stream>>>(cnt, 8 * ntiles, 0u);
-    const unsigned nbp = (unsigned)((np + kBlock * kCicPer - 1) / (kBlock * kCicPer));
-    k_cic_count<<<nbp, kBlock, 0, ctx->stream>>>(n, nt, np, pos, cnt);
+    k_cic_runs<<<nbp, kCicCB, 0, ctx->stream>>>(n, nt, np, pos, cnt, ctx->cic_rec, ctx->cic_nrec);
     k_cic_scan<<<1, 1024, 0, ctx->stream>>>(cnt, ntiles, boff, cur);
-    k_cic_scatter<<<nbp, kBlock, 0, ctx->stream>>>(n, nt, np, pos, cur, ctx->cic_sorted);
-    k_cic_tile<<<(unsigned)ntiles, kCicTB, 0, ctx->stream>>>(n, nt, ctx->cic_sorted, boff, cnt,
+    k_cic_place<<<nbp, kCicCB, 0, ctx->stream>>>(ctx->cic_rec, ctx->cic_nrec, cur, ctx->cic_runs);
+    k_cic_tile<<<(unsigned)ntiles, kCicTB, 0, ctx->stream>>>(n, nt, pos, ctx->cic_runs, boff, cnt,
                                                              scale, delta_out);
     LAUNCHCHK();
     return MG_OK;

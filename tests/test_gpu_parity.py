@@ -135,11 +135,16 @@ def test_cic_matches_oracle(c1):
 def test_cic_binned_equals_direct(n, monkeypatch):
     """Both paths sum the same 32.32 fixed-point weights exactly, so the binned
     path (one tile at n=16, the lower and upper neighbour tile the same at
-    n=32) must agree with the direct atomic path bit for bit."""
+    n=32) must agree with the direct atomic path bit for bit.  Besides a
+    Zel'dovich grid (runs of about a tile edge), a shuffled uniform set gives
+    runs of one particle (thousands of runs per tile, many batches of the
+    tile kernel) and a clump in one cell gives full 64-particle runs."""
     say("cic binned vs direct", n)
     rng = np.random.default_rng(40 + n)
     pos = np.concatenate([synthetic.zeldovich_positions(n, n // 2 + 4, seed=n, dtype=np.float32),
-                          rng.uniform(0, n, (777, 3)).astype(np.float32)])
+                          rng.uniform(0, n, (777, 3)).astype(np.float32),
+                          rng.uniform(0, n, (60000, 3)).astype(np.float32),
+                          (3.1 + 0.7 * rng.random((30001, 3))).astype(np.float32)])
     pos[:20] = np.float32(n - 1e-4)
     pos[20:40] = 0.0
     pos[40:80, 0] = np.float32(15.5)  # lower cell on a tile's last layer
