@@ -159,6 +159,118 @@ def _timed(fn, reps):
     return (time.perf_counter() - t0) * 1e3 / reps
 
 
+def cycle_costs(mg, delta, field, n, fr0, tol):
+    """V, F and W cycles on the same 512^3 f(R) problem (the comparison of
+    the paper's convergence tests): two cycles from the background with no
+    convergence test (FP64 FAS; refined: one outer step of two FP32 cycles),
+    their time and the residual reduction, then the solve to tol."""
+    import math
+
+    from paper_2110_00328_amd import api
+
+    prm = api.model_params(float(n), fr0=fr0)
+    rows = []
+    for prec in ("fp64", "fp32"):
+        for cyc in ("V", "F", "W"):
+            k = 2
+            o = api.solver_opts(cycle=cyc, precision=prec, fixed_cycles=k)
+            st = {}
+
+            def fixed():
+                _, s = mg.solve("fr", prm, delta, out=field, tol=tol, opts=o)
+                st["rel"] = s.rel_resid
+
+            ms = _timed(fixed, 3)
+            ot = api.solver_opts(cycle=cyc, precision=prec)
+            tt = {}
+
+            def to_tol():
+                _, s = mg.solve("fr", prm, delta, out=field, tol=tol, opts=ot)
+                tt.update(cycles=s.vcycles, rel=s.rel_resid)
+
+            ms_tol = _timed(to_tol, 2)
+            digits = -math.log10(st["rel"]) if st["rel"] > 0 else float("inf")
+            rows.append(dict(cycle=cyc, precision=prec, fixed_cycles=k, ms=ms,
+                             rel_after=st["rel"], contraction_per_cycle=st["rel"] ** (1.0 / k),
+                             digits_per_ms=digits / ms, ms_to_tol=ms_tol,
+                             cycles_to_tol=tt["cycles"], rel_at_tol=tt["rel"]))
+    return dict(problem=f"f(R) |f_R0|={fr0:g}, {n}^3 CIC density, from the background",
+                tol=tol, rows=rows)
+
+
+def batched_leg(dev, tol):
+    """The 64-box sweep (64^3 / 96^3 / 128^3, f(R) with log-uniform |f_R0|
+    and symmetron) through mg_solve_batched after tuning, against the same
+    boxes solved one after another, with each box's error against its own
+    single-box FP64 solve."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_2110_00328_amd import api
+
+    # 64 boxes of 64^3 / 96^3 / 128^3, f(R) with log-uniform |f_R0| and symmetron
+    spec = synthetic.c4_boxes()
+    boxes = []
+    for b in spec:
+        nb = b["n"]
+        prm = api.model_params(b["box"], **b["params"])
+        boxes.append(dict(n=nb, model=b["model"], params=prm,
+                          delta=torch.from_numpy(b["delta"].astype(np.float32)).to(dev),
+                          field=torch.empty((nb, nb, nb), dtype=torch.float64, device=dev),
+                          force=torch.empty((3, nb, nb, nb), dtype=torch.float32, device=dev)))
+    cells_total = sum(b["n"] ** 3 for b in boxes)
+    o = api.solver_opts(precision="fp32")
+    bctx = api.Context(boxes[0]["n"], device=dev)
+    os.environ.setdefault("MGGPU_TUNE_CACHE", os.path.join(tempfile.mkdtemp(), "tune.json"))
+    t0 = time.perf_counter()
+    bctx.batched_tune(boxes, opts=o)
+    tune_ms = (time.perf_counter() - t0) * 1e3
+    stats = []
+    b_ms = _timed(lambda: stats.__setitem__(slice(None), bctx.solve_batched(boxes, tol=tol, opts=o)),
+                  3)
+    blk, vec, teams = bctx.batched_config()
+    bctx.close()
+    # each box's batched field and force against its own plain FP64 single-box
+    # solve to the same tolerance (max over boxes of the L2 and max-norm ratios)
+    singles = {nb: api.Context(nb, device=dev) for nb in (64, 96, 128)}
+    worst_field = worst_force = 0.0
+    o64 = api.solver_opts(precision="fp64")
+    for b in boxes:
+        c = singles[b["n"]]
+        f64, _ = c.solve(b["model"], b["params"], b["delta"], tol=tol, opts=o64)
+        g64 = c.force(b["model"], b["params"], f64).double()
+        bg = f64.mean()
+        x, g = b["field"], b["force"].double()
+        worst_field = max(worst_field, float((x - f64).norm() / (f64 - bg).norm()),
+                          float((x - f64).abs().max() / (f64 - bg).abs().max()))
+        worst_force = max(worst_force, float((g - g64).norm() / g64.norm()),
+                          float((g - g64).abs().max() / g64.abs().max()))
+        del f64, g64
+
+    def one_by_one():
+        for b in boxes:
+            c = singles[b["n"]]
+            c.solve(b["model"], b["params"], b["delta"], out=b["field"], tol=tol, opts=o)
+            c.force(b["model"], b["params"], b["field"], out=b["force"])
+
+    s_ms = _timed(one_by_one, 2)
+    for c in singles.values():
+        c.close()
+    return dict(
+        boxes=len(boxes), cells=cells_total, ms=b_ms, boxes_per_s=len(boxes) / (b_ms * 1e-3),
+        cells_per_s=cells_total / (b_ms * 1e-3), block=blk, cells_per_thread=4 if vec else 1,
+        teams={0: "persistent launch, single-workgroup teams",
+               1: "persistent launch, one sized team per box",
+               2: "grouped level launches per (n, model) class"}[teams],
+        tune_ms=tune_ms, max_rel_resid=max(s.rel_resid for s in stats),
+        max_err_vs_fp64_single_box=dict(field=worst_field, force=worst_force),
+        outer_steps=[int(min(s.cycles for s in stats)), int(max(s.cycles for s in stats))],
+        one_by_one_ms=s_ms, batched_speedup=s_ms / b_ms)
+
+
 def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
     """The other workloads the metric names, timed outside the main loop:
     |f_R0| = 1e-6 forward+adjoint, coupled quintessence forward (FP32-refined
@@ -217,6 +329,7 @@ def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
         leg[prec + "_cycles"] = dict(st)
     leg["fp64_over_fp32"] = leg["fp64_ms"] / leg["fp32_ms"]
     out["cq_solve_force"] = leg
+    out["cycle_costs"] = cycle_costs(mg, delta, field, n, a.fr0, tol)
     # the particle side after the fifth force, at the same size: Newtonian
     # potential by FFT, total force (potentials summed, then differenced), CIC
     # interpolation of the three components to every particle, friction term
@@ -240,64 +353,7 @@ def extra_legs(a, mg, pos, delta, field, force, cells, n, tol):
     leg["total_force_GBps"] = 28.0 * m_cells(n) / (leg["total_force_ms"] * 1e6)
     out["particle_side"] = leg
     del phin, ppart, pfric, u
-    # 64 boxes of 64^3 / 96^3 / 128^3, f(R) with log-uniform |f_R0| and symmetron
-    spec = synthetic.c4_boxes()
-    boxes = []
-    for b in spec:
-        nb = b["n"]
-        prm = api.model_params(b["box"], **b["params"])
-        boxes.append(dict(n=nb, model=b["model"], params=prm,
-                          delta=torch.from_numpy(b["delta"].astype(np.float32)).to(dev),
-                          field=torch.empty((nb, nb, nb), dtype=torch.float64, device=dev),
-                          force=torch.empty((3, nb, nb, nb), dtype=torch.float32, device=dev)))
-    cells_total = sum(b["n"] ** 3 for b in boxes)
-    o = api.solver_opts(precision="fp32")
-    bctx = api.Context(boxes[0]["n"], device=dev)
-    os.environ.setdefault("MGGPU_TUNE_CACHE", os.path.join(tempfile.mkdtemp(), "tune.json"))
-    t0 = time.perf_counter()
-    bctx.batched_tune(boxes, opts=o)
-    tune_ms = (time.perf_counter() - t0) * 1e3
-    stats = []
-    b_ms = _timed(lambda: stats.__setitem__(slice(None), bctx.solve_batched(boxes, tol=tol, opts=o)),
-                  3)
-    blk, vec, teams = bctx.batched_config()
-    bctx.close()
-    # each box's batched field and force against its own plain FP64 single-box
-    # solve to the same tolerance (max over boxes of the L2 and max-norm ratios)
-    singles = {nb: api.Context(nb, device=dev) for nb in (64, 96, 128)}
-    worst_field = worst_force = 0.0
-    o64 = api.solver_opts(precision="fp64")
-    for b in boxes:
-        c = singles[b["n"]]
-        f64, _ = c.solve(b["model"], b["params"], b["delta"], tol=tol, opts=o64)
-        g64 = c.force(b["model"], b["params"], f64).double()
-        bg = f64.mean()
-        x, g = b["field"], b["force"].double()
-        worst_field = max(worst_field, float((x - f64).norm() / (f64 - bg).norm()),
-                          float((x - f64).abs().max() / (f64 - bg).abs().max()))
-        worst_force = max(worst_force, float((g - g64).norm() / g64.norm()),
-                          float((g - g64).abs().max() / g64.abs().max()))
-        del f64, g64
-
-    def one_by_one():
-        for b in boxes:
-            c = singles[b["n"]]
-            c.solve(b["model"], b["params"], b["delta"], out=b["field"], tol=tol, opts=o)
-            c.force(b["model"], b["params"], b["field"], out=b["force"])
-
-    s_ms = _timed(one_by_one, 2)
-    for c in singles.values():
-        c.close()
-    out["batched_c4"] = dict(
-        boxes=len(boxes), cells=cells_total, ms=b_ms, boxes_per_s=len(boxes) / (b_ms * 1e-3),
-        cells_per_s=cells_total / (b_ms * 1e-3), block=blk, cells_per_thread=4 if vec else 1,
-        teams={0: "persistent launch, single-workgroup teams",
-               1: "persistent launch, one sized team per box",
-               2: "grouped level launches per (n, model) class"}[teams],
-        tune_ms=tune_ms, max_rel_resid=max(s.rel_resid for s in stats),
-        max_err_vs_fp64_single_box=dict(field=worst_field, force=worst_force),
-        outer_steps=[int(min(s.cycles for s in stats)), int(max(s.cycles for s in stats))],
-        one_by_one_ms=s_ms, batched_speedup=s_ms / b_ms)
+    out["batched_c4"] = batched_leg(dev, tol)
     return out
 
 

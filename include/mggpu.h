@@ -359,10 +359,15 @@ int mg_solve_batched(mg_ctx *ctx, int n_box, const mg_box_desc *boxes,
                      const mg_solver_opts *opts, double tol, mg_stats *per_box);
 
 /* Autotuner of the batched solve: times one outer step (2 FP32 cycles) of
- * the given batch with the grouped level launches and with the persistent
- * launch for each workgroup size in {256, 512, 1024}, 1 or 4 cells per
- * thread, and both team splits; keeps the fastest for this context and
- * writes it to the cache file.  Overwrites nothing the caller owns. */
+ * the given batch with the grouped level launches and, for batches below
+ * 8M cells in all, with the persistent launch for each workgroup size in
+ * {256, 512, 1024}, 1 or 4 cells per thread, and both team splits; keeps
+ * the fastest for this context and writes it to the cache file.
+ * Overwrites nothing the caller owns.  The persistent launch is cooperative;
+ * after any cooperative launch the grouped launches of the process run
+ * slower (their class streams no longer overlap as well: 16.6 instead of
+ * 11.8 ms for 64 boxes of 64^3..128^3), which is why larger batches do not
+ * try it. */
 int mg_batched_tune(mg_ctx *ctx, int n_box, const mg_box_desc *boxes,
                     const mg_solver_opts *opts, int *block_out, int *vec_out);
 /* Shape the last batched call used: workgroup size, vec (1: 4 cells per

@@ -4075,38 +4075,12 @@ int mg_batched_tune(mg_ctx* ctx, int n_box, const mg_box_desc* boxes, const mg_s
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
   double best = 1e300;
-  int bb = 1024, bv = 1, bt = 1;
+  int bb = 256, bv = 1, bt = 2;
   std::vector<BoxDev> host;
   std::vector<BoxOut> outs;
-  int rc = MG_OK;
-  for (int vec = 0; vec < 2 && rc == MG_OK; ++vec) {
-    rc = batch_setup(ctx, n_box, boxes, opts, 1e-300, true, vec, host);
-    for (int team = 0; team < 2 && rc == MG_OK; ++team)
-      for (int ci = 0; ci < 3 && rc == MG_OK; ++ci) {
-        const int blk = kTileBlocks[ci];
-        rc = batch_launch(ctx, host, blk, team);  // warm-up
-        if (rc == MG_OK) rc = batch_collect(ctx, n_box, outs);
-        if (rc != MG_OK) break;
-        HIPCHK(hipEventRecord(t0, ctx->stream));
-        rc = batch_launch(ctx, host, blk, team);
-        if (rc != MG_OK) break;
-        HIPCHK(hipEventRecord(t1, ctx->stream));
-        HIPCHK(hipEventSynchronize(t1));
-        rc = batch_collect(ctx, n_box, outs);
-        if (rc != MG_OK) break;
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, t0, t1));
-        if (ms < best) {
-          best = ms;
-          bb = blk;
-          bv = vec;
-          bt = team;
-        }
-      }
-  }
-  // the grouped level launches (teams == 2), timed the same way
-  if (rc == MG_OK) {
-    rc = grouped_solve(ctx, n_box, boxes, opts, 1e-300, true, outs);  // warm-up
+  // the grouped level launches (teams == 2)
+  int rc = grouped_solve(ctx, n_box, boxes, opts, 1e-300, true, outs);  // warm-up
+  {
     if (rc == MG_OK) {
       HIPCHK(hipEventRecord(t0, ctx->stream));
       rc = grouped_solve(ctx, n_box, boxes, opts, 1e-300, true, outs);
@@ -4122,6 +4096,39 @@ int mg_batched_tune(mg_ctx* ctx, int n_box, const mg_box_desc* boxes, const mg_s
       }
     }
   }
+  // The persistent launch is cooperative, and any cooperative launch slows
+  // the grouped path for the rest of the process: the 64-box 64^3..128^3
+  // batch then takes 16.6 instead of 11.8 ms, about its time with the class
+  // streams serialised.  So it is only tried for batches too small to fill
+  // the chip with level launches (below 8M cells in all), where it can win.
+  int64_t batch_cells = 0;
+  for (int b = 0; b < n_box; ++b) batch_cells += (int64_t)boxes[b].n * boxes[b].n * boxes[b].n;
+  if (batch_cells < ((int64_t)8 << 20))
+    for (int vec = 0; vec < 2 && rc == MG_OK; ++vec) {
+      rc = batch_setup(ctx, n_box, boxes, opts, 1e-300, true, vec, host);
+      for (int team = 0; team < 2 && rc == MG_OK; ++team)
+        for (int ci = 0; ci < 3 && rc == MG_OK; ++ci) {
+          const int blk = kTileBlocks[ci];
+          rc = batch_launch(ctx, host, blk, team);  // warm-up
+          if (rc == MG_OK) rc = batch_collect(ctx, n_box, outs);
+          if (rc != MG_OK) break;
+          HIPCHK(hipEventRecord(t0, ctx->stream));
+          rc = batch_launch(ctx, host, blk, team);
+          if (rc != MG_OK) break;
+          HIPCHK(hipEventRecord(t1, ctx->stream));
+          HIPCHK(hipEventSynchronize(t1));
+          rc = batch_collect(ctx, n_box, outs);
+          if (rc != MG_OK) break;
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+          if (ms < best) {
+            best = ms;
+            bb = blk;
+            bv = vec;
+            bt = team;
+          }
+        }
+    }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (rc != MG_OK) return rc;
