@@ -347,12 +347,21 @@ __global__ __launch_bounds__(kBlock) void k_to_h16(int64_t m4, const float* __re
   st4s<h16>(dst + 4 * g, v, enc);
 }
 // block maxima of |x| over m floats
+// block partial maxima of |x| (exact in float), four values per load over
+// a grid-stride loop of kAbsmaxBlocks blocks; x 16-byte aligned
+constexpr int kAbsmaxBlocks = 2048;
 __global__ __launch_bounds__(kBlock) void k_absmax_f32(int64_t m, const float* __restrict__ x,
                                                        double* __restrict__ part) {
   __shared__ double sh[32];
-  const int64_t g = gid();
-  const double v = g < m ? fabs(double(x[g])) : 0.0;
-  const double t = block_max(v, sh);
+  const int64_t m4 = m >> 2;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  float v = 0.0f;
+  for (int64_t q = gid(); q < m4; q += stride) {
+    const float4 a = reinterpret_cast<const float4*>(x)[q];
+    v = fmaxf(v, fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fmaxf(fabsf(a.z), fabsf(a.w))));
+  }
+  for (int64_t q = 4 * m4 + gid(); q < m; q += stride) v = fmaxf(v, fabsf(x[q]));
+  const double t = block_max(double(v), sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 // Maxima of fixed chunks of m partial maxima, one block per chunk

@@ -1565,8 +1565,10 @@ int adjoint_impl(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, const fl
       k_restrict<float, float><<<nblk(cells(ctx->L[l + 1])), kBlock, 0, ctx->stream>>>(
           ctx->L[l], ctx->L[l + 1], A.w32.dg[l], A.w32.dg[l + 1]);
     if (f16) {
-      k_absmax_f32<<<nblk(m), kBlock, 0, ctx->stream>>>(m, A.w32.dg[0], ctx->part4);
-      ACHK(max_on_device(ctx, nblk(m), ctx->part4, ctx->scal + 2));
+      // at most nblk(m) <= part_cap partials
+      const unsigned nb = std::min<unsigned>(kAbsmaxBlocks, nblk((m + 3) / 4));
+      k_absmax_f32<<<nb, kBlock, 0, ctx->stream>>>(m, A.w32.dg[0], ctx->part4);
+      ACHK(max_on_device(ctx, nb, ctx->part4, ctx->scal + 2));
       HIPCHK(hipMemcpyAsync(ctx->hscal + 2, ctx->scal + 2, sizeof(double), hipMemcpyDeviceToHost,
                             ctx->stream));
       HIPCHK(hipStreamSynchronize(ctx->stream));
