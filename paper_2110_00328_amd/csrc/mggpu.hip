@@ -2045,11 +2045,23 @@ __device__ __forceinline__ CicCell cic_cell(int n, const float* __restrict__ pos
   CicCell c;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    // in double the offset and the fraction are exact for any float position
-    const double s = double(pos[3 * p + a]) - 0.5;
-    const double fl = floor(s);
-    c.t[a] = s - fl;
-    int q = (int)fl;
+    // For 1 <= x < 2^22, s = x - 1/2, floor(s) and s - floor(s) are exact in
+    // FP32 (0.5 is a multiple of ulp(x); s - floor(s) by Sterbenz); other
+    // positions take the same three steps in FP64, where they are exact for
+    // any float.  Both give the same i0 and the same t.
+    const float xf = pos[3 * p + a];
+    int q;
+    if (xf >= 1.0f && xf < 4194304.0f) {
+      const float sf = xf - 0.5f;
+      const float fl = floorf(sf);
+      c.t[a] = double(sf - fl);
+      q = (int)fl;
+    } else {
+      const double s = double(xf) - 0.5;
+      const double fl = floor(s);
+      c.t[a] = s - fl;
+      q = (int)fl;
+    }
     if (q < 0 || q >= n) {  // periodic wrap; only q = -1 for positions in [0, n)
       q %= n;
       if (q < 0) q += n;
@@ -2062,8 +2074,11 @@ __device__ __forceinline__ CicCell cic_cell(int n, const float* __restrict__ pos
 // dx = q&1, dy = (q>>1)&1, dz = q>>2, axis weights (1 - t, t).  The corner
 // whose axis weights are all the larger ones ("big", >= 1/8) takes 2^32
 // minus the other seven; each of those is ((wx wy) wz) 2^32 formed in FP64
-// and rounded to nearest even, at most 2^31 (one factor is <= 1/2), so it
-// converts to 32 bits directly.  No weight is negative.
+// and rounded to nearest even, at most 2^31 (one factor is <= 1/2).  The
+// rounding is done by adding 2^52: the sum lies in [2^52, 2^53), where the
+// spacing of doubles is 1, so its low 32 mantissa bits are the rounded
+// weight (the same value as rint, without the conversion instructions).  No
+// weight is negative.
 __device__ __forceinline__ void cic_weights(const CicCell& c, long long* w) {
   const double wx[2] = {1.0 - c.t[0], c.t[0]};
   const double wy[2] = {1.0 - c.t[1], c.t[1]};
@@ -2074,11 +2089,13 @@ __device__ __forceinline__ void cic_weights(const CicCell& c, long long* w) {
   for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
     for (int dx = 0; dx < 2; ++dx) {
-      const double xy = wx[dx] * wy[dy];
+      const double xy = __dmul_rn(wx[dx], wy[dy]);
 #pragma unroll
       for (int dz = 0; dz < 2; ++dz) {
         const int q = dx | (dy << 1) | (dz << 2);
-        w[q] = q == big ? 0ll : (long long)(uint32_t)rint(xy * wz[dz]);
+        // rounded product, then + 2^52 (no fused multiply-add)
+        const double r = __dadd_rn(__dmul_rn(xy, wz[dz]), 4503599627370496.0);
+        w[q] = q == big ? 0ll : (long long)(uint32_t)__double_as_longlong(r);
         tot += w[q];
       }
     }
@@ -3651,6 +3668,15 @@ void g_smooth(mg_ctx* ctx, hipStream_t st, const GClass& K, const Lev& L, int it
   const GBox* tab = ctx->gtab + K.first;
   const GCtl* ctl = ctx->gctl + K.first;
   const bool vec = g_vec_rows(L);
+  // z-marching when the class's launch still has enough workgroups
+  const int kt = ctx->smooth_march_kt;
+  if (vec && kt > 0 && march_blocks(L, kt, 4) * (unsigned)K.count >= ctx->march_min_blocks) {
+    for (int s = 0; s < sweeps; ++s)
+      for (int colour = 0; colour < 2; ++colour)
+        kg_smooth_kv<M><<<dim3(march_blocks(L, kt, 4), K.count), kBlock, 0, st>>>(tab, ctl, it, l,
+                                                                                 colour, kt);
+    return;
+  }
   const unsigned bx = vec ? nblk(L.half / 4) : nblk(L.half);
   for (int s = 0; s < sweeps; ++s)
     for (int colour = 0; colour < 2; ++colour)
