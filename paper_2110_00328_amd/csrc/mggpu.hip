@@ -3794,6 +3794,13 @@ int grouped_solve(mg_ctx* ctx, int nb, const mg_box_desc* boxes, const mg_solver
   ACHK(g_grow(ctx, nb, pstride));
   const int ns = std::min((int)cls.size(), (int)mg_ctx::kGStreams);
   auto cst = [&](size_t c) { return ctx->gst[c % ns]; };
+  // whatever path leaves this function, the context's stream ends up waiting
+  // for the class streams (after a normal end they are already idle)
+  struct JoinAtExit {
+    mg_ctx* c;
+    int ns;
+    ~JoinAtExit() { (void)g_join(c, ns); }
+  } join_at_exit{ctx, ns};
   char* base = (char*)ctx->bpool;
   auto take = [&](size_t bytes) {
     char* p = base;
