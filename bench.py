@@ -37,8 +37,8 @@ FP32_SMOOTH_BYTES_PER_CELL = 12.0
 # HBM bytes per finest-level launch of that kernel at 512^3, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE (scaled by a plain copy of known size).  Set to
 # None whenever the kernel changes, until the counters are taken again.
-# k_smooth_corr_kv<FR, h16, h16>: 547.5 MB fetched + 268.4 MB written.
-FP32_SMOOTH_TRAFFIC_512 = 815.9e6
+# k_smooth_corr_kv<FR, h16, h16>: 546.8 MB fetched + 268.4 MB written.
+FP32_SMOOTH_TRAFFIC_512 = 815.2e6
 
 
 def parse():
