@@ -128,9 +128,13 @@ int mg_ctx_levels(const mg_ctx *ctx);
  * in code units [0, n); cell c covers [c, c+1) with centre c + 1/2.  Out:
  * delta[n^3] = rho/mean - 1.  Deposits are 32.32 fixed-point integer
  * sums, so the result does not depend on the order of the particles and
- * the total mass is exact.  For n % 16 == 0 the particles are sorted into
- * 16^3 tiles and each tile is summed in LDS; otherwise each corner is a global
- * 64-bit atomic.  Workspace: 12 bytes per particle plus 96 bytes per tile.
+ * the total mass is exact.  For n % 16 == 0 (and n_part < 2^32 - 8192) runs
+ * of consecutive particles in one (16^3 tile, boundary class) bin are sorted
+ * by bin and each tile is summed in LDS; otherwise each corner is a global
+ * 64-bit atomic.  Particles in a spatially coherent order (a Lagrangian grid
+ * order) form runs of several particles and are assigned fastest; any order
+ * gives the same result.  Workspace: 16 bytes per particle (run records and
+ * placed runs, at most one run per particle) plus 96 bytes per tile.
  * MG_EINVAL if n_part <= 0. */
 int cic_assign(mg_ctx *ctx, const float *pos_xyz, int64_t n_part, float *delta_out);
 
