@@ -2387,16 +2387,19 @@ __global__ __launch_bounds__(kCicCB) void k_cic_place(const uint2* __restrict__ 
 // In role s a particle's local coordinate on axis a is its in-tile layer
 // minus kT s_a, and only corners that land inside the tile are added: each
 // corner of each particle lands in exactly one (tile, role).  Runs are taken
-// kCicTB at a time: their lengths are prefix-summed, the batch's particles
-// are numbered consecutively, and a bitmap of run starts (with per-word
-// prefix counts) maps a particle number to its run in one LDS read, so that
-// consecutive threads read consecutive particles of a run.  Workgroups of
-// one XCD (every 8th workgroup id) take a contiguous range of tiles, so
-// tiles that share position cache lines run on the same L2.
+// in batches of at most kCicTB runs and kCicCap particles: their lengths
+// are prefix-summed, the batch's particles numbered consecutively, and a
+// bitmap of run starts (with per-word prefix counts) maps a particle number
+// to its run in one LDS read, so that consecutive threads read consecutive
+// particles of a run.  The LDS footprint (under 40 KB) leaves room for four
+// workgroups per CU.  Workgroups of one XCD (every 8th workgroup id) take a
+// contiguous range of tiles, so tiles that share position cache lines run
+// on the same L2.
 constexpr int kCicSegs = 20;  // 1 + 4 + 4 + 2 + 4 + 2 + 2 + 1
-constexpr int kCicUnroll = 4;  // particles per thread in flight
+constexpr int kCicUnroll = 2;  // particles per thread in flight
 constexpr int kCicTB = 512;    // workgroup size of the tile kernel
-constexpr int kCicWords = kCicTB * 64 / 32;  // bitmap words: a batch holds <= 64 kCicTB particles
+constexpr int kCicWords = kCicTB;          // bitmap words, one per thread
+constexpr int kCicCap = 32 * kCicWords;    // particles per batch (a run is at most 64)
 __global__ __launch_bounds__(kCicTB) void k_cic_tile(int n, int nt, const float* __restrict__ pos,
                                                      const unsigned long long* __restrict__ runs,
                                                      const uint32_t* __restrict__ boff,
@@ -2406,10 +2409,14 @@ __global__ __launch_bounds__(kCicTB) void k_cic_tile(int n, int nt, const float*
   // (every corner is deposited, those outside into the lane's own slot)
   __shared__ unsigned long long acc[kT3 + 64];
   __shared__ uint32_t seg_lo[kCicSegs], seg_end[kCicSegs];
-  __shared__ int seg_role[kCicSegs];
-  __shared__ uint2 rinfo[kCicTB];    // run: first particle minus its batch number, role
-  __shared__ uint2 bm[kCicWords];    // run-start bits, runs starting in earlier words
+  __shared__ uint8_t seg_role[kCicSegs];
+  __shared__ uint32_t rp0[kCicTB];        // run: first particle minus its batch number
+  __shared__ uint8_t rrole[kCicTB];       // run: role
+  __shared__ uint32_t bmbits[kCicWords];  // run-start bits
+  __shared__ uint16_t bmpre[kCicWords];   // runs starting in earlier words
   __shared__ uint32_t wsum[kCicTB / 64];
+  __shared__ uint32_t bnum[2];            // runs and particles of the batch
+  static_assert(kCicTB <= 65535, "run counts fit 16 bits");
   const uint32_t ntiles = (uint32_t)nt * nt * nt;
   uint32_t t = blockIdx.x;
   if (ntiles % 8 == 0) t = (t & 7u) * (ntiles / 8) + (t >> 3);
@@ -2453,16 +2460,17 @@ __global__ __launch_bounds__(kCicTB) void k_cic_tile(int n, int nt, const float*
     if (lane < kCicSegs) {
       seg_lo[lane] = lo;
       seg_end[lane] = end;
-      seg_role[lane] = s;
+      seg_role[lane] = (uint8_t)s;
     }
   }
   __syncthreads();
   const uint32_t total = seg_end[kCicSegs - 1];
   int sg = 0;
-  for (uint32_t r0 = 0; r0 < total; r0 += kCicTB) {
-    // this batch's runs: first particle, role, and the exclusive prefix of
-    // the lengths (the batch number of the run's first particle)
-    for (int w = threadIdx.x; w < kCicWords; w += kCicTB) bm[w].x = 0u;
+  for (uint32_t r0 = 0; r0 < total;) {
+    // this batch's candidate runs: first particle, role, and the inclusive
+    // prefix of the lengths
+    bmbits[threadIdx.x] = 0u;
+    if (threadIdx.x < 2) bnum[threadIdx.x] = 0u;
     const uint32_t r = r0 + threadIdx.x;
     uint32_t len = 0, p0 = 0;
     int role = 0;
@@ -2481,22 +2489,31 @@ __global__ __launch_bounds__(kCicTB) void k_cic_tile(int n, int nt, const float*
       if (lane >= d) inc += y;
     }
     if (lane == 63) wsum[wv] = inc;
-    __syncthreads();  // wsum complete, bitmap cleared
-    uint32_t wpre = 0, all = 0;
+    __syncthreads();  // wsum complete; bitmap and batch counters cleared
+    uint32_t wpre = 0;
 #pragma unroll
-    for (int w = 0; w < kCicTB / 64; ++w) {
-      const uint32_t sw = wsum[w];
-      wpre += w < wv ? sw : 0u;
-      all += sw;
+    for (int w = 0; w < kCicTB / 64; ++w) wpre += w < wv ? wsum[w] : 0u;
+    const uint32_t first = wpre + inc - len, end = wpre + inc;
+    // the batch: the leading runs that end within kCicCap particles (at
+    // least the first run, whose length is at most 64)
+    const bool in = len > 0 && end <= (uint32_t)kCicCap;
+    const unsigned long long bal = __ballot(in);
+    if (in) {
+      rp0[threadIdx.x] = p0 - first;
+      rrole[threadIdx.x] = (uint8_t)role;
+      atomicOr(&bmbits[first >> 5], 1u << (first & 31));
+      // the wave's included runs are a prefix of it: its last one ends last
+      if (lane == 63 - __clzll(bal)) {
+        atomicAdd(&bnum[0], (uint32_t)__popcll(bal));
+        atomicMax(&bnum[1], end);
+      }
     }
-    const uint32_t first = wpre + inc - len;
-    rinfo[threadIdx.x] = make_uint2(p0 - first, (uint32_t)role);
-    if (len) atomicOr(&bm[first >> 5].x, 1u << (first & 31));
-    __syncthreads();  // bits set; wsum is reused by the word scan
+    __syncthreads();  // bits set, batch counts known; wsum (read above) is reused below
+    const uint32_t nb = bnum[0], all = bnum[1];
     {
-      // exclusive prefix of the run starts over the words (2 per thread)
-      const uint32_t c0 = __popc(bm[2 * threadIdx.x].x), c1 = __popc(bm[2 * threadIdx.x + 1].x);
-      uint32_t ic = c0 + c1;
+      // exclusive prefix of the run starts over the words (one per thread)
+      const uint32_t c0 = __popc(bmbits[threadIdx.x]);
+      uint32_t ic = c0;
 #pragma unroll
       for (int d = 1; d < 64; d <<= 1) {
         const uint32_t y = __shfl_up(ic, d, 64);
@@ -2507,9 +2524,7 @@ __global__ __launch_bounds__(kCicTB) void k_cic_tile(int n, int nt, const float*
       uint32_t wp = 0;
 #pragma unroll
       for (int w = 0; w < kCicTB / 64; ++w) wp += w < wv ? wsum[w] : 0u;
-      const uint32_t e0 = wp + ic - c0 - c1;
-      bm[2 * threadIdx.x].y = e0;
-      bm[2 * threadIdx.x + 1].y = e0 + c0;
+      bmpre[threadIdx.x] = (uint16_t)(wp + ic - c0);
     }
     __syncthreads();
     for (uint32_t g0 = threadIdx.x; g0 < all; g0 += kCicUnroll * kCicTB) {
@@ -2522,11 +2537,10 @@ __global__ __launch_bounds__(kCicTB) void k_cic_tile(int n, int nt, const float*
         ok[u] = g < all;
         rl[u] = 0;
         if (ok[u]) {
-          const uint2 e = bm[g >> 5];
-          const uint32_t k = e.y + __popc(e.x & ((2u << (g & 31)) - 1u)) - 1u;
-          const uint2 info = rinfo[k];
-          rl[u] = (int)info.y;
-          cc[u] = cic_cell(n, pos, (int64_t)(uint32_t)(info.x + g));
+          const uint32_t wbits = bmbits[g >> 5];
+          const uint32_t k = (uint32_t)bmpre[g >> 5] + __popc(wbits & ((2u << (g & 31)) - 1u)) - 1u;
+          rl[u] = (int)rrole[k];
+          cc[u] = cic_cell(n, pos, (int64_t)(uint32_t)(rp0[k] + g));
         }
       }
 #pragma unroll
@@ -2551,7 +2565,8 @@ __global__ __launch_bounds__(kCicTB) void k_cic_tile(int n, int nt, const float*
         }
       }
     }
-    __syncthreads();  // rinfo, bm and wsum are rewritten by the next batch
+    __syncthreads();  // rp0, rrole, the bitmap, wsum and bnum are rewritten by the next batch
+    r0 += nb;
   }
   for (int q = threadIdx.x; q < kT3; q += kCicTB) {
     const int x = q % kT, y = (q / kT) % kT, z = q / (kT * kT);
