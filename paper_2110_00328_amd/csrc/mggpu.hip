@@ -2073,12 +2073,13 @@ __device__ __forceinline__ CicCell cic_cell(int n, const float* __restrict__ pos
 // 8 fixed-point weights (units of 2^-32) summing to exactly 2^32, corner q:
 // dx = q&1, dy = (q>>1)&1, dz = q>>2, axis weights (1 - t, t).  The corner
 // whose axis weights are all the larger ones ("big", >= 1/8) takes 2^32
-// minus the other seven; each of those is ((wx wy) wz) 2^32 formed in FP64
-// and rounded to nearest even, at most 2^31 (one factor is <= 1/2).  The
-// rounding is done by adding 2^52: the sum lies in [2^52, 2^53), where the
-// spacing of doubles is 1, so its low 32 mantissa bits are the rounded
-// weight (the same value as rint, without the conversion instructions).  No
-// weight is negative.
+// minus the other seven; each of those is (wx wy) (wz 2^32), the first
+// product rounded to FP64 and the second rounded once, to the nearest
+// integer (ties to even), by a fused multiply-add with 2^52: the result lies
+// in [2^52, 2^53), where the spacing of doubles is 1, so its low 32 mantissa
+// bits are the weight (at most 2^31: one factor is <= 1/2).  The explicit
+// fused multiply-add gives every kernel the same rounding.  No weight is
+// negative.
 __device__ __forceinline__ void cic_weights(const CicCell& c, long long* w) {
   const double wx[2] = {1.0 - c.t[0], c.t[0]};
   const double wy[2] = {1.0 - c.t[1], c.t[1]};
@@ -2093,8 +2094,7 @@ __device__ __forceinline__ void cic_weights(const CicCell& c, long long* w) {
 #pragma unroll
       for (int dz = 0; dz < 2; ++dz) {
         const int q = dx | (dy << 1) | (dz << 2);
-        // rounded product, then + 2^52 (no fused multiply-add)
-        const double r = __dadd_rn(__dmul_rn(xy, wz[dz]), 4503599627370496.0);
+        const double r = __fma_rn(xy, wz[dz], 4503599627370496.0);  // + 2^52
         w[q] = q == big ? 0ll : (long long)(uint32_t)__double_as_longlong(r);
         tot += w[q];
       }
