@@ -135,6 +135,17 @@ __global__ __launch_bounds__(kBlock) void kg_smooth(const GBox* __restrict__ tab
   }
 }
 
+// the same half-sweep marching in z over kt planes (blocks of one box in x)
+template <int M>
+__global__ __launch_bounds__(kBlock) void kg_smooth_kv(const GBox* __restrict__ tab,
+                                                       const GCtl* __restrict__ ctl, int it, int l,
+                                                       int colour, int kt) {
+  if (it >= ctl[blockIdx.y].kb) return;
+  const GBox& B = tab[blockIdx.y];
+  op_smooth_corr_kv<M, float, float>(B.L[l], B.e[l], B.X[l], B.dens[l], B.rho[l], colour,
+                                     B.h2[l], B.C, 0, kt, Store{1.0f, 1.0f, 1.0f, 1.0f});
+}
+
 // residual + restriction of level l, then (second launch) the coarse source
 // vec: 4 coarse cells per thread (the coarse side is a multiple of 4)
 template <int M>

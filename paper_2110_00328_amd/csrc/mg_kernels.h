@@ -936,12 +936,11 @@ __host__ __device__ inline unsigned march_blocks(const Lev& L, int kt, int V) {
 // (j, k-1), (j, k), (j, k+1) in registers, so each plane reads one new
 // other-colour row plus the rows j +- 1.  Per-cell arithmetic and the
 // neighbour summation order are those of op_smooth_corr_v (bit-identical).
-template <int M, typename TX = float, typename TR = float>
-__global__ __launch_bounds__(kBlock) void k_smooth_corr_kv(Lev L, float* e, const TX* X,
-                                                           const float* dens, const TR* rho,
-                                                           int colour, float h2, Consts C,
-                                                           int fresh, int kt,
-                                                           Store S = Store{1, 1, 1, 1}) {
+template <int M, typename TX, typename TR>
+__device__ __forceinline__ void op_smooth_corr_kv(const Lev& L, float* e, const TX* X,
+                                                  const float* dens, const TR* rho, int colour,
+                                                  float h2, const Consts& C, int fresh, int kt,
+                                                  const Store& S) {
   constexpr int V = Vec<float>::V;
   const MarchPos P = march_pos(L, kt, V);
   if (!P.ok) return;
@@ -990,6 +989,14 @@ __global__ __launch_bounds__(kBlock) void k_smooth_corr_kv(Lev L, float* e, cons
       zc[q] = zp[q];
     }
   }
+}
+template <int M, typename TX = float, typename TR = float>
+__global__ __launch_bounds__(kBlock) void k_smooth_corr_kv(Lev L, float* e, const TX* X,
+                                                           const float* dens, const TR* rho,
+                                                           int colour, float h2, Consts C,
+                                                           int fresh, int kt,
+                                                           Store S = Store{1, 1, 1, 1}) {
+  op_smooth_corr_kv<M, TX, TR>(L, e, X, dens, rho, colour, h2, C, fresh, kt, S);
 }
 // The linear half-sweep marching in z (FP32): a thread owns 4 packed cells
 // of its colour in row j and walks kt planes, keeping the other colour's
