@@ -109,8 +109,8 @@ typedef struct mg_ctx mg_ctx;
  * is even and >= 4 (4^3 coarsest for n = 2^l, 6^3 for n = 96).  Device
  * workspace is allocated on first use of each mode and kept until destroy.
  * The environment variable MGGPU_MARCH_MIN_BLOCKS, read here, sets from how
- * many workgroups up the residual/restriction kernels march in z (default
- * 2048; the results are identical either way), MGGPU_SMOOTH_MARCH_KT sets
+ * many workgroups up the smoother and residual/restriction kernels march in
+ * z (default 4096; the results are identical either way), MGGPU_SMOOTH_MARCH_KT sets
  * the planes per thread of the z-marching FP32 smoother used on large levels
  * (default 4; 0 selects the per-row form; identical results), and
  * MGGPU_FP16_STORAGE=0 keeps the finest level's X and rho of the

@@ -82,10 +82,12 @@ struct WorkAdj {
 struct mg_ctx {
   int n = 0;
   hipStream_t stream = nullptr;
-  // the z-marching residual/restriction kernels are used from this many
-  // workgroups up (below it a grid is too sparse to hide the march);
-  // MGGPU_MARCH_MIN_BLOCKS overrides it at context creation
-  unsigned march_min_blocks = 2048;
+  // the z-marching smoother and residual/restriction kernels are used from
+  // this many workgroups up (below it a grid is too sparse to hide the
+  // march: at 512^3 the 256^3 level's smoother, 2048 workgroups, is faster
+  // per row, 32.9 against 33.2 ms per step); MGGPU_MARCH_MIN_BLOCKS
+  // overrides it at context creation
+  unsigned march_min_blocks = 4096;
   // planes per thread of the z-marching FP32 smoother on large levels (0:
   // the per-row kernel); 4 was fastest with 16-bit X and rho at 512^3
   // (164 us per half-sweep against 175 per row; 2, 8, 16: 171, 169, 171);
