@@ -112,7 +112,12 @@ typedef struct mg_ctx mg_ctx;
  * many workgroups up the smoother and residual/restriction kernels march in
  * z (default 4096; the results are identical either way), MGGPU_SMOOTH_MARCH_KT sets
  * the planes per thread of the z-marching FP32 smoother used on large levels
- * (default 4; 0 selects the per-row form; identical results), and
+ * (default 4; 0 selects the per-row form; identical results),
+ * MGGPU_PROLONG_SMOOTH_KT sets the coarse planes per workgroup of the kernel
+ * that forms the prolonged correction inside the first post-smoothing
+ * half-sweep of the f(R), symmetron and linear (adjoint) FP32 cycles on the
+ * levels where the smoother marches in z (default 8; 0 runs prolongation
+ * and half-sweep as separate kernels; identical results), and
  * MGGPU_FP16_STORAGE=0 keeps the finest level's X and rho of the
  * FP32-refined solve in FP32 instead of 16-bit floats (default 1; n % 8 == 0
  * grids; changes rounding inside the FP32 correction cycles only, the FP64

@@ -414,7 +414,9 @@ __device__ __forceinline__ float corr_update(const Consts& C, float h2, float ec
     // e^3 + 3x e^2 + P e + Q = 0, P = m + 6 kap, Q = rho/s_amp - kap sum,
     // m = (1+delta) a*^3/a^3 - 1 + 3x^2, kap = c^2/(s_amp h^2)
     float kap = C.f_ct2_samp * (1.0f / h2);
-    float P = (1.0f + dc) * C.f_s_ratio - 1.0f + 3.0f * x * x + 6.0f * kap;
+    // 6 kap is a level constant: added with explicit rounding so that no
+    // kernel fuses it into the sum and another not
+    float P = __fadd_rn((1.0f + dc) * C.f_s_ratio - 1.0f + 3.0f * x * x, __fmul_rn(6.0f, kap));
     float Q = rho * C.f_isamp - kap * sum;
     float e;
     if (P > 0.0f && fabsf(Q) < 1e-2f * P * fabsf(x)) {

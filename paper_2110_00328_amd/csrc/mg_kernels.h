@@ -596,6 +596,15 @@ __device__ __forceinline__ void op_prolong_add(const Lev& Lf, const Lev& Lc, T* 
   v[g] += acc;
 }
 
+// Prolongation weight pair: 3/4 on the nearer coarse value, 1/4 on the
+// farther, as one explicit multiply and one fused multiply-add, so every
+// kernel that forms P (fused into a smoother or not) rounds identically.
+template <typename T>
+__device__ __forceinline__ T p34(T near, T far) {
+  if constexpr (sizeof(T) == 4) return __fmaf_rn(0.75f, near, __fmul_rn(0.25f, far));
+  else return __fma_rn(0.75, near, __dmul_rn(0.25, far));
+}
+
 // v^h += P c for the 8 children of coarse cell gc (natural index over nc^3):
 // c is the packed coarse correction; trilinear 3/4-1/4 per axis applied
 // separably over the 3x3x3 coarse neighbourhood (27/9/3/1 in total).
@@ -616,16 +625,16 @@ __device__ __forceinline__ void op_prolong_block(const Lev& Lf, const Lev& Lc, T
       T c0 = c[pk_of(Lc, Is[0], Js[b], Ks[d])];
       T c1 = c[pk_of(Lc, Is[1], Js[b], Ks[d])];
       T c2 = c[pk_of(Lc, Is[2], Js[b], Ks[d])];
-      ax[d][b][0] = T(0.75) * c1 + T(0.25) * c0;
-      ax[d][b][1] = T(0.75) * c1 + T(0.25) * c2;
+      ax[d][b][0] = p34<T>(c1, c0);
+      ax[d][b][1] = p34<T>(c1, c2);
     }
   T ay[3][2][2];
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
-      ay[d][0][x] = T(0.75) * ax[d][1][x] + T(0.25) * ax[d][0][x];
-      ay[d][1][x] = T(0.75) * ax[d][1][x] + T(0.25) * ax[d][2][x];
+      ay[d][0][x] = p34<T>(ax[d][1][x], ax[d][0][x]);
+      ay[d][1][x] = p34<T>(ax[d][1][x], ax[d][2][x]);
     }
 #pragma unroll
   for (int z = 0; z < 2; ++z)
@@ -635,7 +644,7 @@ __device__ __forceinline__ void op_prolong_block(const Lev& Lf, const Lev& Lc, T
       const uint32_t row = prow(Lf, j, k) + I;
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
-        T val = T(0.75) * ay[1][y][x] + T(0.25) * ay[z ? 2 : 0][y][x];
+        T val = p34<T>(ay[1][y][x], ay[z ? 2 : 0][y][x]);
         const int colour = (2 * I + x + j + k) & 1;
         v[colour * Lf.half + row] += val;
       }
@@ -738,6 +747,12 @@ __device__ __forceinline__ void op_coarse_src_corr(const Lev& L, const float* __
   rho[g] = G - rho[g];
 }
 
+// Exact FP32 update of one cell of the linear operator below, (r + kh2 sum)
+// / (6 kh2 + dg), with every rounding explicit: a loop-invariant 6 kh2 may
+// otherwise be fused into the add in one kernel and not in another.
+__device__ __forceinline__ float lin_cell_f(float r, float sum, float dg, float kh2) {
+  return __fmul_rn(__fmaf_rn(kh2, sum, r), f_rcp(__fmaf_rn(6.0f, kh2, dg)));
+}
 // Linear (adjoint) operator A v = kap (6v - sum)/h^2 + dg v; kh2 = kap/h^2
 template <typename T>
 __device__ __forceinline__ void op_smooth_lin(const Lev& L, T* __restrict__ e,
@@ -880,7 +895,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_lin_v(Lev L, T* e, const TD* 
   ldNs<T, TR, V>(r + q0, S.r_dec, rr);
 #pragma unroll
   for (int q = 0; q < V; ++q) {
-    if constexpr (sizeof(T) == 4) out[q] = (rr[q] + kh2 * sum[q]) * f_rcp(T(6) * kh2 + d[q]);
+    if constexpr (sizeof(T) == 4) out[q] = lin_cell_f(rr[q], sum[q], d[q], kh2);
     else out[q] = (rr[q] + kh2 * sum[q]) / (T(6) * kh2 + d[q]);
   }
   stv_nt<T>(e + q0, out);
@@ -998,6 +1013,18 @@ __global__ __launch_bounds__(kBlock) void k_smooth_corr_kv(Lev L, float* e, cons
                                                            Store S = Store{1, 1, 1, 1}) {
   op_smooth_corr_kv<M, TX, TR>(L, e, X, dens, rho, colour, h2, C, fresh, kt, S);
 }
+// Exact per-cell update of the linear (adjoint) operator for 4 consecutive
+// packed cells at q0, given the sums of their 6 neighbours.
+template <typename TD, typename TR>
+__device__ __forceinline__ void lin_update4(const TD* __restrict__ dg, const TR* __restrict__ r,
+                                            uint32_t q0, float kh2, const Store& S,
+                                            const float* sum, float* out) {
+  float d[4], rr[4];
+  ld4s<TD>(dg + q0, S.x_dec, d);
+  ld4s<TR>(r + q0, S.r_dec, rr);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = lin_cell_f(rr[q], sum[q], d[q], kh2);
+}
 // The linear half-sweep marching in z (FP32): a thread owns 4 packed cells
 // of its colour in row j and walks kt planes, keeping the other colour's
 // rows (j, k-1), (j, k), (j, k+1) in registers.  Same per-cell arithmetic
@@ -1041,11 +1068,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_lin_kv(Lev L, float* e, const
         sum[q] = (xv[q] + xv[q + 1]) + (ym[q] + yp[q]) + (zm[q] + zp[q]);
     }
     const uint32_t q0 = (uint32_t)colour * (uint32_t)L.half + rw + (uint32_t)ih0;
-    float d[V], rr[V], out[V];
-    ld4s<TD>(dg + q0, S.x_dec, d);
-    ld4s<TR>(r + q0, S.r_dec, rr);
-#pragma unroll
-    for (int q = 0; q < V; ++q) out[q] = (rr[q] + kh2 * sum[q]) * f_rcp(6.0f * kh2 + d[q]);
+    float out[V];
+    lin_update4<TD, TR>(dg, r, q0, kh2, S, sum, out);
     stv_nt<float>(own + rw + ih0, out);
 #pragma unroll
     for (int q = 0; q < V; ++q) {
@@ -1325,8 +1349,8 @@ __device__ __forceinline__ void op_prolong_v(const Lev& Lf, const Lev& Lc, T* __
       }
 #pragma unroll
       for (int q = 0; q < V; ++q) {
-        ax[d][b][q][0] = T(0.75) * cx[q + 1] + T(0.25) * cx[q];
-        ax[d][b][q][1] = T(0.75) * cx[q + 1] + T(0.25) * cx[q + 2];
+        ax[d][b][q][0] = p34<T>(cx[q + 1], cx[q]);
+        ax[d][b][q][1] = p34<T>(cx[q + 1], cx[q + 2]);
       }
     }
 #pragma unroll
@@ -1346,8 +1370,8 @@ __device__ __forceinline__ void op_prolong_v(const Lev& Lf, const Lev& Lc, T* __
           T ay[3];
 #pragma unroll
           for (int d = 0; d < 3; ++d)
-            ay[d] = T(0.75) * ax[d][1][q][x] + T(0.25) * ax[d][y ? 2 : 0][q][x];
-          cur[q] += T(0.75) * ay[1] + T(0.25) * ay[z ? 2 : 0];
+            ay[d] = p34<T>(ax[d][1][q][x], ax[d][y ? 2 : 0][q][x]);
+          cur[q] += p34<T>(ay[1], ay[z ? 2 : 0]);
         }
         stv_nt<T>(dst, cur);
       }
@@ -1421,8 +1445,8 @@ __device__ __forceinline__ void prolong_plane(const Lev& Lc, const T* __restrict
     prolong_row<T>(Lc, c, c2, I0, Js[b], K, cx);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      ax[b][q][0] = T(0.75) * cx[q + 1] + T(0.25) * cx[q];
-      ax[b][q][1] = T(0.75) * cx[q + 1] + T(0.25) * cx[q + 2];
+      ax[b][q][0] = p34<T>(cx[q + 1], cx[q]);
+      ax[b][q][1] = p34<T>(cx[q + 1], cx[q + 2]);
     }
   }
 #pragma unroll
@@ -1431,7 +1455,7 @@ __device__ __forceinline__ void prolong_plane(const Lev& Lc, const T* __restrict
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int x = 0; x < 2; ++x)
-        ay[y][q][x] = T(0.75) * ax[1][q][x] + T(0.25) * ax[y ? 2 : 0][q][x];
+        ay[y][q][x] = p34<T>(ax[1][q][x], ax[y ? 2 : 0][q][x]);
 }
 __host__ __device__ inline unsigned prolong_march_blocks(int nc, int kt) {
   const unsigned ngrp = (unsigned)nc * (unsigned)nc / 4u;
@@ -1472,7 +1496,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_kv(Lev Lf, Lev Lc, T* __rest
           ldn_nt<T, 4>(dst, cur);
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            cur[q] += T(0.75) * ay[1][y][q][x] + T(0.25) * ay[z ? 2 : 0][y][q][x];
+            cur[q] += p34<T>(ay[1][y][q][x], ay[z ? 2 : 0][y][q][x]);
           stn_nt<T, 4>(dst, cur);
         }
       }
@@ -1485,6 +1509,302 @@ __global__ __launch_bounds__(kBlock) void k_prolong_kv(Lev Lf, Lev Lc, T* __rest
           ay[0][y][q][x] = ay[1][y][q][x];
           ay[1][y][q][x] = ay[2][y][q][x];
         }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prolongation fused into the first post-smoothing half-sweep of a smoother
+// that solves each cell exactly (f(R), symmetron, the linear adjoint).
+// There the prolonged colour-1 values e1 + P(c - c2) are read only as the
+// neighbours of the colour-0 half-sweep: the colour-1 half-sweep after it
+// overwrites e1 without reading it (and the colour-0 prolongation is not
+// needed either).  So they are formed in registers and never stored, and
+// the kernel writes colour 0 only: per fine cell it reads e1, the stored X
+// and rho of colour 0 and 1/8 of the coarse data, instead of reading and
+// writing e1 once more in a separate prolongation.
+//
+// A thread owns coarse cells I0..I0+3 of coarse row J (fine rows 2J, 2J+1,
+// packed cells I0..I0+3 of both colours) and walks the coarse planes
+// K0..K1-1, i.e. the fine planes 2K0..2K1-1.  A block holds the whole
+// coarse rows J0..J0+R-1 (R >= 2, no tile of a single row); for each coarse
+// plane its threads swap the colour-1 values of the two current fine
+// planes through LDS (x and y neighbours), its first row also forms the
+// outside fine row 2J0-1 and its last row 2(J0+R), from the coarse rows
+// they load anyway.  z neighbours stay in registers.  The prolongation
+// arithmetic is k_prolong_kv's, the neighbour sum and cell update those of
+// the z-marching half-sweeps, so the result is bit-identical to the two
+// kernels run one after the other.
+// ---------------------------------------------------------------------------
+// 4 stored cells as loaded, decoded later exactly as ld4s decodes them (so
+// the loads can be issued before the LDS exchange and wait behind it)
+template <typename TS>
+struct Raw4 {
+  nt_f4 v;
+};
+template <>
+struct Raw4<h16> {
+  nt_h4 v;
+};
+template <typename TS>
+__device__ __forceinline__ Raw4<TS> ld4raw(const TS* __restrict__ p) {
+  Raw4<TS> r;
+  if constexpr (sizeof(TS) == 4) r.v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+  else r.v = __builtin_nontemporal_load(reinterpret_cast<const nt_h4*>(p));
+  return r;
+}
+template <typename TS>
+__device__ __forceinline__ void dec4s(const Raw4<TS>& r, float dec, float* out) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if constexpr (sizeof(TS) == 4) out[q] = r.v[q];
+    else out[q] = float(r.v[q]) * dec;
+  }
+}
+// Cell update policies for four consecutive colour-0 cells at packed index
+// q0: load() the cell data, apply() the update to the neighbour sums.
+// kPreload: load a step's cell data before the LDS exchange (f(R), linear:
+// 31.3 against 31.7 ms per 512^3 f(R) step); the symmetron's extra density
+// operand would cost a wave per SIMD, so it loads after the exchange.
+template <int M, typename TX, typename TR>
+struct UpdCorr {
+  static constexpr bool kPreload = M != SYM;
+  const TX* X;
+  const float* dens;
+  const TR* rho;
+  float h2;
+  Store S;
+  Consts C;
+  struct In {
+    Raw4<TX> x;
+    Raw4<TR> r;
+    Raw4<float> d;
+  };
+  __device__ __forceinline__ In load(uint32_t q0) const {
+    In a;
+    a.x = ld4raw<TX>(X + q0);
+    a.r = ld4raw<TR>(rho + q0);
+    if (M != FR) a.d = ld4raw<float>(dens + q0);
+    return a;
+  }
+  __device__ __forceinline__ void apply(const In& a, const float* sum, float* out) const {
+    float x[4], rr[4], dc[4] = {0, 0, 0, 0}, eo[4] = {0, 0, 0, 0};
+    dec4s<TX>(a.x, S.x_dec, x);
+    dec4s<TR>(a.r, S.r_dec, rr);
+    if (M != FR) dec4s<float>(a.d, 1.0f, dc);
+    corr_update4<M>(C, h2, eo, sum, x, dc, rr, out);
+  }
+};
+template <typename TD, typename TR>
+struct UpdLin {
+  static constexpr bool kPreload = true;
+  const TD* dg;
+  const TR* r;
+  float kh2;
+  Store S;
+  struct In {
+    Raw4<TD> d;
+    Raw4<TR> r;
+  };
+  __device__ __forceinline__ In load(uint32_t q0) const {
+    In a;
+    a.d = ld4raw<TD>(dg + q0);
+    a.r = ld4raw<TR>(r + q0);
+    return a;
+  }
+  __device__ __forceinline__ void apply(const In& a, const float* sum, float* out) const {
+    float d[4], rr[4];
+    dec4s<TD>(a.d, S.x_dec, d);
+    dec4s<TR>(a.r, S.r_dec, rr);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = lin_cell_f(rr[q], sum[q], d[q], kh2);
+  }
+};
+// Coarse plane K interpolated in x and y for the fine rows 2J (a[0]) and
+// 2J+1 (a[1]) of the thread's 4 coarse cells, both x children, and for one
+// outside row h: 2J-1 (lo) or 2J+2 (!lo).  Same steps as prolong_plane.
+__device__ __forceinline__ void prolong_plane_h(const Lev& Lc, const float* __restrict__ c,
+                                                const float* __restrict__ c2, int I0,
+                                                const int* Js, int K, bool lo,
+                                                float (*a)[4][2], float (*h)[2]) {
+  float ax[3][4][2];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    float cx[6];
+    prolong_row<float>(Lc, c, c2, I0, Js[b], K, cx);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ax[b][q][0] = p34<float>(cx[q + 1], cx[q]);
+      ax[b][q][1] = p34<float>(cx[q + 1], cx[q + 2]);
+    }
+  }
+#pragma unroll
+  for (int y = 0; y < 2; ++y)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int x = 0; x < 2; ++x) a[y][q][x] = p34<float>(ax[1][q][x], ax[y ? 2 : 0][q][x]);
+  // row 2J-1 is child 1 of coarse row J-1, row 2J+2 child 0 of row J+1
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int x = 0; x < 2; ++x) h[q][x] = p34<float>(lo ? ax[0][q][x] : ax[2][q][x], ax[1][q][x]);
+}
+// LDS of one block: [buffer][fine plane of the pair][fine row of the block]
+// [packed cell]; R rows of nc/4 threads fill at most kBlock threads, so
+// 2R nc <= 8 kBlock.
+constexpr int kPSRowCells = 8 * kBlock;
+__host__ __device__ inline int prolong_smooth_rows(int nc) {
+  if (nc % 4 != 0 || nc < 8 || nc / 4 > kBlock / 2) return 0;  // needs R >= 2
+  int R = kBlock / (nc / 4);
+  if (R > nc) R = nc;
+  while (R > 2 && nc % R == 1) --R;  // no tile of a single coarse row
+  return nc % R == 1 ? 0 : R;
+}
+template <class U>
+__global__ __launch_bounds__(kBlock) void k_prolong_smooth0(Lev Lf, Lev Lc, float* __restrict__ e,
+                                                            const float* __restrict__ c,
+                                                            const float* __restrict__ c2, int kt,
+                                                            U upd) {
+  __shared__ __align__(16) float sh[2][2][kPSRowCells];
+  const int nc = Lc.n, n = Lf.n, gpr = nc >> 2;
+  const int R = (int)blockDim.x / gpr;
+  const uint32_t ntile = ((uint32_t)nc + (uint32_t)R - 1) / (uint32_t)R;
+  const uint32_t b = (uint32_t)xcd_block();
+  const uint32_t kb = b / ntile, tile = b - kb * ntile;
+  const int rl = (int)threadIdx.x / gpr, g = (int)threadIdx.x - rl * gpr;
+  const int J0 = (int)tile * R, J = J0 + rl;
+  const int Jend = J0 + R < nc ? J0 + R : nc;
+  const bool act = J < nc;
+  const int Jr = act ? J : nc - 1;  // rows past the last one compute a copy of it
+  const bool first = J == J0, last = J == Jend - 1;
+  const int I0 = 4 * g;
+  const int K0 = (int)kb * kt, K1 = K0 + kt < nc ? K0 + kt : nc;
+  const int Js[3] = {Jr == 0 ? nc - 1 : Jr - 1, Jr, Jr + 1 == nc ? 0 : Jr + 1};
+  const int jh = first ? (Jr == 0 ? n - 1 : 2 * Jr - 1) : (Jr + 1 == nc ? 0 : 2 * Jr + 2);
+  const bool need_h = act && (first || last);
+  const float* e1 = e + Lf.half;
+  // e1 + P on the fine plane k of own row y, from the interpolated coarse
+  // planes `near` (weight 3/4) and `far`
+  auto own_rows = [&](int k, const float (*near)[4][2], const float (*far)[4][2], float (*E)[4]) {
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int j = 2 * Jr + y, x = (1 + j + k) & 1;
+      float old[4];
+      ldn_nt<float, 4>(e1 + prow(Lf, j, k) + I0, old);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) E[y][q] = old[q] + p34<float>(near[y][q][x], far[y][q][x]);
+    }
+  };
+  auto out_row = [&](int k, const float (*near)[2], const float (*far)[2], float* E) {
+    const int x = (1 + jh + k) & 1;
+    float old[4] = {0, 0, 0, 0};
+    if (need_h) ldn<float, 4>(e1 + prow(Lf, jh, k) + I0, old);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) E[q] = old[q] + p34<float>(near[q][x], far[q][x]);
+  };
+  float aK[2][4][2], hK[4][2], aN[2][4][2], hN[4][2];
+  float Eb[2][4];          // fine plane 2K-1, own rows
+  float Ec[2][4], Ech[4];  // fine plane 2K: own rows, outside row
+  {
+    const int Kp = K0 == 0 ? nc - 1 : K0 - 1;
+    prolong_plane_h(Lc, c, c2, I0, Js, Kp, first, aN, hN);
+    prolong_plane_h(Lc, c, c2, I0, Js, K0, first, aK, hK);
+    own_rows(K0 == 0 ? n - 1 : 2 * K0 - 1, aN, aK, Eb);  // child z = 1 of plane K0-1
+    own_rows(2 * K0, aK, aN, Ec);                        // child z = 0 of plane K0
+    out_row(2 * K0, hK, hN, Ech);
+  }
+  for (int K = K0; K < K1; ++K) {
+    const int Kn = K + 1 == nc ? 0 : K + 1;
+    const int k0 = 2 * K, k1 = 2 * K + 1, k2 = 2 * Kn;
+    typename U::In in[2][2];  // cell data of the two planes' own rows
+    if constexpr (U::kPreload) {
+#pragma unroll
+      for (int z = 0; z < 2; ++z)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          in[z][y] = upd.load(prow(Lf, 2 * Jr + y, k0 + z) + (uint32_t)I0);
+    }
+    prolong_plane_h(Lc, c, c2, I0, Js, Kn, first, aN, hN);
+    float Ed[2][4], Edh[4], Ee[2][4], Eeh[4];
+    own_rows(k1, aK, aN, Ed);  // child z = 1 of plane K
+    out_row(k1, hK, hN, Edh);
+    own_rows(k2, aN, aK, Ee);  // child z = 0 of plane K+1
+    out_row(k2, hN, hK, Eeh);
+    float* s0 = sh[K & 1][0];
+    float* s1 = sh[K & 1][1];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      stn<float, 4>(s0 + (2 * rl + y) * nc + I0, Ec[y]);
+      stn<float, 4>(s1 + (2 * rl + y) * nc + I0, Ed[y]);
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int z = 0; z < 2; ++z) {
+        const float* s = z ? s1 : s0;
+        const int k = z ? k1 : k0;
+        const float(*cen)[4] = z ? Ed : Ec;
+        const float(*zmv)[4] = z ? Ec : Eb;
+        const float(*zpv)[4] = z ? Ee : Ed;
+        const float* hv = z ? Edh : Ech;
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          const int j = 2 * Jr + y;
+          const float* srow = s + (2 * rl + y) * nc;
+          float xv[5], ym[4], yp[4], sum[4], out[4];
+          if ((j + k) & 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xv[q] = cen[y][q];
+            xv[4] = srow[I0 + 4 == nc ? 0 : I0 + 4];
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xv[q + 1] = cen[y][q];
+            xv[0] = srow[I0 == 0 ? nc - 1 : I0 - 1];
+          }
+          if (y == 0) {
+            if (first) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) ym[q] = hv[q];
+            } else {
+              ldn<float, 4>(srow - nc + I0, ym);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) yp[q] = cen[1][q];
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ym[q] = cen[0][q];
+            if (last) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) yp[q] = hv[q];
+            } else {
+              ldn<float, 4>(srow + nc + I0, yp);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            sum[q] = (xv[q] + xv[q + 1]) + (ym[q] + yp[q]) + (zmv[y][q] + zpv[y][q]);
+          const uint32_t r = prow(Lf, j, k) + (uint32_t)I0;
+          if constexpr (!U::kPreload) in[z][y] = upd.load(r);
+          upd.apply(in[z][y], sum, out);
+          stv_nt<float>(e + r, out);
+        }
+      }
+    }
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Eb[y][q] = Ed[y][q];
+        Ec[y][q] = Ee[y][q];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) aK[y][q][x] = aN[y][q][x];
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Ech[q] = Eeh[q];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) hK[q][x] = hN[q][x];
+    }
   }
 }
 

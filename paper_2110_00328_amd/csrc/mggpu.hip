@@ -93,6 +93,12 @@ struct mg_ctx {
   // (164 us per half-sweep against 175 per row; 2, 8, 16: 171, 169, 171);
   // MGGPU_SMOOTH_MARCH_KT overrides it at context creation
   int smooth_march_kt = 4;
+  // coarse planes per workgroup of the prolongation fused into the first
+  // post-smoothing half-sweep (0: separate prolongation and half-sweep),
+  // used where the smoother marches in z.  At 512^3 f(R) a step took 31.7
+  // ms with 8, 31.8 with 4, 32.1 with 2, 32.2 with 16 and 32.9 unfused;
+  // MGGPU_PROLONG_SMOOTH_KT overrides it at context creation
+  int psmooth_kt = 8;
   // scale applied to each FP32 correction before the FP64 update (1: the
   // method; another value forces the divergence path from the host in tests;
   // MGGPU_TEST_CORRECTION_SCALE overrides it at context creation)
@@ -987,13 +993,16 @@ __global__ __launch_bounds__(kBlock) void k_scale(float* __restrict__ e, int64_t
 
 template <int M>
 // fresh: the correction buffer was not cleared; the first sweep takes it as 0
-int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps, bool fresh = false) {
+// skip0: the first colour-0 half-sweep was done by the fused prolongation
+int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps, bool fresh = false,
+             bool skip0 = false) {
   Work32& W = ctx->w32;
   const Lev& L = ctx->L[l];
   const bool vec = (L.nh % Vec<float>::V) == 0;
   const int64_t nv = L.half / Vec<float>::V;
   for (int s = 0; s < sweeps; ++s)
     for (int colour = 0; colour < 2; ++colour) {
+      if (skip0 && s == 0 && colour == 0) continue;
       // timed class: full half-sweeps of the finest level (a fresh colour-0
       // half-sweep reads no neighbours and is left out)
       const bool light = fresh && s == 0 && colour == 0;
@@ -1024,6 +1033,24 @@ int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps, bool fresh = false
     }
   LAUNCHCHK();
   return MG_OK;
+}
+
+// Whether level l's prolongation from l+1 and its first post-smoothing
+// half-sweep run as one fused kernel: an exact per-cell FP32 smoother that
+// marches in z on this level, a coarse side the fused kernel tiles.
+bool fuse_prolong(const mg_ctx* ctx, int l) {
+  const Lev& Lf = ctx->L[l];
+  const Lev& Lc = ctx->L[l + 1];
+  const int kt = ctx->smooth_march_kt;
+  return ctx->psmooth_kt > 0 && kt > 0 && Lf.nh % 4 == 0 && prolong_smooth_rows(Lc.n) > 0 &&
+         march_blocks(Lf, kt, 4) >= ctx->march_min_blocks;
+}
+template <class U>
+void launch_prolong_smooth0(mg_ctx* ctx, const Lev& Lf, const Lev& Lc, float* e, const float* c,
+                            const float* c2, const U& upd) {
+  const int R = prolong_smooth_rows(Lc.n), kt = ctx->psmooth_kt;
+  const unsigned ntile = (unsigned)((Lc.n + R - 1) / R), nz = (unsigned)((Lc.n + kt - 1) / kt);
+  k_prolong_smooth0<U><<<ntile * nz, R * (Lc.n / 4), 0, ctx->stream>>>(Lf, Lc, e, c, c2, kt, upd);
 }
 
 // rx: restrict the linearisation point X on the way down (first cycle of
@@ -1099,6 +1126,17 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   } else {
     ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_F, rx));
     ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V, false));
+  }
+  if (M != CQ && vec && fuse_prolong(ctx, l)) {
+    // e += P(e_H - R e) formed inside the first colour-0 half-sweep
+    with_level_store(ctx, l, [&](auto* X, auto* R) {
+      using TX = std::remove_pointer_t<decltype(X)>;
+      using TR = std::remove_pointer_t<decltype(R)>;
+      const UpdCorr<M, TX, TR> U{X, W.dens[l], R, float(lev_h2(l)), level_store(ctx, l), C};
+      launch_prolong_smooth0(ctx, Lf, Lc, W.e[l], W.e[l + 1], W.eR[l + 1], U);
+    });
+    LAUNCHCHK();
+    return smooth32<M>(ctx, C, l, o->nu_post, false, true);
   }
   if (vec) {
     // e += P(e_H - R e); colour 0 too only for the Newton (CQ) smoother
@@ -1442,9 +1480,10 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
   const bool vec = (Lf.nh % Vec<T>::V) == 0;
   const int64_t nv = Lf.half / Vec<T>::V;
   const Store S0 = l == 0 ? ctx->a0.S : Store{1.0f, 1.0f, 1.0f, 1.0f};
-  auto smooth = [&](int sweeps, bool first_fresh) {
+  auto smooth = [&](int sweeps, bool first_fresh, bool skip0 = false) {
     for (int s = 0; s < sweeps; ++s)
       for (int colour = 0; colour < 2; ++colour) {
+        if (skip0 && s == 0 && colour == 0) continue;  // done by the fused prolongation
         int q = l == 0 ? prof_begin(ctx, sizeof(T) == 4 ? MG_PROF_LIN32 : MG_PROF_LIN64) : -1;
         const int kt = ctx->smooth_march_kt;
         const int fr = (first_fresh && s == 0) ? 1 : 0;
@@ -1506,6 +1545,21 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
   } else {
     ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_F));
     ACHK(lin_cycle<T>(ctx, W, kap, o, l + 1, MG_CYCLE_V));
+  }
+  if constexpr (sizeof(T) == 4) {
+    if (cvec && fuse_prolong(ctx, l)) {
+      with_lin_store<T>(ctx, W, l, [&](auto* D, auto* R) {
+        using TD = std::remove_pointer_t<decltype(D)>;
+        using TR = std::remove_pointer_t<decltype(R)>;
+        const UpdLin<TD, TR> U{D, R, float(kh2), S0};
+        launch_prolong_smooth0(ctx, Lf, Lc, (float*)W.e[l], (const float*)W.e[l + 1],
+                               (const float*)nullptr, U);
+      });
+      LAUNCHCHK();
+      smooth(o->nu_post, false, true);
+      LAUNCHCHK();
+      return MG_OK;
+    }
   }
   if (cvec)
     launch_prolong<T, 1>(ctx, Lf, Lc, W.e[l], W.e[l + 1], (const T*)nullptr);
@@ -2709,6 +2763,10 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
   if (const char* cd = getenv("MGGPU_CIC_DIRECT")) ctx->cic_direct = atoi(cd) != 0;
   if (const char* ts = getenv("MGGPU_TEST_CORRECTION_SCALE")) ctx->test_escale = (float)atof(ts);
   if (const char* fs = getenv("MGGPU_FP16_STORAGE")) ctx->fp16 = atoi(fs) != 0;
+  if (const char* pk = getenv("MGGPU_PROLONG_SMOOTH_KT")) {
+    const int kt = atoi(pk);
+    ctx->psmooth_kt = kt > 0 && kt <= 64 ? kt : 0;
+  }
   if (const char* sk = getenv("MGGPU_SMOOTH_MARCH_KT")) {
     const int kt = atoi(sk);
     ctx->smooth_march_kt = kt > 0 && kt <= 64 ? kt : 0;

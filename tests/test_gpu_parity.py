@@ -489,6 +489,45 @@ def test_marching_restriction_is_bit_identical(monkeypatch, model, prec, n):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("model,n,kt", [("fr", 64, "4"), ("sym", 96, "4"), ("fr", 160, "3"),
+                                         ("sym", 64, "1")])
+def test_fused_prolongation_is_bit_identical(monkeypatch, model, n, kt):
+    """The prolongation fused into the first post-smoothing half-sweep (FP32
+    correction solve and FP32 adjoint) gives bit-identical solves and
+    adjoints to the separate prolongation and half-sweep: forced on at every
+    level here, at 64^3 (coarse sides 32, 16, 8: one tile of whole rows),
+    96^3 (48, 24, 12: 21 rows per tile, a ragged last tile) and 160^3 (80,
+    40, 20: ragged tiles) with 1, 3 or 4 coarse planes per workgroup
+    (3 leaves a ragged last chunk in z)."""
+    box = float(n)
+    say("fused prolongation", model, n, kt)
+    P, prm = cfg(model, n, box)
+    delta = torch.from_numpy(lognormal(n, 43)).to(DEV)
+    opts = api.solver_opts(precision="fp32")
+    out = []
+    for pkt in ("0", kt):
+        monkeypatch.setenv("MGGPU_MARCH_MIN_BLOCKS", "0")
+        monkeypatch.setenv("MGGPU_SMOOTH_MARCH_KT", "4")
+        monkeypatch.setenv("MGGPU_PROLONG_SMOOTH_KT", pkt)
+        mg = api.Context(n, device=DEV)
+        field, st = mg.solve(model, prm, delta, tol=1e-8, opts=opts)
+        cells = torch.from_numpy(np.random.default_rng(44).choice(n ** 3, 200, replace=False)).to(DEV)
+        force = mg.force(model, prm, field)
+        _, gforce = mg.loss_force_sq(force, cells)
+        gfield = mg.force_adjoint(model, prm, field, gforce)
+        gd, st2 = mg.solve_adjoint(model, prm, delta, field, gfield, tol=1e-8, opts=opts)
+        out.append((field.cpu().numpy(), gd.cpu().numpy(), st.cycles, st.vcycles, st2.cycles))
+        mg.close()
+    say(f"  cycles {out[0][2:]} / {out[1][2:]}")
+    assert out[0][2:] == out[1][2:]
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    ref, _, _, _ = oracle.solve(P, delta.cpu().numpy().astype(np.float64), tol=1e-12)
+    err = field_err(model, out[1][0], to_field(model, ref), P)
+    say(f"  field_err={err:.2e}")
+    assert err < 1e-5
+
+
 def _background(model, P):
     if model == "fr":
         return -oracle.background(P)  # the library's f(R) field is f_R = -w
