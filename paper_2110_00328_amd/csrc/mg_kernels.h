@@ -1215,6 +1215,7 @@ __global__ __launch_bounds__(kBlock) void k_lin_outer_fused_kv(
   constexpr int V = kVOuter;
   __shared__ double sh[32];
   const MarchPos P = march_pos(L, kt, V);
+  const bool zero_start = !lam && !e && shift == 0.0;
   double acc = 0.0, accs = 0.0, amax = 0.0;
   if (P.ok) {
     double win[2][3][V];
@@ -1239,7 +1240,12 @@ __global__ __launch_bounds__(kBlock) void k_lin_outer_fused_kv(
           sum[q] += 6.0 * shift;
         }
         if (e) stn<double, V>(lam_new + q0, lc);
-        ldn<double, V>(dg + q0, dd);
+        if (zero_start) {  // lam = 0: the residual is b, dg * 0 = 0 (dg finite)
+#pragma unroll
+          for (int q = 0; q < V; ++q) dd[q] = 0.0;
+        } else {
+          ldn<double, V>(dg + q0, dd);
+        }
         ldn<double, V>(b + q0, bb);
         TO ro[V], zo[V];
 #pragma unroll
