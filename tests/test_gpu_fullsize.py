@@ -5,7 +5,9 @@ at their real sizes, against the FP64 CPU oracle.
   configuration (CIC of 512^3 FP32 Zel'dovich particles, FP32-refined
   V(1,1) to relative residual 1e-6): CIC against the oracle's CIC; field and
   force against the oracle's solve of the oracle's own density to 1e-10; the
-  oracle's residual of the GPU field; the plain FP64 GPU solve beside it.
+  oracle's residual of the GPU field; the plain FP64 GPU solve beside it;
+  the fused prolongation/half-sweep kernels against the separate ones, bit
+  for bit, through the forward solve and the adjoint.
 - 512^3 coupled quintessence, with and without exp(beta phi~/c~^2) before
   (1+delta): field and force against the oracle's solve of the same density,
   the oracle's residual of the GPU field, FP32-refined against FP64.
@@ -106,6 +108,34 @@ def test_c3_fr_solve_and_force_match_oracle(c3, fr0):
     for prec, (ferr, gerr, fmax, gmax, rel_o2, rel_g) in out.items():
         assert rel_o2 <= 1e-6 and abs(rel_o2 - rel_g) <= 1e-3 * rel_g + 1e-12
         assert ferr < 1e-5 and gerr < 1e-5 and fmax < 1e-5 and gmax < 1e-5
+
+
+def test_c3_fused_prolongation_is_bit_identical(c3, monkeypatch):
+    """The bench's pipeline and launch configuration (512^3, 16-bit level-0
+    storage): the prolongation fused into the first post-smoothing
+    half-sweep of the finest level, forward and adjoint, gives the same
+    field and density gradient, bit for bit, as the separate kernels."""
+    n, delta = c3["n"], c3["delta"]
+    prm = api.model_params(float(n), fr0=1e-5)
+    cells = torch.from_numpy(np.random.default_rng(7).choice(n ** 3, 4096, replace=False)).to(DEV)
+    opts = api.solver_opts(precision="fp32")
+    outs = []
+    for pk in (None, "0"):
+        if pk is None:
+            monkeypatch.delenv("MGGPU_PROLONG_SMOOTH_KT", raising=False)
+        else:
+            monkeypatch.setenv("MGGPU_PROLONG_SMOOTH_KT", pk)
+        mg = api.Context(n, device=DEV)
+        field, st = mg.solve("fr", prm, delta, tol=1e-6, opts=opts)
+        _, gforce = mg.loss_force_sq(mg.force("fr", prm, field), cells)
+        gfield = mg.force_adjoint("fr", prm, field, gforce)
+        gd, st2 = mg.solve_adjoint("fr", prm, delta, field, gfield, tol=1e-6, opts=opts)
+        outs.append((field.cpu().numpy(), gd.cpu().numpy(), st.vcycles, st2.vcycles))
+        say(f"  fused={pk is None}: V-cycles {st.vcycles} / {st2.vcycles}")
+        mg.close()
+    assert outs[0][2:] == outs[1][2:]
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
 
 
 @pytest.mark.parametrize("keep_exp", [1, 0])

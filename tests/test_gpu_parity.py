@@ -489,18 +489,19 @@ def test_marching_restriction_is_bit_identical(monkeypatch, model, prec, n):
     assert err < 1e-5
 
 
-@pytest.mark.parametrize("model,n,kt", [("fr", 64, "4"), ("sym", 96, "4"), ("fr", 160, "3"),
-                                         ("sym", 64, "1")])
-def test_fused_prolongation_is_bit_identical(monkeypatch, model, n, kt):
+@pytest.mark.parametrize("model,n,kt,fp16", [("fr", 64, "4", "1"), ("sym", 96, "4", "1"),
+                                              ("fr", 160, "3", "1"), ("sym", 64, "1", "1"),
+                                              ("fr", 64, "2", "0"), ("sym", 96, "8", "0")])
+def test_fused_prolongation_is_bit_identical(monkeypatch, model, n, kt, fp16):
     """The prolongation fused into the first post-smoothing half-sweep (FP32
     correction solve and FP32 adjoint) gives bit-identical solves and
     adjoints to the separate prolongation and half-sweep: forced on at every
     level here, at 64^3 (coarse sides 32, 16, 8: one tile of whole rows),
     96^3 (48, 24, 12: 21 rows per tile, a ragged last tile) and 160^3 (80,
-    40, 20: ragged tiles) with 1, 3 or 4 coarse planes per workgroup
-    (3 leaves a ragged last chunk in z)."""
+    40, 20: ragged tiles) with 1 to 8 coarse planes per workgroup (3 leaves
+    a ragged last chunk in z), with 16-bit and with FP32 level-0 storage."""
     box = float(n)
-    say("fused prolongation", model, n, kt)
+    say("fused prolongation", model, n, kt, fp16)
     P, prm = cfg(model, n, box)
     delta = torch.from_numpy(lognormal(n, 43)).to(DEV)
     opts = api.solver_opts(precision="fp32")
@@ -509,6 +510,7 @@ def test_fused_prolongation_is_bit_identical(monkeypatch, model, n, kt):
         monkeypatch.setenv("MGGPU_MARCH_MIN_BLOCKS", "0")
         monkeypatch.setenv("MGGPU_SMOOTH_MARCH_KT", "4")
         monkeypatch.setenv("MGGPU_PROLONG_SMOOTH_KT", pkt)
+        monkeypatch.setenv("MGGPU_FP16_STORAGE", fp16)
         mg = api.Context(n, device=DEV)
         field, st = mg.solve(model, prm, delta, tol=1e-8, opts=opts)
         cells = torch.from_numpy(np.random.default_rng(44).choice(n ** 3, 200, replace=False)).to(DEV)
