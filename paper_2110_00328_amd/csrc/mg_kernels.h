@@ -701,15 +701,50 @@ __device__ __forceinline__ float cell_resid_corr(const Lev& L, const float* __re
   return corr_G<M>(C, h2, e[g], sum, X[g], dc) - r;
 }
 
-// coarse cell gc: Re -> eH and eR, R(G(e) - rho) -> rhoH, optionally R X -> XH
+// Coarse outputs of a correction-form restriction at packed coarse index pc
+// from the fine sums se (of e), sd (of the residual G(e) - rho) and sx (of
+// X, when formed).
+// Plain form (Xf null): eH = eR = R e, rhoH = R(G(e) - rho), XH = R X when
+// XH is given; the coarse-source pass then sets rhoH = G_H(R e) - rhoH, and
+// the coarse correction is e_H - R e.
+// Shifted form (Xf given): the coarse problem is posed around the
+// restricted current approximation, XH = R X + R e (R X formed, and with rx
+// stored in Xf, or read from Xf).  Since G_H(R e + d; R X) - G_H(R e; R X)
+// = G_H(d; R X + R e), the same coarse equation for d = e_H - R e reads
+// G_H(d; XH) = R(rho - G(e)), so rhoH = -R(G(e) - rho), d starts at zero
+// (eH = 0 when given, else the coarse smoother takes it as zero) and is
+// itself the coarse correction: no coarse source and no eR.
+__device__ __forceinline__ void store_coarse_corr(uint32_t pc, float se, float sd, float sx,
+                                                  float* eH, float* eR, float* rhoH, float* XH,
+                                                  float* Xf, int rx) {
+  const float re = se * 0.125f;
+  rhoH[pc] = Xf ? -(sd * 0.125f) : sd * 0.125f;
+  if (Xf) {
+    float xf;
+    if (rx) {
+      xf = sx * 0.125f;
+      Xf[pc] = xf;
+    } else {
+      xf = Xf[pc];
+    }
+    XH[pc] = xf + re;
+    if (eH) eH[pc] = 0.0f;
+  } else {
+    eH[pc] = re;
+    eR[pc] = re;
+    if (XH) XH[pc] = sx * 0.125f;
+  }
+}
+// coarse cell gc: restriction in the plain or shifted form (store_coarse_corr)
 template <int M>
 __device__ __forceinline__ void op_resid_restrict_corr(
     const Lev& Lf, const Lev& Lc, const float* __restrict__ e, const float* __restrict__ X,
     const float* __restrict__ dens, const float* __restrict__ rho, float h2,
     float* __restrict__ eH, float* __restrict__ eR, float* __restrict__ rhoH,
-    float* __restrict__ XH, const Consts& C, int64_t gc) {
+    float* __restrict__ XH, const Consts& C, int64_t gc, float* Xf = nullptr, int rx = 0) {
   int I, J, K;
   dec_nat(gc, Lc, I, J, K);
+  const bool want_x = XH && (!Xf || rx);
   float se = 0.0f, sd = 0.0f, sx = 0.0f;
 #pragma unroll
   for (int d = 0; d < 2; ++d)
@@ -725,16 +760,11 @@ __device__ __forceinline__ void op_resid_restrict_corr(
         float x = X[g];
         float dc = (M == FR) ? 0.0f : dens[g];
         se += ec;
-        if (XH) sx += x;
+        if (want_x) sx += x;
         sd += corr_G<M>(C, h2, ec, sum, x, dc) - rho[g];
       }
     }
-  uint32_t pc = pk_of(Lc, I, J, K);
-  float re = se * 0.125f;
-  eH[pc] = re;
-  eR[pc] = re;
-  rhoH[pc] = sd * 0.125f;
-  if (XH) XH[pc] = sx * 0.125f;
+  store_coarse_corr(pk_of(Lc, I, J, K), se, sd, sx, eH, eR, rhoH, XH, Xf, rx);
 }
 
 template <int M>
@@ -1822,10 +1852,11 @@ __device__ __forceinline__ void op_resid_restrict_corr_v(
     const Lev& Lf, const Lev& Lc, const float* __restrict__ e, const TX* __restrict__ X,
     const float* __restrict__ dens, const TR* __restrict__ rho, float h2, float* eH, float* eR,
     float* rhoH, float* XH, const Consts& C, int skip1, uint32_t g4,
-    Store S = Store{1, 1, 1, 1}) {
+    Store S = Store{1, 1, 1, 1}, float* Xf = nullptr, int rx = 0) {
   constexpr int V = Vec<float>::V;
   int I0, J, K;
   dec_nat(g4 * V, Lc, I0, J, K);
+  const bool want_x = XH && (!Xf || rx);
   float se[V] = {0, 0, 0, 0}, sd[V] = {0, 0, 0, 0}, sx[V] = {0, 0, 0, 0};
 #pragma unroll 1
   for (int d = 0; d < 2; ++d)
@@ -1840,7 +1871,7 @@ __device__ __forceinline__ void op_resid_restrict_corr_v(
         if (col == 1 && skip1) {
 #pragma unroll
           for (int q = 0; q < V; ++q) se[q] += ec[q];
-          if (XH) {
+          if (want_x) {
             ld4s<TX>(X + q0, S.x_dec, x);
 #pragma unroll
             for (int q = 0; q < V; ++q) sx[q] += x[q];
@@ -1860,24 +1891,19 @@ __device__ __forceinline__ void op_resid_restrict_corr_v(
       }
     }
 #pragma unroll
-  for (int q = 0; q < V; ++q) {
-    uint32_t pc = pk_of(Lc, I0 + q, J, K);
-    float re = se[q] * 0.125f;
-    eH[pc] = re;
-    eR[pc] = re;
-    rhoH[pc] = sd[q] * 0.125f;
-    if (XH) XH[pc] = sx[q] * 0.125f;
-  }
+  for (int q = 0; q < V; ++q)
+    store_coarse_corr(pk_of(Lc, I0 + q, J, K), se[q], sd[q], sx[q], eH, eR, rhoH, XH, Xf, rx);
 }
 template <int M, typename TX = float, typename TR = float>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_v(
     Lev Lf, Lev Lc, const float* __restrict__ e, const TX* __restrict__ X,
     const float* __restrict__ dens, const TR* __restrict__ rho, float h2, float* eH, float* eR,
-    float* rhoH, float* XH, Consts C, int skip1, Store S = Store{1, 1, 1, 1}) {
+    float* rhoH, float* XH, Consts C, int skip1, Store S = Store{1, 1, 1, 1},
+    float* Xf = nullptr, int rx = 0) {
   uint32_t g4 = (uint32_t)gid();
   if (g4 < (uint32_t)(2 * Lc.half / Vec<float>::V))
     op_resid_restrict_corr_v<M, TX, TR>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, skip1,
-                                        g4, S);
+                                        g4, S, Xf, rx);
 }
 
 // Residual and restriction marching in z, for exact per-cell smoothers
@@ -1929,6 +1955,20 @@ __device__ __forceinline__ void st_coarse4(const Lev& Lc, T* __restrict__ a, int
   *reinterpret_cast<T2*>(a + (uint32_t)p * (uint32_t)Lc.half + row) = ev;
   *reinterpret_cast<T2*>(a + (uint32_t)(1 - p) * (uint32_t)Lc.half + row) = od;
 }
+// load 4 natural coarse values of row (J, K) from I0 (st_coarse4's layout)
+template <typename T>
+__device__ __forceinline__ void ld_coarse4(const Lev& Lc, const T* __restrict__ a, int I0, int J,
+                                           int K, T* v) {
+  typedef typename Vec2Of<T>::type T2;
+  const int p = (J + K) & 1;
+  const uint32_t row = prow(Lc, J, K) + (uint32_t)(I0 >> 1);
+  const T2 ev = *reinterpret_cast<const T2*>(a + (uint32_t)p * (uint32_t)Lc.half + row);
+  const T2 od = *reinterpret_cast<const T2*>(a + (uint32_t)(1 - p) * (uint32_t)Lc.half + row);
+  v[0] = ev.x;
+  v[2] = ev.y;
+  v[1] = od.x;
+  v[3] = od.y;
+}
 struct RRPos {
   int I0, J, Jm2, Jp2, K0, K1;  // Jm2 = fine row 2J-1, Jp2 = fine row 2J+2 (periodic)
   bool ok;
@@ -1957,10 +1997,12 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_kv(
     Lev Lf, Lev Lc, const float* __restrict__ e, const TX* __restrict__ X,
     const float* __restrict__ dens, const TR* __restrict__ rho, float h2,
     float* __restrict__ eH, float* __restrict__ eR, float* __restrict__ rhoH,
-    float* __restrict__ XH, Consts C, int kt, Store S = Store{1, 1, 1, 1}) {
+    float* __restrict__ XH, Consts C, int kt, Store S = Store{1, 1, 1, 1}, float* Xf = nullptr,
+    int rx = 0) {
   const RRPos P = rr_pos(Lc, kt);
   if (!P.ok) return;
   const int n = Lf.n, I0 = P.I0, J = P.J;
+  const bool want_x = XH && (!Xf || rx);
   const float* o1 = e + Lf.half;
   auto row1 = [&](int j, int k, float* v) { ldn<float, 4>(o1 + prow(Lf, j, k) + I0, v); };
   RestrictWin<float> W;
@@ -2007,24 +2049,38 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr_kv(
         // colour 1: restricted only
 #pragma unroll
         for (int q = 0; q < 4; ++q) se[q] += cen[q];
-        if (XH) {
+        if (want_x) {
           ld4s<TX>(X + Lf.half + q0, S.x_dec, x);
 #pragma unroll
           for (int q = 0; q < 4; ++q) sx[q] += x[q];
         }
       }
     }
-    float re[4], rd[4], rx[4];
+    // coarse outputs as in store_coarse_corr, 4 natural cells at a time
+    float re[4], rd[4], rxv[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       re[q] = se[q] * 0.125f;
-      rd[q] = sd[q] * 0.125f;
-      rx[q] = sx[q] * 0.125f;
+      rd[q] = Xf ? -(sd[q] * 0.125f) : sd[q] * 0.125f;
+      rxv[q] = sx[q] * 0.125f;
     }
-    st_coarse4<float>(Lc, eH, I0, J, K, re);
-    st_coarse4<float>(Lc, eR, I0, J, K, re);
     st_coarse4<float>(Lc, rhoH, I0, J, K, rd);
-    if (XH) st_coarse4<float>(Lc, XH, I0, J, K, rx);
+    if (Xf) {
+      if (rx) st_coarse4<float>(Lc, Xf, I0, J, K, rxv);
+      else ld_coarse4<float>(Lc, Xf, I0, J, K, rxv);
+      float xn[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xn[q] = rxv[q] + re[q];
+      st_coarse4<float>(Lc, XH, I0, J, K, xn);
+      if (eH) {
+        const float zero[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        st_coarse4<float>(Lc, eH, I0, J, K, zero);
+      }
+    } else {
+      st_coarse4<float>(Lc, eH, I0, J, K, re);
+      st_coarse4<float>(Lc, eR, I0, J, K, re);
+      if (XH) st_coarse4<float>(Lc, XH, I0, J, K, rxv);
+    }
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -2275,10 +2331,11 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr(Lev Lf, Lev Lc, 
                                                                 const float* X, const float* dens,
                                                                 const float* rho, float h2,
                                                                 float* eH, float* eR, float* rhoH,
-                                                                float* XH, Consts C) {
+                                                                float* XH, Consts C,
+                                                                float* Xf = nullptr, int rx = 0) {
   int64_t g = gid();
   if (g < 2 * Lc.half)
-    op_resid_restrict_corr<M>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, g);
+    op_resid_restrict_corr<M>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, g, Xf, rx);
 }
 // the same, 4 packed cells of one colour per thread (needs nh % 4 == 0);
 // per-cell arithmetic and summation order as above

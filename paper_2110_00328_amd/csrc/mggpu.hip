@@ -1089,6 +1089,20 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
   // zero residual
   const int skip1 = (M != CQ && o->nu_pre > 0) ? 1 : 0;
   const Store S = level_store(ctx, l);
+  // The coarse problem is posed around the restricted current approximation
+  // (the restriction's shifted form): W.X[l+1] = R X + R e, where R X of
+  // this level's linearisation point is formed when that point has changed
+  // (rx) and kept in W.eR[l+1] otherwise; the coarse correction starts at
+  // zero and is prolonged as it is.  It starts fresh where the coarse
+  // level's first half-sweep can take the uncleared buffer as zero (a
+  // vectorised smoother that sweeps before anything reads e); elsewhere the
+  // restriction writes zeros.
+  const Lev& Lc1 = ctx->L[l + 1];
+  const bool cfresh = l + 1 < ctx->fused_from && Lc1.nh % Vec<float>::V == 0 &&
+                      (o->nu_pre > 0 || l + 1 == ctx->nlev - 1);
+  float* ezero = cfresh ? (float*)nullptr : W.e[l + 1];
+  float* Xf = W.eR[l + 1];
+  const int rxi = rx ? 1 : 0;
   if (skip1 && Lc.n % 4 == 0 && Lc.n >= 8 &&
       prolong_march_blocks(Lc.n, kRestrictKT) >= ctx->march_min_blocks)
     with_level_store(ctx, l, [&](auto* X, auto* R) {
@@ -1096,56 +1110,51 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
       using TR = std::remove_pointer_t<decltype(R)>;
       k_resid_restrict_corr_kv<M, TX, TR>
           <<<prolong_march_blocks(Lc.n, kRestrictKT), kBlock, 0, ctx->stream>>>(
-              Lf, Lc, W.e[l], X, W.dens[l], R, float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
-              W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C, kRestrictKT, S);
+              Lf, Lc, W.e[l], X, W.dens[l], R, float(lev_h2(l)), ezero, (float*)nullptr,
+              W.rho[l + 1], W.X[l + 1], C, kRestrictKT, S, Xf, rxi);
     });
   else if (vec)
     with_level_store(ctx, l, [&](auto* X, auto* R) {
       using TX = std::remove_pointer_t<decltype(X)>;
       using TR = std::remove_pointer_t<decltype(R)>;
       k_resid_restrict_corr_v<M, TX, TR><<<nblk(ncv), kBlock, 0, ctx->stream>>>(
-          Lf, Lc, W.e[l], X, W.dens[l], R, float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
-          W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C, skip1, S);
+          Lf, Lc, W.e[l], X, W.dens[l], R, float(lev_h2(l)), ezero, (float*)nullptr,
+          W.rho[l + 1], W.X[l + 1], C, skip1, S, Xf, rxi);
     });
   else
     k_resid_restrict_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
-        Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), W.e[l + 1], W.eR[l + 1],
-        W.rho[l + 1], rx ? W.X[l + 1] : (float*)nullptr, C);
-  if (Lc.nh % Vec<float>::V == 0)
-    k_coarse_src_corr_v<M><<<nblk(cells(Lc) / Vec<float>::V), kBlock, 0, ctx->stream>>>(
-        Lc, W.eR[l + 1], W.X[l + 1], W.dens[l + 1], W.rho[l + 1], float(lev_h2(l + 1)), C);
-  else
-    k_coarse_src_corr<M><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(
-        Lc, W.eR[l + 1], W.X[l + 1], W.dens[l + 1], W.rho[l + 1], float(lev_h2(l + 1)), C);
+        Lf, Lc, W.e[l], W.X[l], W.dens[l], W.rho[l], float(lev_h2(l)), ezero, (float*)nullptr,
+        W.rho[l + 1], W.X[l + 1], C, Xf, rxi);
   LAUNCHCHK();
+  // the coarse level's linearisation point has changed: its own restriction
+  // forms R X again on the first visit; a second visit (W, F) continues
+  // from the first visit's correction
   if (type == MG_CYCLE_V) {
-    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V, rx));
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V, true, cfresh));
   } else if (type == MG_CYCLE_W) {
-    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_W, rx));
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_W, true, cfresh));
     ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_W, false));
   } else {
-    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_F, rx));
+    ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_F, true, cfresh));
     ACHK(cycle32<M>(ctx, C, o, l + 1, MG_CYCLE_V, false));
   }
   if (M != CQ && vec && fuse_prolong(ctx, l)) {
-    // e += P(e_H - R e) formed inside the first colour-0 half-sweep
+    // e += P e_H formed inside the first colour-0 half-sweep
     with_level_store(ctx, l, [&](auto* X, auto* R) {
       using TX = std::remove_pointer_t<decltype(X)>;
       using TR = std::remove_pointer_t<decltype(R)>;
       const UpdCorr<M, TX, TR> U{X, W.dens[l], R, float(lev_h2(l)), level_store(ctx, l), C};
-      launch_prolong_smooth0(ctx, Lf, Lc, W.e[l], W.e[l + 1], W.eR[l + 1], U);
+      launch_prolong_smooth0(ctx, Lf, Lc, W.e[l], W.e[l + 1], (const float*)nullptr, U);
     });
     LAUNCHCHK();
     return smooth32<M>(ctx, C, l, o->nu_post, false, true);
   }
   if (vec) {
-    // e += P(e_H - R e); colour 0 too only for the Newton (CQ) smoother
-    launch_prolong<float, M == CQ ? 0 : 1>(ctx, Lf, Lc, W.e[l], W.e[l + 1], W.eR[l + 1]);
+    // e += P e_H; colour 0 too only for the Newton (CQ) smoother
+    launch_prolong<float, M == CQ ? 0 : 1>(ctx, Lf, Lc, W.e[l], W.e[l + 1], (const float*)nullptr);
   } else {
-    k_coarse_diff<float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(cells(Lc), W.e[l + 1],
-                                                                        W.eR[l + 1]);
     k_prolong_block<float><<<nblk(cells(Lc)), kBlock, 0, ctx->stream>>>(Lf, Lc, W.e[l],
-                                                                          W.eR[l + 1]);
+                                                                          W.e[l + 1]);
   }
   LAUNCHCHK();
   return smooth32<M>(ctx, C, l, o->nu_post);
