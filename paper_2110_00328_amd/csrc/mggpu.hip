@@ -53,6 +53,9 @@ struct Work32 {  // FP32 correction mode
   float* X[kMaxLev] = {};
   float* rho[kMaxLev] = {};
   float* dens[kMaxLev] = {};
+  // levels run one kernel at a time: R X of the next finer level's
+  // linearisation point (the coarse problem's fixed part); levels inside the
+  // single-workgroup kernel: R e of the finer level
   float* eR[kMaxLev] = {};
   h16* X16 = nullptr;          // level-0 X in 16 bits (when the context stores 16-bit data)
   h16* R16 = nullptr;          // level-0 rho in 16 bits
