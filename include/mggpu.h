@@ -113,11 +113,13 @@ typedef struct mg_ctx mg_ctx;
  * z (default 4096; the results are identical either way), MGGPU_SMOOTH_MARCH_KT sets
  * the planes per thread of the z-marching FP32 smoother used on large levels
  * (default 4; 0 selects the per-row form; identical results),
- * MGGPU_PROLONG_SMOOTH_KT sets the coarse planes per workgroup of the kernel
- * that forms the prolonged correction inside the first post-smoothing
- * half-sweep of the f(R), symmetron and linear (adjoint) FP32 cycles on the
- * levels where the smoother marches in z (default 8; 0 runs prolongation
- * and half-sweep as separate kernels; identical results), and
+ * MGGPU_PROLONG_SMOOTH_KT sets the coarse planes per workgroup (default 8;
+ * 0 runs prolongation and half-sweep as separate kernels; identical
+ * results) of the kernel that forms the prolonged correction inside the
+ * first post-smoothing half-sweep of the f(R), symmetron and linear
+ * (adjoint) FP32 cycles, used on the levels where its grid reaches
+ * MGGPU_PROLONG_SMOOTH_MIN_BLOCKS workgroups (default 512; the depth is
+ * halved to reach it), and
  * MGGPU_FP16_STORAGE=0 keeps the finest level's X and rho of the
  * FP32-refined solve in FP32 instead of 16-bit floats (default 1; n % 8 == 0
  * grids; changes rounding inside the FP32 correction cycles only, the FP64

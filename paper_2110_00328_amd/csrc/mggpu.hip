@@ -102,6 +102,12 @@ struct mg_ctx {
   // ms with 8, 31.8 with 4, 32.1 with 2, 32.2 with 16 and 32.9 unfused;
   // MGGPU_PROLONG_SMOOTH_KT overrides it at context creation
   int psmooth_kt = 8;
+  // fewest workgroups of a fused prolongation launch (the depth is halved to
+  // reach it).  512 also fuses the 256^3 level of a 512^3 solve (4 planes
+  // per workgroup): 29.89 ms per step against 29.95 / 30.00 with 1024 / 2048
+  // (2 and 1 planes there) and 29.99 with 256; MGGPU_PROLONG_SMOOTH_MIN_BLOCKS
+  // overrides it at context creation
+  unsigned psmooth_min_blocks = 512;
   // scale applied to each FP32 correction before the FP64 update (1: the
   // method; another value forces the divergence path from the host in tests;
   // MGGPU_TEST_CORRECTION_SCALE overrides it at context creation)
@@ -1038,20 +1044,28 @@ int smooth32(mg_ctx* ctx, const Consts& C, int l, int sweeps, bool fresh = false
   return MG_OK;
 }
 
-// Whether level l's prolongation from l+1 and its first post-smoothing
-// half-sweep run as one fused kernel: an exact per-cell FP32 smoother that
-// marches in z on this level, a coarse side the fused kernel tiles.
-bool fuse_prolong(const mg_ctx* ctx, int l) {
+// Coarse planes per workgroup of the prolongation fused into level l's first
+// post-smoothing half-sweep (exact per-cell FP32 smoothers), or 0 where the
+// two run separately: the configured depth, halved until the grid has
+// ctx->psmooth_min_blocks workgroups; 0 if one plane per workgroup is not
+// enough or the coarse side does not tile.
+int fuse_prolong_kt(const mg_ctx* ctx, int l) {
   const Lev& Lf = ctx->L[l];
   const Lev& Lc = ctx->L[l + 1];
-  const int kt = ctx->smooth_march_kt;
-  return ctx->psmooth_kt > 0 && kt > 0 && Lf.nh % 4 == 0 && prolong_smooth_rows(Lc.n) > 0 &&
-         march_blocks(Lf, kt, 4) >= ctx->march_min_blocks;
+  const int R = prolong_smooth_rows(Lc.n);
+  if (ctx->psmooth_kt <= 0 || ctx->smooth_march_kt <= 0 || Lf.nh % 4 != 0 || R == 0) return 0;
+  const unsigned ntile = (unsigned)((Lc.n + R - 1) / R);
+  for (int kt = ctx->psmooth_kt; kt >= 1; kt /= 2)
+    if (ntile * (unsigned)((Lc.n + kt - 1) / kt) >= ctx->psmooth_min_blocks) return kt;
+  return 0;
 }
+bool fuse_prolong(const mg_ctx* ctx, int l) { return fuse_prolong_kt(ctx, l) > 0; }
 template <class U>
-void launch_prolong_smooth0(mg_ctx* ctx, const Lev& Lf, const Lev& Lc, float* e, const float* c,
-                            const float* c2, const U& upd) {
-  const int R = prolong_smooth_rows(Lc.n), kt = ctx->psmooth_kt;
+void launch_prolong_smooth0(mg_ctx* ctx, int l, float* e, const float* c, const float* c2,
+                            const U& upd) {
+  const Lev& Lf = ctx->L[l];
+  const Lev& Lc = ctx->L[l + 1];
+  const int R = prolong_smooth_rows(Lc.n), kt = fuse_prolong_kt(ctx, l);
   const unsigned ntile = (unsigned)((Lc.n + R - 1) / R), nz = (unsigned)((Lc.n + kt - 1) / kt);
   k_prolong_smooth0<U><<<ntile * nz, R * (Lc.n / 4), 0, ctx->stream>>>(Lf, Lc, e, c, c2, kt, upd);
 }
@@ -1147,7 +1161,7 @@ int cycle32(mg_ctx* ctx, const Consts& C, const mg_solver_opts* o, int l, int ty
       using TX = std::remove_pointer_t<decltype(X)>;
       using TR = std::remove_pointer_t<decltype(R)>;
       const UpdCorr<M, TX, TR> U{X, W.dens[l], R, float(lev_h2(l)), level_store(ctx, l), C};
-      launch_prolong_smooth0(ctx, Lf, Lc, W.e[l], W.e[l + 1], (const float*)nullptr, U);
+      launch_prolong_smooth0(ctx, l, W.e[l], W.e[l + 1], (const float*)nullptr, U);
     });
     LAUNCHCHK();
     return smooth32<M>(ctx, C, l, o->nu_post, false, true);
@@ -1564,7 +1578,7 @@ int lin_cycle(mg_ctx* ctx, WorkLin<T>& W, double kap, const mg_solver_opts* o, i
         using TD = std::remove_pointer_t<decltype(D)>;
         using TR = std::remove_pointer_t<decltype(R)>;
         const UpdLin<TD, TR> U{D, R, float(kh2), S0};
-        launch_prolong_smooth0(ctx, Lf, Lc, (float*)W.e[l], (const float*)W.e[l + 1],
+        launch_prolong_smooth0(ctx, l, (float*)W.e[l], (const float*)W.e[l + 1],
                                (const float*)nullptr, U);
       });
       LAUNCHCHK();
@@ -2779,6 +2793,8 @@ int mg_ctx_create(mg_ctx** out, int n, void* hip_stream) {
     const int kt = atoi(pk);
     ctx->psmooth_kt = kt > 0 && kt <= 64 ? kt : 0;
   }
+  if (const char* pm = getenv("MGGPU_PROLONG_SMOOTH_MIN_BLOCKS"))
+    ctx->psmooth_min_blocks = (unsigned)atoi(pm);
   if (const char* sk = getenv("MGGPU_SMOOTH_MARCH_KT")) {
     const int kt = atoi(sk);
     ctx->smooth_march_kt = kt > 0 && kt <= 64 ? kt : 0;

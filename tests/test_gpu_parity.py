@@ -468,9 +468,11 @@ def test_marching_restriction_is_bit_identical(monkeypatch, model, prec, n):
     for mode in ("per-row", "march"):
         monkeypatch.delenv("MGGPU_MARCH_MIN_BLOCKS", raising=False)
         monkeypatch.setenv("MGGPU_SMOOTH_MARCH_KT", "0")
+        monkeypatch.delenv("MGGPU_PROLONG_SMOOTH_MIN_BLOCKS", raising=False)
         if mode != "per-row":
             monkeypatch.setenv("MGGPU_MARCH_MIN_BLOCKS", "0")
             monkeypatch.setenv("MGGPU_SMOOTH_MARCH_KT", "4")
+            monkeypatch.setenv("MGGPU_PROLONG_SMOOTH_MIN_BLOCKS", "0")
         mg = api.Context(n, device=DEV)
         field, st = mg.solve(model, prm, delta, tol=1e-8, opts=opts)
         cells = torch.from_numpy(np.random.default_rng(42).choice(n ** 3, 200, replace=False)).to(DEV)
@@ -510,6 +512,7 @@ def test_fused_prolongation_is_bit_identical(monkeypatch, model, n, kt, fp16):
         monkeypatch.setenv("MGGPU_MARCH_MIN_BLOCKS", "0")
         monkeypatch.setenv("MGGPU_SMOOTH_MARCH_KT", "4")
         monkeypatch.setenv("MGGPU_PROLONG_SMOOTH_KT", pkt)
+        monkeypatch.setenv("MGGPU_PROLONG_SMOOTH_MIN_BLOCKS", "0")
         monkeypatch.setenv("MGGPU_FP16_STORAGE", fp16)
         mg = api.Context(n, device=DEV)
         field, st = mg.solve(model, prm, delta, tol=1e-8, opts=opts)
