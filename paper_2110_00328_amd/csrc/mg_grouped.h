@@ -146,7 +146,10 @@ __global__ __launch_bounds__(kBlock) void kg_smooth_kv(const GBox* __restrict__ 
                                      B.h2[l], B.C, 0, kt, Store{1.0f, 1.0f, 1.0f, 1.0f});
 }
 
-// residual + restriction of level l, then (second launch) the coarse source
+// residual + restriction of level l in the shifted form (store_coarse_corr):
+// the coarse problem is posed around X_H = R X + R e (R X of level l kept in
+// eR[l+1], formed again with rx), the coarse correction starts at zero and
+// no coarse-source pass follows.
 // vec: 4 coarse cells per thread (the coarse side is a multiple of 4)
 template <int M>
 __global__ __launch_bounds__(kBlock) void kg_down(const GBox* __restrict__ tab,
@@ -156,37 +159,20 @@ __global__ __launch_bounds__(kBlock) void kg_down(const GBox* __restrict__ tab,
   const GBox& B = tab[blockIdx.y];
   const Lev& Lf = B.L[l];
   const Lev& Lc = B.L[l + 1];
-  float* XH = rx ? B.X[l + 1] : (float*)nullptr;
   const uint32_t g = gthread();
   if (vec) {
     if (g < (uint32_t)(2 * Lc.half / 4))
       op_resid_restrict_corr_v<M>(Lf, Lc, B.e[l], B.X[l], B.dens[l], B.rho[l], B.h2[l],
-                                  B.e[l + 1], B.eR[l + 1], B.rho[l + 1], XH, B.C, skip1, g);
+                                  B.e[l + 1], (float*)nullptr, B.rho[l + 1], B.X[l + 1], B.C,
+                                  skip1, g, Store{1, 1, 1, 1}, B.eR[l + 1], rx);
   } else if (g < (uint32_t)(2 * Lc.half)) {
     op_resid_restrict_corr<M>(Lf, Lc, B.e[l], B.X[l], B.dens[l], B.rho[l], B.h2[l], B.e[l + 1],
-                              B.eR[l + 1], B.rho[l + 1], XH, B.C, g);
+                              (float*)nullptr, B.rho[l + 1], B.X[l + 1], B.C, g, B.eR[l + 1], rx);
   }
 }
-// vec: 4 packed cells per thread (the level's rows hold a multiple of 4)
-template <int M>
-__global__ __launch_bounds__(kBlock) void kg_csrc(const GBox* __restrict__ tab,
-                                                  const GCtl* __restrict__ ctl, int it, int l,
-                                                  int vec) {
-  if (it >= ctl[blockIdx.y].kb) return;
-  const GBox& B = tab[blockIdx.y];
-  const Lev& L = B.L[l];
-  const uint32_t g = gthread();
-  if (vec) {
-    if (g < (uint32_t)(2 * L.half / 4))
-      op_coarse_src_corr_v<M>(L, B.eR[l], B.X[l], B.dens[l], B.rho[l], B.h2[l], B.C, g);
-  } else if (g < (uint32_t)(2 * L.half)) {
-    op_coarse_src_corr<M>(L, B.eR[l], B.X[l], B.dens[l], B.rho[l], B.h2[l], B.C, g);
-  }
-}
-
-// e_l += P(e_H - R e_l); with COL0 = 1 colour 0 is left to the next exact
-// half-sweep (not for the Newton smoother of CQ).  The per-cell form (not
-// vectorised) first forms the coarse difference in place.
+// e_l += P e_H (the coarse correction of the shifted form); with COL0 = 1
+// colour 0 is left to the next exact half-sweep (not for the Newton
+// smoother of CQ)
 template <int COL0>
 __global__ __launch_bounds__(kBlock) void kg_up(const GBox* __restrict__ tab,
                                                 const GCtl* __restrict__ ctl, int it, int l) {
@@ -194,15 +180,7 @@ __global__ __launch_bounds__(kBlock) void kg_up(const GBox* __restrict__ tab,
   const GBox& B = tab[blockIdx.y];
   const uint32_t g = gthread();
   if (g < (uint32_t)(2 * B.L[l + 1].half / 4))
-    op_prolong_v<float, COL0>(B.L[l], B.L[l + 1], B.e[l], B.e[l + 1], B.eR[l + 1], g);
-}
-__global__ __launch_bounds__(kBlock) void kg_coarse_diff(const GBox* __restrict__ tab,
-                                                         const GCtl* __restrict__ ctl, int it,
-                                                         int l) {
-  if (it >= ctl[blockIdx.y].kb) return;
-  const GBox& B = tab[blockIdx.y];
-  const uint32_t g = gthread();
-  if (g < (uint32_t)(2 * B.L[l + 1].half)) B.eR[l + 1][g] = B.e[l + 1][g] - B.eR[l + 1][g];
+    op_prolong_v<float, COL0>(B.L[l], B.L[l + 1], B.e[l], B.e[l + 1], (const float*)nullptr, g);
 }
 __global__ __launch_bounds__(kBlock) void kg_up_block(const GBox* __restrict__ tab,
                                                       const GCtl* __restrict__ ctl, int it,
@@ -211,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void kg_up_block(const GBox* __restrict__ t
   const GBox& B = tab[blockIdx.y];
   const uint32_t g = gthread();
   if (g < (uint32_t)(2 * B.L[l + 1].half))
-    op_prolong_block<float>(B.L[l], B.L[l + 1], B.e[l], B.eR[l + 1], g);
+    op_prolong_block<float>(B.L[l], B.L[l + 1], B.e[l], B.e[l + 1], g);
 }
 
 // the small levels of every box of the class: one workgroup per box

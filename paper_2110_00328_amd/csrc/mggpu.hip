@@ -3818,26 +3818,25 @@ int g_cycle(mg_ctx* ctx, hipStream_t st, const GClass& K, const Lev* L,
   g_smooth<M>(ctx, st, K, L[l], it, l, o->nu_pre);
   const int skip1 = (M != CQ && o->nu_pre > 0) ? 1 : 0;
   const bool rvec = g_vec_coarse(Lc) && g_vec_rows(L[l]);
-  const bool cvec = g_vec_rows(Lc);
+  // shifted coarse form (as in cycle32): the coarse correction starts at
+  // zero, written by the restriction; the coarse level's linearisation
+  // point changes, so its first visit forms R X again
   kg_down<M><<<dim3(rvec ? nblk(2 * Lc.half / 4) : nblk(2 * Lc.half), K.count), kBlock, 0,
                st>>>(tab, ctl, it, l, rx ? 1 : 0, skip1, rvec ? 1 : 0);
-  kg_csrc<M><<<dim3(cvec ? nblk(2 * Lc.half / 4) : nblk(2 * Lc.half), K.count), kBlock, 0,
-               st>>>(tab, ctl, it, l + 1, cvec ? 1 : 0);
   LAUNCHCHK();
   if (type == MG_CYCLE_V) {
-    ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_V, rx));
+    ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_V, true));
   } else if (type == MG_CYCLE_W) {
-    ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_W, rx));
+    ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_W, true));
     ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_W, false));
   } else {
-    ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_F, rx));
+    ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_F, true));
     ACHK(g_cycle<M>(ctx, st, K, L, o, it, l + 1, MG_CYCLE_V, false));
   }
   if (g_vec_coarse(Lc)) {
     kg_up<M == CQ ? 0 : 1><<<dim3(nblk(2 * Lc.half / 4), K.count), kBlock, 0, st>>>(
         tab, ctl, it, l);
   } else {
-    kg_coarse_diff<<<dim3(nblk(2 * Lc.half), K.count), kBlock, 0, st>>>(tab, ctl, it, l);
     kg_up_block<<<dim3(nblk(2 * Lc.half), K.count), kBlock, 0, st>>>(tab, ctl, it, l);
   }
   g_smooth<M>(ctx, st, K, L[l], it, l, o->nu_post);
