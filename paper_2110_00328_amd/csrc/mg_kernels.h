@@ -2337,47 +2337,6 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_corr(Lev Lf, Lev Lc, 
   if (g < 2 * Lc.half)
     op_resid_restrict_corr<M>(Lf, Lc, e, X, dens, rho, h2, eH, eR, rhoH, XH, C, g, Xf, rx);
 }
-// the same, 4 packed cells of one colour per thread (needs nh % 4 == 0);
-// per-cell arithmetic and summation order as above
-template <int M>
-__device__ __forceinline__ void op_coarse_src_corr_v(const Lev& L, const float* __restrict__ eR,
-                                                     const float* __restrict__ X,
-                                                     const float* __restrict__ dens,
-                                                     float* __restrict__ rho, float h2,
-                                                     const Consts& C, uint32_t g4) {
-  constexpr int V = Vec<float>::V;
-  const uint32_t g = g4 * V;
-  const int colour = g >= (uint32_t)L.half ? 1 : 0;
-  int ih0, j, k;
-  dec(g - (uint32_t)colour * (uint32_t)L.half, L, ih0, j, k);
-  float sum[V], ec[V], x[V], r[V], dc[V] = {0, 0, 0, 0};
-  nbsum_vec<float>(L, eR + (1 - colour) * L.half, ih0, j, k, (j + k + colour) & 1, sum);
-  ldv<float>(eR + g, ec);
-  ldv_nt<float>(X + g, x);
-  if (M != FR) ldv_nt<float>(dens + g, dc);
-  ldv_nt<float>(rho + g, r);
-#pragma unroll
-  for (int q = 0; q < V; ++q) r[q] = corr_G<M>(C, h2, ec[q], sum[q], x[q], dc[q]) - r[q];
-  stv_nt<float>(rho + g, r);
-}
-template <int M>
-__global__ __launch_bounds__(kBlock) void k_coarse_src_corr_v(Lev L, const float* __restrict__ eR,
-                                                              const float* __restrict__ X,
-                                                              const float* __restrict__ dens,
-                                                              float* __restrict__ rho, float h2,
-                                                              Consts C) {
-  const uint32_t g4 = (uint32_t)gid();
-  if (g4 < (uint32_t)(2 * L.half / Vec<float>::V))
-    op_coarse_src_corr_v<M>(L, eR, X, dens, rho, h2, C, g4);
-}
-template <int M>
-__global__ __launch_bounds__(kBlock) void k_coarse_src_corr(Lev L, const float* eR, const float* X,
-                                                            const float* dens, float* rho,
-                                                            float h2, Consts C) {
-  int64_t g = gid();
-  if (g < 2 * L.half) op_coarse_src_corr<M>(L, eR, X, dens, rho, h2, C, g);
-}
-
 // FP64 outer step of the refined mode: d = F(w64) (FP64), rho = -d, X = w64,
 // e = 0; per-block sum of d^2.
 template <int M>
