@@ -98,7 +98,8 @@ struct mg_ctx {
   int smooth_march_kt = 4;
   // coarse planes per workgroup of the prolongation fused into the first
   // post-smoothing half-sweep (0: separate prolongation and half-sweep),
-  // used where the smoother marches in z.  At 512^3 f(R) a step took 31.7
+  // halved where the grid would be too small (psmooth_min_blocks).  On the
+  // finest level of a 512^3 f(R) solve (plain coarse form) a step took 31.7
   // ms with 8, 31.8 with 4, 32.1 with 2, 32.2 with 16 and 32.9 unfused;
   // MGGPU_PROLONG_SMOOTH_KT overrides it at context creation
   int psmooth_kt = 8;
